@@ -1,0 +1,53 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only draws data.  It holds none of the sampler's arithmetic, so both the
+CPU oracle and the HIP path can consume its arrays without sharing any computation.
+
+Workloads (all x sorted ascending, numpy.random.default_rng(seed), draws in the
+order written below):
+
+* ``small_1d``   -- n=1000, x ~ U[0,1], y = sin(2 pi x) + 0.5 x^2 + N(0, 0.1^2), seed 0.
+  Shaped like the paper's small-n simulation (Section 5.1): a smooth function and
+  Gaussian noise at n = 1000.
+* ``large_1d``   -- n=2^20, x ~ U[0,1], y = sum_{k=1..5} a_k sin(2 pi f_k x + phi_k)
+  + N(0, 0.05^2) with f_k ~ U[1,20], a_k ~ N(0,1), phi_k ~ U[0, 2 pi), seed 1.
+  Shaped like the large-n simulation (Section 5.2) but at n = 2^20.
+* ``sinusoid_1d(n, seed, noise)`` -- the large_1d generator at any n (parity cases,
+  batched chains, served jobs).
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+
+def small_1d(n: int = 1000, seed: int = 0, noise: float = 0.1):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0.0, 1.0, n))
+    y = np.sin(2.0 * math.pi * x) + 0.5 * x * x + rng.normal(0.0, noise, n)
+    return x, y
+
+
+def sinusoid_1d(n: int, seed: int = 1, noise: float = 0.05, ncomp: int = 5):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0.0, 1.0, n))
+    freq = rng.uniform(1.0, 20.0, ncomp)
+    amp = rng.normal(0.0, 1.0, ncomp)
+    phase = rng.uniform(0.0, 2.0 * math.pi, ncomp)
+    f = np.zeros(n)
+    for k in range(ncomp):
+        f += amp[k] * np.sin(2.0 * math.pi * freq[k] * x + phase[k])
+    y = f + rng.normal(0.0, noise, n)
+    return x, y
+
+
+def large_1d(n: int = 1 << 20, seed: int = 1):
+    return sinusoid_1d(n, seed=seed, noise=0.05)
+
+
+# Sampler settings of the two single-chain workloads.  Every constant the paper leaves
+# open is spelled out here (nugget, priors, grid, start values).
+SMALL_1D = dict(n=1000, leaf=64, tol=1e-12, ell0=0.1, tau0=100.0, sigf2_0=1.0,
+                nugget=1e-6, iters=50, seed=0)
+LARGE_1D = dict(n=1 << 20, leaf=128, tol=1e-10, ell0=0.02, tau0=400.0, sigf2_0=1.0,
+                nugget=1e-6, iters=200, seed=1)
