@@ -1,0 +1,215 @@
+/*
+ * fifa_gp.h -- C ABI of the MI355X FIFA-GP hot path (libfifagp.so).
+ *
+ * One Gibbs iteration of the fast increased-fidelity approximate GP sampler of
+ * Moran & Wheeler (arXiv 2006.06537) on sorted 1-D inputs: build a HODLR
+ * approximation K~_1 of the unit-amplitude covariance, factor alpha K~_1 + beta I
+ * symmetrically as W W', solve, take log-determinants, draw f by Algorithm 1 and
+ * update tau, sigma_f^2 and the length-scale (Section 4.1).
+ *
+ * Conventions shared by every call
+ *   - Memory: every `double*` / `int64_t*` argument is DEVICE memory owned by the
+ *     caller unless the comment says "host".  Vectors are FP64, column-major when
+ *     they hold several right-hand sides (leading dimension `ld` >= n).
+ *   - Handles (fg_hodlr, fg_factor, fg_chain) own device memory allocated by the
+ *     library; destroy them with the matching *_destroy call.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  All calls
+ *     are stream-ordered and asynchronous unless stated; the return code covers
+ *     argument/configuration errors and launch failures only.  Failures found on
+ *     the device (a non-positive leaf pivot, a node singular value >= 1, a Gamma
+ *     sampler that ran out of tries) are recorded in the handle's status word and
+ *     read with fg_sync_status (which synchronises the stream).
+ *   - No exception crosses the ABI and nothing aborts.  fg_last_error() returns a
+ *     thread-local message for the last non-zero return code.
+ *   - Indices are 32-bit inside the library: n must satisfy 1 <= n < 2^31.
+ *   - Kernel: k_1(x,x') = exp(-(x-x')^2 / (2 ell^2)) (squared exponential, Section
+ *     2.1 / 4.1 with rho = 1/(2 ell^2)) or exp(-|x-x'|/ell) (exponential, a Matern
+ *     kernel of Section 2.1).  `nugget` is added to the diagonal before the
+ *     H-matrix construction (Section 4.1, "Additional considerations").
+ */
+#ifndef FIFA_GP_H
+#define FIFA_GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fg_status;
+#define FG_OK 0
+#define FG_EINVAL (-1)     /* bad argument or configuration                         */
+#define FG_ENOMEM (-2)     /* device allocation failed                              */
+#define FG_ENOTSPD (-3)    /* matrix not positive definite (leaf pivot / sigma >= 1) */
+#define FG_ETOL (-4)       /* tolerance needs more than 60 interpolation nodes      */
+#define FG_ENOTCONV (-5)   /* an iteration (Gamma tries, Jacobi sweeps) ran out     */
+#define FG_EDEVICE (-6)    /* HIP runtime error                                     */
+
+typedef void* fg_stream;                 /* hipStream_t */
+typedef struct fg_hodlr_s* fg_hodlr;     /* compressed K~_1, device resident */
+typedef struct fg_factor_s* fg_factor;   /* W with W W' = alpha K~_1 + beta I + diag(d) */
+typedef struct fg_chain_s* fg_chain;     /* one Gibbs chain and its cached factors */
+
+#define FG_KERNEL_SE 0
+#define FG_KERNEL_EXP 1
+
+typedef struct {
+  int32_t kind;          /* FG_KERNEL_SE or FG_KERNEL_EXP                 */
+  double lengthscale;    /* ell > 0                                        */
+  double nugget;         /* >= 0, added to the diagonal of K_1             */
+} fg_kernel;
+
+/* ---------------------------------------------------------------------------
+ * hodlr_build -- HODLR approximation K~_1 of K_1 = [k_1(x_i,x_j)] + nugget I.
+ * Section 3.2 (HODLR format: recursive 2x2 partition, dense diagonal leaves,
+ * low-rank off-diagonal blocks whose max-norm error is bounded by construction)
+ * and the inputs of Algorithm 1 (tolerance eps, maximum block size B).
+ *   x     device, n values, sorted ascending (non-decreasing); copied.
+ *   leaf  maximum leaf size B, 2 <= B <= 128.
+ *   tol   absolute max-norm bound on |K_1 - K~_1|, tol > 0.
+ * Each off-diagonal block: window rows within R of the split (k_1 < tol/3 beyond
+ * it), first-kind Chebyshev interpolation (per-variable error bound tol/6), then
+ * truncated SVD at max(tol/3, 8 u s_1).  Node ranks are decided on the device.
+ * Synchronises `stream` once (x is copied to the host for the tree plan).
+ * Errors: FG_EINVAL (n, leaf, tol, ell, unsorted x), FG_ETOL, FG_ENOMEM.
+ * ------------------------------------------------------------------------- */
+fg_status hodlr_build(const double* x, int64_t n, fg_kernel kernel, int32_t leaf,
+                      double tol, fg_stream stream, fg_hodlr* out);
+
+/* Host copy of the node ranks in heap order (node 0 = root, children 2h+1,
+ * 2h+2; 2^L - 1 internal nodes).  `ranks` is host memory of `cap` entries;
+ * `*count` receives 2^L - 1.  Synchronises the stream. */
+fg_status hodlr_ranks(fg_hodlr A, int32_t* ranks, int32_t cap, int32_t* count,
+                      fg_stream stream);
+
+/* Host copy of the tree: *levels = L, *n_out = n.  Either pointer may be NULL. */
+fg_status hodlr_info(fg_hodlr A, int32_t* levels, int64_t* n_out);
+
+/* Host copy of each node's singular values of the interpolant (heap order, `cap`
+ * doubles per node, zero padded).  For rank-decision diagnostics.  Syncs. */
+fg_status hodlr_singular_values(fg_hodlr A, double* sv, int32_t cap, fg_stream stream);
+
+/* out[t] = K~_1[i[t], j[t]] for t < count (device index arrays, int64). */
+fg_status hodlr_entries(fg_hodlr A, const int64_t* i, const int64_t* j, int64_t count,
+                        double* out, fg_stream stream);
+
+/* y = (alpha K~_1 + beta I) v for nrhs columns (ld >= n).  v and y must not
+ * overlap.  O(n log n) per column (Algorithm 1's H-matrix products). */
+fg_status hodlr_matvec(fg_hodlr A, double alpha, double beta, const double* v, double* y,
+                       int32_t nrhs, int64_t ld, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * hodlr_factor -- symmetric factor W W' = alpha K~_1 + beta I + diag(d)
+ * (SI "HODLR decomposition and factorization": W = A_L ... A_0, block-diagonal
+ * leaf Cholesky factor times one identity-plus-low-rank factor per level).  The
+ * node factor is the canonical one, W_nu = [[I, 0], [C', (I - C'C)^(1/2)]] with
+ * C the whitened off-diagonal block, so W depends on the matrix only.
+ *   alpha > 0, beta >= 0 (host values); diag: device, n values or NULL.
+ * The factor keeps a reference to A's data: destroy it before A.
+ * Device failures: FG_ENOTSPD in the factor's status word.
+ * ------------------------------------------------------------------------- */
+fg_status hodlr_factor(fg_hodlr A, double alpha, double beta, const double* diag,
+                       fg_stream stream, fg_factor* out);
+
+/* x = (W W')^-1 b = W^-T W^-1 b for nrhs columns.  b and x may be the same. */
+fg_status hodlr_solve(fg_factor F, const double* b, double* x, int32_t nrhs, int64_t ld,
+                      fg_stream stream);
+
+/* *logdet_dev = log det(W W') = 2 sum log diag(L_leaf) + sum_nodes sum_i
+ * log(1 - sigma_i^2) (SI "Determinant computation speedup": block determinants
+ * and Sylvester's theorem).  logdet_dev: device, one double. */
+fg_status hodlr_logdet(fg_factor F, double* logdet_dev, fg_stream stream);
+
+/* y = op(W) v with op = W (transpose=0, inverse=0), W' (1,0), W^-1 (0,1),
+ * W^-T (1,1); nrhs columns.  v and y may be the same. */
+fg_status hodlr_apply_w(fg_factor F, int32_t transpose, int32_t inverse, const double* v,
+                        double* y, int32_t nrhs, int64_t ld, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Counter-based normals: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
+ * counter (block, tag, iteration, stream), uniforms ((w >> 12) + 0.5) 2^-52,
+ * Box-Muller in pairs (cos, sin).  out: device, n doubles.
+ * ------------------------------------------------------------------------- */
+fg_status fg_normals(uint64_t seed, uint64_t tag, uint64_t iteration, uint64_t stream_id,
+                     int64_t n, double* out, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * gp_draw_f -- Algorithm 1 (Section 4.1.1) with K~ = sigf2 K~_1, W = sqrt(sigf2) W_1,
+ * M~ = tau K~ + I:  a, b ~ N(0, I) (tags 1 and 2 of (seed, iteration, stream_id));
+ * Z = sqrt(tau) K~ a + W b;  M~ w = Z;  M~ r = tau y;  f = w + K~ r.
+ *   K1  compressed K~_1;  W1 factor of K~_1 (alpha 1, beta 0);
+ *   WM  factor of K~_1 with alpha = tau*sigf2, beta = 1.
+ *   y, f, r device n-vectors; mu (device, n, or NULL) receives K~ r, the
+ *   approximate posterior mean of Lemma 4.1; r = Sigma~^-1 y.
+ * ------------------------------------------------------------------------- */
+fg_status gp_draw_f(fg_hodlr K1, fg_factor W1, fg_factor WM, double sigf2, double tau,
+                    const double* y, uint64_t seed, uint64_t iteration, uint64_t stream_id,
+                    double* f, double* r, double* mu, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Gibbs chain (Section 4.1): sweep f -> tau -> sigma_f^-2 -> length-scale.
+ *   tau     | - ~ Ga((a1+n)/2, (b1 + |y-f|^2)/2)            (shape, rate)
+ *   sf^-2   | - ~ Ga((a2+n)/2, (b2 + f' K~_1^-1 f)/2)
+ *   ell on the grid ell_k = ell0 10^((k - center)/50), k = 0..grid_size-1, by a
+ *   Metropolis step on neighbours k +- 1 (the paper's suggested replacement for the
+ *   discrete conditional): accept with min(1, exp(D)),
+ *   D = -1/2 (log|K~_1'| - log|K~_1|) - (q' - q)/(2 sigf2),  q = |W_1^-1 f|^2.
+ * Random numbers: tags 1 (a), 2 (b), 3 (tau Gamma), 4 (sigma Gamma), 5
+ * (proposal), 6 (acceptance) of (seed, iteration, stream_id).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t kind;          /* FG_KERNEL_SE / FG_KERNEL_EXP */
+  double ell0;           /* grid centre length-scale */
+  double nugget;         /* added to K_1's diagonal */
+  int32_t leaf;          /* maximum leaf size */
+  double tol;            /* max-norm tolerance on K_1 */
+  double tau0;           /* initial noise precision */
+  double sigf2_0;        /* initial sigma_f^2 */
+  double a1, b1, a2, b2; /* Gamma prior parameters (tau ~ Ga(a1/2, b1/2), ...) */
+  int32_t grid_size;     /* number of length-scales (e.g. 100) */
+  int32_t grid_center;   /* starting index (e.g. 50) */
+  uint64_t seed;
+  uint64_t stream_id;    /* chain id in the Philox counter */
+} fg_chain_cfg;
+
+typedef struct {
+  int64_t iteration;     /* completed sweeps */
+  double tau, sigf2, ell;
+  int32_t k;             /* grid index of ell */
+  int32_t last_proposal; /* proposed grid index of the last sweep (-1/grid_size = off grid) */
+  int32_t last_accept;   /* 1 if the last proposal was accepted */
+  int32_t accepts;       /* accepted proposals so far */
+  double logdet_sigma;   /* log|Sigma~| of the last f-draw, Sigma~ = K~ + I/tau */
+  double yr;             /* y' Sigma~^-1 y */
+  double loglik;         /* Eq. 2 (with 1/2 on log det) at the last f-draw */
+  double sse;            /* |y - f|^2 */
+  double q;              /* f' K~_1^-1 f at the current length-scale */
+  double logdet1;        /* log|K~_1| at the current length-scale */
+  double mh_log_ratio;   /* D of the last Metropolis step (0 if off grid) */
+  int32_t status;        /* device status word (FG_OK or a negative code) */
+} fg_chain_snapshot;
+
+/* x, y: device n-vectors (x sorted); copied.  Builds and factors K~_1 at ell0. */
+fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const double* y,
+                             int64_t n, fg_stream stream, fg_chain* out);
+/* Runs `iters` sweeps.  Synchronises once per sweep (the accepted length-scale
+ * selects which cached factor the next sweep uses). */
+fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream);
+/* Host snapshot of the scalars; if f_out (device, n) is not NULL it receives f
+ * (and r_out, mu_out likewise: Sigma~^-1 y and K~ r of the last f-draw). */
+fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_out,
+                            double* r_out, double* mu_out, fg_stream stream);
+
+/* Status word of a handle (synchronises the stream first). */
+fg_status hodlr_status(fg_hodlr A, fg_stream stream);
+fg_status factor_status(fg_factor F, fg_stream stream);
+
+const char* fg_last_error(void);
+void hodlr_destroy(fg_hodlr A);
+void factor_destroy(fg_factor F);
+void gibbs_chain_destroy(fg_chain c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIFA_GP_H */

@@ -1,0 +1,213 @@
+"""FIFA-GP hot path on MI355X: HODLR build / symmetric factor / solve / log-det,
+Algorithm 1 draws and the Gibbs sweep of Moran & Wheeler (arXiv 2006.06537).
+
+Thin Python face of libfifagp.so.  Tensors are torch FP64 tensors on the HIP
+device; every call goes straight to the C ABI of include/fifa_gp.h on the current
+stream.  Nothing here computes: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, check,
+                   lib)
+
+__all__ = ["Hodlr", "Factor", "Chain", "normals", "draw_f", "KERNEL_SE", "KERNEL_EXP",
+           "FgError", "lib"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev(t, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("expected a float64 tensor on the HIP device")
+    if not t.is_contiguous() and t.dim() == 1:
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"expected {n} rows, got {t.shape[0]}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _cols(t):
+    """(nrhs, ld) of a vector or of a column-major block stored as a (nrhs, ld) tensor."""
+    if t.dim() == 1:
+        return 1, t.shape[0]
+    if not t.is_contiguous():
+        raise ValueError("multi-column blocks are (nrhs, n) contiguous tensors")
+    return t.shape[0], t.shape[1]
+
+
+class Hodlr:
+    """Compressed K~_1 (hodlr_build)."""
+
+    def __init__(self, x, lengthscale, nugget=1e-6, leaf=128, tol=1e-10, kind=KERNEL_SE):
+        self.n = int(x.shape[0])
+        h = C.c_void_p()
+        check(lib().hodlr_build(_dev(x), self.n, Kernel(kind, lengthscale, nugget), leaf, tol,
+                                _stream(), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def levels(self):
+        L = C.c_int32()
+        check(lib().hodlr_info(self._h, C.byref(L), None))
+        return L.value
+
+    def ranks(self):
+        cnt = C.c_int32()
+        nint = (1 << self.levels()) - 1
+        buf = (C.c_int32 * max(nint, 1))()
+        check(lib().hodlr_ranks(self._h, buf, max(nint, 1), C.byref(cnt), _stream()))
+        return [buf[i] for i in range(cnt.value)]
+
+    def singular_values(self, cap=60):
+        nint = (1 << self.levels()) - 1
+        buf = (C.c_double * max(nint * cap, 1))()
+        check(lib().hodlr_singular_values(self._h, buf, cap, _stream()))
+        return [[buf[h * cap + j] for j in range(cap)] for h in range(nint)]
+
+    def entries(self, i, j):
+        torch = _torch()
+        out = torch.empty(i.shape[0], dtype=torch.float64, device=i.device)
+        check(lib().hodlr_entries(self._h, C.c_void_p(i.data_ptr()), C.c_void_p(j.data_ptr()),
+                                  int(i.shape[0]), _dev(out), _stream()))
+        return out
+
+    def matvec(self, v, alpha=1.0, beta=0.0):
+        torch = _torch()
+        y = torch.empty_like(v)
+        nrhs, ld = _cols(v)
+        check(lib().hodlr_matvec(self._h, alpha, beta, _dev(v), _dev(y), nrhs, ld, _stream()))
+        return y
+
+    def status(self):
+        return lib().hodlr_status(self._h, _stream())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        try:
+            if h is not None and h.value and _lib._lib is not None:
+                _lib._lib.hodlr_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self._h = None
+
+
+class Factor:
+    """W W' = alpha K~_1 + beta I + diag(d) (hodlr_factor)."""
+
+    def __init__(self, H: Hodlr, alpha=1.0, beta=0.0, diag=None):
+        self.H = H  # keep the matrix alive
+        f = C.c_void_p()
+        check(lib().hodlr_factor(H.handle, alpha, beta, _dev(diag) if diag is not None else None,
+                                 _stream(), C.byref(f)))
+        self._f = f
+
+    @property
+    def handle(self):
+        return self._f
+
+    def logdet(self):
+        torch = _torch()
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        check(lib().hodlr_logdet(self._f, _dev(out), _stream()))
+        return out
+
+    def solve(self, b):
+        torch = _torch()
+        x = torch.empty_like(b)
+        nrhs, ld = _cols(b)
+        check(lib().hodlr_solve(self._f, _dev(b), _dev(x), nrhs, ld, _stream()))
+        return x
+
+    def apply(self, v, transpose=False, inverse=False):
+        torch = _torch()
+        y = torch.empty_like(v)
+        nrhs, ld = _cols(v)
+        check(lib().hodlr_apply_w(self._f, int(transpose), int(inverse), _dev(v), _dev(y), nrhs,
+                                  ld, _stream()))
+        return y
+
+    def status(self):
+        return lib().factor_status(self._f, _stream())
+
+    def __del__(self):
+        f = getattr(self, "_f", None)
+        try:
+            if f is not None and f.value and _lib._lib is not None:
+                _lib._lib.factor_destroy(f)
+        except Exception:  # interpreter shutdown
+            pass
+        self._f = None
+
+
+def normals(n, seed, tag, iteration, stream_id):
+    torch = _torch()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    check(lib().fg_normals(seed, tag, iteration, stream_id, n, _dev(out), _stream()))
+    return out
+
+
+def draw_f(K1: Hodlr, W1: Factor, WM: Factor, sigf2, tau, y, seed, iteration, stream_id):
+    """Algorithm 1: returns (f, r, mu)."""
+    torch = _torch()
+    f = torch.empty_like(y)
+    r = torch.empty_like(y)
+    mu = torch.empty_like(y)
+    check(lib().gp_draw_f(K1.handle, W1.handle, WM.handle, sigf2, tau, _dev(y), seed, iteration,
+                          stream_id, _dev(f), _dev(r), _dev(mu), _stream()))
+    return f, r, mu
+
+
+class Chain:
+    """One Gibbs chain (gibbs_chain_create / gibbs_step / gibbs_chain_state)."""
+
+    def __init__(self, x, y, ell0, tau0, sigf2_0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
+                 seed=0, stream_id=0, kind=KERNEL_SE, priors=(1.0, 1.0, 1.0, 1.0),
+                 grid_size=100, grid_center=50):
+        self.n = int(x.shape[0])
+        cfg = ChainCfg(kind, ell0, nugget, leaf, tol, tau0, sigf2_0, priors[0], priors[1],
+                       priors[2], priors[3], grid_size, grid_center, seed, stream_id)
+        c = C.c_void_p()
+        check(lib().gibbs_chain_create(C.byref(cfg), _dev(x, self.n), _dev(y, self.n), self.n,
+                                       _stream(), C.byref(c)))
+        self._c = c
+
+    def step(self, iters=1):
+        check(lib().gibbs_step(self._c, iters, _stream()))
+
+    def state(self, with_vectors=False):
+        torch = _torch()
+        snap = ChainSnapshot()
+        if with_vectors:
+            f = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            r = torch.empty_like(f)
+            mu = torch.empty_like(f)
+            check(lib().gibbs_chain_state(self._c, C.byref(snap), _dev(f), _dev(r), _dev(mu),
+                                          _stream()))
+            d = snap.as_dict()
+            d.update(f=f, r=r, mu=mu)
+            return d
+        check(lib().gibbs_chain_state(self._c, C.byref(snap), None, None, None, _stream()))
+        return snap.as_dict()
+
+    def __del__(self):
+        c = getattr(self, "_c", None)
+        try:
+            if c is not None and c.value and _lib._lib is not None:
+                _lib._lib.gibbs_chain_destroy(c)
+        except Exception:  # interpreter shutdown
+            pass
+        self._c = None

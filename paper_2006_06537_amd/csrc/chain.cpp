@@ -1,0 +1,249 @@
+// One FIFA-GP Gibbs chain on the device (Section 4.1): f by Algorithm 1, tau and
+// sigma_f^-2 by their conjugate Gamma conditionals, and the length-scale by a Metropolis
+// step on a grid (the replacement for the discrete conditional that the paper
+// suggests).  The chain keeps two slots of (K~_1, W_1) -- the current length-scale and
+// the proposal -- and swaps them on acceptance; all plans of the grid are made and
+// uploaded once, so a sweep only enqueues kernels and synchronises once at its end.
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fg_internal.h"
+#include "fg_rng.h"
+
+struct fg_chain_s {
+  fg_chain_cfg cfg{};
+  int n = 0;
+  std::vector<double> grid;
+  std::vector<fg::PlanPack*> packs;
+  fg::Caps caps;
+  fg::HodlrData H[2];
+  fg::FactorData W[2];
+  fg::FactorData WM;
+  int cur = 0;
+  int k = 0;
+  int64_t iter = 0;
+  double *x = nullptr, *y = nullptr, *f = nullptr, *r = nullptr, *mu = nullptr;
+  double* vecs = nullptr;     // 4 n workspace
+  double* dotwork = nullptr;  // reduction partials
+  fg::DevState* st = nullptr;
+  fg::DevState* st_host = nullptr;  // pinned
+};
+
+using fg::set_error;
+
+static fg_status cfail(fg_status st, const std::string& m) {
+  set_error(m);
+  return st;
+}
+
+static void chain_free(fg_chain c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
+  fg::factor_free(c->WM);
+  for (auto* p : c->packs) fg::plan_pack_destroy(p);
+  double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork};
+  for (double* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->st) (void)hipFree(c->st);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+}
+
+extern "C" {
+
+fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const double* y, int64_t n,
+                             fg_stream stream, fg_chain* out) {
+  if (!out) return cfail(FG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !x || !y) return cfail(FG_EINVAL, "NULL argument");
+  if (n < 1 || n >= (int64_t(1) << 31)) return cfail(FG_EINVAL, "n out of range");
+  if (cfg->grid_size < 1 || cfg->grid_center < 0 || cfg->grid_center >= cfg->grid_size)
+    return cfail(FG_EINVAL, "bad grid");
+  if (!(cfg->tau0 > 0) || !(cfg->sigf2_0 > 0) || !(cfg->ell0 > 0))
+    return cfail(FG_EINVAL, "tau0, sigf2_0 and ell0 must be > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  fg_chain c = new fg_chain_s();
+  c->cfg = *cfg;
+  c->n = int(n);
+  std::vector<double> xh(n);
+  if (hipMemcpyAsync(xh.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_EDEVICE, "copy of x to the host failed");
+  }
+  c->grid.resize(cfg->grid_size);
+  for (int g = 0; g < cfg->grid_size; ++g)
+    c->grid[g] = cfg->ell0 * std::pow(10.0, (g - cfg->grid_center) / 50.0);
+  fg_status st;
+  std::string err;
+  for (int g = 0; g < cfg->grid_size; ++g) {
+    fg::PlanPack* pk = fg::plan_pack_create(xh.data(), int(n), cfg->kind, c->grid[g], cfg->nugget,
+                                            cfg->leaf, cfg->tol, s, st, err);
+    if (!pk) { chain_free(c); return cfail(st, err); }
+    c->packs.push_back(pk);
+    c->caps.add(*pk);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if ((st = fg::hodlr_alloc(c->H[i], c->caps, err)) != FG_OK ||
+        (st = fg::factor_alloc(c->W[i], c->caps, err)) != FG_OK) {
+      chain_free(c);
+      return cfail(st, err);
+    }
+  }
+  if ((st = fg::factor_alloc(c->WM, c->caps, err)) != FG_OK) { chain_free(c); return cfail(st, err); }
+  const size_t nb = sizeof(double) * (size_t)n;
+  if (hipMalloc(reinterpret_cast<void**>(&c->x), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->f), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->r), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->mu), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->vecs), 4 * nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 2048) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(fg::DevState)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::DevState)) != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_ENOMEM, "chain allocation failed");
+  }
+  hipMemcpyAsync(c->x, x, nb, hipMemcpyDeviceToDevice, s);
+  hipMemcpyAsync(c->y, y, nb, hipMemcpyDeviceToDevice, s);
+  hipMemsetAsync(c->f, 0, nb, s);
+  for (int i = 0; i < 2; ++i) hipMemcpyAsync(c->H[i].x, x, nb, hipMemcpyDeviceToDevice, s);
+  // initial state and the factor of K~_1 at the starting length-scale
+  fg::DevState init{};
+  init.tau = cfg->tau0;
+  init.sigf2 = cfg->sigf2_0;
+  init.k = cfg->grid_center;
+  *c->st_host = init;
+  hipMemcpyAsync(c->st, c->st_host, sizeof(fg::DevState), hipMemcpyHostToDevice, s);
+  c->k = cfg->grid_center;
+  c->cur = 0;
+  c->H[0].pk = c->packs[c->k];
+  fg::launch_build(c->H[0], s);
+  c->W[0].H = &c->H[0];
+  c->W[0].alpha = 1.0;
+  c->W[0].beta = 0.0;
+  fg::launch_factor(c->W[0], nullptr, nullptr, nullptr, s);
+  hipMemcpyAsync(&c->st->logdet1, c->W[0].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_EDEVICE, "chain set-up failed on the device");
+  }
+  *out = c;
+  return FG_OK;
+}
+
+fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
+  if (!c || iters < 0) return cfail(FG_EINVAL, "bad arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = c->n;
+  const fg_chain_cfg& cf = c->cfg;
+  double* v0 = c->vecs;
+  double* v1 = v0 + n;
+  double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, tau y]
+  double* v3 = v2 + n;
+  for (int it = 0; it < iters; ++it) {
+    const uint64_t t = (uint64_t)c->iter;
+    const int cur = c->cur, oth = 1 - cur;
+    fg::launch_sweep_begin(c->st, s);
+    // f | -  (Algorithm 1)
+    c->WM.H = &c->H[cur];
+    c->WM.alpha = 0.0;  // taken from the device scalar
+    c->WM.beta = 1.0;
+    fg::launch_factor(c->WM, &c->st->alphaM, nullptr, nullptr, s);
+    hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+    fg::launch_normals(cf.seed, 1, t, cf.stream_id, n, v0, s);
+    fg::launch_normals(cf.seed, 2, t, cf.stream_id, n, v1, s);
+    fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
+    fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
+    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
+    fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
+    fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
+    fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
+                      c->H[cur].work, s);
+    fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
+    hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
+    fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
+    // tau | -
+    fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, t, cf.stream_id, s);
+    // sigma_f^-2 | -
+    hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    fg::launch_apply_w(c->W[cur], 2, v0, 1, n, c->W[cur].work, s);
+    fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
+    fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, t, cf.stream_id, s);
+    // length-scale | -  (Metropolis on the grid; the proposal uniform is known on the host)
+    uint64_t w[4];
+    fg::philox4x64_10(0, 5, t, cf.stream_id, cf.seed, 0, w);
+    const int kp = c->k + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
+    const int ongrid = (kp >= 0 && kp < cf.grid_size) ? 1 : 0;
+    if (ongrid) {
+      fg::launch_zero_int(c->H[oth].status, 1, s);
+      fg::launch_zero_int(c->W[oth].status, 1, s);
+      c->H[oth].pk = c->packs[kp];
+      fg::launch_build(c->H[oth], s);
+      c->W[oth].H = &c->H[oth];
+      c->W[oth].alpha = 1.0;
+      c->W[oth].beta = 0.0;
+      fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, s);
+      hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+      hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
+      fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
+    }
+    fg::launch_mh_step(c->st, kp, ongrid, cf.seed, t, cf.stream_id,
+                       ongrid ? c->H[oth].status : nullptr, ongrid ? c->W[oth].status : nullptr, s);
+    hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
+    if (c->st_host->accept) {
+      c->cur = oth;
+      c->k = kp;
+    }
+    c->iter += 1;
+  }
+  return FG_OK;
+}
+
+fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_out, double* r_out,
+                            double* mu_out, fg_stream stream) {
+  if (!c || !host_out) return cfail(FG_EINVAL, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nb = sizeof(double) * c->n;
+  if (f_out) hipMemcpyAsync(f_out, c->f, nb, hipMemcpyDeviceToDevice, s);
+  if (r_out) hipMemcpyAsync(r_out, c->r, nb, hipMemcpyDeviceToDevice, s);
+  if (mu_out) hipMemcpyAsync(mu_out, c->mu, nb, hipMemcpyDeviceToDevice, s);
+  hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "state copy failed");
+  int fst = 0;
+  int hs = 0, ws = 0, ms = 0;
+  hipMemcpy(&hs, c->H[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
+  hipMemcpy(&ws, c->W[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
+  hipMemcpy(&ms, c->WM.status, sizeof(int), hipMemcpyDeviceToHost);
+  fst = c->st_host->status | hs | ws | ms;
+  const fg::DevState& d = *c->st_host;
+  host_out->iteration = c->iter;
+  host_out->tau = d.tau;
+  host_out->sigf2 = d.sigf2;
+  host_out->k = d.k;
+  host_out->ell = c->grid[d.k];
+  host_out->last_proposal = d.kprop;
+  host_out->last_accept = d.accept;
+  host_out->accepts = d.accepts;
+  host_out->logdet_sigma = d.logdet_sigma;
+  host_out->yr = d.yr;
+  host_out->loglik = d.loglik;
+  host_out->sse = d.sse;
+  host_out->q = d.q;
+  host_out->logdet1 = d.logdet1;
+  host_out->mh_log_ratio = d.mh;
+  host_out->status = (fst & fg::ST_NOTSPD) ? FG_ENOTSPD : (fst & fg::ST_NOTCONV) ? FG_ENOTCONV : FG_OK;
+  return FG_OK;
+}
+
+void gibbs_chain_destroy(fg_chain c) { chain_free(c); }
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal declarations of libfifagp (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fifa_gp.h"
+
+namespace fg {
+
+constexpr int PMAX = 60;          // interpolation nodes per side (and rank cap)
+constexpr int BMAX = 128;         // maximum leaf size
+constexpr int NTHREADS = 256;     // work-group size of every kernel
+constexpr int RCH = 256;          // rows per level-task (reduce / update)
+constexpr int MCH = 4096;         // rows per moment / panel-generation task
+constexpr double KAPPA_H = 1.086435;  // Cramer: |H_n(x)| e^{-x^2/2} <= KAPPA_H 2^{n/2} sqrt(n!)
+
+// status bits written by kernels (device word, OR-ed)
+constexpr int ST_NOTSPD = 1;
+constexpr int ST_NOTCONV = 2;
+constexpr int ST_TOL = 4;
+
+// One internal tree node: rows [lo, hi) split at mid; window rows [i0, mid) of the
+// left child and [mid, j1) of the right child carry the off-diagonal block.
+struct NodePlan {
+  int lo, mid, hi;
+  int i0, j1;
+  int pI, pJ;          // basis sizes (Chebyshev nodes, or window size when exact)
+  int exactI, exactJ;  // 1: the window's inputs themselves are the nodes
+  int level;
+  int toff_u, toff_v;  // offsets (doubles) of T_U (pI x kcap) and T_V (pJ x kcap)
+  int mom_off_i, mom_off_j;  // offsets (doubles) of the final moments of each side
+  int pad;
+  double aI, bI, aJ, bJ;     // interpolation intervals
+};
+
+// A contiguous row range of one side of one node.
+struct Task {
+  int h;     // heap index of the internal node
+  int side;  // 0: left child rows (U), 1: right child rows (V)
+  int r0, r1;
+};
+
+// Host-side plan of one HODLR build (tree + windows + interpolation sizes).
+struct HostPlan {
+  int n = 0, B = 0, L = 0, nint = 0, nleaf = 0;
+  int kind = 0;
+  double ell = 0, nugget = 0, tol = 0;
+  std::vector<int> leaf_lo;              // nleaf + 1
+  std::vector<NodePlan> nodes;           // nint
+  std::vector<int> kcap, coff;           // per level
+  int Ktot = 0, kcapmax = 0, pmax = 0;
+  int tbuf_size = 0;                     // doubles for all T_U / T_V
+  int mom_size = 0;                      // doubles for final moments
+  std::vector<Task> mtasks;              // moment tasks (Chebyshev sides, window rows)
+  std::vector<int> mtask_off;            // per node side: first moment-task index (2*nint+1)
+  int mpart_stride = 0;                  // doubles per moment partial (2*PMAX-1 padded)
+  std::vector<Task> gtasks;              // panel-generation tasks (all rows of both sides)
+  std::vector<Task> ltasks;              // level tasks, grouped by level
+  std::vector<int> ltask_off;            // L + 1
+  std::vector<int> node_task_off;        // per node side: first level task (2*nint+1)
+  int max_ltasks = 0;
+  int nmt = 0, ngt = 0, nlt = 0;         // task counts (kept after the vectors are freed)
+};
+
+// Builds the plan; returns FG_OK, FG_EINVAL or FG_ETOL (message in err).
+fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                    double tol, HostPlan& P, std::string& err);
+
+// Device copy of a plan plus per-level device arrays.
+struct DevPlan {
+  NodePlan* nodes = nullptr;
+  int* leaf_lo = nullptr;
+  Task* mtasks = nullptr;
+  int* mtask_off = nullptr;
+  Task* gtasks = nullptr;
+  Task* ltasks = nullptr;
+  int* node_task_off = nullptr;
+  int* coff = nullptr;
+  int* kcap = nullptr;
+  int* nodemat_off = nullptr;
+};
+
+// One plan on host and device, plus the buffer sizes it needs.
+struct PlanPack {
+  HostPlan P;                    // task vectors are released after upload (counts kept)
+  DevPlan D;
+  std::vector<int> nodemat_off;  // per node offset (doubles) of G_V, F1, F2
+  size_t nodemat_size = 0;
+  size_t zpart_size = 0, zfin_size = 0, coef_size = 0;  // factorization scratch (doubles)
+  size_t mpart_size = 0;
+  size_t mv_work = 0, ap_work = 0;
+};
+
+// Plans the tree for x (host copy), uploads it; nullptr on error (status, err set).
+PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                           double tol, hipStream_t s, fg_status& st, std::string& err);
+void plan_pack_destroy(PlanPack* pk);
+
+// Buffers of one compressed matrix, sized for `cap` (>= the plan it currently holds).
+struct HodlrData {
+  const PlanPack* pk = nullptr;
+  double* x = nullptr;       // n
+  double* tbuf = nullptr;    // T_U / T_V
+  double* mpart = nullptr;   // moment partials
+  double* sv = nullptr;      // nint x PMAX singular values
+  int* rank = nullptr;       // nint
+  int* kmax = nullptr;       // L (device-decided max rank per level)
+  int* rcols = nullptr;      // L x Ktot: right-column lists per level
+  int* rcount = nullptr;     // L
+  double* panel = nullptr;   // ld x Ktot, column-major (U rows in left children)
+  int ld = 0;
+  int* status = nullptr;     // device status word
+  double* work = nullptr;    // matvec workspace
+};
+
+struct FactorData {
+  const HodlrData* H = nullptr;
+  double alpha = 1, beta = 0;
+  double* leafL = nullptr;     // nleaf x B x B
+  double* leafLinv = nullptr;  // nleaf x B x B
+  double* leaf_ld = nullptr;   // nleaf
+  double* panel = nullptr;     // whitened panels, same layout as H->panel
+  double* nodemat = nullptr;   // per node: G_V, F1, F2 (k x k each)
+  double* node_ld = nullptr;   // nint
+  double* zpart = nullptr;     // reduce partials
+  double* zfin = nullptr;      // per node final Gram blocks of one level
+  double* coef = nullptr;      // per node update coefficients of one level
+  double* logdet = nullptr;    // device scalar
+  int* status = nullptr;
+  double* work = nullptr;      // sweep workspace
+};
+
+// capacity of a set of plans
+struct Caps {
+  int n = 0, B = 0, L = 0, nint = 0, nleaf = 0;
+  size_t tbuf = 1, mpart = 1, Ktot = 1, nodemat = 1, zpart = 1, zfin = 1, coef = 1;
+  size_t mv_work = 1, ap_work = 1;
+  void add(const PlanPack& pk);
+};
+fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err);
+void hodlr_free(HodlrData& H);
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err);
+void factor_free(FactorData& F);
+
+// -------- kernels' host launchers (stream-ordered) --------
+void launch_build(HodlrData& H, hipStream_t s);
+void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
+                   const double* diag, hipStream_t s);
+void launch_logdet_sum(FactorData& F, hipStream_t s);
+// op: 0 = W, 1 = W', 2 = W^-1, 3 = W^-T; in place on v (ld x nrhs)
+void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
+                    hipStream_t s);
+// y = alpha K~_1 v + beta v (alpha/beta from device pointers when non-null)
+void launch_matvec(const HodlrData& H, double alpha, double beta, const double* alpha_dev,
+                   const double* beta_dev, const double* v, double* y, int nrhs, int ld,
+                   double* work, hipStream_t s);
+void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int64_t count,
+                    double* out, hipStream_t s);
+void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
+                    double* out, hipStream_t s);
+// out = scale * sum (a-b)^2 or sum a*b etc (deterministic two-stage)
+void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
+                hipStream_t s);
+void launch_axpby(int n, const double* x, const double* y, double* out,
+                  const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
+
+size_t matvec_work_doubles(const HostPlan& P, int nrhs);
+size_t apply_work_doubles(const HostPlan& P, int nrhs);
+
+// error helper
+void set_error(const std::string& msg);
+
+}  // namespace fg

@@ -1,0 +1,319 @@
+// Vector operators of a HODLR matrix and of its symmetric factor (gfx950 kernels):
+// W v, W' v, W^-1 v, W^-T v (level sweeps over the canonical node factors) and the
+// product (alpha K~_1 + beta I) v (dense leaves evaluated on the fly + low-rank
+// blocks, all levels in one pass).
+//
+// Per node, with s = U~' v_I and t = V~' v_J (level reduce) the node operators are
+//   W      : v_J += V~ (s + F1 t)
+//   W'     : v_I += U~ t,                 v_J += V~ F1 t
+//   W^-1   : v_J += V~ (-s + F2 (t - G_V s))
+//   W^-T   : w = F2 t; v_I -= U~ (t + G_V w); v_J += V~ w
+// and the order of levels follows W = L_D W_(L-1) ... W_(0).
+#include "fg_internal.h"
+
+namespace fg {
+
+constexpr int NRHS_MAX = 4;
+
+__device__ __forceinline__ double kernel_v(int kind, double ell, double a, double b) {
+  const double d = a - b;
+  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
+  return exp(-fabs(d) / ell);
+}
+
+__device__ __forceinline__ double wave_red(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// leaf block operator, in place on v: op 0 L, 1 L', 2 Linv, 3 Linv'
+__global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
+                                                         const double* __restrict__ M, int Bc,
+                                                         int trans, double* __restrict__ v,
+                                                         int nrhs, int ld) {
+  const int b = blockIdx.x;
+  if (b >= nleaf) return;
+  const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  __shared__ double vs[NRHS_MAX][BMAX];
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
+    vs[idx / m][idx % m] = v[(size_t)(idx / m) * ld + lo + idx % m];
+  __syncthreads();
+  const double* Mb = M + (size_t)b * Bc * Bc;
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS) {
+    const int r = idx % m, c = idx / m;
+    double acc = 0.0;
+    if (!trans) {
+      for (int s = 0; s <= r; ++s) acc += Mb[r + s * Bc] * vs[c][s];
+    } else {
+      for (int s = r; s < m; ++s) acc += Mb[s + r * Bc] * vs[c][s];
+    }
+    v[(size_t)c * ld + lo + r] = acc;
+  }
+}
+
+// level reduce with a vector right operand: z[t][a][c] = sum_rows P[i, coff + a] v[i, c]
+__global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
+    const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
+    const int* __restrict__ coff, const int* __restrict__ kmax, const double* __restrict__ P,
+    int ld, const double* __restrict__ v, int nrhs, int ldv, double* __restrict__ zpart,
+    int zs_task) {
+  const int t = blockIdx.x;
+  if (t >= ntask) return;
+  const Task tk = tasks[tbase + t];
+  const int l = nodes[tk.h].level;
+  const int c0 = coff[l], kl = kmax[l];
+  const int rw = tk.r1 - tk.r0;
+  __shared__ double vs[NRHS_MAX][RCH];
+  for (int idx = threadIdx.x; idx < rw * nrhs; idx += NTHREADS)
+    vs[idx / rw][idx % rw] = v[(size_t)(idx / rw) * ldv + tk.r0 + idx % rw];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = wv; a < kl; a += NTHREADS / 64) {
+    double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
+    const double* pc = P + (size_t)(c0 + a) * ld + tk.r0;
+    for (int i = lane; i < rw; i += 64) {
+      const double pv = pc[i];
+      for (int c = 0; c < nrhs; ++c) acc[c] += pv * vs[c][i];
+    }
+    for (int c = 0; c < nrhs; ++c) {
+      const double s = wave_red(acc[c]);
+      if (lane == 0) zpart[(size_t)t * zs_task + a * nrhs + c] = s;
+    }
+  }
+}
+
+// per-node coefficients.  op: 0 W, 1 W', 2 W^-1, 3 W^-T, 4 matvec (alpha scaling)
+__global__ void __launch_bounds__(NTHREADS) k_node_coef(
+    int op, int hbase, int nnode, const int* __restrict__ rank,
+    const int* __restrict__ node_task_off, int tbase, const double* __restrict__ zpart,
+    int zs_task, int nrhs, const double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
+    double alpha_v, const double* __restrict__ alpha_p, double* __restrict__ coef, int cs_node) {
+  const int jn = blockIdx.x;
+  if (jn >= nnode) return;
+  const int h = hbase + jn;
+  const int k = rank[h];
+  if (k == 0) return;
+  __shared__ double S[PMAX][NRHS_MAX], T[PMAX][NRHS_MAX], X[PMAX][NRHS_MAX];
+  const int kn = k * nrhs;
+  for (int idx = threadIdx.x; idx < 2 * kn; idx += NTHREADS) {
+    const int side = idx / kn, e = idx % kn;
+    const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
+    double s = 0.0;
+    for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + e];
+    if (side) T[e / nrhs][e % nrhs] = s; else S[e / nrhs][e % nrhs] = s;
+  }
+  __syncthreads();
+  double* cI = coef + (size_t)jn * cs_node;
+  double* cJ = cI + PMAX * NRHS_MAX;
+  if (op == 4) {
+    const double al = alpha_p ? *alpha_p : alpha_v;
+    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+      cI[e] = al * T[e / nrhs][e % nrhs];
+      cJ[e] = al * S[e / nrhs][e % nrhs];
+    }
+    return;
+  }
+  const double* GV = nodemat + nodemat_off[h];
+  const double* F1 = GV + k * k;
+  const double* F2 = GV + 2 * k * k;
+  if (op == 0 || op == 1) {
+    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+      const int a = e / nrhs, c = e % nrhs;
+      double f = 0.0;
+      for (int d = 0; d < k; ++d) f += F1[a + d * k] * T[d][c];
+      if (op == 0) { cI[e] = 0.0; cJ[e] = S[a][c] + f; }
+      else { cI[e] = T[a][c]; cJ[e] = f; }
+    }
+    return;
+  }
+  if (op == 2) {
+    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+      const int a = e / nrhs, c = e % nrhs;
+      double u = T[a][c];
+      for (int d = 0; d < k; ++d) u -= GV[a + d * k] * S[d][c];
+      X[a][c] = u;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+      const int a = e / nrhs, c = e % nrhs;
+      double f = -S[a][c];
+      for (int d = 0; d < k; ++d) f += F2[a + d * k] * X[d][c];
+      cI[e] = 0.0;
+      cJ[e] = f;
+    }
+    return;
+  }
+  // op == 3
+  for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    const int a = e / nrhs, c = e % nrhs;
+    double w = 0.0;
+    for (int d = 0; d < k; ++d) w += F2[a + d * k] * T[d][c];
+    X[a][c] = w;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    const int a = e / nrhs, c = e % nrhs;
+    double g = T[a][c];
+    for (int d = 0; d < k; ++d) g += GV[a + d * k] * X[d][c];
+    cI[e] = -g;
+    cJ[e] = X[a][c];
+  }
+}
+
+// v[rows of side] += P[rows, coff + a] coef_side[a][c]
+__global__ void __launch_bounds__(NTHREADS) k_update_vec(
+    const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
+    int hbase, const int* __restrict__ rank, const int* __restrict__ coff,
+    const double* __restrict__ P, int ld, double* __restrict__ v, int nrhs, int ldv,
+    const double* __restrict__ coef, int cs_node, int skip_left) {
+  const int t = blockIdx.x;
+  if (t >= ntask) return;
+  const Task tk = tasks[tbase + t];
+  if (skip_left && tk.side == 0) return;
+  const int k = rank[tk.h];
+  if (k == 0) return;
+  const int l = nodes[tk.h].level;
+  const double* cf = coef + (size_t)(tk.h - hbase) * cs_node + tk.side * PMAX * NRHS_MAX;
+  __shared__ double cs[PMAX * NRHS_MAX];
+  for (int e = threadIdx.x; e < k * nrhs; e += NTHREADS) cs[e] = cf[e];
+  __syncthreads();
+  const double* p0 = P + (size_t)coff[l] * ld;
+  for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+    double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < k; ++a) {
+      const double pv = p0[(size_t)a * ld + r];
+      for (int c = 0; c < nrhs; ++c) acc[c] += pv * cs[a * nrhs + c];
+    }
+    for (int c = 0; c < nrhs; ++c) v[(size_t)c * ldv + r] += acc[c];
+  }
+}
+
+// y = alpha (K_leaf + nugget I) v + beta v + sum_levels panel rows x coefficients
+__global__ void __launch_bounds__(BMAX) k_mv_apply(
+    const int* __restrict__ leaf_lo, int nleaf, int L, const double* __restrict__ x, int kind,
+    double ell, double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
+    const double* __restrict__ beta_p, const double* __restrict__ v, double* __restrict__ y,
+    int nrhs, int ld, const int* __restrict__ rank, const int* __restrict__ coff,
+    const double* __restrict__ P, int ldp, const double* __restrict__ coef, int cs_node) {
+  const int b = blockIdx.x;
+  if (b >= nleaf) return;
+  const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  const double alpha = alpha_p ? *alpha_p : alpha_v;
+  const double beta = beta_p ? *beta_p : beta_v;
+  __shared__ double xs[BMAX];
+  __shared__ double vs[NRHS_MAX][BMAX];
+  for (int r = threadIdx.x; r < m; r += BMAX) {
+    xs[r] = x[lo + r];
+    for (int c = 0; c < nrhs; ++c) vs[c][r] = v[(size_t)c * ld + lo + r];
+  }
+  __syncthreads();
+  const int r = threadIdx.x;
+  if (r >= m) return;
+  const int i = lo + r;
+  double acc[NRHS_MAX];
+  for (int c = 0; c < nrhs; ++c) acc[c] = (beta + alpha * nugget) * vs[c][r];
+  const double xr = xs[r];
+  double kacc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
+  for (int s2 = 0; s2 < m; ++s2) {
+    const double kv = kernel_v(kind, ell, xr, xs[s2]);
+    for (int c = 0; c < nrhs; ++c) kacc[c] += kv * vs[c][s2];
+  }
+  for (int c = 0; c < nrhs; ++c) acc[c] += alpha * kacc[c];
+  for (int l = 0; l < L; ++l) {
+    const int h = (1 << l) - 1 + (b >> (L - l));
+    const int k = rank[h];
+    if (k == 0) continue;
+    const int side = (b >> (L - l - 1)) & 1;
+    const double* cf = coef + (size_t)h * cs_node + side * PMAX * NRHS_MAX;
+    const double* p0 = P + (size_t)coff[l] * ldp + i;
+    for (int a = 0; a < k; ++a) {
+      const double pv = p0[(size_t)a * ldp];
+      for (int c = 0; c < nrhs; ++c) acc[c] += pv * cf[a * nrhs + c];
+    }
+  }
+  for (int c = 0; c < nrhs; ++c) y[(size_t)c * ld + i] = acc[c];
+}
+
+// ---------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------
+size_t apply_work_doubles(const HostPlan& P, int nrhs) {
+  (void)nrhs;
+  const size_t zp = (size_t)std::max(P.max_ltasks, 1) * PMAX * NRHS_MAX;
+  const size_t cf = (size_t)std::max(P.nint, 1) * 2 * PMAX * NRHS_MAX;
+  return zp + cf;
+}
+
+size_t matvec_work_doubles(const HostPlan& P, int nrhs) {
+  (void)nrhs;
+  const size_t zp = (size_t)std::max(P.nlt, 1) * PMAX * NRHS_MAX;
+  const size_t cf = (size_t)std::max(P.nint, 1) * 2 * PMAX * NRHS_MAX;
+  return zp + cf;
+}
+
+static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int ld, double* work,
+                        hipStream_t s) {
+  const HodlrData& H = *F.H;
+  const HostPlan& P = H.pk->P;
+  const DevPlan& D = H.pk->D;
+  const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
+  const int zs_task = PMAX * NRHS_MAX;
+  double* zpart = work;
+  double* coef = work + (size_t)std::max(P.max_ltasks, 1) * zs_task;
+  const int cs_node = 2 * PMAX * NRHS_MAX;
+  const int hbase = (1 << l) - 1;
+  k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, F.panel,
+                                       H.ld, v, nrhs, ld, zpart, zs_task);
+  k_node_coef<<<1 << l, NTHREADS, 0, s>>>(op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart,
+                                          zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr,
+                                          coef, cs_node);
+  const int skip_left = (op == 0 || op == 2) ? 1 : 0;
+  k_update_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
+                                       F.panel, H.ld, v, nrhs, ld, coef, cs_node, skip_left);
+}
+
+void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
+                    hipStream_t s) {
+  const HostPlan& P = F.H->pk->P;
+  const int* leaf_lo = F.H->pk->D.leaf_lo;
+  // W = L_D W_(L-1) ... W_(0)
+  if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
+    for (int l = 0; l < P.L; ++l) sweep_level(F, 0, l, v, nrhs, ld, work, s);
+    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafL, P.B, 0, v, nrhs, ld);
+  } else if (op == 1) {   // W' v = W_(0)' ... W_(L-1)' L_D' v
+    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafL, P.B, 1, v, nrhs, ld);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level(F, 1, l, v, nrhs, ld, work, s);
+  } else if (op == 2) {   // W^-1 v = W_(0)^-1 ... W_(L-1)^-1 L_D^-1 v
+    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafLinv, P.B, 0, v, nrhs,
+                                             ld);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level(F, 2, l, v, nrhs, ld, work, s);
+  } else {                // W^-T v = L_D^-T W_(L-1)^-T ... W_(0)^-T v
+    for (int l = 0; l < P.L; ++l) sweep_level(F, 3, l, v, nrhs, ld, work, s);
+    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafLinv, P.B, 1, v, nrhs,
+                                             ld);
+  }
+}
+
+void launch_matvec(const HodlrData& H, double alpha, double beta, const double* alpha_dev,
+                   const double* beta_dev, const double* v, double* y, int nrhs, int ld,
+                   double* work, hipStream_t s) {
+  const HostPlan& P = H.pk->P;
+  const DevPlan& D = H.pk->D;
+  const int zs_task = PMAX * NRHS_MAX;
+  const int nt = P.nlt;
+  double* zpart = work;
+  double* coef = work + (size_t)std::max(nt, 1) * zs_task;
+  const int cs_node = 2 * PMAX * NRHS_MAX;
+  if (P.L > 0) {
+    k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel,
+                                         H.ld, v, nrhs, ld, zpart, zs_task);
+    k_node_coef<<<P.nint, NTHREADS, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart,
+                                            zs_task, nrhs, nullptr, nullptr, alpha, alpha_dev, coef,
+                                            cs_node);
+  }
+  k_mv_apply<<<P.nleaf, BMAX, 0, s>>>(D.leaf_lo, P.nleaf, P.L, H.x, P.kind, P.ell, P.nugget,
+                                      alpha, alpha_dev, beta, beta_dev, v, y, nrhs, ld, H.rank,
+                                      D.coff, H.panel, H.ld, coef, cs_node);
+}
+
+}  // namespace fg

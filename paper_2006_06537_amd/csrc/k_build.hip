@@ -1,0 +1,493 @@
+// HODLR construction kernels (gfx950): interpolation moments, per-node compression
+// (Cholesky-QR of the Chebyshev basis + one-sided Jacobi SVD of the p x p core),
+// rank bookkeeping and panel generation.
+//
+// Off-diagonal block of node (I, J) on its windows: the first-kind Chebyshev
+// interpolant in both variables, written in the Chebyshev polynomial basis:
+//   K(x, y) ~ T_I(x) C_T T_J(y)',  C_T = A_I C A_J',  C[s,t] = k_1(xi_s, eta_t),
+//   A[k,s] = (2 - [k=0]) / p cos(k (2s+1) pi / (2p))        (discrete cosine transform).
+// G_I = T_I' T_I over the window rows follows from the moments mu_m = sum_i T_m(t_i)
+// through T_j T_k = (T_{j+k} + T_{|j-k|}) / 2, so the basis is never stored.
+// With G = R'R (Cholesky), X = R_I C_T R_J' has the singular values of the interpolant;
+// the block is truncated to the singular values above max(tol/3, 8 u s_1) and stored
+// as U = T_I(x) T_U, V = T_J(y) T_V with T_U = R_I^-1 U_X sqrt(S), T_V = R_J^-1 V_X sqrt(S).
+#include <cfloat>
+
+#include "fg_internal.h"
+
+namespace fg {
+
+__device__ __forceinline__ double kernel1(int kind, double ell, double a, double b) {
+  const double d = a - b;
+  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
+  return exp(-fabs(d) / ell);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------
+// moments: partial sums of T_m(t_i), m < 2p-1, over the rows of one task
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ tasks, int ntask,
+                                                      const NodePlan* __restrict__ nodes,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ mpart, int stride) {
+  const int t = blockIdx.x;
+  if (t >= ntask) return;
+  const Task tk = tasks[t];
+  const NodePlan q = nodes[tk.h];
+  const int p = tk.side ? q.pJ : q.pI;
+  const double a = tk.side ? q.aJ : q.aI, b = tk.side ? q.bJ : q.bI;
+  const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+  const int nm = 2 * p - 1;
+  __shared__ double red[NTHREADS / 64][32];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int mb = 0; mb < nm; mb += 32) {
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+      const double tt = hw > 0.0 ? (x[r] - c) / hw : 0.0;
+      double tm2 = 1.0, tm1 = tt;  // T_0, T_1
+      // advance to T_mb
+      for (int m = 0; m < mb; ++m) {
+        const double tn = 2.0 * tt * tm1 - tm2;
+        tm2 = tm1;
+        tm1 = tn;
+      }
+      // now tm2 = T_mb, tm1 = T_{mb+1}
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        acc[j] += tm2;
+        const double tn = 2.0 * tt * tm1 - tm2;
+        tm2 = tm1;
+        tm1 = tn;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) red[wv][j] = acc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && mb + threadIdx.x < nm) {
+      double s = 0.0;
+      for (int w = 0; w < NTHREADS / 64; ++w) s += red[w][threadIdx.x];
+      mpart[(size_t)t * stride + mb + threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// small dense helpers on LDS matrices (column-major, leading dimension ldm)
+// ---------------------------------------------------------------------------------
+// in-place lower Cholesky of an m x m SPD matrix; returns false on a non-positive pivot
+__device__ bool lds_cholesky(double* A, int m, int ldm) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = A[j + j * ldm];
+      if (!(d > 0.0)) bad = 1;
+      A[j + j * ldm] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double ljj = A[j + j * ldm];
+    for (int r = j + 1 + threadIdx.x; r < m; r += NTHREADS) A[r + j * ldm] /= ljj;
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int idx = threadIdx.x; idx < w * w; idx += NTHREADS) {
+      const int r = j + 1 + idx % w, cc = j + 1 + idx / w;
+      if (cc <= r) A[r + cc * ldm] -= A[r + j * ldm] * A[cc + j * ldm];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
+    const int r = idx % m, cc = idx / m;
+    if (cc > r) A[r + cc * ldm] = 0.0;
+  }
+  __syncthreads();
+  return bad == 0;
+}
+
+// One-sided Jacobi on the columns of M (mr x qc, mr >= qc) with right vectors Q (qc x qc).
+// Returns false if 40 sweeps did not converge.
+__device__ bool lds_jacobi_svd(double* M, int mr, int qc, int ldm, double* Q, int ldq) {
+  __shared__ int rotated;
+  __shared__ int perm[PMAX + 1];
+  for (int idx = threadIdx.x; idx < qc * qc; idx += NTHREADS)
+    Q[idx % qc + (idx / qc) * ldq] = (idx % qc == idx / qc) ? 1.0 : 0.0;
+  const int qe = qc + (qc & 1);  // even number of players
+  const int npair = qe / 2;
+  const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;  // 8 lanes per pair
+  __syncthreads();
+  if (qc < 2) return true;
+  bool conv = false;
+  for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < qe - 1; ++step) {
+      if (threadIdx.x < qe) {
+        const int j = threadIdx.x;
+        perm[j] = (j == 0) ? 0 : 1 + ((j - 1 + step) % (qe - 1));
+      }
+      __syncthreads();
+      if (g < npair) {
+        int i = perm[g], k = perm[qe - 1 - g];
+        if (i > k) { const int tmp = i; i = k; k = tmp; }
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (k < qc) {
+          for (int r = gl; r < mr; r += 8) {
+            const double u = M[r + i * ldm], v = M[r + k * ldm];
+            al += u * u; be += v * v; ga += u * v;
+          }
+        }
+        for (int o = 4; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 8);
+          be += __shfl_xor(be, o, 8);
+          ga += __shfl_xor(ga, o, 8);
+        }
+        if (k < qc && fabs(ga) > 2.0 * DBL_EPSILON * sqrt(al * be) && ga != 0.0) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int r = gl; r < mr; r += 8) {
+            const double u = M[r + i * ldm], v = M[r + k * ldm];
+            M[r + i * ldm] = cs * u - sn * v;
+            M[r + k * ldm] = sn * u + cs * v;
+          }
+          for (int r = gl; r < qc; r += 8) {
+            const double u = Q[r + i * ldq], v = Q[r + k * ldq];
+            Q[r + i * ldq] = cs * u - sn * v;
+            Q[r + k * ldq] = sn * u + cs * v;
+          }
+          if (gl == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    conv = (rotated == 0);
+    __syncthreads();
+  }
+  return conv;
+}
+
+// ---------------------------------------------------------------------------------
+// compression: one work-group per internal node
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTHREADS) k_compress(
+    const NodePlan* __restrict__ nodes, int nint, const double* __restrict__ x, int kind,
+    double ell, double tol, const double* __restrict__ mpart, int mstride,
+    const int* __restrict__ mtask_off, const int* __restrict__ kcap, double* __restrict__ tbuf,
+    double* __restrict__ sv, int* __restrict__ rank, int* __restrict__ status, int pm) {
+  const int h = blockIdx.x;
+  if (h >= nint) return;
+  const NodePlan q = nodes[h];
+  const int pI = q.pI, pJ = q.pJ;
+  if (threadIdx.x < PMAX) sv[(size_t)h * PMAX + threadIdx.x] = 0.0;
+  if (pI == 0 || pJ == 0) {
+    if (threadIdx.x == 0) rank[h] = 0;
+    return;
+  }
+  extern __shared__ double lds[];
+  const int ld = pm;
+  double* GI = lds;
+  double* GJ = GI + pm * pm;
+  double* Cm = GJ + pm * pm;
+  double* Tm = Cm + pm * pm;
+  double* Vm = Tm + pm * pm;
+  __shared__ double sig[PMAX];
+  __shared__ int order[PMAX];
+  __shared__ int kk;
+  // Gram matrices of the two bases
+  for (int side = 0; side < 2; ++side) {
+    double* G = side ? GJ : GI;
+    const int p = side ? pJ : pI;
+    const int exact = side ? q.exactJ : q.exactI;
+    if (exact) {
+      for (int idx = threadIdx.x; idx < p * p; idx += NTHREADS)
+        G[idx % p + (idx / p) * ld] = (idx % p == idx / p) ? 1.0 : 0.0;
+    } else {
+      // final moments: sum the task partials in task order
+      __shared__ double mom[2 * PMAX];
+      const int t0 = mtask_off[2 * h + side], t1 = mtask_off[2 * h + side + 1];
+      for (int m = threadIdx.x; m < 2 * p - 1; m += NTHREADS) {
+        double s = 0.0;
+        for (int t = t0; t < t1; ++t) s += mpart[(size_t)t * mstride + m];
+        mom[m] = s;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < p * p; idx += NTHREADS) {
+        const int r = idx % p, cc = idx / p;
+        G[r + cc * ld] = 0.5 * (mom[r + cc] + mom[r > cc ? r - cc : cc - r]);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  const bool okI = lds_cholesky(GI, pI, ld);
+  const bool okJ = lds_cholesky(GJ, pJ, ld);
+  if (!okI || !okJ) {
+    if (threadIdx.x == 0) { atomicOr(status, ST_NOTSPD); rank[h] = 0; }
+    return;
+  }
+  // kernel values at the interpolation nodes
+  const double cI = 0.5 * (q.aI + q.bI), hI = 0.5 * (q.bI - q.aI);
+  const double cJ = 0.5 * (q.aJ + q.bJ), hJ = 0.5 * (q.bJ - q.aJ);
+  for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
+    const int s = idx % pI, t = idx / pI;
+    const double xs = q.exactI ? x[q.i0 + s] : cI + hI * cos((2 * s + 1) * M_PI / (2.0 * pI));
+    const double yt = q.exactJ ? x[q.mid + t] : cJ + hJ * cos((2 * t + 1) * M_PI / (2.0 * pJ));
+    Cm[s + t * ld] = kernel1(kind, ell, xs, yt);
+  }
+  __syncthreads();
+  // C_T = A_I C A_J'
+  if (!q.exactI) {
+    for (int idx = threadIdx.x; idx < pI * pI; idx += NTHREADS) {
+      const int k = idx % pI, s = idx / pI;
+      Vm[k + s * ld] = (k == 0 ? 1.0 : 2.0) / pI * cos(k * (2 * s + 1) * M_PI / (2.0 * pI));
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
+      const int k = idx % pI, t = idx / pI;
+      double acc = 0.0;
+      for (int s = 0; s < pI; ++s) acc += Vm[k + s * ld] * Cm[s + t * ld];
+      Tm[k + t * ld] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS)
+      Cm[idx % pI + (idx / pI) * ld] = Tm[idx % pI + (idx / pI) * ld];
+    __syncthreads();
+  }
+  if (!q.exactJ) {
+    for (int idx = threadIdx.x; idx < pJ * pJ; idx += NTHREADS) {
+      const int k = idx % pJ, s = idx / pJ;
+      Vm[k + s * ld] = (k == 0 ? 1.0 : 2.0) / pJ * cos(k * (2 * s + 1) * M_PI / (2.0 * pJ));
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
+      const int s = idx % pI, k = idx / pI;
+      double acc = 0.0;
+      for (int t = 0; t < pJ; ++t) acc += Cm[s + t * ld] * Vm[k + t * ld];
+      Tm[s + k * ld] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS)
+      Cm[idx % pI + (idx / pI) * ld] = Tm[idx % pI + (idx / pI) * ld];
+    __syncthreads();
+  }
+  // X = L_I' C_T L_J   (G = L L', R = L')
+  for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
+    const int r = idx % pI, t = idx / pI;
+    double acc = 0.0;
+    for (int s = r; s < pI; ++s) acc += GI[s + r * ld] * Cm[s + t * ld];
+    Tm[r + t * ld] = acc;
+  }
+  __syncthreads();
+  const bool trans = pJ > pI;  // SVD of the taller orientation
+  const int mr = trans ? pJ : pI, qc = trans ? pI : pJ;
+  for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
+    const int r = idx % pI, t = idx / pI;
+    double acc = 0.0;
+    for (int s = t; s < pJ; ++s) acc += Tm[r + s * ld] * GJ[s + t * ld];
+    if (trans) Cm[t + r * ld] = acc; else Cm[r + t * ld] = acc;
+  }
+  __syncthreads();
+  const bool conv = lds_jacobi_svd(Cm, mr, qc, ld, Vm, ld);
+  if (!conv && threadIdx.x == 0) atomicOr(status, ST_NOTCONV);
+  // singular values, descending order, rank
+  if (threadIdx.x < qc) {
+    double s = 0.0;
+    for (int r = 0; r < mr; ++r) s += Cm[r + threadIdx.x * ld] * Cm[r + threadIdx.x * ld];
+    sig[threadIdx.x] = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < qc; ++j) order[j] = j;
+    for (int a = 0; a < qc; ++a) {  // selection sort, stable for ties
+      int best = a;
+      for (int b = a + 1; b < qc; ++b)
+        if (sig[order[b]] > sig[order[best]]) best = b;
+      const int tmp = order[a]; order[a] = order[best]; order[best] = tmp;
+    }
+    const double thr = fmax(tol / 3.0, 8.0 * (DBL_EPSILON * 0.5) * sig[order[0]]);
+    int k = 0;
+    while (k < qc && sig[order[k]] > thr) ++k;
+    kk = k;
+    rank[h] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x < qc) sv[(size_t)h * PMAX + threadIdx.x] = sig[order[threadIdx.x]];
+  // T_U = L_I^-T (U_X sqrt s), T_V = L_J^-T (V_X sqrt s)
+  const int k = kk;
+  const int kc = kcap[q.level];
+  double* TU = tbuf + q.toff_u;
+  double* TV = tbuf + q.toff_v;
+  // column c of U_X sqrt(s) and V_X sqrt(s) for sorted index c
+  for (int idx = threadIdx.x; idx < 2 * k; idx += NTHREADS) {
+    const int c = idx % k, side = idx / k;
+    const int j = order[c];
+    const double sj = sig[j], rs = sqrt(sj);
+    const int p = side ? pJ : pI;
+    const double* L = side ? GJ : GI;
+    double* out = side ? (TV + (size_t)c * pJ) : (TU + (size_t)c * pI);
+    // rhs entries: left vector if (side == 0) != trans ... see orientation table
+    // no transpose: U_X = M[:,j]/s_j (length pI), V_X = Q[:,j] (length pJ)
+    // transpose   : U_X = Q[:,j] (length pI),   V_X = M[:,j]/s_j (length pJ)
+    const bool fromM = (side == 0) != trans;
+    // back substitution L' y = rhs, written directly into out
+    for (int r = p - 1; r >= 0; --r) {
+      const double rhs = fromM ? Cm[r + j * ld] / sj * rs : Vm[r + j * ld] * rs;
+      double acc = rhs;
+      for (int s = r + 1; s < p; ++s) acc -= L[s + r * ld] * out[s];
+      out[r] = acc / L[r + r * ld];
+    }
+  }
+  (void)kc;
+}
+
+// ---------------------------------------------------------------------------------
+// per-level maximum rank and the right-column lists used by the factorization
+// ---------------------------------------------------------------------------------
+__global__ void k_rank_levels(const int* __restrict__ rank, int L, const int* __restrict__ coff,
+                              int Ktot, int* __restrict__ kmax, int* __restrict__ rcols,
+                              int* __restrict__ rcount) {
+  if (blockIdx.x != 0) return;
+  __shared__ int km[32];
+  if (threadIdx.x < L) {
+    const int l = threadIdx.x;
+    int m = 0;
+    for (int h = (1 << l) - 1; h < (2 << l) - 1; ++h) m = max(m, rank[h]);
+    km[l] = m;
+    kmax[l] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < L) {
+    const int l = threadIdx.x;
+    int c = 0;
+    for (int a = 0; a < km[l]; ++a) rcols[l * Ktot + c++] = coff[l] + a;
+    for (int lp = 0; lp < l; ++lp)
+      for (int a = 0; a < km[lp]; ++a) rcols[l * Ktot + c++] = coff[lp] + a;
+    rcount[l] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// panel generation: U rows of left children, V rows of right children (all levels)
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTHREADS) k_panel_gen(
+    const Task* __restrict__ tasks, int ntask, const NodePlan* __restrict__ nodes,
+    const double* __restrict__ x, const double* __restrict__ tbuf, const int* __restrict__ rank,
+    const int* __restrict__ kmax, const int* __restrict__ coff, double* __restrict__ panel,
+    int ld) {
+  const int t = blockIdx.x;
+  if (t >= ntask) return;
+  const Task tk = tasks[t];
+  const NodePlan q = nodes[tk.h];
+  const int l = q.level;
+  const int k = rank[tk.h], kl = kmax[l];
+  const int p = tk.side ? q.pJ : q.pI;
+  const int exact = tk.side ? q.exactJ : q.exactI;
+  const int w0 = tk.side ? q.mid : q.i0, w1 = tk.side ? q.j1 : q.mid;
+  const double a = tk.side ? q.aJ : q.aI, b = tk.side ? q.bJ : q.bI;
+  const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+  const double* T = tbuf + (tk.side ? q.toff_v : q.toff_u);
+  __shared__ double Ts[PMAX * PMAX];
+  for (int idx = threadIdx.x; idx < p * k; idx += NTHREADS) Ts[idx] = T[idx];
+  __syncthreads();
+  double* col0 = panel + (size_t)coff[l] * ld;
+  for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+    const bool inwin = (r >= w0 && r < w1);
+    if (!inwin || k == 0) {
+      for (int cc = 0; cc < kl; ++cc) col0[(size_t)cc * ld + r] = 0.0;
+      continue;
+    }
+    if (exact) {
+      const int e = r - w0;
+      for (int cc = 0; cc < k; ++cc) col0[(size_t)cc * ld + r] = Ts[cc * p + e];
+    } else {
+      const double tt = hw > 0.0 ? (x[r] - c) / hw : 0.0;
+      for (int cc = 0; cc < k; ++cc) {
+        double tm2 = 1.0, tm1 = tt, acc = Ts[cc * p];
+        if (p > 1) acc += tt * Ts[cc * p + 1];
+        for (int m = 2; m < p; ++m) {
+          const double tn = 2.0 * tt * tm1 - tm2;
+          acc += tn * Ts[cc * p + m];
+          tm2 = tm1;
+          tm1 = tn;
+        }
+        col0[(size_t)cc * ld + r] = acc;
+      }
+    }
+    for (int cc = k; cc < kl; ++cc) col0[(size_t)cc * ld + r] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// sampled entries of K~_1
+// ---------------------------------------------------------------------------------
+__global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
+                          const double* __restrict__ x, int kind, double ell, double nugget,
+                          const int* __restrict__ kmax, const int* __restrict__ coff,
+                          const double* __restrict__ panel, int ld, const int64_t* __restrict__ ii,
+                          const int64_t* __restrict__ jj, int64_t count, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int i = (int)ii[t], j = (int)jj[t];
+  if (i > j) { const int tmp = i; i = j; j = tmp; }
+  int h = 0;
+  while (h < nint) {
+    const NodePlan q = nodes[h];
+    if (j < q.mid) h = 2 * h + 1;
+    else if (i >= q.mid) h = 2 * h + 2;
+    else {
+      double acc = 0.0;
+      const double* c0 = panel + (size_t)coff[q.level] * ld;
+      for (int c = 0; c < kmax[q.level]; ++c) acc += c0[(size_t)c * ld + i] * c0[(size_t)c * ld + j];
+      out[t] = acc;
+      return;
+    }
+  }
+  out[t] = kernel1(kind, ell, x[i], x[j]) + (i == j ? nugget : 0.0);
+}
+
+// ---------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------
+void launch_build(HodlrData& H, hipStream_t s) {
+  const HostPlan& P = H.pk->P;
+  const DevPlan& D = H.pk->D;
+  if (P.L == 0) return;
+  const int nm = P.nmt;
+  if (nm > 0)
+    k_moments<<<nm, NTHREADS, 0, s>>>(D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
+  const int pm = std::max(P.pmax, 1);
+  const size_t lds = sizeof(double) * 5 * pm * pm;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(lds));
+  k_compress<<<P.nint, NTHREADS, lds, s>>>(D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart,
+                                           P.mpart_stride, D.mtask_off, D.kcap, H.tbuf, H.sv,
+                                           H.rank, H.status, pm);
+  k_rank_levels<<<1, 64, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
+  const int ng = P.ngt;
+  k_panel_gen<<<ng, NTHREADS, 0, s>>>(D.gtasks, ng, D.nodes, H.x, H.tbuf, H.rank, H.kmax,
+                                      D.coff, H.panel, H.ld);
+}
+
+void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int64_t count,
+                    double* out, hipStream_t s) {
+  if (count <= 0) return;
+  const int nb = int((count + 255) / 256);
+  const HostPlan& P = H.pk->P;
+  k_entries<<<nb, 256, 0, s>>>(H.pk->D.nodes, P.nint, H.x, P.kind, P.ell, P.nugget, H.kmax,
+                               H.pk->D.coff, H.panel, H.ld, i, j, count, out);
+}
+
+}  // namespace fg

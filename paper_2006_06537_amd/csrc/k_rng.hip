@@ -1,0 +1,214 @@
+// Random numbers, reductions and the scalar steps of the Gibbs sweep (gfx950).
+//
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+// with the key bumped by the Weyl constants after each round.  Key (seed, 0), counter
+// (block, tag, iteration, stream); uniform ((w >> 12) + 0.5) 2^-52 lies in (0, 1).
+// Normals: Box-Muller on (u0, u1) and (u2, u3) of each block, cosine then sine.
+// Gamma(a, 1): Marsaglia & Tsang (2000), try t on block t (normal from u0, u1 by the
+// cosine branch, acceptance uniform u2), at most 64 tries.
+#include "fg_internal.h"
+#include "fg_rng.h"
+
+namespace fg {
+
+__global__ void k_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
+                          double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (n + 3) / 4;
+  if (j >= nb) return;
+  uint64_t w[4];
+  philox4x64_10((uint64_t)j, tag, iter, strm, seed, 0, w);
+  const double u0 = to_unit(w[0]), u1 = to_unit(w[1]), u2 = to_unit(w[2]), u3 = to_unit(w[3]);
+  const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
+  const double z[4] = {r01 * cos(2.0 * M_PI * u1), r01 * sin(2.0 * M_PI * u1),
+                       r23 * cos(2.0 * M_PI * u3), r23 * sin(2.0 * M_PI * u3)};
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = 4 * j + e;
+    if (i < n) out[i] = z[e];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// deterministic two-stage reductions.  mode 0: sum a*b, 1: sum (a-b)^2
+// ---------------------------------------------------------------------------------
+constexpr int DOT_BLOCKS = 1024;
+
+__device__ __forceinline__ double wsum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_dot_stage1(const double* __restrict__ a,
+                                                         const double* __restrict__ b, int n,
+                                                         int mode, double* __restrict__ part) {
+  __shared__ double red[NTHREADS / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * NTHREADS + threadIdx.x; i < n; i += DOT_BLOCKS * NTHREADS) {
+    const double d = (mode == 1) ? a[i] - b[i] : a[i];
+    s += (mode == 1) ? d * d : d * b[i];
+  }
+  s = wsum64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NTHREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(NTHREADS) k_dot_stage2(const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+  __shared__ double red[NTHREADS / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < DOT_BLOCKS; i += NTHREADS) s += part[i];
+  s = wsum64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NTHREADS / 64; ++w) t += red[w];
+    *out = t;
+  }
+}
+
+void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
+                hipStream_t s) {
+  k_dot_stage1<<<DOT_BLOCKS, NTHREADS, 0, s>>>(a, b, n, mode, work);
+  k_dot_stage2<<<1, NTHREADS, 0, s>>>(work, out);
+}
+
+// out = ca * x + cb * y  (coefficients from device pointers when given)
+__global__ void k_axpby(int n, const double* __restrict__ x, const double* __restrict__ y,
+                        double* __restrict__ out, const double* __restrict__ ca_p, double ca,
+                        const double* __restrict__ cb_p, double cb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = ca_p ? *ca_p : ca;
+  const double b = cb_p ? *cb_p : cb;
+  double v = a * x[i];
+  if (y) v += b * y[i];
+  out[i] = v;
+}
+
+void launch_axpby(int n, const double* x, const double* y, double* out, const double* ca_dev,
+                  double ca, const double* cb_dev, double cb, hipStream_t s) {
+  if (n <= 0) return;
+  k_axpby<<<(n + 255) / 256, 256, 0, s>>>(n, x, y, out, ca_dev, ca, cb_dev, cb);
+}
+
+void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
+                    double* out, hipStream_t s) {
+  const int64_t nb = (n + 3) / 4;
+  if (nb <= 0) return;
+  k_normals<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(seed, tag, iter, strm, n, out);
+}
+
+// ---------------------------------------------------------------------------------
+// scalar steps of the sweep (one thread)
+// ---------------------------------------------------------------------------------
+__device__ double gamma_mt(double shape, uint64_t seed, uint64_t tag, uint64_t iter,
+                           uint64_t strm, int* status) {
+  const bool boost = shape < 1.0;
+  const double a = boost ? shape + 1.0 : shape;
+  const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
+  for (int t = 0; t < 64; ++t) {
+    uint64_t w[4];
+    philox4x64_10((uint64_t)t, tag, iter, strm, seed, 0, w);
+    const double u0 = to_unit(w[0]), u1 = to_unit(w[1]), u2 = to_unit(w[2]), u3 = to_unit(w[3]);
+    const double z = sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+    double v = 1.0 + c * z;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    if (log(u2) < 0.5 * z * z + d - d * v + d * log(v)) {
+      double g = d * v;
+      if (boost) g *= pow(u3, 1.0 / shape);
+      return g;
+    }
+  }
+  atomicOr(status, ST_NOTCONV);
+  return d;
+}
+
+// derived scalars at the start of a sweep
+__global__ void k_sweep_begin(DevState* st) {
+  st->alphaM = st->tau * st->sigf2;
+  st->c_ka = sqrt(st->tau) * st->sigf2;
+  st->sigf = sqrt(st->sigf2);
+  st->tau_draw = st->tau;
+}
+
+__global__ void k_set_draw_scalars(DevState* st, double tau, double sigf2) {
+  st->tau = tau;
+  st->sigf2 = sigf2;
+  st->alphaM = tau * sigf2;
+  st->c_ka = sqrt(tau) * sigf2;
+  st->sigf = sqrt(sigf2);
+  st->tau_draw = tau;
+}
+
+// log-likelihood bookkeeping of the f draw and the tau update
+__global__ void k_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
+                           uint64_t strm) {
+  const double tau0 = st->tau_draw;
+  st->logdet_sigma = st->logdetM - n * log(tau0);
+  st->loglik = -0.5 * n * log(2.0 * M_PI) - 0.5 * st->logdet_sigma - 0.5 * st->yr;
+  const double g = gamma_mt(0.5 * (a1 + n), seed, 3, iter, strm, &st->status);
+  st->tau = g / (0.5 * (b1 + st->sse));
+}
+
+__global__ void k_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed,
+                            uint64_t iter, uint64_t strm) {
+  const double g = gamma_mt(0.5 * (a2 + n), seed, 4, iter, strm, &st->status);
+  st->sigf2 = 1.0 / (g / (0.5 * (b2 + st->q)));
+}
+
+__global__ void k_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t iter,
+                          uint64_t strm, const int* pst_a, const int* pst_b) {
+  st->kprop = kprop;
+  st->accept = 0;
+  st->mh = 0.0;
+  if (!ongrid) return;
+  // a proposal whose matrix is not positive definite on the device is rejected
+  if ((pst_a && (*pst_a & ST_NOTSPD)) || (pst_b && (*pst_b & ST_NOTSPD))) return;
+  const double D = -0.5 * (st->logdet1p - st->logdet1) - (st->qprop - st->q) / (2.0 * st->sigf2);
+  st->mh = D;
+  uint64_t w[4];
+  philox4x64_10(0, 6, iter, strm, seed, 0, w);
+  const double u = to_unit(w[0]);
+  if (log(u) < D) {
+    st->accept = 1;
+    st->accepts += 1;
+    st->k = kprop;
+    st->logdet1 = st->logdet1p;
+    st->q = st->qprop;
+  }
+}
+
+void launch_sweep_begin(DevState* st, hipStream_t s) { k_sweep_begin<<<1, 1, 0, s>>>(st); }
+void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s) {
+  k_set_draw_scalars<<<1, 1, 0, s>>>(st, tau, sigf2);
+}
+void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
+                     uint64_t strm, hipStream_t s) {
+  k_tau_step<<<1, 1, 0, s>>>(st, n, a1, b1, seed, iter, strm);
+}
+void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t iter,
+                      uint64_t strm, hipStream_t s) {
+  k_sigf_step<<<1, 1, 0, s>>>(st, n, a2, b2, seed, iter, strm);
+}
+void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t iter,
+                    uint64_t strm, const int* pst_a, const int* pst_b, hipStream_t s) {
+  k_mh_step<<<1, 1, 0, s>>>(st, kprop, ongrid, seed, iter, strm, pst_a, pst_b);
+}
+
+__global__ void k_zero_int(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+void launch_zero_int(int* p, int n, hipStream_t s) {
+  if (n > 0) k_zero_int<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+}
+
+}  // namespace fg

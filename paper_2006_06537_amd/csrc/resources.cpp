@@ -1,0 +1,170 @@
+// Device resources of plans, compressed matrices and factors (host code).
+#include <algorithm>
+#include <cstring>
+
+#include "fg_internal.h"
+
+namespace fg {
+
+template <class T>
+static fg_status dalloc(T** p, size_t count, std::string& err) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    err = "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed";
+    return FG_ENOMEM;
+  }
+  return FG_OK;
+}
+
+template <class T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <class T>
+static fg_status upload(T** dst, const std::vector<T>& v, hipStream_t s, std::string& err) {
+  fg_status st = dalloc(dst, v.size(), err);
+  if (st != FG_OK) return st;
+  if (!v.empty() &&
+      hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess) {
+    err = "plan upload failed";
+    return FG_EDEVICE;
+  }
+  return FG_OK;
+}
+
+PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                           double tol, hipStream_t s, fg_status& st, std::string& err) {
+  PlanPack* pk = new PlanPack();
+  st = make_plan(xh, n, kind, ell, nugget, leaf, tol, pk->P, err);
+  if (st != FG_OK) { delete pk; return nullptr; }
+  HostPlan& P = pk->P;
+  // per node offsets of (G_V, F1, F2) and factor scratch sizes
+  pk->nodemat_off.resize(std::max(P.nint, 1));
+  size_t off = 0;
+  for (int h = 0; h < P.nint; ++h) {
+    pk->nodemat_off[h] = int(off);
+    const size_t kc = P.kcap[P.nodes[h].level];
+    off += 3 * kc * kc;
+  }
+  pk->nodemat_size = std::max<size_t>(off, 1);
+  for (int l = 0; l < P.L; ++l) {
+    const size_t Wcap = P.coff[l + 1];
+    const size_t per = (size_t)P.kcap[l] * Wcap;
+    const size_t nt = P.ltask_off[l + 1] - P.ltask_off[l];
+    pk->zpart_size = std::max(pk->zpart_size, nt * per);
+    pk->zfin_size = std::max(pk->zfin_size, (size_t(1) << l) * 2 * per);
+    pk->coef_size = std::max(pk->coef_size, (size_t(1) << l) * per);
+  }
+  pk->mpart_size = (size_t)std::max(P.nmt, 1) * P.mpart_stride;
+  pk->mv_work = matvec_work_doubles(P, 4);
+  pk->ap_work = apply_work_doubles(P, 4);
+  DevPlan& D = pk->D;
+  std::vector<int> kc(P.kcap), co(P.coff);
+  if (kc.empty()) kc.push_back(0);
+  if ((st = upload(&D.nodes, P.nodes, s, err)) != FG_OK ||
+      (st = upload(&D.leaf_lo, P.leaf_lo, s, err)) != FG_OK ||
+      (st = upload(&D.mtasks, P.mtasks, s, err)) != FG_OK ||
+      (st = upload(&D.mtask_off, P.mtask_off, s, err)) != FG_OK ||
+      (st = upload(&D.gtasks, P.gtasks, s, err)) != FG_OK ||
+      (st = upload(&D.ltasks, P.ltasks, s, err)) != FG_OK ||
+      (st = upload(&D.node_task_off, P.node_task_off, s, err)) != FG_OK ||
+      (st = upload(&D.coff, co, s, err)) != FG_OK || (st = upload(&D.kcap, kc, s, err)) != FG_OK ||
+      (st = upload(&D.nodemat_off, pk->nodemat_off, s, err)) != FG_OK) {
+    plan_pack_destroy(pk);
+    return nullptr;
+  }
+  // the uploads read host vectors: finish them before the vectors are released
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    err = "stream synchronisation failed";
+    st = FG_EDEVICE;
+    plan_pack_destroy(pk);
+    return nullptr;
+  }
+  std::vector<Task>().swap(P.mtasks);
+  std::vector<Task>().swap(P.gtasks);
+  std::vector<Task>().swap(P.ltasks);
+  return pk;
+}
+
+void plan_pack_destroy(PlanPack* pk) {
+  if (!pk) return;
+  DevPlan& D = pk->D;
+  dfree(D.nodes); dfree(D.leaf_lo); dfree(D.mtasks); dfree(D.mtask_off); dfree(D.gtasks);
+  dfree(D.ltasks); dfree(D.node_task_off); dfree(D.coff); dfree(D.kcap); dfree(D.nodemat_off);
+  delete pk;
+}
+
+void Caps::add(const PlanPack& pk) {
+  const HostPlan& P = pk.P;
+  n = P.n; B = P.B; L = P.L; nint = P.nint; nleaf = P.nleaf;
+  tbuf = std::max(tbuf, (size_t)P.tbuf_size);
+  mpart = std::max(mpart, pk.mpart_size);
+  Ktot = std::max(Ktot, (size_t)std::max(P.Ktot, 1));
+  nodemat = std::max(nodemat, pk.nodemat_size);
+  zpart = std::max(zpart, pk.zpart_size);
+  zfin = std::max(zfin, pk.zfin_size);
+  coef = std::max(coef, pk.coef_size);
+  mv_work = std::max(mv_work, pk.mv_work);
+  ap_work = std::max(ap_work, pk.ap_work);
+}
+
+static int round_ld(int n) { return (n + 63) / 64 * 64; }
+
+fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err) {
+  fg_status st;
+  H.ld = round_ld(c.n);
+  const int Lm = std::max(c.L, 1);
+  if ((st = dalloc(&H.x, c.n, err)) != FG_OK || (st = dalloc(&H.tbuf, c.tbuf, err)) != FG_OK ||
+      (st = dalloc(&H.mpart, c.mpart, err)) != FG_OK ||
+      (st = dalloc(&H.sv, (size_t)std::max(c.nint, 1) * PMAX, err)) != FG_OK ||
+      (st = dalloc(&H.rank, std::max(c.nint, 1), err)) != FG_OK ||
+      (st = dalloc(&H.kmax, Lm, err)) != FG_OK ||
+      (st = dalloc(&H.rcols, (size_t)Lm * c.Ktot, err)) != FG_OK ||
+      (st = dalloc(&H.rcount, Lm, err)) != FG_OK ||
+      (st = dalloc(&H.panel, (size_t)H.ld * c.Ktot, err)) != FG_OK ||
+      (st = dalloc(&H.status, 1, err)) != FG_OK || (st = dalloc(&H.work, c.mv_work, err)) != FG_OK) {
+    hodlr_free(H);
+    return st;
+  }
+  (void)hipMemset(H.status, 0, sizeof(int));
+  (void)hipMemset(H.kmax, 0, sizeof(int) * Lm);
+  return FG_OK;
+}
+
+void hodlr_free(HodlrData& H) {
+  dfree(H.x); dfree(H.tbuf); dfree(H.mpart); dfree(H.sv); dfree(H.rank); dfree(H.kmax);
+  dfree(H.rcols); dfree(H.rcount); dfree(H.panel); dfree(H.status); dfree(H.work);
+}
+
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err) {
+  fg_status st;
+  const size_t ld = round_ld(c.n);
+  const size_t bb = (size_t)c.nleaf * c.B * c.B;
+  if ((st = dalloc(&F.leafL, bb, err)) != FG_OK || (st = dalloc(&F.leafLinv, bb, err)) != FG_OK ||
+      (st = dalloc(&F.leaf_ld, c.nleaf, err)) != FG_OK ||
+      (st = dalloc(&F.panel, ld * c.Ktot, err)) != FG_OK ||
+      (st = dalloc(&F.nodemat, c.nodemat, err)) != FG_OK ||
+      (st = dalloc(&F.node_ld, std::max(c.nint, 1), err)) != FG_OK ||
+      (st = dalloc(&F.zpart, c.zpart, err)) != FG_OK ||
+      (st = dalloc(&F.zfin, c.zfin, err)) != FG_OK || (st = dalloc(&F.coef, c.coef, err)) != FG_OK ||
+      (st = dalloc(&F.logdet, 1, err)) != FG_OK || (st = dalloc(&F.status, 1, err)) != FG_OK ||
+      (st = dalloc(&F.work, c.ap_work, err)) != FG_OK) {
+    factor_free(F);
+    return st;
+  }
+  (void)hipMemset(F.status, 0, sizeof(int));
+  (void)hipMemset(F.node_ld, 0, sizeof(double) * std::max(c.nint, 1));
+  return FG_OK;
+}
+
+void factor_free(FactorData& F) {
+  dfree(F.leafL); dfree(F.leafLinv); dfree(F.leaf_ld); dfree(F.panel); dfree(F.nodemat);
+  dfree(F.node_ld); dfree(F.zpart); dfree(F.zfin); dfree(F.coef); dfree(F.logdet);
+  dfree(F.status); dfree(F.work);
+}
+
+}  // namespace fg

@@ -1,0 +1,57 @@
+"""Gibbs-sweep parity (through gibbs_chain_create / gibbs_step / gibbs_chain_state)
+with the oracle's chain on the small 1-D workload, plus determinism."""
+import numpy as np
+import pytest
+
+from oracle import kernels, sampler
+from workloads import SMALL_1D, small_1d
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def fg():
+    import paper_2006_06537_amd as m
+    return m
+
+
+def _chain(x, y, cfg, seed):
+    dev = torch.device("cuda:0")
+    return fg().Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev),
+                      ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
+                      nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"], seed=seed)
+
+
+def test_chain_matches_oracle_small_workload():
+    c = SMALL_1D
+    x, y = small_1d(c["n"], c["seed"])
+    g = _chain(x, y, c, c["seed"])
+    o = sampler.Chain(x, y, kernels.SE, c["ell0"], c["nugget"], c["leaf"], c["tol"], c["tau0"],
+                      c["sigf2_0"], c["seed"])
+    for it in range(12):
+        g.step(1)
+        s = g.state(with_vectors=(it == 11))
+        r = o.step()
+        assert s["k"] == r["k"], f"iteration {it}: grid index {s['k']} vs {r['k']}"
+        assert s["last_accept"] == int(r["accept"])
+        assert s["last_proposal"] == r["proposal"]
+        for key in ["tau", "sigf2", "loglik", "logdet_sigma"]:
+            assert abs(s[key] - r[key]) <= 1e-9 * abs(r[key]), (it, key, s[key], r[key])
+        assert s["status"] == 0
+    f = s["f"].cpu().numpy()
+    assert np.linalg.norm(f - o.f) <= 1e-9 * np.linalg.norm(o.f)
+    mu = s["mu"].cpu().numpy()
+    assert np.linalg.norm(mu - r["mu"]) <= 1e-9 * np.linalg.norm(r["mu"])
+
+
+def test_chain_deterministic():
+    c = SMALL_1D
+    x, y = small_1d(600, 4)
+    a = _chain(x, y, c, 3)
+    b = _chain(x, y, c, 3)
+    a.step(6)
+    b.step(6)
+    sa, sb = a.state(True), b.state(True)
+    for key in ["tau", "sigf2", "k", "loglik", "accepts"]:
+        assert sa[key] == sb[key]
+    assert torch.equal(sa["f"], sb["f"])

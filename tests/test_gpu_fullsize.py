@@ -1,0 +1,84 @@
+"""Parity at the full large 1-D workload (n = 2^20, leaf 128, tol 1e-10, ell 0.02):
+sampled entries of K~_1, log-determinants of K~_1 and of M~ = tau K~_1 + I, the solve
+r = M~^-1 tau y and the posterior mean mu~ = K~_1 r / tau, against the oracle run at
+the same size."""
+import numpy as np
+import pytest
+
+from oracle import hodlr as oh, kernels
+from workloads import LARGE_1D, large_1d
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def big():
+    import paper_2006_06537_amd as fg
+    c = LARGE_1D
+    x, y = large_1d()
+    dev = torch.device("cuda:0")
+    K1 = fg.Hodlr(torch.tensor(x, device=dev), c["ell0"], nugget=c["nugget"], leaf=c["leaf"],
+                  tol=c["tol"])
+    H = oh.HODLR(x, kernels.SE, c["ell0"], c["nugget"], c["leaf"], c["tol"])
+    return dict(fg=fg, x=x, y=y, K1=K1, H=H, dev=dev, c=c)
+
+
+def _entry(H, i, j):
+    """K~_1[i, j] from the oracle's blocks, descending the tree to the separating node."""
+    if i > j:
+        i, j = j, i
+    jn = 0
+    for l in range(H.tree.L):
+        lo, mid, hi = H.tree.node(l, jn)
+        if j < mid:
+            jn = 2 * jn
+        elif i >= mid:
+            jn = 2 * jn + 1
+        else:
+            b = H.blocks[(l, jn)]
+            return float(b.U[i - lo] @ b.V[j - mid])
+    v = float(kernels.k1(H.kind, H.ell, H.x[[i]], H.x[[j]])[0, 0])
+    return v + (H.nugget if i == j else 0.0)
+
+
+def test_ranks_and_sampled_entries(big):
+    H, K1 = big["H"], big["K1"]
+    got = K1.ranks()
+    ref = [H.blocks[(l, j)].k for l in range(H.tree.L) for j in range(1 << l)]
+    bad = [h for h in range(len(ref)) if got[h] != ref[h]]
+    assert len(bad) <= max(1, len(ref) // 1000), bad[:10]
+    rs = np.random.default_rng(0)
+    n = H.n
+    ii = rs.integers(0, n, 4000)
+    # half the samples near the diagonal, where the blocks are largest
+    jj = np.clip(ii + rs.integers(-20000, 20000, 4000), 0, n - 1)
+    jj[::2] = rs.integers(0, n, 2000)
+    g = K1.entries(torch.tensor(ii, device=big["dev"]), torch.tensor(jj, device=big["dev"]))
+    g = g.cpu().numpy()
+    ref = np.array([_entry(H, int(a), int(b)) for a, b in zip(ii, jj)])
+    assert np.abs(g - ref).max() <= 1e-9
+
+
+def test_logdet_solve_mean(big):
+    fg, H, K1, c = big["fg"], big["H"], big["K1"], big["c"]
+    tau = c["tau0"]
+    WM = fg.Factor(K1, tau, 1.0)
+    OM = oh.Factor(H, tau, 1.0)
+    assert WM.status() == 0
+    ld = float(WM.logdet().cpu()[0])
+    assert abs(ld - OM.logdet()) <= 1e-9 * abs(OM.logdet())
+    yt = torch.tensor(big["y"], device=big["dev"])
+    r = WM.solve(tau * yt).cpu().numpy()
+    ro = OM.solve(tau * big["y"])
+    assert np.linalg.norm(r - ro) <= 1e-9 * np.linalg.norm(ro)
+    mu = K1.matvec(torch.tensor(ro, device=big["dev"])).cpu().numpy()
+    mo = H.matvec(ro)
+    assert np.linalg.norm(mu - mo) <= 1e-9 * np.linalg.norm(mo)
+
+
+def test_logdet_k1(big):
+    fg, H, K1 = big["fg"], big["H"], big["K1"]
+    W1 = fg.Factor(K1, 1.0, 0.0)
+    O1 = oh.Factor(H, 1.0, 0.0)
+    assert abs(float(W1.logdet().cpu()[0]) - O1.logdet()) <= 1e-9 * abs(O1.logdet())
