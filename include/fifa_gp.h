@@ -18,7 +18,8 @@
  *     argument/configuration errors and launch failures only.  Failures found on
  *     the device (a non-positive leaf pivot, a node singular value >= 1, a Gamma
  *     sampler that ran out of tries) are recorded in the handle's status word and
- *     read with fg_sync_status (which synchronises the stream).
+ *     read with hodlr_status / factor_status / gibbs_chain_state (which synchronise
+ *     the stream).
  *   - No exception crosses the ABI and nothing aborts.  fg_last_error() returns a
  *     thread-local message for the last non-zero return code.
  *   - Indices are 32-bit inside the library: n must satisfy 1 <= n < 2^31.
@@ -199,6 +200,21 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream);
  * (and r_out, mu_out likewise: Sigma~^-1 y and K~ r of the last f-draw). */
 fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_out,
                             double* r_out, double* mu_out, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Live kernel timing (diagnostics).  fg_timer_start(id) makes the library record
+ * HIP events, on the launch stream, around every following launch of kernel `id`
+ * (FG_KID_LEAF: leaf Cholesky + whitening of the panels; FG_KID_REDUCE: level Gram
+ * reduction; FG_KID_UPDATE: level update of the coarser panels).  fg_timer_stop
+ * synchronises the device and returns the summed kernel time (ms), the launch count
+ * and the algorithmic HBM bytes of those launches (each kernel's minimum traffic:
+ * every operand read once and every result written once).  Not thread-safe.
+ * ------------------------------------------------------------------------- */
+#define FG_KID_LEAF 1
+#define FG_KID_REDUCE 2
+#define FG_KID_UPDATE 3
+fg_status fg_timer_start(int32_t kernel_id);
+fg_status fg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
 
 /* Status word of a handle (synchronises the stream first). */
 fg_status hodlr_status(fg_hodlr A, fg_stream stream);

@@ -13,8 +13,27 @@ from . import _lib
 from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, check,
                    lib)
 
-__all__ = ["Hodlr", "Factor", "Chain", "normals", "draw_f", "KERNEL_SE", "KERNEL_EXP",
-           "FgError", "lib"]
+__all__ = ["Hodlr", "Factor", "Chain", "KernelTimer", "normals", "draw_f", "KERNEL_SE",
+           "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE"]
+
+KID_LEAF, KID_REDUCE, KID_UPDATE = 1, 2, 3
+KID_NAMES = {KID_LEAF: "k_leaf", KID_REDUCE: "k_reduce_panel", KID_UPDATE: "k_update_panel"}
+
+
+class KernelTimer:
+    """HIP-event timing of one library kernel over a region (fg_timer_start/stop)."""
+
+    def __init__(self, kernel_id):
+        self.kid = kernel_id
+        self.name = KID_NAMES[kernel_id]
+
+    def start(self):
+        check(lib().fg_timer_start(self.kid))
+
+    def stop(self):
+        ms, cnt, by = C.c_double(), C.c_int64(), C.c_double()
+        check(lib().fg_timer_stop(C.byref(ms), C.byref(cnt), C.byref(by)))
+        return ms.value, cnt.value, by.value
 
 
 def _torch():

@@ -17,6 +17,11 @@ constexpr int RCH = 256;          // rows per level-task (reduce / update)
 constexpr int MCH = 4096;         // rows per moment / panel-generation task
 constexpr double KAPPA_H = 1.086435;  // Cramer: |H_n(x)| e^{-x^2/2} <= KAPPA_H 2^{n/2} sqrt(n!)
 
+// kernels selectable for live timing (same values as FG_KID_* in fifa_gp.h)
+constexpr int KID_LEAF = 1;
+constexpr int KID_REDUCE = 2;
+constexpr int KID_UPDATE = 3;
+
 // status bits written by kernels (device word, OR-ed)
 constexpr int ST_NOTSPD = 1;
 constexpr int ST_NOTCONV = 2;

@@ -1,0 +1,12 @@
+// Live kernel timing hooks (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fg_internal.h"
+
+namespace fg {
+bool timer_wants(int kid);
+void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const int* kmax_dev,
+                  int ntask);
+void timer_after(int kid, hipStream_t s);
+}  // namespace fg

@@ -13,6 +13,7 @@
 #include <cfloat>
 
 #include "fg_internal.h"
+#include "fg_timer.h"
 
 namespace fg {
 
@@ -29,10 +30,68 @@ __device__ __forceinline__ double wsum(double v) {
 
 // ---------------------------------------------------------------------------------
 // leaves: Cholesky, its inverse, log-det and the whitening of every panel row
+//
+// One work-group of 256 threads per leaf (m <= 128 rows).  The leaf matrix lives in
+// registers in a 16 x 16 thread grid: thread (tr, tc) holds the 8 x 8 elements
+// (tr + 16 i, tc + 16 j).  Right-looking Cholesky, forward substitution and the
+// inverse (substitution on identity columns) all run as column steps: the owners of
+// column j (and of row j of the right-hand sides) publish it through a double-
+// buffered LDS vector, one barrier per step, and every thread updates its elements.
 // ---------------------------------------------------------------------------------
-constexpr int YCH = 16;  // panel columns per whitening chunk
+constexpr int LG = 16;        // thread grid side
+constexpr int LE = BMAX / LG; // elements per thread per dimension (8)
+constexpr int YQ = 4;         // right-hand-side columns per thread (64 per pass)
 
-__global__ void __launch_bounds__(NTHREADS) k_leaf(
+template <int N>
+__device__ __forceinline__ double pick(const double (&v)[N], int idx) {
+  double r = 0.0;
+#pragma unroll
+  for (int t = 0; t < N; ++t) r = (t == idx) ? v[t] : r;
+  return r;
+}
+
+// y (rows tr + 16 i, columns tc + 16 q of a 64-column block) <- L^-1 y, steps j0..m-1.
+__device__ __forceinline__ void leaf_trsm(const double (&a)[LE][LE], double (&y)[LE][YQ], int m,
+                                          int j0, double (*colL)[BMAX], double (*rowY)[64],
+                                          int tr, int tc) {
+  for (int j = j0; j < m; ++j) {
+    const int buf = j & 1, js = j >> 4;
+    if (tc == (j & 15)) {
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        if (r >= j && r < m) colL[buf][r] = pick(a[i], js);
+      }
+    }
+    if (tr == (j & 15)) {
+#pragma unroll
+      for (int q = 0; q < YQ; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < LE; ++i) v = (i == js) ? y[i][q] : v;
+        rowY[buf][tc + LG * q] = v;
+      }
+    }
+    __syncthreads();
+    const double dinv = 1.0 / colL[buf][j];
+    double yj[YQ];
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) yj[q] = rowY[buf][tc + LG * q] * dinv;
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int r = tr + LG * i;
+      const double lr = (r > j && r < m) ? colL[buf][r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < YQ; ++q) y[i][q] -= lr * yj[q];
+      if (r == j) {
+#pragma unroll
+        for (int q = 0; q < YQ; ++q) y[i][q] = yj[q];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
     double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
@@ -44,87 +103,145 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf(
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const double alpha = alpha_p ? *alpha_p : alpha_v;
   const double beta = beta_p ? *beta_p : beta_v;
-  extern __shared__ double lds[];
-  double* A = lds;                   // Bc x Bc, column-major, ld = Bc
-  double* Y = A + Bc * Bc;           // Bc x YCH
-  double* xs = Y + Bc * YCH;         // Bc
-  double* tmp = xs + Bc;             // Bc
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  __shared__ double xs[BMAX];
+  __shared__ double colL[2][BMAX];
+  __shared__ double rowY[2][64];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   for (int r = threadIdx.x; r < m; r += NTHREADS) xs[r] = x[lo + r];
   __syncthreads();
-  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
-    const int r = idx % m, c = idx / m;
-    double v = alpha * kern1(kind, ell, xs[r], xs[c]);
-    if (r == c) v += alpha * nugget + beta + (diag ? diag[lo + r] : 0.0);
-    A[r + c * Bc] = v;
-  }
-  __syncthreads();
-  // Cholesky, lower, in place
-  for (int j = 0; j < m; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = A[j + j * Bc];
-      if (!(d > 0.0)) bad = 1;
-      A[j + j * Bc] = d > 0.0 ? sqrt(d) : 1.0;
-    }
-    __syncthreads();
-    const double ljj = A[j + j * Bc];
-    for (int r = j + 1 + threadIdx.x; r < m; r += NTHREADS) A[r + j * Bc] /= ljj;
-    __syncthreads();
-    const int w = m - j - 1;
-    for (int idx = threadIdx.x; idx < w * w; idx += NTHREADS) {
-      const int r = j + 1 + idx % w, c = j + 1 + idx / w;
-      if (c <= r) A[r + c * Bc] -= A[r + j * Bc] * A[c + j * Bc];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s += log(A[j + j * Bc]);
-    leaf_ld[b] = 2.0 * s;
-    if (bad) atomicOr(status, ST_NOTSPD);
-  }
-  double* Lg = leafL + (size_t)b * Bc * Bc;
-  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
-    const int r = idx % m, c = idx / m;
-    Lg[r + c * Bc] = (c <= r) ? A[r + c * Bc] : 0.0;
-  }
-  __syncthreads();
-  // triangular inverse in place (columns from the last)
-  for (int j = m - 1; j >= 0; --j) {
-    if (threadIdx.x == 0) A[j + j * Bc] = 1.0 / A[j + j * Bc];
-    for (int r = j + 1 + threadIdx.x; r < m; r += NTHREADS) tmp[r] = A[r + j * Bc];
-    __syncthreads();
-    const double ajj = -A[j + j * Bc];
-    for (int r = j + 1 + threadIdx.x; r < m; r += NTHREADS) {
-      double acc = 0.0;
-      for (int c = j + 1; c <= r; ++c) acc += A[r + c * Bc] * tmp[c];
-      A[r + j * Bc] = ajj * acc;
-    }
-    __syncthreads();
-  }
-  double* Lig = leafLinv + (size_t)b * Bc * Bc;
-  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
-    const int r = idx % m, c = idx / m;
-    Lig[r + c * Bc] = (c <= r) ? A[r + c * Bc] : 0.0;
-  }
-  // whitening of all panel rows of this leaf: dst = sqrt(alpha) L^-1 src
-  const double sa = sqrt(alpha);
-  for (int l = 0; l < L; ++l) {
-    const int kl = kmax[l];
-    for (int c0 = 0; c0 < kl; c0 += YCH) {
-      const int cw = min(YCH, kl - c0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < m * cw; idx += NTHREADS) {
-        const int r = idx % m, c = idx / m;
-        Y[r + c * Bc] = src[(size_t)(coff[l] + c0 + c) * ld + lo + r];
+  double a[LE][LE];
+#pragma unroll
+  for (int i = 0; i < LE; ++i) {
+    const int r = tr + LG * i;
+#pragma unroll
+    for (int jj = 0; jj < LE; ++jj) {
+      const int c = tc + LG * jj;
+      double v = (r == c) ? 1.0 : 0.0;
+      if (r < m && c < m) {
+        v = alpha * kern1(kind, ell, xs[r], xs[c]);
+        if (r == c) v += alpha * nugget + beta + (diag ? diag[lo + r] : 0.0);
       }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < m * cw; idx += NTHREADS) {
-        const int r = idx % m, c = idx / m;
-        double acc = 0.0;
-        for (int s = 0; s <= r; ++s) acc += A[r + s * Bc] * Y[s + c * Bc];
-        dst[(size_t)(coff[l] + c0 + c) * ld + lo + r] = sa * acc;
+      a[i][jj] = v;
+    }
+  }
+  // Cholesky: column j of L = (column j of the updated matrix) / sqrt(pivot)
+  double ldsum = 0.0;
+  bool mybad = false;
+  for (int j = 0; j < m; ++j) {
+    const int buf = j & 1, js = j >> 4;
+    if (tc == (j & 15)) {
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        if (r >= j && r < m) colL[buf][r] = pick(a[i], js);
+      }
+    }
+    __syncthreads();
+    const double d = colL[buf][j];
+    const bool ok = d > 0.0;
+    mybad |= !ok;
+    const double inv = ok ? 1.0 / sqrt(d) : 1.0;
+    if (threadIdx.x == 0) ldsum += ok ? log(d) : 0.0;
+    double lr[LE], lc[LE];
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int r = tr + LG * i;
+      lr[i] = (r > j && r < m) ? colL[buf][r] * inv : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < LE; ++jj) {
+      const int c = tc + LG * jj;
+      lc[jj] = (c > j && c < m) ? colL[buf][c] * inv : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < LE; ++i)
+#pragma unroll
+      for (int jj = 0; jj < LE; ++jj) a[i][jj] -= lr[i] * lc[jj];
+    if (tc == (j & 15)) {
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        const double v = (r >= j && r < m) ? colL[buf][r] * inv : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < LE; ++jj)
+          if (jj == js) a[i][jj] = v;
+      }
+    }
+  }
+  if (mybad) atomicOr(&bad, 1);
+  if (threadIdx.x == 0) leaf_ld[b] = ldsum;  // sum log(pivot) = 2 sum log diag(L)
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicOr(status, ST_NOTSPD);
+  // L to global (lower triangle, column-major, ld = Bc)
+  double* Lg = leafL + (size_t)b * Bc * Bc;
+#pragma unroll
+  for (int jj = 0; jj < LE; ++jj) {
+    const int c = tc + LG * jj;
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int r = tr + LG * i;
+      if (r < m && c < m) Lg[r + (size_t)c * Bc] = (c <= r) ? a[i][jj] : 0.0;
+    }
+  }
+  // L^-1 by substitution on identity columns, 64 columns per pass
+  double* Lig = leafLinv + (size_t)b * Bc * Bc;
+  for (int c0 = 0; c0 < m; c0 += 64) {
+    double y[LE][YQ];
+#pragma unroll
+    for (int i = 0; i < LE; ++i)
+#pragma unroll
+      for (int q = 0; q < YQ; ++q) y[i][q] = (tr + LG * i == c0 + tc + LG * q) ? 1.0 : 0.0;
+    leaf_trsm(a, y, m, c0, colL, rowY, tr, tc);
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int c = c0 + tc + LG * q;
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        if (r < m && c < m) Lig[r + (size_t)c * Bc] = (c <= r) ? y[i][q] : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  // whitening of all panel rows of this leaf: dst = sqrt(alpha) L^-1 src.  The active
+  // columns of all levels are numbered 0..total-1 and handled 64 per pass.
+  const double sa = sqrt(alpha);
+  int total = 0;
+  for (int l = 0; l < L; ++l) total += kmax[l];
+  for (int p0 = 0; p0 < total; p0 += 64) {
+    int gcq[YQ];
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      int f = p0 + tc + LG * q;
+      gcq[q] = -1;
+      if (f < total) {
+        for (int l = 0; l < L; ++l) {
+          const int km = kmax[l];
+          if (f < km) { gcq[q] = coff[l] + f; break; }
+          f -= km;
+        }
+      }
+    }
+    double y[LE][YQ];
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        y[i][q] = (gcq[q] >= 0 && r < m) ? src[(size_t)gcq[q] * ld + lo + r] : 0.0;
+      }
+    }
+    __syncthreads();
+    leaf_trsm(a, y, m, 0, colL, rowY, tr, tc);
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      if (gcq[q] < 0) continue;
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        const int r = tr + LG * i;
+        if (r < m) dst[(size_t)gcq[q] * ld + lo + r] = sa * y[i][q];
       }
     }
   }
@@ -490,14 +607,12 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
   const int Bc = P.B;
-  const size_t lds_leaf = sizeof(double) * (size_t)(Bc * Bc + Bc * YCH + 2 * Bc);
-  if (lds_leaf > 65536)
-    (void)hipFuncSetAttribute((const void*)k_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(lds_leaf));
-  k_leaf<<<P.nleaf, NTHREADS, lds_leaf, s>>>(
+  timer_before(KID_LEAF, s, -1, P, H.kmax, 0);
+  k_leaf<<<P.nleaf, NTHREADS, 0, s>>>(
       D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
       diag, Bc, F.leafL, F.leafLinv, F.leaf_ld, F.status, H.panel, F.panel, H.ld, D.coff, H.kmax,
       P.L);
+  timer_after(KID_LEAF, s);
   const int kc = std::max(P.kcapmax, 1);
   const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
   if (lds_node > 65536)
@@ -507,17 +622,22 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
     const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
     const int Wcap = P.coff[l + 1];  // columns of levels <= l (capacity)
     const int zs_a = Wcap, zs_task = P.kcap[l] * Wcap;
+    timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
     k_reduce_panel<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
                                            H.rcount, P.Ktot, F.panel, H.ld, F.zpart, zs_a, zs_task);
+    timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
     k_node_factor<<<1 << l, NTHREADS, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
         kc);
-    if (l > 0)
+    if (l > 0) {
+      timer_before(KID_UPDATE, s, l, P, H.kmax, nt);
       k_update_panel<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
                                              H.rcols, H.rcount, P.Ktot, F.panel, H.ld, F.coef,
                                              cs_node, cs_a);
+      timer_after(KID_UPDATE, s);
+    }
   }
   launch_logdet_sum(F, s);
 }
