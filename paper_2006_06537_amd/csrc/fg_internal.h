@@ -13,7 +13,7 @@ namespace fg {
 constexpr int PMAX = 60;          // interpolation nodes per side (and rank cap)
 constexpr int BMAX = 128;         // maximum leaf size
 constexpr int NTHREADS = 256;     // work-group size of every kernel
-constexpr int RCH = 256;          // rows per level-task (reduce / update)
+constexpr int RCH = 1024;         // rows per level-task (reduce / update)
 constexpr int MCH = 4096;         // rows per moment / panel-generation task
 constexpr double KAPPA_H = 1.086435;  // Cramer: |H_n(x)| e^{-x^2/2} <= KAPPA_H 2^{n/2} sqrt(n!)
 
@@ -26,6 +26,13 @@ constexpr int KID_UPDATE = 3;
 constexpr int ST_NOTSPD = 1;
 constexpr int ST_NOTCONV = 2;
 constexpr int ST_TOL = 4;
+
+// Panels are stored in 16-row tiles: rows of a tile are contiguous (128 bytes per
+// column), then the K columns of that tile, then the next tile.  A 16-row segment of
+// one column is a single cache line and the columns of a tile are adjacent.
+__host__ __device__ __forceinline__ size_t pix(int r, int c, int K) {
+  return ((size_t)(r >> 4) * (size_t)K + (size_t)c) * 16 + (size_t)(r & 15);
+}
 
 // One internal tree node: rows [lo, hi) split at mid; window rows [i0, mid) of the
 // left child and [mid, j1) of the right child carry the off-diagonal block.
@@ -67,6 +74,7 @@ struct HostPlan {
   std::vector<int> ltask_off;            // L + 1
   std::vector<int> node_task_off;        // per node side: first level task (2*nint+1)
   int max_ltasks = 0;
+  std::vector<int> max_tps;              // per level: most tasks on one node side
   int nmt = 0, ngt = 0, nlt = 0;         // task counts (kept after the vectors are freed)
 };
 
@@ -169,6 +177,8 @@ void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, i
 // out = scale * sum (a-b)^2 or sum a*b etc (deterministic two-stage)
 void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
                 hipStream_t s);
+void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
+                 int nsides, int esz, double* zfin, int zf_side, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,
                   const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
 

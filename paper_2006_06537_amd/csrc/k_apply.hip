@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__
 __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
     const int* __restrict__ coff, const int* __restrict__ kmax, const double* __restrict__ P,
-    int ld, const double* __restrict__ v, int nrhs, int ldv, double* __restrict__ zpart,
+    int K, const double* __restrict__ v, int nrhs, int ldv, double* __restrict__ zpart,
     int zs_task) {
   const int t = blockIdx.x;
   if (t >= ntask) return;
@@ -70,9 +70,8 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int a = wv; a < kl; a += NTHREADS / 64) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
-    const double* pc = P + (size_t)(c0 + a) * ld + tk.r0;
     for (int i = lane; i < rw; i += 64) {
-      const double pv = pc[i];
+      const double pv = P[pix(tk.r0 + i, c0 + a, K)];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * vs[c][i];
     }
     for (int c = 0; c < nrhs; ++c) {
@@ -83,11 +82,12 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
 }
 
 // per-node coefficients.  op: 0 W, 1 W', 2 W^-1, 3 W^-T, 4 matvec (alpha scaling)
-__global__ void __launch_bounds__(NTHREADS) k_node_coef(
+__global__ void __launch_bounds__(64) k_node_coef(
     int op, int hbase, int nnode, const int* __restrict__ rank,
     const int* __restrict__ node_task_off, int tbase, const double* __restrict__ zpart,
     int zs_task, int nrhs, const double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
-    double alpha_v, const double* __restrict__ alpha_p, double* __restrict__ coef, int cs_node) {
+    double alpha_v, const double* __restrict__ alpha_p, double* __restrict__ coef, int cs_node,
+    const double* __restrict__ zsum) {
   const int jn = blockIdx.x;
   if (jn >= nnode) return;
   const int h = hbase + jn;
@@ -95,11 +95,16 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
   if (k == 0) return;
   __shared__ double S[PMAX][NRHS_MAX], T[PMAX][NRHS_MAX], X[PMAX][NRHS_MAX];
   const int kn = k * nrhs;
-  for (int idx = threadIdx.x; idx < 2 * kn; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < 2 * kn; idx += blockDim.x) {
     const int side = idx / kn, e = idx % kn;
-    const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
     double s = 0.0;
-    for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + e];
+    if (zsum) {  // presummed per node side (k_zsum)
+      s = zsum[(size_t)(2 * jn + side) * zs_task + e];
+    } else {
+      const int t0 = node_task_off[2 * h + side] - tbase;
+      const int t1 = node_task_off[2 * h + side + 1] - tbase;
+      for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + e];
+    }
     if (side) T[e / nrhs][e % nrhs] = s; else S[e / nrhs][e % nrhs] = s;
   }
   __syncthreads();
@@ -107,7 +112,7 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
   double* cJ = cI + PMAX * NRHS_MAX;
   if (op == 4) {
     const double al = alpha_p ? *alpha_p : alpha_v;
-    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    for (int e = threadIdx.x; e < kn; e += blockDim.x) {
       cI[e] = al * T[e / nrhs][e % nrhs];
       cJ[e] = al * S[e / nrhs][e % nrhs];
     }
@@ -117,7 +122,7 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
   const double* F1 = GV + k * k;
   const double* F2 = GV + 2 * k * k;
   if (op == 0 || op == 1) {
-    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    for (int e = threadIdx.x; e < kn; e += blockDim.x) {
       const int a = e / nrhs, c = e % nrhs;
       double f = 0.0;
       for (int d = 0; d < k; ++d) f += F1[a + d * k] * T[d][c];
@@ -127,14 +132,14 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
     return;
   }
   if (op == 2) {
-    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    for (int e = threadIdx.x; e < kn; e += blockDim.x) {
       const int a = e / nrhs, c = e % nrhs;
       double u = T[a][c];
       for (int d = 0; d < k; ++d) u -= GV[a + d * k] * S[d][c];
       X[a][c] = u;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+    for (int e = threadIdx.x; e < kn; e += blockDim.x) {
       const int a = e / nrhs, c = e % nrhs;
       double f = -S[a][c];
       for (int d = 0; d < k; ++d) f += F2[a + d * k] * X[d][c];
@@ -144,14 +149,14 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
     return;
   }
   // op == 3
-  for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+  for (int e = threadIdx.x; e < kn; e += blockDim.x) {
     const int a = e / nrhs, c = e % nrhs;
     double w = 0.0;
     for (int d = 0; d < k; ++d) w += F2[a + d * k] * T[d][c];
     X[a][c] = w;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kn; e += NTHREADS) {
+  for (int e = threadIdx.x; e < kn; e += blockDim.x) {
     const int a = e / nrhs, c = e % nrhs;
     double g = T[a][c];
     for (int d = 0; d < k; ++d) g += GV[a + d * k] * X[d][c];
@@ -164,7 +169,7 @@ __global__ void __launch_bounds__(NTHREADS) k_node_coef(
 __global__ void __launch_bounds__(NTHREADS) k_update_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
     int hbase, const int* __restrict__ rank, const int* __restrict__ coff,
-    const double* __restrict__ P, int ld, double* __restrict__ v, int nrhs, int ldv,
+    const double* __restrict__ P, int K, double* __restrict__ v, int nrhs, int ldv,
     const double* __restrict__ coef, int cs_node, int skip_left) {
   const int t = blockIdx.x;
   if (t >= ntask) return;
@@ -177,11 +182,11 @@ __global__ void __launch_bounds__(NTHREADS) k_update_vec(
   __shared__ double cs[PMAX * NRHS_MAX];
   for (int e = threadIdx.x; e < k * nrhs; e += NTHREADS) cs[e] = cf[e];
   __syncthreads();
-  const double* p0 = P + (size_t)coff[l] * ld;
+  const int cb = coff[l];
   for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
     for (int a = 0; a < k; ++a) {
-      const double pv = p0[(size_t)a * ld + r];
+      const double pv = P[pix(r, cb + a, K)];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * cs[a * nrhs + c];
     }
     for (int c = 0; c < nrhs; ++c) v[(size_t)c * ldv + r] += acc[c];
@@ -194,7 +199,7 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
     double ell, double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ v, double* __restrict__ y,
     int nrhs, int ld, const int* __restrict__ rank, const int* __restrict__ coff,
-    const double* __restrict__ P, int ldp, const double* __restrict__ coef, int cs_node) {
+    const double* __restrict__ P, int K, const double* __restrict__ coef, int cs_node) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
@@ -225,9 +230,9 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
     if (k == 0) continue;
     const int side = (b >> (L - l - 1)) & 1;
     const double* cf = coef + (size_t)h * cs_node + side * PMAX * NRHS_MAX;
-    const double* p0 = P + (size_t)coff[l] * ldp + i;
+    const int cb = coff[l];
     for (int a = 0; a < k; ++a) {
-      const double pv = p0[(size_t)a * ldp];
+      const double pv = P[pix(i, cb + a, K)];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * cf[a * nrhs + c];
     }
   }
@@ -237,18 +242,19 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
 // ---------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------
+// workspace: task partials | per-node coefficients | per-node-side presummed partials
 size_t apply_work_doubles(const HostPlan& P, int nrhs) {
   (void)nrhs;
   const size_t zp = (size_t)std::max(P.max_ltasks, 1) * PMAX * NRHS_MAX;
   const size_t cf = (size_t)std::max(P.nint, 1) * 2 * PMAX * NRHS_MAX;
-  return zp + cf;
+  return zp + 2 * cf;
 }
 
 size_t matvec_work_doubles(const HostPlan& P, int nrhs) {
   (void)nrhs;
   const size_t zp = (size_t)std::max(P.nlt, 1) * PMAX * NRHS_MAX;
   const size_t cf = (size_t)std::max(P.nint, 1) * 2 * PMAX * NRHS_MAX;
-  return zp + cf;
+  return zp + 2 * cf;
 }
 
 static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int ld, double* work,
@@ -263,13 +269,18 @@ static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int l
   const int cs_node = 2 * PMAX * NRHS_MAX;
   const int hbase = (1 << l) - 1;
   k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, F.panel,
-                                       H.ld, v, nrhs, ld, zpart, zs_task);
-  k_node_coef<<<1 << l, NTHREADS, 0, s>>>(op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart,
-                                          zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr,
-                                          coef, cs_node);
+                                       P.Ktot, v, nrhs, ld, zpart, zs_task);
+  double* zs = nullptr;
+  if (P.max_tps[l] > 1) {
+    zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
+    launch_zsum(zpart, zs_task, tb, D.node_task_off, hbase, 2 << l, zs_task, zs, zs_task, s);
+  }
+  k_node_coef<<<1 << l, 64, 0, s>>>(op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart,
+                                    zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr, coef,
+                                    cs_node, zs);
   const int skip_left = (op == 0 || op == 2) ? 1 : 0;
   k_update_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
-                                       F.panel, H.ld, v, nrhs, ld, coef, cs_node, skip_left);
+                                       F.panel, P.Ktot, v, nrhs, ld, coef, cs_node, skip_left);
 }
 
 void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
@@ -306,14 +317,15 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
   const int cs_node = 2 * PMAX * NRHS_MAX;
   if (P.L > 0) {
     k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel,
-                                         H.ld, v, nrhs, ld, zpart, zs_task);
-    k_node_coef<<<P.nint, NTHREADS, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart,
-                                            zs_task, nrhs, nullptr, nullptr, alpha, alpha_dev, coef,
-                                            cs_node);
+                                         P.Ktot, v, nrhs, ld, zpart, zs_task);
+    double* zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
+    launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task, s);
+    k_node_coef<<<P.nint, 64, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart, zs_task,
+                                      nrhs, nullptr, nullptr, alpha, alpha_dev, coef, cs_node, zs);
   }
   k_mv_apply<<<P.nleaf, BMAX, 0, s>>>(D.leaf_lo, P.nleaf, P.L, H.x, P.kind, P.ell, P.nugget,
                                       alpha, alpha_dev, beta, beta_dev, v, y, nrhs, ld, H.rank,
-                                      D.coff, H.panel, H.ld, coef, cs_node);
+                                      D.coff, H.panel, P.Ktot, coef, cs_node);
 }
 
 }  // namespace fg

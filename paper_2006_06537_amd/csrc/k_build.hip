@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
     const Task* __restrict__ tasks, int ntask, const NodePlan* __restrict__ nodes,
     const double* __restrict__ x, const double* __restrict__ tbuf, const int* __restrict__ rank,
     const int* __restrict__ kmax, const int* __restrict__ coff, double* __restrict__ panel,
-    int ld) {
+    int K) {
   const int t = blockIdx.x;
   if (t >= ntask) return;
   const Task tk = tasks[t];
@@ -401,16 +401,16 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
   __shared__ double Ts[PMAX * PMAX];
   for (int idx = threadIdx.x; idx < p * k; idx += NTHREADS) Ts[idx] = T[idx];
   __syncthreads();
-  double* col0 = panel + (size_t)coff[l] * ld;
+  const int cb = coff[l];
   for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
     const bool inwin = (r >= w0 && r < w1);
     if (!inwin || k == 0) {
-      for (int cc = 0; cc < kl; ++cc) col0[(size_t)cc * ld + r] = 0.0;
+      for (int cc = 0; cc < kl; ++cc) panel[pix(r, cb + cc, K)] = 0.0;
       continue;
     }
     if (exact) {
       const int e = r - w0;
-      for (int cc = 0; cc < k; ++cc) col0[(size_t)cc * ld + r] = Ts[cc * p + e];
+      for (int cc = 0; cc < k; ++cc) panel[pix(r, cb + cc, K)] = Ts[cc * p + e];
     } else {
       const double tt = hw > 0.0 ? (x[r] - c) / hw : 0.0;
       for (int cc = 0; cc < k; ++cc) {
@@ -422,10 +422,10 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
           tm2 = tm1;
           tm1 = tn;
         }
-        col0[(size_t)cc * ld + r] = acc;
+        panel[pix(r, cb + cc, K)] = acc;
       }
     }
-    for (int cc = k; cc < kl; ++cc) col0[(size_t)cc * ld + r] = 0.0;
+    for (int cc = k; cc < kl; ++cc) panel[pix(r, cb + cc, K)] = 0.0;
   }
 }
 
@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
 __global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
                           const double* __restrict__ x, int kind, double ell, double nugget,
                           const int* __restrict__ kmax, const int* __restrict__ coff,
-                          const double* __restrict__ panel, int ld, const int64_t* __restrict__ ii,
+                          const double* __restrict__ panel, int K, const int64_t* __restrict__ ii,
                           const int64_t* __restrict__ jj, int64_t count, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
@@ -448,8 +448,8 @@ __global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
     else if (i >= q.mid) h = 2 * h + 2;
     else {
       double acc = 0.0;
-      const double* c0 = panel + (size_t)coff[q.level] * ld;
-      for (int c = 0; c < kmax[q.level]; ++c) acc += c0[(size_t)c * ld + i] * c0[(size_t)c * ld + j];
+      const int cb = coff[q.level];
+      for (int c = 0; c < kmax[q.level]; ++c) acc += panel[pix(i, cb + c, K)] * panel[pix(j, cb + c, K)];
       out[t] = acc;
       return;
     }
@@ -478,7 +478,7 @@ void launch_build(HodlrData& H, hipStream_t s) {
   k_rank_levels<<<1, 64, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
   const int ng = P.ngt;
   k_panel_gen<<<ng, NTHREADS, 0, s>>>(D.gtasks, ng, D.nodes, H.x, H.tbuf, H.rank, H.kmax,
-                                      D.coff, H.panel, H.ld);
+                                      D.coff, H.panel, P.Ktot);
 }
 
 void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int64_t count,
@@ -487,7 +487,7 @@ void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int6
   const int nb = int((count + 255) / 256);
   const HostPlan& P = H.pk->P;
   k_entries<<<nb, 256, 0, s>>>(H.pk->D.nodes, P.nint, H.x, P.kind, P.ell, P.nugget, H.kmax,
-                               H.pk->D.coff, H.panel, H.ld, i, j, count, out);
+                               H.pk->D.coff, H.panel, P.Ktot, i, j, count, out);
 }
 
 }  // namespace fg

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
     double* __restrict__ leafL, double* __restrict__ leafLinv, double* __restrict__ leaf_ld,
-    int* __restrict__ status, const double* __restrict__ src, double* __restrict__ dst, int ld,
+    int* __restrict__ status, const double* __restrict__ src, double* __restrict__ dst, int K,
     const int* __restrict__ coff, const int* __restrict__ kmax, int L) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         const int r = tr + LG * i;
-        y[i][q] = (gcq[q] >= 0 && r < m) ? src[(size_t)gcq[q] * ld + lo + r] : 0.0;
+        y[i][q] = (gcq[q] >= 0 && r < m) ? src[pix(lo + r, gcq[q], K)] : 0.0;
       }
     }
     __syncthreads();
@@ -241,64 +241,129 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         const int r = tr + LG * i;
-        if (r < m) dst[(size_t)gcq[q] * ld + lo + r] = sa * y[i][q];
+        if (r < m) dst[pix(lo + r, gcq[q], K)] = sa * y[i][q];
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------------
-// level reduce (panel x panel): Z[a][b] = sum_i P[i, coff_l + a] R[i, rcols_l[b]]
+// level reduce (panel x panel): Z[a][b] = sum_i P[i, coff_l + a] P[i, rcols_l[b]]
+//
+// A tall-skinny product (rows are the reduction dimension) on FP64 matrix cores:
+// v_mfma_f64_16x16x4f64 takes A (16 x 4) with lane l holding A[l%16][l/16], B (4 x 16)
+// with lane l holding B[l/16][l%16], and accumulates D (16 x 16) with lane l holding
+// D[l/16 + 4 v][l%16], v = 0..3 (layout checked on gfx950).  Here M = left columns a, N = right columns b and
+// K = rows.  A work-group stages 32 rows x (left + 64 right) columns in LDS per step
+// (coalesced along rows); each wave owns 16 right columns and all left tiles.
 // ---------------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Each wave owns 16 right columns of one task and every 16-column left tile; it walks
+// the task's rows 16 at a time with no LDS and no barrier.  For step s (0..3) of a
+// 16-row group, K-slot k holds row base + 4k + s, so lane l reads rows base + 4 (l/16)
+// .. +3 of its column: 32 contiguous bytes, and the four steps use each 128-byte line
+// of the 16-row tile completely.
 __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
     const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ coff,
     const int* __restrict__ kmax, const int* __restrict__ rcols, const int* __restrict__ rcount,
-    int Ktot, const double* __restrict__ P, int ld, double* __restrict__ zpart, int zs_a,
-    int zs_task) {
+    int K, const double* __restrict__ P, double* __restrict__ zpart, int zs_a, int zs_task) {
   const int t = blockIdx.x;
   if (t >= ntask) return;
-  const Task tk = tasks[tbase + t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c0 = coff[l], kl = kmax[l], W = rcount[l];
-  const int* rc = rcols + (size_t)l * Ktot;
-  __shared__ double Ls[PMAX][64];
-  __shared__ double Rs[64][65];
-  const int bb = threadIdx.x & 63, a0 = threadIdx.x >> 6;
-  for (int b0 = 0; b0 < W; b0 += 64) {
-    const int bw = min(64, W - b0);
-    double acc[15];
+  const int b0 = blockIdx.y * 64 + wv * 16;
+  if (b0 >= W || kl == 0) return;
+  const Task tk = tasks[tbase + t];
+  const int na = (kl + 15) >> 4;
+  const int cl = lane & 15, kg = lane >> 4;
+  const int bcol = b0 + cl;
+  const int gcb = bcol < W ? rcols[(size_t)l * K + bcol] : -1;
+  int acol[4];
 #pragma unroll
-    for (int m = 0; m < 15; ++m) acc[m] = 0.0;
-    for (int r = tk.r0; r < tk.r1; r += 64) {
-      const int rw = min(64, tk.r1 - r);
-      for (int idx = threadIdx.x; idx < kl * 64; idx += NTHREADS) {
-        const int row = idx & 63, col = idx >> 6;
-        Ls[col][row] = row < rw ? P[(size_t)(c0 + col) * ld + r + row] : 0.0;
-      }
-      for (int idx = threadIdx.x; idx < bw * 64; idx += NTHREADS) {
-        const int row = idx & 63, col = idx >> 6;
-        Rs[row][col] = row < rw ? P[(size_t)rc[b0 + col] * ld + r + row] : 0.0;
-      }
-      __syncthreads();
-      if (bb < bw) {
-        for (int i = 0; i < rw; ++i) {
-          const double rv = Rs[i][bb];
+  for (int q = 0; q < 4; ++q) acol[q] = (q * 16 + cl < kl) ? c0 + q * 16 + cl : -1;
+  d4 acc[4];
 #pragma unroll
-          for (int m = 0; m < 15; ++m) {
-            const int a = a0 + 4 * m;
-            if (a < kl) acc[m] += Ls[a][i] * rv;
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool aligned = ((tk.r0 | tk.r1) & 15) == 0;
+  for (int base = tk.r0; base < tk.r1; base += 16) {
+    double bv[4];
+    if (aligned) {
+      const double* pb = P + pix(base + 4 * kg, gcb < 0 ? 0 : gcb, K);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[s] = gcb >= 0 ? pb[s] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = base + 4 * kg + s;
+        bv[s] = (gcb >= 0 && row < tk.r1) ? P[pix(row, gcb, K)] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < na) {
+        double av[4];
+        if (aligned) {
+          const double* pa = P + pix(base + 4 * kg, acol[q] < 0 ? 0 : acol[q], K);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) av[s] = acol[q] >= 0 ? pa[s] : 0.0;
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int row = base + 4 * kg + s;
+            av[s] = (acol[q] >= 0 && row < tk.r1) ? P[pix(row, acol[q], K)] : 0.0;
           }
         }
-      }
-      __syncthreads();
-    }
-    if (bb < bw) {
 #pragma unroll
-      for (int m = 0; m < 15; ++m) {
-        const int a = a0 + 4 * m;
-        if (a < kl) zpart[(size_t)t * zs_task + (size_t)a * zs_a + b0 + bb] = acc[m];
+        for (int s = 0; s < 4; ++s)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc[q], 0, 0, 0);
       }
     }
   }
+  if (bcol < W) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < na) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = q * 16 + kg + 4 * v;
+          if (a < kl) zpart[(size_t)t * zs_task + (size_t)a * zs_a + bcol] = acc[q][v];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// deterministic sum of task partials per node side: zfin[side][e] = sum_t zpart[t][e]
+// (4 task lanes per entry, combined in a fixed order)
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zpart, int zs_task,
+                                                   int tbase, const int* __restrict__ node_task_off,
+                                                   int hbase, int nsides, int esz,
+                                                   double* __restrict__ zfin, int zf_side) {
+  const int sd = blockIdx.x;
+  if (sd >= nsides) return;
+  const int h = hbase + (sd >> 1), side = sd & 1;
+  const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
+  const int e = blockIdx.y * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  __shared__ double red[4][64];
+  double s = 0.0;
+  if (e < esz)
+    for (int t = t0 + g; t < t1; t += 4) s += zpart[(size_t)t * zs_task + e];
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && e < esz)
+    zfin[(size_t)sd * zf_side + e] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
+                 int nsides, int esz, double* zfin, int zf_side, hipStream_t s) {
+  if (nsides <= 0 || esz <= 0) return;
+  const dim3 grid(nsides, (esz + 63) / 64);
+  k_zsum<<<grid, NTHREADS, 0, s>>>(zpart, zs_task, tbase, node_task_off, hbase, nsides, esz, zfin,
+                                   zf_side);
 }
 
 // ---------------------------------------------------------------------------------
@@ -307,9 +372,9 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
 __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
   __shared__ int perm[PMAX + 1];
   __shared__ double cs[PMAX / 2 + 1], sn[PMAX / 2 + 1];
-  __shared__ double red[NTHREADS / 64][2];
+  __shared__ double red[4][2];
   __shared__ int done;
-  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS)
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x)
     E[idx % m + (idx / m) * lda] = (idx % m == idx / m) ? 1.0 : 0.0;
   __syncthreads();
   if (m < 2) return true;
@@ -317,7 +382,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
   bool conv = false;
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
       const double v = A[idx % m + (idx / m) * lda];
       tot += v * v;
       if (idx % m != idx / m) off += v * v;
@@ -328,7 +393,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
     __syncthreads();
     if (threadIdx.x == 0) {
       double o = 0.0, s = 0.0;
-      for (int w = 0; w < NTHREADS / 64; ++w) { o += red[w][0]; s += red[w][1]; }
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { o += red[w][0]; s += red[w][1]; }
       // converged once the off-diagonal part is at the rounding level of the matrix
       const double lim = 4.0 * m * DBL_EPSILON;
       done = (o <= lim * lim * s) ? 1 : 0;
@@ -359,7 +424,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
       }
       __syncthreads();
       // rows p, q  (A <- J' A)
-      for (int idx = threadIdx.x; idx < np * m; idx += NTHREADS) {
+      for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
         const int pr = idx / m, col = idx % m;
         int p = perm[pr], q = perm[me - 1 - pr];
         if (p > q) { const int tmp = p; p = q; q = tmp; }
@@ -371,7 +436,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
       }
       __syncthreads();
       // columns p, q  (A <- A J, E <- E J)
-      for (int idx = threadIdx.x; idx < np * m; idx += NTHREADS) {
+      for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
         const int pr = idx / m, row = idx % m;
         int p = perm[pr], q = perm[me - 1 - pr];
         if (p > q) { const int tmp = p; p = q; q = tmp; }
@@ -394,7 +459,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
 // node factor of one level (factorization): Gram blocks -> (G_V, F1, F2), log-det
 // and the update coefficients of the coarser panels
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTHREADS) k_node_factor(
+__global__ void __launch_bounds__(64) k_node_factor(
     int l, const int* __restrict__ rank, const int* __restrict__ kmax,
     const int* __restrict__ rcount, const int* __restrict__ node_task_off, int tbase,
     const double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
@@ -408,20 +473,10 @@ __global__ void __launch_bounds__(NTHREADS) k_node_factor(
     if (threadIdx.x == 0) node_ld[h] = 0.0;
     return;
   }
-  // final Gram blocks Z_side[a][b] (a < k, b < W), summed over tasks in order
+  // final Gram blocks Z_side[a][b] = Z[a * zs_a + b] (summed by k_zsum)
   double* ZI = zfin + (size_t)j * 2 * zf_side;
   double* ZJ = ZI + zf_side;
-  for (int side = 0; side < 2; ++side) {
-    const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
-    double* Z = side ? ZJ : ZI;
-    for (int idx = threadIdx.x; idx < k * W; idx += NTHREADS) {
-      const int a = idx / W, b = idx % W;
-      double s = 0.0;
-      for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + (size_t)a * zs_a + b];
-      Z[(size_t)a * W + b] = s;
-    }
-  }
-  __syncthreads();
+  const int zW = zs_a;
   extern __shared__ double lds[];
   double* GU = lds;
   double* GV = GU + kc * kc;
@@ -429,37 +484,37 @@ __global__ void __launch_bounds__(NTHREADS) k_node_factor(
   double* Hm = E + kc * kc;
   double* X = Hm + kc * kc;
   __shared__ double lam[PMAX], g1[PMAX], g2[PMAX];
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
-    GU[a + b * kc] = 0.5 * (ZI[(size_t)a * W + b] + ZI[(size_t)b * W + a]);
-    GV[a + b * kc] = 0.5 * (ZJ[(size_t)a * W + b] + ZJ[(size_t)b * W + a]);
+    GU[a + b * kc] = 0.5 * (ZI[(size_t)a * zW + b] + ZI[(size_t)b * zW + a]);
+    GV[a + b * kc] = 0.5 * (ZJ[(size_t)a * zW + b] + ZJ[(size_t)b * zW + a]);
   }
   __syncthreads();
   bool ok = lds_sym_eig(GU, E, k, kc);
   if (threadIdx.x < k) lam[threadIdx.x] = sqrt(fmax(GU[threadIdx.x + threadIdx.x * kc], 0.0));
   __syncthreads();
   // S_U = diag(sqrt(lambda)) E'  -> X
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     X[a + b * kc] = lam[a] * E[b + a * kc];
   }
   __syncthreads();
   // E <- S_U G_V ; Hm <- E S_U'
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += X[a + c * kc] * GV[c + b * kc];
     E[a + b * kc] = acc;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += E[a + c * kc] * X[b + c * kc];
     Hm[a + b * kc] = acc;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {  // symmetrise
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {  // symmetrise
     const int a = idx % k, b = idx / k;
     if (a < b) {
       const double v = 0.5 * (Hm[a + b * kc] + Hm[b + a * kc]);
@@ -486,7 +541,7 @@ __global__ void __launch_bounds__(NTHREADS) k_node_factor(
   }
   __syncthreads();
   // B = S_U' P  -> GU
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += X[c + a * kc] * E[c + b * kc];
@@ -495,7 +550,7 @@ __global__ void __launch_bounds__(NTHREADS) k_node_factor(
   __syncthreads();
   // F1 -> Hm, F2 -> E ; store G_V, F1, F2
   double* out = nodemat + nodemat_off[h];
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double f1 = 0.0, f2 = 0.0;
     for (int c = 0; c < k; ++c) {
@@ -508,36 +563,41 @@ __global__ void __launch_bounds__(NTHREADS) k_node_factor(
     out[2 * k * k + a + b * k] = f2;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * k; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     E[a + b * kc] = out[2 * k * k + a + b * k];
   }
   __syncthreads();
   // coefficients of the coarser panels: U = T - G_V S (into ZJ), A = -S + F2 U
-  for (int idx = threadIdx.x; idx < k * Wc; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * Wc; idx += blockDim.x) {
     const int a = idx / Wc, b = kl + idx % Wc;
-    double acc = ZJ[(size_t)a * W + b];
-    for (int d = 0; d < k; ++d) acc -= GV[a + d * kc] * ZI[(size_t)d * W + b];
-    ZJ[(size_t)a * W + b] = acc;
+    double acc = ZJ[(size_t)a * zW + b];
+    for (int d = 0; d < k; ++d) acc -= GV[a + d * kc] * ZI[(size_t)d * zW + b];
+    ZJ[(size_t)a * zW + b] = acc;
   }
   __syncthreads();
   double* cf = coef + (size_t)j * cs_node;
-  for (int idx = threadIdx.x; idx < k * Wc; idx += NTHREADS) {
+  for (int idx = threadIdx.x; idx < k * Wc; idx += blockDim.x) {
     const int a = idx / Wc, bc = idx % Wc, b = kl + bc;
-    double acc = -ZI[(size_t)a * W + b];
-    for (int c = 0; c < k; ++c) acc += E[a + c * kc] * ZJ[(size_t)c * W + b];
+    double acc = -ZI[(size_t)a * zW + b];
+    for (int c = 0; c < k; ++c) acc += E[a + c * kc] * ZJ[(size_t)c * zW + b];
     cf[(size_t)a * cs_a + bc] = acc;
   }
 }
 
 // ---------------------------------------------------------------------------------
 // level update (factorization): coarser columns of right-child rows += V~ A
+// One thread per row: the row of V~ sits in registers (16 at a time), the coefficient
+// tile (k x 64 columns) is broadcast from LDS, and every coarser column is read and
+// written once, coalesced along rows.
 // ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NTHREADS) k_update_panel(
     const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ rank,
     const int* __restrict__ coff, const int* __restrict__ kmax, const int* __restrict__ rcols,
-    const int* __restrict__ rcount, int Ktot, double* __restrict__ P, int ld,
+    const int* __restrict__ rcount, int K, double* __restrict__ P, int unused_ld,
     const double* __restrict__ coef, int cs_node, int cs_a) {
+  const int Ktot = K;
+  (void)unused_ld;
   const int t = blockIdx.x;
   if (t >= ntask) return;
   const Task tk = tasks[tbase + t];
@@ -549,30 +609,28 @@ __global__ void __launch_bounds__(NTHREADS) k_update_panel(
   const int j = tk.h - ((1 << l) - 1);
   const int* yc = rcols + (size_t)l * Ktot + kl;
   const double* cf = coef + (size_t)j * cs_node;
-  __shared__ double As[PMAX][64];
-  __shared__ double Vs[PMAX][64];
-  const int i = threadIdx.x & 63, bg = threadIdx.x >> 6;
-  for (int b0 = 0; b0 < Wc; b0 += 64) {
-    const int bw = min(64, Wc - b0);
+  __shared__ double As[64][64];
+  __shared__ int ycol[64];
+  for (int bt = 0; bt < Wc; bt += 64) {
+    const int bw = min(64, Wc - bt);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < k * 64; idx += NTHREADS) {
+    const int k16 = (k + 15) & ~15;  // rows read by the 16-wide register blocks
+    for (int idx = threadIdx.x; idx < k16 * 64; idx += NTHREADS) {
       const int a = idx >> 6, b = idx & 63;
-      As[a][b] = b < bw ? cf[(size_t)a * cs_a + b0 + b] : 0.0;
+      As[a][b] = (a < k && b < bw) ? cf[(size_t)a * cs_a + bt + b] : 0.0;
     }
-    for (int r = tk.r0; r < tk.r1; r += 64) {
-      const int rw = min(64, tk.r1 - r);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < k * 64; idx += NTHREADS) {
-        const int a = idx >> 6, row = idx & 63;
-        Vs[a][row] = row < rw ? P[(size_t)(c0 + a) * ld + r + row] : 0.0;
-      }
-      __syncthreads();
-      if (i < rw) {
-        for (int b = bg; b < bw; b += 4) {
+    if (threadIdx.x < 64) ycol[threadIdx.x] = threadIdx.x < bw ? yc[bt + threadIdx.x] : 0;
+    __syncthreads();
+    for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+      for (int a0 = 0; a0 < k; a0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) v[a] = (a0 + a < k) ? P[pix(r, c0 + a0 + a, K)] : 0.0;
+        for (int b = 0; b < bw; ++b) {
           double acc = 0.0;
-          for (int a = 0; a < k; ++a) acc += Vs[a][i] * As[a][b];
-          double* y = P + (size_t)yc[b0 + b] * ld + r + i;
-          *y += acc;
+#pragma unroll
+          for (int a = 0; a < 16; ++a) acc += v[a] * As[a0 + a][b];
+          P[pix(r, ycol[b], K)] += acc;
         }
       }
     }
@@ -610,24 +668,29 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
   timer_before(KID_LEAF, s, -1, P, H.kmax, 0);
   k_leaf<<<P.nleaf, NTHREADS, 0, s>>>(
       D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
-      diag, Bc, F.leafL, F.leafLinv, F.leaf_ld, F.status, H.panel, F.panel, H.ld, D.coff, H.kmax,
+      diag, Bc, F.leafL, F.leafLinv, F.leaf_ld, F.status, H.panel, F.panel, P.Ktot, D.coff, H.kmax,
       P.L);
   timer_after(KID_LEAF, s);
-  const int kc = std::max(P.kcapmax, 1);
-  const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
-  if (lds_node > 65536)
+  const int kcm = std::max(P.kcapmax, 1);
+  const size_t lds_max = sizeof(double) * 5 * (size_t)kcm * kcm;
+  if (lds_max > 65536)
     (void)hipFuncSetAttribute((const void*)k_node_factor,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_node));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_max));
   for (int l = P.L - 1; l >= 0; --l) {
     const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
     const int Wcap = P.coff[l + 1];  // columns of levels <= l (capacity)
     const int zs_a = Wcap, zs_task = P.kcap[l] * Wcap;
     timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
-    k_reduce_panel<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
-                                           H.rcount, P.Ktot, F.panel, H.ld, F.zpart, zs_a, zs_task);
+    const dim3 grid_r(nt, (Wcap + 63) / 64);
+    k_reduce_panel<<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
+                                               H.rcount, P.Ktot, F.panel, F.zpart, zs_a, zs_task);
     timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
-    k_node_factor<<<1 << l, NTHREADS, lds_node, s>>>(
+    launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
+                zs_task, s);
+    const int kc = std::max(P.kcap[l], 1);
+    const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
+    k_node_factor<<<1 << l, 64, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
         kc);

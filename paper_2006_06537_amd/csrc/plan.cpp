@@ -152,8 +152,13 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
   }
   P.node_task_off[2 * P.nint] = int(P.ltasks.size());
   P.ltask_off[L] = int(P.ltasks.size());
+  P.max_tps.assign(std::max(L, 1), 1);
   for (int l = 0; l < L; ++l)
     P.max_ltasks = std::max(P.max_ltasks, P.ltask_off[l + 1] - P.ltask_off[l]);
+  for (int h = 0; h < P.nint; ++h)
+    for (int sd = 0; sd < 2; ++sd)
+      P.max_tps[P.nodes[h].level] = std::max(P.max_tps[P.nodes[h].level],
+                                             P.node_task_off[2 * h + sd + 1] - P.node_task_off[2 * h + sd]);
   P.nmt = int(P.mtasks.size());
   P.ngt = int(P.gtasks.size());
   P.nlt = int(P.ltasks.size());
