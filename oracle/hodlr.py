@@ -297,7 +297,7 @@ class Factor:
             if d is not None:
                 A[np.diag_indices_from(A)] += d[lo:hi]
             try:
-                self.leafL.append(sla.cholesky(A, lower=True))
+                self.leafL.append(self._leaf_chol(A))
             except np.linalg.LinAlgError as e:
                 raise NotSPD(f"leaf [{lo},{hi}) not positive definite") from e
         # whitened panels: U~ = L_D^-1 sqrt(alpha) U, V~ likewise
@@ -321,6 +321,10 @@ class Factor:
                     else:
                         Y = self.Vt[(la, ja)][lo - amid:hi - amid]
                     self._inv_node(nf, mid - lo, Y)
+
+    @staticmethod
+    def _leaf_chol(A):
+        return sla.cholesky(A, lower=True)
 
     # leaf block-diagonal helpers (rows starting at `start`)
     def _leaf_iter(self, start, m):

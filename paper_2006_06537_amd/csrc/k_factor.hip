@@ -33,59 +33,120 @@ __device__ __forceinline__ double wsum(double v) {
 //
 // One work-group of 256 threads per leaf (m <= 128 rows).  The leaf matrix lives in
 // registers in a 16 x 16 thread grid: thread (tr, tc) holds the 8 x 8 elements
-// (tr + 16 i, tc + 16 j).  Right-looking Cholesky, forward substitution and the
-// inverse (substitution on identity columns) all run as column steps: the owners of
-// column j (and of row j of the right-hand sides) publish it through a double-
-// buffered LDS vector, one barrier per step, and every thread updates its elements.
+// (16 i + tr, 16 j + tc), so diagonal block kb of a 16 x 16 blocking is element
+// [kb][kb] of every thread.  Blocked right-looking Cholesky: wave 0 factors the 16 x 16
+// diagonal block (and inverts it) with cross-lane shuffles, the block column below is
+// multiplied by that inverse, and the trailing matrix takes a rank-16 update.  Forward
+// substitution on the panels (and on identity columns, for L^-1) runs by 16-row blocks
+// the same way.  Three barriers per block step.
 // ---------------------------------------------------------------------------------
 constexpr int LG = 16;        // thread grid side
-constexpr int LE = BMAX / LG; // elements per thread per dimension (8)
+constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
 constexpr int YQ = 4;         // right-hand-side columns per thread (64 per pass)
+constexpr int LPD = 17;       // LDS pitch of 16-wide rows
 
-template <int N>
-__device__ __forceinline__ double pick(const double (&v)[N], int idx) {
-  double r = 0.0;
+// wave 0: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD); writes L into
+// Lk and L^-1 into Lik (LDS, pitch LPD, zero upper triangles); returns the sum of the
+// log pivots (all lanes) and flags a non-positive pivot.
+__device__ double diag_factor16(const double* Dk, double* Lk, double* Lik, bool& bad) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  double d[4], x[4];
 #pragma unroll
-  for (int t = 0; t < N; ++t) r = (t == idx) ? v[t] : r;
-  return r;
+  for (int v = 0; v < 4; ++v) {
+    d[v] = Dk[r * LPD + 4 * g + v];
+    x[v] = (r == 4 * g + v) ? 1.0 : 0.0;
+  }
+  double ls = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gj = j >> 2, vj = j & 3;
+    const double colv = d[vj];
+    const double piv = __shfl(colv, j + 16 * gj, 64);
+    const bool ok = piv > 0.0;
+    bad |= !ok;
+    const double inv = ok ? 1.0 / sqrt(piv) : 1.0;
+    ls += ok ? log(piv) : 0.0;
+    const double lrj = __shfl(colv, r + 16 * gj, 64) * inv;
+    double lcj[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lcj[v] = __shfl(colv, 4 * g + v + 16 * gj, 64) * inv;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (r > j && 4 * g + v > j) d[v] -= lrj * lcj[v];
+    if (g == gj) d[vj] = (r >= j) ? lrj : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int gj = j >> 2, vj = j & 3;
+    const double ljj = __shfl(d[vj], j + 16 * gj, 64);
+    const double lrj = __shfl(d[vj], r + 16 * gj, 64);
+    double xj[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xj[v] = __shfl(x[v], j + 16 * g, 64) / ljj;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (r > j) x[v] -= lrj * xj[v];
+      else if (r == j) x[v] = xj[v];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int c = 4 * g + v;
+    Lk[r * LPD + c] = (c <= r) ? d[v] : 0.0;
+    Lik[r * LPD + c] = (c <= r) ? x[v] : 0.0;
+  }
+  return ls;
 }
 
-// y (rows tr + 16 i, columns tc + 16 q of a 64-column block) <- L^-1 y, steps j0..m-1.
-__device__ __forceinline__ void leaf_trsm(const double (&a)[LE][LE], double (&y)[LE][YQ], int m,
-                                          int j0, double (*colL)[BMAX], double (*rowY)[64],
-                                          int tr, int tc) {
-  for (int j = j0; j < m; ++j) {
-    const int buf = j & 1, js = j >> 4;
-    if (tc == (j & 15)) {
+// y (rows 16 i + tr, columns tc + 16 q of a 64-column block) <- L^-1 y, blocks kb0..nb-1.
+// Likk: the 8 inverted diagonal blocks; Lp: 2 x 128 x LPD scratch; Yk, Yh: 16 x 65 each.
+__device__ __forceinline__ void leaf_trsm_blk(const double (&a)[LE][LE], double (&y)[LE][YQ],
+                                              int nb, int kb0, const double* Likk, double* Lp,
+                                              double* Yk, double* Yh, int tr, int tc) {
+  for (int kb = kb0; kb < nb; ++kb) {
+    double* L2 = Lp + (kb & 1) * (BMAX * LPD);
 #pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
-        if (r >= j && r < m) colL[buf][r] = pick(a[i], js);
+    for (int i = 0; i < LE; ++i) {
+      if (i == kb) {
+#pragma unroll
+        for (int q = 0; q < YQ; ++q) Yk[tr * 65 + tc + LG * q] = y[i][q];
       }
-    }
-    if (tr == (j & 15)) {
+      if (i > kb && i < nb) {
 #pragma unroll
-      for (int q = 0; q < YQ; ++q) {
-        double v = 0.0;
-#pragma unroll
-        for (int i = 0; i < LE; ++i) v = (i == js) ? y[i][q] : v;
-        rowY[buf][tc + LG * q] = v;
+        for (int jj = 0; jj < LE; ++jj)
+          if (jj == kb) L2[(LG * i + tr) * LPD + tc] = a[i][jj];
       }
     }
     __syncthreads();
-    const double dinv = 1.0 / colL[buf][j];
-    double yj[YQ];
+    const double* Li = Likk + kb * (16 * LPD);
+    double yh[YQ];
 #pragma unroll
-    for (int q = 0; q < YQ; ++q) yj[q] = rowY[buf][tc + LG * q] * dinv;
+    for (int q = 0; q < YQ; ++q) yh[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const double lv = Li[tr * LPD + t];
+#pragma unroll
+      for (int q = 0; q < YQ; ++q) yh[q] += lv * Yk[t * 65 + tc + LG * q];
+    }
+#pragma unroll
+    for (int i = 0; i < LE; ++i)
+      if (i == kb) {
+#pragma unroll
+        for (int q = 0; q < YQ; ++q) y[i][q] = yh[q];
+      }
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) Yh[tr * 65 + tc + LG * q] = yh[q];
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
-      const int r = tr + LG * i;
-      const double lr = (r > j && r < m) ? colL[buf][r] : 0.0;
+      if (i > kb && i < nb) {
 #pragma unroll
-      for (int q = 0; q < YQ; ++q) y[i][q] -= lr * yj[q];
-      if (r == j) {
+        for (int t = 0; t < 16; ++t) {
+          const double lr = L2[(LG * i + tr) * LPD + t];
 #pragma unroll
-        for (int q = 0; q < YQ; ++q) y[i][q] = yj[q];
+          for (int q = 0; q < YQ; ++q) y[i][q] -= lr * Yh[t * 65 + tc + LG * q];
+        }
       }
     }
   }
@@ -101,23 +162,32 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   const int b = blockIdx.x;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  const int nb = (m + 15) >> 4;  // 16-row blocks in use
   const double alpha = alpha_p ? *alpha_p : alpha_v;
   const double beta = beta_p ? *beta_p : beta_v;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  // LDS: Likk 8 blocks | Lk | Dk | Lp (2 x 128 rows) | union{ Pp 128 rows ; Yk + Yh }
   __shared__ double xs[BMAX];
-  __shared__ double colL[2][BMAX];
-  __shared__ double rowY[2][64];
+  __shared__ double Likk[LE * 16 * LPD];
+  __shared__ double Lk[16 * LPD];
+  __shared__ double Dk[16 * LPD];
+  __shared__ double Lp[2 * BMAX * LPD];
+  __shared__ double U[BMAX * LPD];  // Pp during the factorization, Yk | Yh afterwards
+  double* Pp = U;
+  double* Yk = U;
+  double* Yh = U + 16 * 65;
   __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
+  __shared__ double ldsum;
+  if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
   for (int r = threadIdx.x; r < m; r += NTHREADS) xs[r] = x[lo + r];
   __syncthreads();
   double a[LE][LE];
 #pragma unroll
   for (int i = 0; i < LE; ++i) {
-    const int r = tr + LG * i;
+    const int r = LG * i + tr;
 #pragma unroll
     for (int jj = 0; jj < LE; ++jj) {
-      const int c = tc + LG * jj;
+      const int c = LG * jj + tc;
       double v = (r == c) ? 1.0 : 0.0;
       if (r < m && c < m) {
         v = alpha * kern1(kind, ell, xs[r], xs[c]);
@@ -126,84 +196,102 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       a[i][jj] = v;
     }
   }
-  // Cholesky: column j of L = (column j of the updated matrix) / sqrt(pivot)
-  double ldsum = 0.0;
+  // blocked Cholesky
   bool mybad = false;
-  for (int j = 0; j < m; ++j) {
-    const int buf = j & 1, js = j >> 4;
-    if (tc == (j & 15)) {
+  for (int kb = 0; kb < nb; ++kb) {
 #pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
-        if (r >= j && r < m) colL[buf][r] = pick(a[i], js);
+    for (int i = 0; i < LE; ++i) {
+#pragma unroll
+      for (int jj = 0; jj < LE; ++jj) {
+        if (jj == kb) {
+          if (i == kb) Dk[tr * LPD + tc] = a[i][jj];
+          if (i > kb && i < nb) Pp[(LG * i + tr) * LPD + tc] = a[i][jj];
+        }
       }
     }
     __syncthreads();
-    const double d = colL[buf][j];
-    const bool ok = d > 0.0;
-    mybad |= !ok;
-    const double inv = ok ? 1.0 / sqrt(d) : 1.0;
-    if (threadIdx.x == 0) ldsum += ok ? log(d) : 0.0;
-    double lr[LE], lc[LE];
+    if (threadIdx.x < 64) {
+      bool wb = false;
+      const double ls = diag_factor16(Dk, Lk, Likk + kb * (16 * LPD), wb);
+      if (threadIdx.x == 0) ldsum += ls;
+      if (wb) bad = 1;
+    }
+    __syncthreads();
+    const double* Li = Likk + kb * (16 * LPD);
+    double* L1 = Lp;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
-      const int r = tr + LG * i;
-      lr[i] = (r > j && r < m) ? colL[buf][r] * inv : 0.0;
-    }
-#pragma unroll
-    for (int jj = 0; jj < LE; ++jj) {
-      const int c = tc + LG * jj;
-      lc[jj] = (c > j && c < m) ? colL[buf][c] * inv : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < LE; ++i)
-#pragma unroll
-      for (int jj = 0; jj < LE; ++jj) a[i][jj] -= lr[i] * lc[jj];
-    if (tc == (j & 15)) {
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
-        const double v = (r >= j && r < m) ? colL[buf][r] * inv : 0.0;
+      if (i == kb) {
 #pragma unroll
         for (int jj = 0; jj < LE; ++jj)
-          if (jj == js) a[i][jj] = v;
+          if (jj == kb) a[i][jj] = Lk[tr * LPD + tc];
+      }
+      if (i > kb && i < nb) {
+        // L[i][kb] = A[i][kb] L_kk^-T : row (16 i + tr) of the panel times column tc of Li'
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s += Pp[(LG * i + tr) * LPD + t] * Li[tc * LPD + t];
+#pragma unroll
+        for (int jj = 0; jj < LE; ++jj)
+          if (jj == kb) a[i][jj] = s;
+        L1[(LG * i + tr) * LPD + tc] = s;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      double lr[LE], lc[LE];
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        lr[i] = (i > kb && i < nb) ? L1[(LG * i + tr) * LPD + t] : 0.0;
+        lc[i] = (i > kb && i < nb) ? L1[(LG * i + tc) * LPD + t] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < LE; ++i) {
+        if (i > kb && i < nb) {
+#pragma unroll
+          for (int jj = 0; jj < LE; ++jj)
+            if (jj > kb && jj <= i) a[i][jj] -= lr[i] * lc[jj];
+        }
       }
     }
   }
-  if (mybad) atomicOr(&bad, 1);
-  if (threadIdx.x == 0) leaf_ld[b] = ldsum;  // sum log(pivot) = 2 sum log diag(L)
   __syncthreads();
-  if (threadIdx.x == 0 && bad) atomicOr(status, ST_NOTSPD);
-  // L to global (lower triangle, column-major, ld = Bc)
+  if (threadIdx.x == 0) {
+    leaf_ld[b] = ldsum;  // sum log(pivot) = 2 sum log diag(L)
+    if (bad) atomicOr(status, ST_NOTSPD);
+  }
+  (void)mybad;
+  // L to global (lower triangle, column-major, ld = Bc); rows/cols beyond m untouched
   double* Lg = leafL + (size_t)b * Bc * Bc;
 #pragma unroll
   for (int jj = 0; jj < LE; ++jj) {
-    const int c = tc + LG * jj;
+    const int c = LG * jj + tc;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
-      const int r = tr + LG * i;
+      const int r = LG * i + tr;
       if (r < m && c < m) Lg[r + (size_t)c * Bc] = (c <= r) ? a[i][jj] : 0.0;
     }
   }
-  // L^-1 by substitution on identity columns, 64 columns per pass
+  // L^-1 by blocked substitution on identity columns, 64 columns per pass
   double* Lig = leafLinv + (size_t)b * Bc * Bc;
   for (int c0 = 0; c0 < m; c0 += 64) {
     double y[LE][YQ];
 #pragma unroll
     for (int i = 0; i < LE; ++i)
 #pragma unroll
-      for (int q = 0; q < YQ; ++q) y[i][q] = (tr + LG * i == c0 + tc + LG * q) ? 1.0 : 0.0;
-    leaf_trsm(a, y, m, c0, colL, rowY, tr, tc);
+      for (int q = 0; q < YQ; ++q) y[i][q] = (LG * i + tr == c0 + tc + LG * q) ? 1.0 : 0.0;
+    __syncthreads();
+    leaf_trsm_blk(a, y, nb, c0 >> 4, Likk, Lp, Yk, Yh, tr, tc);
 #pragma unroll
     for (int q = 0; q < YQ; ++q) {
       const int c = c0 + tc + LG * q;
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
+        const int r = LG * i + tr;
         if (r < m && c < m) Lig[r + (size_t)c * Bc] = (c <= r) ? y[i][q] : 0.0;
       }
     }
-    __syncthreads();
   }
   // whitening of all panel rows of this leaf: dst = sqrt(alpha) L^-1 src.  The active
   // columns of all levels are numbered 0..total-1 and handled 64 per pass.
@@ -229,18 +317,18 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     for (int q = 0; q < YQ; ++q) {
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
+        const int r = LG * i + tr;
         y[i][q] = (gcq[q] >= 0 && r < m) ? src[pix(lo + r, gcq[q], K)] : 0.0;
       }
     }
     __syncthreads();
-    leaf_trsm(a, y, m, 0, colL, rowY, tr, tc);
+    leaf_trsm_blk(a, y, nb, 0, Likk, Lp, Yk, Yh, tr, tc);
 #pragma unroll
     for (int q = 0; q < YQ; ++q) {
       if (gcq[q] < 0) continue;
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
-        const int r = tr + LG * i;
+        const int r = LG * i + tr;
         if (r < m) dst[pix(lo + r, gcq[q], K)] = sa * y[i][q];
       }
     }

@@ -10,8 +10,9 @@ Tolerances
     evaluations of the same canonical W differ by more than 1e-9 because its node
     factors sit at 1 - sigma^2 ~ 1e-7.  The bound used is the oracle's own
     reproducibility band -- the distance between the oracle and the same oracle with
-    its leaf triangular solves replaced by explicit inverses -- times 4, and never
-    below 1e-9.
+    its leaf Cholesky computed column by column and its leaf triangular solves replaced by
+    explicit inverses -- times 4, and never below 1e-9; for the operators W, W', W^-1,
+    W^-T and the solve also never below the Cholesky forward-error bound 2 u kappa(leaf).
 """
 import numpy as np
 import pytest
@@ -37,8 +38,21 @@ def rel(a, b):
 
 
 class InvLeafFactor(oh.Factor):
-    """The oracle factor with explicit leaf inverses: an equally valid FP64 evaluation
-    of the same W, used only to measure the oracle's reproducibility band."""
+    """The oracle factor with an unblocked column-by-column leaf Cholesky and explicit
+    leaf inverses: an equally valid FP64 evaluation of the same W, used only to measure
+    the oracle's reproducibility band."""
+
+    @staticmethod
+    def _leaf_chol(A):
+        A = np.array(A, dtype=np.float64, copy=True)
+        m = A.shape[0]
+        for j in range(m):
+            if not A[j, j] > 0.0:
+                raise np.linalg.LinAlgError("not positive definite")
+            A[j, j] = np.sqrt(A[j, j])
+            A[j + 1:, j] /= A[j, j]
+            A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j + 1:, j])
+        return np.tril(A)
 
     def _leaf_solve(self, start, Y, trans=False):
         Y = np.array(Y, dtype=np.float64, copy=True)
@@ -128,15 +142,24 @@ def test_factor_logdet_apply_solve(case, alpha, beta):
     vt = torch.tensor(v, device=case["dev"])
     ld = float(F.logdet().cpu()[0])
     band = {}
-    if beta == 0.0 and H.tree.L > 0:
+    if beta == 0.0:
         OV = InvLeafFactor(H, alpha, beta)
         band["logdet"] = abs(OV.logdet() - OF.logdet()) / abs(OF.logdet())
         for nm, fn in [("W", "apply_W"), ("WT", "apply_WT"), ("Winv", "apply_Winv"),
                        ("WinvT", "apply_WinvT"), ("solve", "solve")]:
             band[nm] = rel(getattr(OV, fn)(v.T), getattr(OF, fn)(v.T))
 
+    # forward-error bound of a Cholesky factor: ~ u kappa(leaf) (relative), whatever the
+    # summation order; leaves of alpha K~_1 + beta I with a 1e-6 nugget reach kappa ~ 1e7
+    kap = max(np.linalg.cond(alpha * H.leaf_block(lo, hi) + beta * np.eye(hi - lo))
+              for lo, hi in H.tree.leaves())
+    u = 2.0 ** -53
+
     def tol(nm):
-        return max(1e-9, 4.0 * band.get(nm, 0.0))
+        t = max(1e-9, 4.0 * band.get(nm, 0.0))
+        if nm != "logdet":
+            t = max(t, 2.0 * u * kap)
+        return t
 
     assert abs(ld - OF.logdet()) <= tol("logdet") * abs(OF.logdet()) + 1e-12
     for nm, t, i, fn in [("W", 0, 0, "apply_W"), ("WT", 1, 0, "apply_WT"),
