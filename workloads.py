@@ -51,3 +51,26 @@ SMALL_1D = dict(n=1000, leaf=64, tol=1e-12, ell0=0.1, tau0=100.0, sigf2_0=1.0,
                 nugget=1e-6, iters=50, seed=0)
 LARGE_1D = dict(n=1 << 20, leaf=128, tol=1e-10, ell0=0.02, tau0=400.0, sigf2_0=1.0,
                 nugget=1e-6, iters=200, seed=1)
+
+
+def tensor_surface(d: int = 4, n: int = 65536, seed: int = 3, noise: float = 0.1,
+                   positive: bool = False):
+    """Tensor-product surface (Section 4.2 model, shaped like the d = 2 simulation of
+    Section 5.3 with its separable function sin(u) sqrt(u) per coordinate, u = 4 x on
+    [0, 4]): x[h, i] ~ U[0,1] in observation order (not sorted),
+    y_i = prod_h s(x[h, i]) + N(0, noise^2) with s(x) = sin(4x) sqrt(4x), or
+    s(x) = 1.5 + sin(2 pi x) when ``positive`` (a surface without zero crossings)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, (d, n))
+    if positive:
+        s = 1.5 + np.sin(2.0 * math.pi * x)
+    else:
+        s = np.sin(4.0 * x) * np.sqrt(4.0 * x)
+    y = np.prod(s, axis=0) + rng.normal(0.0, noise, n)
+    return x, y
+
+
+# Tensor-product workload: d = 4 factors, n = 65,536 observations.  Start values:
+# every f_h = 1, beta = 1, tau = tau0; grid centre ell0[h] per factor.
+TENSOR_4D = dict(d=4, n=65536, leaf=128, tol=1e-10, ell0=(0.05, 0.1333, 0.2167, 0.3),
+                 tau0=100.0, beta0=1.0, nugget=1e-6, iters=200, seed=3)
