@@ -50,6 +50,7 @@ typedef void* fg_stream;                 /* hipStream_t */
 typedef struct fg_hodlr_s* fg_hodlr;     /* compressed K~_1, device resident */
 typedef struct fg_factor_s* fg_factor;   /* W with W W' = alpha K~_1 + beta I + diag(d) */
 typedef struct fg_chain_s* fg_chain;     /* one Gibbs chain and its cached factors */
+typedef struct fg_tp_chain_s* fg_tp_chain; /* one tensor-product chain (Section 4.2) */
 
 #define FG_KERNEL_SE 0
 #define FG_KERNEL_EXP 1
@@ -148,6 +149,24 @@ fg_status gp_draw_f(fg_hodlr K1, fg_factor W1, fg_factor WM, double sigf2, doubl
                     double* f, double* r, double* mu, fg_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gp_draw_f_hetero -- Algorithm 1.h (Appendix, heteroskedastic noise) for a
+ * unit-variance prior K~ = K~_1 and diagonal noise precisions D:
+ *   a ~ N(0, D) (a = sqrt(D) a_std), b ~ N(0, I);  Z = K~ a + W b;
+ *   Z* = P~^-1 Z;  Z** = D^-1 Z*;  R = K~ P~^-1 y;  f = R + Z**.
+ *   K   compressed K~_1;  WK  factor of K~_1 (alpha 1, beta 0);
+ *   WP  factor of K~_1 + diag(1/D) (hodlr_factor with alpha 1, beta 0, diag 1/D).
+ *   D, y  device n-vectors (D > 0);  f, R  device n-vectors (R may be NULL):
+ *   R = K~ P~^-1 y is the approximate posterior mean of the Appendix lemma.
+ *   factor  -1: a_std, b on tags 1 and 2 of (seed, iteration, stream_id);
+ *           h >= 0: tags 1 + 16 (h+1) and 2 + 16 (h+1) (factor h of a tensor chain).
+ * Errors: FG_EINVAL (NULL, size mismatch, factor < -1).
+ * ------------------------------------------------------------------------- */
+fg_status gp_draw_f_hetero(fg_hodlr K, fg_factor WK, fg_factor WP, const double* D,
+                           const double* y, uint64_t seed, uint64_t iteration,
+                           uint64_t stream_id, int32_t factor, double* f, double* R,
+                           fg_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Gibbs chain (Section 4.1): sweep f -> tau -> sigma_f^-2 -> length-scale.
  *   tau     | - ~ Ga((a1+n)/2, (b1 + |y-f|^2)/2)            (shape, rate)
  *   sf^-2   | - ~ Ga((a2+n)/2, (b2 + f' K~_1^-1 f)/2)
@@ -202,6 +221,64 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
                             double* r_out, double* mu_out, fg_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Tensor-product surface chain (Section 4.2): y_i = beta prod_h f_h(x[h,i]) + e_i,
+ * e_i ~ N(0, 1/tau), f_h unit-variance GPs (kernel `kind`, length-scale on a grid
+ * per factor).  One sweep, in order:
+ *   f_h | -  for h = 0..d-1 by Algorithm 1.h on dimension h's sorted inputs, with
+ *            g_i = beta prod_{k != h} f_k(x[k,i]), D = tau g^2, observations y/g
+ *            (|g| floored at 1e-150, sign kept, zero taken as positive);
+ *   beta | - ~ N(tau G'y / p, 1/p), p = tau G'G + 1/s_beta^2, G_i = prod_h f_h;
+ *   tau  | - ~ Ga((a1+n)/2, (b1 + |y - beta G|^2)/2);
+ *   ell_h | - for h = 0..d-1: grid Metropolis step as in the 1-D chain with the
+ *            unit-variance prior, D = -1/2 (log|K~_h'| - log|K~_h|) - (q' - q)/2.
+ * Start: f_h = 1, beta = beta0, tau = tau0, every grid index at grid_center.
+ * Random numbers: factor h uses the 1-D tags plus 16 (h+1) (a, b, proposal,
+ * acceptance); tau uses tag 3; beta the normal of tag 7.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t kind;          /* FG_KERNEL_SE / FG_KERNEL_EXP */
+  int32_t d;             /* number of factors, 1..8 */
+  double ell0[8];        /* grid centre length-scale per factor */
+  double nugget;         /* added to every K_h's diagonal */
+  int32_t leaf;          /* maximum leaf size */
+  double tol;            /* max-norm tolerance on each K_h */
+  double tau0, beta0;    /* start values */
+  double a1, b1;         /* tau ~ Ga(a1/2, b1/2) */
+  double s_beta;         /* beta ~ N(0, s_beta^2) */
+  int32_t grid_size;     /* length-scales per factor */
+  int32_t grid_center;   /* starting index */
+  uint64_t seed;
+  uint64_t stream_id;
+} fg_tp_cfg;
+
+typedef struct {
+  int64_t iteration;
+  double tau, beta;
+  double sse;                /* |y - beta G|^2 of the last tau step */
+  double beta_mean, beta_sd; /* moments of the last beta draw */
+  int32_t k[8];              /* grid index per factor */
+  int32_t last_proposal[8];
+  int32_t last_accept[8];
+  int32_t accepts[8];
+  double ell[8];
+  double logdet[8];          /* log|K~_h| at the current length-scales */
+  double q[8];               /* f_h' K~_h^-1 f_h at the current length-scales */
+  double mh_log_ratio[8];
+  int32_t status;
+} fg_tp_snapshot;
+
+/* x: device d x n (row h = dimension h, observation order, any order of values);
+ * y: device n.  Both copied; each dimension is sorted on the host (stable).
+ * Synchronises the stream.  Errors: FG_EINVAL, FG_ETOL, FG_ENOMEM, FG_EDEVICE. */
+fg_status tp_chain_create(const fg_tp_cfg* cfg, const double* x, const double* y, int64_t n,
+                          fg_stream stream, fg_tp_chain* out);
+/* Runs `iters` sweeps; synchronises once per sweep. */
+fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream);
+/* Host snapshot; F_out (device d x n, observation order, or NULL) receives f_h(x[h,i]). */
+fg_status tp_chain_state(fg_tp_chain c, fg_tp_snapshot* host_out, double* F_out,
+                         fg_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Live kernel timing (diagnostics).  fg_timer_start(id) makes the library record
  * HIP events, on the launch stream, around every following launch of kernel `id`
  * (FG_KID_LEAF: leaf Cholesky + whitening of the panels; FG_KID_REDUCE: level Gram
@@ -224,6 +301,7 @@ const char* fg_last_error(void);
 void hodlr_destroy(fg_hodlr A);
 void factor_destroy(fg_factor F);
 void gibbs_chain_destroy(fg_chain c);
+void tp_chain_destroy(fg_tp_chain c);
 
 #ifdef __cplusplus
 }

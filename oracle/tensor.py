@@ -134,13 +134,14 @@ class TensorChain:
         self.tau = g / (0.5 * (self.b1 + rec["sse"]))
         # ell_h | -  (grid Metropolis per dimension)
         rec["q"], rec["proposal"], rec["accept"], rec["mh_log_ratio"] = [], [], [], []
+        rec["logdet_prop"], rec["q_prop"] = [], []
         for h in range(self.d):
             fs = self.F[h][self.perm[h]]
             u = self.W[h].apply_Winv(fs)
             q = float(u @ u)
             up = rng.uniform(sd, factor_tag(rng.TAG_PROP, h), t, s)
             kp = self.k[h] + (1 if up < 0.5 else -1)
-            acc, D = False, 0.0
+            acc, D, ldp, qp = False, 0.0, 0.0, 0.0
             if 0 <= kp < len(self.grids[h]):
                 Hp = self._build(h, kp)
                 Wp = hodlr.Factor(Hp, 1.0, 0.0)
@@ -156,6 +157,8 @@ class TensorChain:
             rec["proposal"].append(kp)
             rec["accept"].append(acc)
             rec["mh_log_ratio"].append(D)
+            rec["logdet_prop"].append(ldp)
+            rec["q_prop"].append(qp)
         rec["tau"], rec["beta"], rec["k"] = self.tau, self.beta, list(self.k)
         rec["logdet"] = list(self.logdet)
         self.it += 1

@@ -10,10 +10,11 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, check,
-                   lib)
+from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, TpCfg,
+                   TpSnapshot, check, lib)
 
-__all__ = ["Hodlr", "Factor", "Chain", "KernelTimer", "normals", "draw_f", "KERNEL_SE",
+__all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
+           "draw_f_hetero", "KERNEL_SE",
            "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE"]
 
 KID_LEAF, KID_REDUCE, KID_UPDATE = 1, 2, 3
@@ -188,6 +189,62 @@ def draw_f(K1: Hodlr, W1: Factor, WM: Factor, sigf2, tau, y, seed, iteration, st
     check(lib().gp_draw_f(K1.handle, W1.handle, WM.handle, sigf2, tau, _dev(y), seed, iteration,
                           stream_id, _dev(f), _dev(r), _dev(mu), _stream()))
     return f, r, mu
+
+
+def draw_f_hetero(K: Hodlr, WK: Factor, WP: Factor, D, y, seed, iteration, stream_id, factor=-1):
+    """Algorithm 1.h: returns (f, R); WP must factor K~_1 + diag(1/D)."""
+    torch = _torch()
+    f = torch.empty_like(y)
+    R = torch.empty_like(y)
+    check(lib().gp_draw_f_hetero(K.handle, WK.handle, WP.handle, _dev(D), _dev(y), seed,
+                                 iteration, stream_id, factor, _dev(f), _dev(R), _stream()))
+    return f, R
+
+
+class TensorChain:
+    """Tensor-product surface chain (tp_chain_create / tp_step / tp_chain_state).
+    x: (d, n) float64 device tensor in observation order; y: n."""
+
+    def __init__(self, x, y, ell0, tau0=100.0, beta0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
+                 seed=0, stream_id=0, kind=KERNEL_SE, a1=1.0, b1=1.0, s_beta=10.0,
+                 grid_size=100, grid_center=50):
+        torch = _torch()
+        self.d, self.n = int(x.shape[0]), int(x.shape[1])
+        if len(ell0) != self.d:
+            raise ValueError("one ell0 per factor")
+        x = x.contiguous()
+        e = (C.c_double * 8)(*([float(v) for v in ell0] + [0.0] * (8 - self.d)))
+        cfg = TpCfg(kind, self.d, e, nugget, leaf, tol, tau0, beta0, a1, b1, s_beta, grid_size,
+                    grid_center, seed, stream_id)
+        c = C.c_void_p()
+        check(lib().tp_chain_create(C.byref(cfg), _dev(x.reshape(-1)), _dev(y, self.n), self.n,
+                                    _stream(), C.byref(c)))
+        self._c = c
+        self._torch = torch
+
+    def step(self, iters=1):
+        check(lib().tp_step(self._c, iters, _stream()))
+
+    def state(self, with_factors=False):
+        snap = TpSnapshot()
+        F = None
+        if with_factors:
+            F = self._torch.empty((self.d, self.n), dtype=self._torch.float64, device="cuda")
+        check(lib().tp_chain_state(self._c, C.byref(snap), _dev(F.reshape(-1)) if F is not None
+                                   else None, _stream()))
+        out = snap.as_dict(self.d)
+        if F is not None:
+            out["F"] = F
+        return out
+
+    def __del__(self):
+        c = getattr(self, "_c", None)
+        try:
+            if c is not None and c.value and _lib._lib is not None:
+                _lib._lib.tp_chain_destroy(c)
+        except Exception:  # interpreter shutdown
+            pass
+        self._c = None
 
 
 class Chain:

@@ -20,9 +20,10 @@ STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", 
 # names declared in include/fifa_gp.h, in declaration order
 EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", "hodlr_entries",
            "hodlr_matvec", "hodlr_factor", "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
-           "fg_normals", "gp_draw_f", "gibbs_chain_create", "gibbs_step", "gibbs_chain_state",
-           "fg_timer_start", "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy", "factor_destroy",
-           "gibbs_chain_destroy"]
+           "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
+           "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state", "fg_timer_start",
+           "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
+           "factor_destroy", "gibbs_chain_destroy", "tp_chain_destroy"]
 
 
 class FgError(RuntimeError):
@@ -55,6 +56,30 @@ class ChainSnapshot(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TpCfg(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("ell0", C.c_double * 8),
+                ("nugget", C.c_double), ("leaf", C.c_int32), ("tol", C.c_double),
+                ("tau0", C.c_double), ("beta0", C.c_double), ("a1", C.c_double),
+                ("b1", C.c_double), ("s_beta", C.c_double), ("grid_size", C.c_int32),
+                ("grid_center", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64)]
+
+
+class TpSnapshot(C.Structure):
+    _fields_ = [("iteration", C.c_int64), ("tau", C.c_double), ("beta", C.c_double),
+                ("sse", C.c_double), ("beta_mean", C.c_double), ("beta_sd", C.c_double),
+                ("k", C.c_int32 * 8), ("last_proposal", C.c_int32 * 8),
+                ("last_accept", C.c_int32 * 8), ("accepts", C.c_int32 * 8),
+                ("ell", C.c_double * 8), ("logdet", C.c_double * 8), ("q", C.c_double * 8),
+                ("mh_log_ratio", C.c_double * 8), ("status", C.c_int32)]
+
+    def as_dict(self, d):
+        out = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            out[f] = list(v)[:d] if hasattr(v, "__len__") else v
+        return out
+
+
 _lib = None
 
 P = C.c_void_p
@@ -84,6 +109,11 @@ def lib():
         "hodlr_apply_w": ([P, I32, I32, DP, DP, I32, I64, P], I32),
         "fg_normals": ([U64, U64, U64, U64, I64, DP, P], I32),
         "gp_draw_f": ([P, P, P, D, D, DP, U64, U64, U64, DP, DP, DP, P], I32),
+        "gp_draw_f_hetero": ([P, P, P, DP, DP, U64, U64, U64, I32, DP, DP, P], I32),
+        "tp_chain_create": ([C.POINTER(TpCfg), DP, DP, I64, P, C.POINTER(P)], I32),
+        "tp_step": ([P, I32, P], I32),
+        "tp_chain_state": ([P, C.POINTER(TpSnapshot), DP, P], I32),
+        "tp_chain_destroy": ([P], None),
         "gibbs_chain_create": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
         "gibbs_step": ([P, I32, P], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),

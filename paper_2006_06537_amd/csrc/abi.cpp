@@ -5,6 +5,7 @@
 
 #include "fg_internal.h"
 #include "fg_rng.h"
+#include "fg_tensor.h"
 
 namespace fg {
 static thread_local std::string g_err;
@@ -248,6 +249,36 @@ fg_status gp_draw_f(fg_hodlr K1, fg_factor W1, fg_factor WM, double sigf2, doubl
   if (hipMemcpyAsync(r, z + n, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(FG_EDEVICE, "copy failed");
   return check_launch("gp_draw_f");
+}
+
+fg_status gp_draw_f_hetero(fg_hodlr K, fg_factor WK, fg_factor WP, const double* D,
+                           const double* y, uint64_t seed, uint64_t iteration,
+                           uint64_t stream_id, int32_t factor, double* f, double* R,
+                           fg_stream stream) {
+  if (!K || !WK || !WP || !D || !y || !f) return fail(FG_EINVAL, "NULL argument");
+  if (factor < -1 || factor >= fg::TP_DMAX) return fail(FG_EINVAL, "factor out of range");
+  const int n = K->pk->P.n;
+  if (WK->n != n || WP->n != n) return fail(FG_EINVAL, "size mismatch");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t ta = factor < 0 ? 1 : fg::tp_factor_tag(1, factor);
+  const uint64_t tb = factor < 0 ? 2 : fg::tp_factor_tag(2, factor);
+  double* a = WP->vecs;
+  double* b = a + n;
+  double* z = b + n;  // columns z and z + n form the 2-RHS block [Z, y]
+  fg::launch_normals(seed, ta, iteration, stream_id, n, a, s);
+  fg::launch_scale_sqrt(n, D, a, s);
+  fg::launch_normals(seed, tb, iteration, stream_id, n, b, s);
+  fg::launch_matvec(K->d, 1.0, 0.0, nullptr, nullptr, a, z, 1, n, K->d.work, s);
+  fg::launch_apply_w(WK->d, 0, b, 1, n, WK->d.work, s);
+  fg::launch_axpby(n, z, b, z, nullptr, 1.0, nullptr, 1.0, s);
+  if (hipMemcpyAsync(z + n, y, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(FG_EDEVICE, "copy failed");
+  fg::launch_apply_w(WP->d, 2, z, 2, n, WP->d.work, s);
+  fg::launch_apply_w(WP->d, 3, z, 2, n, WP->d.work, s);
+  double* r = R ? R : a;
+  fg::launch_matvec(K->d, 1.0, 0.0, nullptr, nullptr, z + n, r, 1, n, K->d.work, s);
+  fg::launch_hetero_finish(n, r, z, D, f, nullptr, nullptr, s);
+  return check_launch("gp_draw_f_hetero");
 }
 
 fg_status hodlr_status(fg_hodlr A, fg_stream stream) {

@@ -1,0 +1,300 @@
+// Tensor-product surface chain on the device (Section 4.2): y_i = beta prod_h f_h(x[h,i])
+// + e_i with unit-variance GP factors.  One sweep draws f_1..f_d in turn by Algorithm
+// 1.h (Appendix), then beta, then tau, then each factor's length-scale by the grid
+// Metropolis step.  Per factor the chain keeps two slots of (K~_h, W_h) -- current
+// length-scale and proposal -- and one shared factor of P~ = K~_h + D^-1 (the factors
+// are drawn one after the other, so one buffer serves all of them).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fg_internal.h"
+#include "fg_rng.h"
+#include "fg_tensor.h"
+
+struct fg_tp_chain_s {
+  fg_tp_cfg cfg{};
+  int n = 0, d = 0;
+  std::vector<std::vector<double>> grid;           // per factor
+  std::vector<std::vector<fg::PlanPack*>> packs;   // per factor, per grid point
+  fg::Caps caps;
+  fg::HodlrData H[fg::TP_DMAX][2];
+  fg::FactorData W[fg::TP_DMAX][2];
+  fg::FactorData WP;
+  int cur[fg::TP_DMAX] = {};
+  int k[fg::TP_DMAX] = {};
+  int64_t iter = 0;
+  int* perm = nullptr;     // d x n: sorted position -> observation index
+  double* F = nullptr;     // d x n, observation order
+  double* fs = nullptr;    // d x n, sorted order of each dimension
+  double* y = nullptr;     // n
+  double* vecs = nullptr;  // 8 n: D, Dinv, y~, G, and four work vectors
+  double* dotwork = nullptr;
+  fg::TpState* st = nullptr;
+  fg::TpState* st_host = nullptr;
+};
+
+using fg::set_error;
+
+static fg_status tfail(fg_status st, const std::string& m) {
+  set_error(m);
+  return st;
+}
+
+static void tp_free(fg_tp_chain c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  for (int h = 0; h < fg::TP_DMAX; ++h)
+    for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[h][i]); fg::factor_free(c->W[h][i]); }
+  fg::factor_free(c->WP);
+  for (auto& v : c->packs)
+    for (auto* p : v) fg::plan_pack_destroy(p);
+  void* bufs[] = {c->perm, c->F, c->fs, c->y, c->vecs, c->dotwork, c->st};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+}
+
+extern "C" {
+
+fg_status tp_chain_create(const fg_tp_cfg* cfg, const double* x, const double* y, int64_t n,
+                          fg_stream stream, fg_tp_chain* out) {
+  if (!out) return tfail(FG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !x || !y) return tfail(FG_EINVAL, "NULL argument");
+  if (cfg->d < 1 || cfg->d > fg::TP_DMAX) return tfail(FG_EINVAL, "d must be in 1..8");
+  if (n < 1 || n >= (int64_t(1) << 31) / fg::TP_DMAX) return tfail(FG_EINVAL, "n out of range");
+  if (cfg->grid_size < 1 || cfg->grid_center < 0 || cfg->grid_center >= cfg->grid_size)
+    return tfail(FG_EINVAL, "bad grid");
+  if (!(cfg->tau0 > 0) || !std::isfinite(cfg->beta0) || !(cfg->s_beta > 0))
+    return tfail(FG_EINVAL, "tau0 and s_beta must be > 0, beta0 finite");
+  for (int h = 0; h < cfg->d; ++h)
+    if (!(cfg->ell0[h] > 0)) return tfail(FG_EINVAL, "ell0 must be > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int d = cfg->d, nn = int(n);
+  std::vector<double> xh((size_t)d * nn);
+  if (hipMemcpyAsync(xh.data(), x, xh.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return tfail(FG_EDEVICE, "copy of x to the host failed");
+  for (double v : xh)
+    if (!std::isfinite(v)) return tfail(FG_EINVAL, "x must be finite");
+  fg_tp_chain c = new fg_tp_chain_s();
+  c->cfg = *cfg;
+  c->n = nn;
+  c->d = d;
+  // per-dimension ascending order (stable, so ties keep observation order)
+  std::vector<int> permh((size_t)d * nn);
+  std::vector<double> xs((size_t)d * nn);
+  for (int h = 0; h < d; ++h) {
+    int* p = permh.data() + (size_t)h * nn;
+    const double* xr = xh.data() + (size_t)h * nn;
+    std::iota(p, p + nn, 0);
+    std::stable_sort(p, p + nn, [xr](int a, int b) { return xr[a] < xr[b]; });
+    for (int j = 0; j < nn; ++j) xs[(size_t)h * nn + j] = xr[p[j]];
+  }
+  fg_status st;
+  std::string err;
+  c->grid.resize(d);
+  c->packs.resize(d);
+  for (int h = 0; h < d; ++h) {
+    c->grid[h].resize(cfg->grid_size);
+    for (int g = 0; g < cfg->grid_size; ++g) {
+      c->grid[h][g] = cfg->ell0[h] * std::pow(10.0, (g - cfg->grid_center) / 50.0);
+      fg::PlanPack* pk = fg::plan_pack_create(xs.data() + (size_t)h * nn, nn, cfg->kind,
+                                              c->grid[h][g], cfg->nugget, cfg->leaf, cfg->tol, s,
+                                              st, err);
+      if (!pk) { tp_free(c); return tfail(st, err); }
+      c->packs[h].push_back(pk);
+      c->caps.add(*pk);
+    }
+  }
+  for (int h = 0; h < d; ++h)
+    for (int i = 0; i < 2; ++i)
+      if ((st = fg::hodlr_alloc(c->H[h][i], c->caps, err)) != FG_OK ||
+          (st = fg::factor_alloc(c->W[h][i], c->caps, err)) != FG_OK) {
+        tp_free(c);
+        return tfail(st, err);
+      }
+  if ((st = fg::factor_alloc(c->WP, c->caps, err)) != FG_OK) { tp_free(c); return tfail(st, err); }
+  const size_t nb = sizeof(double) * (size_t)nn;
+  if (hipMalloc(reinterpret_cast<void**>(&c->perm), sizeof(int) * (size_t)d * nn) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->F), nb * d) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->fs), nb * d) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->vecs), nb * 8) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 2048) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(fg::TpState)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::TpState)) != hipSuccess) {
+    tp_free(c);
+    return tfail(FG_ENOMEM, "tensor chain allocation failed");
+  }
+  hipMemcpyAsync(c->perm, permh.data(), sizeof(int) * permh.size(), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->y, y, nb, hipMemcpyDeviceToDevice, s);
+  std::vector<double> ones((size_t)d * nn, 1.0);
+  hipMemcpyAsync(c->F, ones.data(), nb * d, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(c->fs, ones.data(), nb * d, hipMemcpyHostToDevice, s);
+  for (int h = 0; h < d; ++h)
+    for (int i = 0; i < 2; ++i)
+      hipMemcpyAsync(c->H[h][i].x, xs.data() + (size_t)h * nn, nb, hipMemcpyHostToDevice, s);
+  fg::TpState init{};
+  init.tau = cfg->tau0;
+  init.beta = cfg->beta0;
+  for (int h = 0; h < d; ++h) init.k[h] = cfg->grid_center;
+  *c->st_host = init;
+  hipMemcpyAsync(c->st, c->st_host, sizeof(fg::TpState), hipMemcpyHostToDevice, s);
+  for (int h = 0; h < d; ++h) {
+    c->k[h] = cfg->grid_center;
+    c->cur[h] = 0;
+    c->H[h][0].pk = c->packs[h][c->k[h]];
+    fg::launch_build(c->H[h][0], s);
+    c->W[h][0].H = &c->H[h][0];
+    c->W[h][0].alpha = 1.0;
+    c->W[h][0].beta = 0.0;
+    fg::launch_factor(c->W[h][0], nullptr, nullptr, nullptr, s);
+    hipMemcpyAsync(&c->st->logdet[h], c->W[h][0].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
+    tp_free(c);
+    return tfail(FG_EDEVICE, "tensor chain set-up failed on the device");
+  }
+  *out = c;
+  return FG_OK;
+}
+
+fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream) {
+  if (!c || iters < 0) return tfail(FG_EINVAL, "bad arguments");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = c->n, d = c->d;
+  const fg_tp_cfg& cf = c->cfg;
+  double* D = c->vecs;
+  double* Dinv = D + n;
+  double* yt = Dinv + n;
+  double* G = yt + n;
+  double* v0 = G + n;
+  double* v1 = v0 + n;
+  double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, y~]
+  double* v3 = v2 + n;
+  for (int it = 0; it < iters; ++it) {
+    const uint64_t t = (uint64_t)c->iter;
+    // f_h | -  for h = 1..d in turn (Algorithm 1.h)
+    for (int h = 0; h < d; ++h) {
+      fg::HodlrData& H = c->H[h][c->cur[h]];
+      fg::FactorData& Wh = c->W[h][c->cur[h]];
+      const int* ph = c->perm + (size_t)h * n;
+      fg::launch_tp_prepare(n, d, h, ph, c->F, c->y, c->st, D, Dinv, yt, s);
+      c->WP.H = &H;
+      c->WP.alpha = 1.0;
+      c->WP.beta = 0.0;
+      fg::launch_factor(c->WP, nullptr, nullptr, Dinv, s);
+      fg::launch_normals(cf.seed, fg::tp_factor_tag(1, h), t, cf.stream_id, n, v0, s);
+      fg::launch_scale_sqrt(n, D, v0, s);
+      fg::launch_normals(cf.seed, fg::tp_factor_tag(2, h), t, cf.stream_id, n, v1, s);
+      fg::launch_matvec(H, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H.work, s);
+      fg::launch_apply_w(Wh, 0, v1, 1, n, Wh.work, s);
+      fg::launch_axpby(n, v2, v1, v2, nullptr, 1.0, nullptr, 1.0, s);
+      hipMemcpyAsync(v3, yt, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      fg::launch_apply_w(c->WP, 2, v2, 2, n, c->WP.work, s);
+      fg::launch_apply_w(c->WP, 3, v2, 2, n, c->WP.work, s);
+      fg::launch_matvec(H, 1.0, 0.0, nullptr, nullptr, v3, v0, 1, n, H.work, s);
+      fg::launch_hetero_finish(n, v0, v2, D, c->fs + (size_t)h * n, ph, c->F + (size_t)h * n, s);
+    }
+    // beta | -
+    fg::launch_tp_product(n, d, c->F, G, s);
+    fg::launch_dot(G, G, n, 0, &c->st->GG, c->dotwork, s);
+    fg::launch_dot(G, c->y, n, 0, &c->st->Gy, c->dotwork + 1024, s);
+    fg::launch_tp_beta_step(c->st, cf.s_beta, cf.seed, t, cf.stream_id, s);
+    // tau | -
+    fg::launch_axpby(n, G, nullptr, v0, &c->st->beta, 0.0, nullptr, 0.0, s);
+    fg::launch_dot(c->y, v0, n, 1, &c->st->sse, c->dotwork, s);
+    fg::launch_tp_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, t, cf.stream_id, s);
+    // ell_h | -  (grid Metropolis per factor; proposals are known on the host)
+    int kp[fg::TP_DMAX], ong[fg::TP_DMAX];
+    for (int h = 0; h < d; ++h) {
+      const int cur = c->cur[h], oth = 1 - cur;
+      const double* fh = c->fs + (size_t)h * n;
+      hipMemcpyAsync(v1, fh, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      fg::launch_apply_w(c->W[h][cur], 2, v1, 1, n, c->W[h][cur].work, s);
+      fg::launch_dot(v1, v1, n, 0, &c->st->q[h], c->dotwork, s);
+      uint64_t w[4];
+      fg::philox4x64_10(0, fg::tp_factor_tag(5, h), t, cf.stream_id, cf.seed, 0, w);
+      kp[h] = c->k[h] + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
+      ong[h] = (kp[h] >= 0 && kp[h] < cf.grid_size) ? 1 : 0;
+      if (ong[h]) {
+        fg::launch_zero_int(c->H[h][oth].status, 1, s);
+        fg::launch_zero_int(c->W[h][oth].status, 1, s);
+        c->H[h][oth].pk = c->packs[h][kp[h]];
+        fg::launch_build(c->H[h][oth], s);
+        c->W[h][oth].H = &c->H[h][oth];
+        c->W[h][oth].alpha = 1.0;
+        c->W[h][oth].beta = 0.0;
+        fg::launch_factor(c->W[h][oth], nullptr, nullptr, nullptr, s);
+        hipMemcpyAsync(&c->st->logdetp[h], c->W[h][oth].logdet, sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(v1, fh, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        fg::launch_apply_w(c->W[h][oth], 2, v1, 1, n, c->W[h][oth].work, s);
+        fg::launch_dot(v1, v1, n, 0, &c->st->qp[h], c->dotwork, s);
+      }
+      fg::launch_tp_mh_step(c->st, h, kp[h], ong[h], cf.seed, t, cf.stream_id,
+                            ong[h] ? c->H[h][oth].status : nullptr,
+                            ong[h] ? c->W[h][oth].status : nullptr, s);
+    }
+    hipMemcpyAsync(c->st_host, c->st, sizeof(fg::TpState), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return tfail(FG_EDEVICE, "sweep failed on the device");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return tfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
+    for (int h = 0; h < d; ++h)
+      if (c->st_host->accept[h]) {
+        c->cur[h] = 1 - c->cur[h];
+        c->k[h] = kp[h];
+      }
+    c->iter += 1;
+  }
+  return FG_OK;
+}
+
+fg_status tp_chain_state(fg_tp_chain c, fg_tp_snapshot* host_out, double* F_out,
+                         fg_stream stream) {
+  if (!c || !host_out) return tfail(FG_EINVAL, "NULL argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (F_out)
+    hipMemcpyAsync(F_out, c->F, sizeof(double) * (size_t)c->d * c->n, hipMemcpyDeviceToDevice, s);
+  hipMemcpyAsync(c->st_host, c->st, sizeof(fg::TpState), hipMemcpyDeviceToHost, s);
+  if (hipStreamSynchronize(s) != hipSuccess) return tfail(FG_EDEVICE, "state copy failed");
+  int fst = c->st_host->status;
+  for (int h = 0; h < c->d; ++h) {
+    int a = 0, b = 0;
+    hipMemcpy(&a, c->H[h][c->cur[h]].status, sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(&b, c->W[h][c->cur[h]].status, sizeof(int), hipMemcpyDeviceToHost);
+    fst |= a | b;
+  }
+  int wp = 0;
+  hipMemcpy(&wp, c->WP.status, sizeof(int), hipMemcpyDeviceToHost);
+  fst |= wp;
+  const fg::TpState& q = *c->st_host;
+  *host_out = fg_tp_snapshot{};
+  host_out->iteration = c->iter;
+  host_out->tau = q.tau;
+  host_out->beta = q.beta;
+  host_out->sse = q.sse;
+  host_out->beta_mean = q.beta_mean;
+  host_out->beta_sd = q.beta_sd;
+  for (int h = 0; h < c->d; ++h) {
+    host_out->k[h] = q.k[h];
+    host_out->ell[h] = c->grid[h][q.k[h]];
+    host_out->last_proposal[h] = q.kprop[h];
+    host_out->last_accept[h] = q.accept[h];
+    host_out->accepts[h] = q.accepts[h];
+    host_out->logdet[h] = q.logdet[h];
+    host_out->q[h] = q.q[h];
+    host_out->mh_log_ratio[h] = q.mh[h];
+  }
+  host_out->status = (fst & fg::ST_NOTSPD) ? FG_ENOTSPD : (fst & fg::ST_NOTCONV) ? FG_ENOTCONV : FG_OK;
+  return FG_OK;
+}
+
+void tp_chain_destroy(fg_tp_chain c) { tp_free(c); }
+
+}  // extern "C"

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "fg_internal.h"
+
 namespace fg {
 
 __host__ __device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
@@ -35,6 +37,32 @@ __host__ __device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
 // 52-bit uniform strictly inside (0, 1); every step is exact in FP64.
 __host__ __device__ inline double to_unit(uint64_t w) {
   return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+// Gamma(shape, 1) by Marsaglia & Tsang (ACM TOMS 26(3), 2000): try t uses block t of
+// the counter, z from (u0, u1) by the cosine branch, acceptance uniform u2; shape < 1
+// takes Gamma(shape + 1) u3^(1/shape).  At most 64 tries (then ST_NOTCONV).
+__device__ inline double gamma_mt(double shape, uint64_t seed, uint64_t tag, uint64_t iter,
+                           uint64_t strm, int* status) {
+  const bool boost = shape < 1.0;
+  const double a = boost ? shape + 1.0 : shape;
+  const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
+  for (int t = 0; t < 64; ++t) {
+    uint64_t w[4];
+    philox4x64_10((uint64_t)t, tag, iter, strm, seed, 0, w);
+    const double u0 = to_unit(w[0]), u1 = to_unit(w[1]), u2 = to_unit(w[2]), u3 = to_unit(w[3]);
+    const double z = sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+    double v = 1.0 + c * z;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    if (log(u2) < 0.5 * z * z + d - d * v + d * log(v)) {
+      double g = d * v;
+      if (boost) g *= pow(u3, 1.0 / shape);
+      return g;
+    }
+  }
+  atomicOr(status, ST_NOTCONV);
+  return d;
 }
 
 // Scalars of one chain kept in device memory so that a sweep needs no host round trip.

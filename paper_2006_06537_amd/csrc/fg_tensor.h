@@ -1,0 +1,39 @@
+// Tensor-product sampler internals (device state and launchers).
+#pragma once
+#include "fg_internal.h"
+
+namespace fg {
+
+constexpr int TP_DMAX = 8;          // most factors of one tensor-product chain
+constexpr uint64_t TP_TAG_BETA = 7;
+constexpr uint64_t TP_TAG_STRIDE = 16;
+
+// tag of the 1-D sampler's draw `tag` for factor h
+__host__ __device__ inline uint64_t tp_factor_tag(uint64_t tag, int h) {
+  return tag + TP_TAG_STRIDE * (uint64_t)(h + 1);
+}
+
+struct TpState {
+  double tau, beta;
+  double GG, Gy, sse;               // G'G, G'y, |y - beta G|^2
+  double beta_mean, beta_sd;        // moments of the last beta draw
+  double logdet[TP_DMAX], logdetp[TP_DMAX];
+  double q[TP_DMAX], qp[TP_DMAX], mh[TP_DMAX];
+  int k[TP_DMAX], kprop[TP_DMAX], accept[TP_DMAX], accepts[TP_DMAX];
+  int status, pad;
+};
+
+void launch_tp_prepare(int n, int d, int h, const int* perm, const double* F, const double* y,
+                       const TpState* st, double* D, double* Dinv, double* yt, hipStream_t s);
+void launch_scale_sqrt(int n, const double* D, double* v, hipStream_t s);
+void launch_hetero_finish(int n, const double* R, const double* Zs, const double* D, double* f,
+                          const int* perm, double* Fh, hipStream_t s);
+void launch_tp_product(int n, int d, const double* F, double* G, hipStream_t s);
+void launch_tp_beta_step(TpState* st, double s_beta, uint64_t seed, uint64_t iter, uint64_t strm,
+                         hipStream_t s);
+void launch_tp_tau_step(TpState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
+                        uint64_t strm, hipStream_t s);
+void launch_tp_mh_step(TpState* st, int h, int kprop, int ongrid, uint64_t seed, uint64_t iter,
+                       uint64_t strm, const int* pst_a, const int* pst_b, hipStream_t s);
+
+}  // namespace fg

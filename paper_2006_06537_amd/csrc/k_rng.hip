@@ -108,29 +108,6 @@ void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, i
 // ---------------------------------------------------------------------------------
 // scalar steps of the sweep (one thread)
 // ---------------------------------------------------------------------------------
-__device__ double gamma_mt(double shape, uint64_t seed, uint64_t tag, uint64_t iter,
-                           uint64_t strm, int* status) {
-  const bool boost = shape < 1.0;
-  const double a = boost ? shape + 1.0 : shape;
-  const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
-  for (int t = 0; t < 64; ++t) {
-    uint64_t w[4];
-    philox4x64_10((uint64_t)t, tag, iter, strm, seed, 0, w);
-    const double u0 = to_unit(w[0]), u1 = to_unit(w[1]), u2 = to_unit(w[2]), u3 = to_unit(w[3]);
-    const double z = sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
-    double v = 1.0 + c * z;
-    if (v <= 0.0) continue;
-    v = v * v * v;
-    if (log(u2) < 0.5 * z * z + d - d * v + d * log(v)) {
-      double g = d * v;
-      if (boost) g *= pow(u3, 1.0 / shape);
-      return g;
-    }
-  }
-  atomicOr(status, ST_NOTCONV);
-  return d;
-}
-
 // derived scalars at the start of a sweep
 __global__ void k_sweep_begin(DevState* st) {
   st->alphaM = st->tau * st->sigf2;

@@ -1,0 +1,151 @@
+"""Parity of the tensor-product path (Algorithm 1.h and the tensor sweep, through the
+C ABI) with the oracle, on the same seeded inputs.
+
+Tolerance: relative 1e-9 (2-norm) for vectors and scalars, exact for grid indices,
+proposals and accept flags -- the bar used for the 1-D sampler's draws.  The
+quadratic forms q = |W_h^-1 f_h|^2 carry twice the bar of a W^-1 product of K~_h,
+max(1e-9, 2 u kappa(leaf)) -- the leaf Cholesky forward-error bound of the factor
+parity tests -- and the Metropolis log ratio D = -1/2 (l' - l) - (q' - q)/2, a
+difference of such terms, the sum of their bounds."""
+import numpy as np
+import pytest
+
+from oracle import hodlr as oh, kernels, rng, sampler, tensor
+from workloads import TENSOR_4D, small_1d, tensor_surface
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def fg():
+    import paper_2006_06537_amd as m
+    return m
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+HCASES = [
+    # n, leaf, ell, tol, seed, factor
+    (1000, 64, 0.1, 1e-12, 0, -1),
+    (3001, 64, 0.03, 1e-10, 1, 2),   # ragged leaves, factor tags
+    (1537, 32, 0.01, 1e-10, 3, 0),
+    (50, 64, 0.2, 1e-10, 5, -1),     # one leaf
+]
+
+
+@pytest.mark.parametrize("case", HCASES, ids=[f"n{c[0]}-B{c[1]}-h{c[5]}" for c in HCASES])
+def test_draw_f_hetero_matches_oracle(case):
+    n, leaf, ell, tol, seed, factor = case
+    x, y = small_1d(n=n, seed=seed)
+    # precisions shaped like tau g^2 of a tensor sweep: g crosses zero, D spans decades
+    g = np.sin(7.0 * x + 0.3) * np.sqrt(4.0 * x + 0.1)
+    g = tensor.clamp_g(g)
+    D = 100.0 * g * g
+    dev = torch.device("cuda:0")
+    xt, yt, Dt = (torch.tensor(v, device=dev) for v in (x, y, D))
+    K = fg().Hodlr(xt, ell, nugget=1e-6, leaf=leaf, tol=tol)
+    WK = fg().Factor(K, 1.0, 0.0)
+    WP = fg().Factor(K, 1.0, 0.0, diag=1.0 / Dt)
+    assert WP.status() == 0
+    f, R = fg().draw_f_hetero(K, WK, WP, Dt, yt, 17, 4, 9, factor)
+    ta = rng.TAG_A if factor < 0 else tensor.factor_tag(rng.TAG_A, factor)
+    tb = rng.TAG_B if factor < 0 else tensor.factor_tag(rng.TAG_B, factor)
+    a = rng.normals(n, 17, ta, 4, 9)
+    b = rng.normals(n, 17, tb, 4, 9)
+    H = oh.HODLR(x, kernels.SE, ell, 1e-6, leaf, tol)
+    of, oR = sampler.draw_f_hetero(H, oh.Factor(H, 1.0, 0.0), oh.Factor(H, 1.0, 0.0, 1.0 / D), D,
+                                   y, a, b)
+    assert rel(R.cpu().numpy(), oR) <= 1e-9
+    assert rel(f.cpu().numpy(), of) <= 1e-9
+
+
+def _pair(d, n, leaf, tol, ell0, seed, positive=False, tau0=100.0):
+    x, y = tensor_surface(d, n, seed=seed, positive=positive)
+    dev = torch.device("cuda:0")
+    g = fg().TensorChain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0,
+                         tau0=tau0, beta0=1.0, nugget=1e-6, leaf=leaf, tol=tol, seed=seed)
+    o = tensor.TensorChain(x, y, kernels.SE, ell0, 1e-6, leaf, tol, tau0, 1.0, seed)
+    return g, o
+
+
+def _tw(o, h, k):
+    """Bar of a W_h^-1 product at grid point k: max(1e-9, 2 u kappa(leaf)), the leaf
+    Cholesky forward-error bound used for the K~_1 factor operators."""
+    if not 0 <= k < len(o.grids[h]):
+        return 1e-9
+    ell = o.grids[h][k]
+    xs = o.xs[h]
+    kap = max(np.linalg.cond(kernels.K1_dense(kernels.SE, ell, 1e-6, xs[lo:hi]))
+              for lo, hi in o.H[h].tree.leaves())
+    return max(1e-9, 2.0 * 2.0 ** -53 * kap)
+
+
+def _compare(s, r, o, it, kb):
+    d = o.d
+    assert s["k"] == r["k"], (it, s["k"], r["k"])
+    assert s["last_proposal"] == r["proposal"], it
+    assert s["last_accept"] == [int(a) for a in r["accept"]], it
+    for key in ["tau", "beta", "sse", "beta_mean", "beta_sd"]:
+        ref = r[key]
+        assert abs(s[key] - ref) <= 1e-9 * abs(ref), (it, key, s[key], ref)
+    for h in range(d):
+        # q = |W_h^-1 f_h|^2: twice the relative bar of W_h^-1 (plus its square)
+        tq = _tw(o, h, r["k"][h])
+        q_now = r["q_prop"][h] if r["accept"][h] else r["q"][h]  # q at the current ell_h
+        assert abs(s["q"][h] - q_now) <= 2.5 * tq * abs(q_now), (it, h)
+        assert abs(s["logdet"][h] - r["logdet"][h]) <= 1e-9 * abs(r["logdet"][h]), (it, h)
+        # D is a difference of terms of size |log det| and q: each carries the 1e-9 bar
+        bound = (1e-9 * (abs(r["logdet_prop"][h]) + abs(r["logdet"][h]))
+                 + 2.5 * _tw(o, h, r["proposal"][h]) * abs(r["q_prop"][h])
+                 + 2.5 * _tw(o, h, kb[h]) * abs(r["q"][h]))
+        assert abs(s["mh_log_ratio"][h] - r["mh_log_ratio"][h]) <= bound, (it, h)
+    assert s["status"] == 0
+
+
+@pytest.mark.parametrize("positive", [False, True], ids=["sin-sqrt", "positive"])
+def test_tensor_chain_matches_oracle(positive):
+    g, o = _pair(3, 2000, 64, 1e-10, (0.05, 0.1, 0.2), 3, positive=positive)
+    for it in range(4):
+        g.step(1)
+        s = g.state(with_factors=(it == 3))
+        kb = list(o.k)
+        r = o.step()
+        _compare(s, r, o, it, kb)
+    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+
+
+def test_tensor_chain_one_factor_ragged():
+    g, o = _pair(1, 777, 32, 1e-10, (0.07,), 8)
+    for it in range(3):
+        g.step(1)
+        s = g.state(with_factors=True)
+        kb = list(o.k)
+        _compare(s, o.step(), o, it, kb)
+    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+
+
+def test_tensor_chain_full_size_first_sweep():
+    """The d = 4, n = 65,536 tensor workload: first sweep against the oracle."""
+    T = TENSOR_4D
+    g, o = _pair(T["d"], T["n"], T["leaf"], T["tol"], T["ell0"], T["seed"], tau0=T["tau0"])
+    g.step(1)
+    s = g.state(with_factors=True)
+    kb = list(o.k)
+    _compare(s, o.step(), o, 0, kb)
+    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+
+
+def test_tensor_chain_deterministic():
+    x, y = tensor_surface(2, 900, seed=6)
+    dev = torch.device("cuda:0")
+    runs = []
+    for _ in range(2):
+        c = fg().TensorChain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), (0.1, 0.2),
+                             leaf=64, seed=6)
+        c.step(3)
+        runs.append(c.state(with_factors=True))
+    assert torch.equal(runs[0]["F"], runs[1]["F"])
+    assert runs[0]["tau"] == runs[1]["tau"] and runs[0]["beta"] == runs[1]["beta"]
