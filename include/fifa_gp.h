@@ -215,6 +215,19 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
 /* Runs `iters` sweeps.  Synchronises once per sweep (the accepted length-scale
  * selects which cached factor the next sweep uses). */
 fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream);
+/* ---------------------------------------------------------------------------
+ * gibbs_step_batch -- `iters` sweeps of each of `nchains` distinct chains, spread
+ * round-robin over `nstreams` (1..4) library streams of default priority, with one
+ * host synchronisation per batched sweep instead of one per chain.  With
+ * use_graphs != 0 each chain's sweep is captured once per (slot, grid index,
+ * proposal) as a HIP graph and replayed (up to 48 captured sweeps per chain; none
+ * while a kernel timer runs).  Results are identical to gibbs_step on each chain:
+ * chains share no buffers and every reduction is deterministic.  The batch starts
+ * after the work queued on `stream` and has finished when the call returns.
+ * Errors: FG_EINVAL (NULL or repeated chain, nstreams out of range), FG_EDEVICE.
+ * ------------------------------------------------------------------------- */
+fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int32_t nstreams,
+                           int32_t use_graphs, fg_stream stream);
 /* Host snapshot of the scalars; if f_out (device, n) is not NULL it receives f
  * (and r_out, mu_out likewise: Sigma~^-1 y and K~ r of the last f-draw). */
 fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_out,

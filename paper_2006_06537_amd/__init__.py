@@ -14,7 +14,7 @@ from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kern
                    TpSnapshot, check, lib)
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
-           "draw_f_hetero", "KERNEL_SE",
+           "draw_f_hetero", "step_batch", "KERNEL_SE",
            "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE"]
 
 KID_LEAF, KID_REDUCE, KID_UPDATE = 1, 2, 3
@@ -245,6 +245,12 @@ class TensorChain:
         except Exception:  # interpreter shutdown
             pass
         self._c = None
+
+
+def step_batch(chains, iters=1, nstreams=4, graphs=True):
+    """gibbs_step_batch over a list of Chain objects."""
+    arr = (C.c_void_p * max(len(chains), 1))(*[c._c for c in chains])
+    check(lib().gibbs_step_batch(arr, len(chains), iters, nstreams, int(graphs), _stream()))
 
 
 class Chain:

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", 
 EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", "hodlr_entries",
            "hodlr_matvec", "hodlr_factor", "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
-           "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state", "fg_timer_start",
+           "gibbs_step_batch", "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state", "fg_timer_start",
            "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
            "factor_destroy", "gibbs_chain_destroy", "tp_chain_destroy"]
 
@@ -116,6 +116,7 @@ def lib():
         "tp_chain_destroy": ([P], None),
         "gibbs_chain_create": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
         "gibbs_step": ([P, I32, P], I32),
+        "gibbs_step_batch": ([C.POINTER(P), I32, I32, I32, I32, P], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),
         "fg_timer_start": ([I32], I32),
         "fg_timer_stop": ([C.POINTER(D), C.POINTER(I64), C.POINTER(D)], I32),

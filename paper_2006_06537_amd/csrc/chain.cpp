@@ -5,11 +5,13 @@
 // the proposal -- and swaps them on acceptance; all plans of the grid are made and
 // uploaded once, so a sweep only enqueues kernels and synchronises once at its end.
 #include <cmath>
+#include <map>
 #include <string>
 #include <vector>
 
 #include "fg_internal.h"
 #include "fg_rng.h"
+#include "fg_timer.h"
 
 struct fg_chain_s {
   fg_chain_cfg cfg{};
@@ -28,7 +30,11 @@ struct fg_chain_s {
   double* dotwork = nullptr;  // reduction partials
   fg::DevState* st = nullptr;
   fg::DevState* st_host = nullptr;  // pinned
+  std::map<uint64_t, hipGraphExec_t> graphs;  // captured sweeps by (cur, k, proposal)
+  std::vector<uint64_t> graph_order;          // insertion order, for eviction
 };
+
+constexpr size_t GRAPH_CACHE = 48;  // captured sweeps kept per chain
 
 using fg::set_error;
 
@@ -40,6 +46,7 @@ static fg_status cfail(fg_status st, const std::string& m) {
 static void chain_free(fg_chain c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   fg::factor_free(c->WM);
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
@@ -50,6 +57,145 @@ static void chain_free(fg_chain c) {
   if (c->st_host) (void)hipHostFree(c->st_host);
   delete c;
 }
+
+namespace {
+
+struct Proposal {
+  int kp, ongrid;
+};
+
+// The grid proposal of the next sweep: its uniform is addressed by the iteration
+// count, which the host knows, so the proposal needs no device round trip.
+Proposal propose(fg_chain c) {
+  uint64_t w[4];
+  fg::philox4x64_10(0, 5, (uint64_t)c->iter, c->cfg.stream_id, c->cfg.seed, 0, w);
+  Proposal p;
+  p.kp = c->k + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
+  p.ongrid = (p.kp >= 0 && p.kp < c->cfg.grid_size) ? 1 : 0;
+  return p;
+}
+
+// Enqueues one sweep on s.  Every argument is fixed by (cur, k, proposal): the
+// iteration word lives in device memory, so the sequence can be captured once and
+// replayed.  Ends with the copy of the device state to pinned host memory.
+void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
+  const int n = c->n;
+  const fg_chain_cfg& cf = c->cfg;
+  double* v0 = c->vecs;
+  double* v1 = v0 + n;
+  double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, tau y]
+  double* v3 = v2 + n;
+  const uint64_t* itp = &c->st->iter;
+  const int cur = c->cur, oth = 1 - cur;
+  fg::launch_sweep_begin(c->st, s);
+  // f | -  (Algorithm 1)
+  c->WM.H = &c->H[cur];
+  c->WM.alpha = 0.0;  // taken from the device scalar
+  c->WM.beta = 1.0;
+  fg::launch_factor(c->WM, &c->st->alphaM, nullptr, nullptr, s);
+  hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
+  fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
+  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
+  fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+  fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
+  fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
+  fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
+  fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
+  fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
+                    c->H[cur].work, s);
+  fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
+  hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
+  fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
+  // tau | -
+  fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, cf.stream_id, s);
+  // sigma_f^-2 | -
+  hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  fg::launch_apply_w(c->W[cur], 2, v0, 1, n, c->W[cur].work, s);
+  fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
+  fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
+  // length-scale | -  (Metropolis on the grid)
+  if (pr.ongrid) {
+    fg::launch_zero_int(c->H[oth].status, 1, s);
+    fg::launch_zero_int(c->W[oth].status, 1, s);
+    c->H[oth].pk = c->packs[pr.kp];
+    fg::launch_build(c->H[oth], s);
+    c->W[oth].H = &c->H[oth];
+    c->W[oth].alpha = 1.0;
+    c->W[oth].beta = 0.0;
+    fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, s);
+    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
+    fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
+  }
+  fg::launch_mh_step(c->st, pr.kp, pr.ongrid, cf.seed, cf.stream_id,
+                     pr.ongrid ? c->H[oth].status : nullptr, pr.ongrid ? c->W[oth].status : nullptr, s);
+  hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+}
+
+// after the sweep's stream has been synchronised: the accepted proposal becomes current
+void finish_sweep(fg_chain c, const Proposal& pr) {
+  if (c->st_host->accept) {
+    c->cur = 1 - c->cur;
+    c->k = pr.kp;
+  }
+  c->iter += 1;
+}
+
+// A few default-priority streams shared by batched calls.
+constexpr int BATCH_STREAMS = 4;
+struct BatchStreams {
+  bool init = false;
+  hipStream_t s[BATCH_STREAMS] = {};
+  hipEvent_t ev_in = nullptr;
+};
+BatchStreams g_batch;
+
+fg_status batch_streams_init() {
+  if (g_batch.init) return FG_OK;
+  for (int q = 0; q < BATCH_STREAMS; ++q)
+    if (hipStreamCreateWithFlags(&g_batch.s[q], hipStreamNonBlocking) != hipSuccess)
+      return cfail(FG_EDEVICE, "stream creation failed");
+  if (hipEventCreateWithFlags(&g_batch.ev_in, hipEventDisableTiming) != hipSuccess)
+    return cfail(FG_EDEVICE, "event creation failed");
+  g_batch.init = true;
+  return FG_OK;
+}
+
+// The captured sweep for (cur, k, proposal), instantiated on first use.
+fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExec_t& out) {
+  const uint64_t key = ((uint64_t)c->cur << 40) | ((uint64_t)(uint32_t)c->k << 20) |
+                       (uint64_t)(uint32_t)(pr.kp + 1);
+  auto it = c->graphs.find(key);
+  if (it != c->graphs.end()) {
+    out = it->second;
+    return FG_OK;
+  }
+  if (c->graphs.size() >= GRAPH_CACHE) {  // drop the oldest entry
+    const uint64_t old = c->graph_order.front();
+    c->graph_order.erase(c->graph_order.begin());
+    (void)hipGraphExecDestroy(c->graphs[old]);
+    c->graphs.erase(old);
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return cfail(FG_EDEVICE, "stream capture failed to start");
+  enqueue_sweep(c, pr, q);
+  if (hipStreamEndCapture(q, &g) != hipSuccess || !g)
+    return cfail(FG_EDEVICE, "stream capture failed");
+  hipGraphExec_t ge = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return cfail(FG_EDEVICE, "graph instantiation failed");
+  c->graphs[key] = ge;
+  c->graph_order.push_back(key);
+  out = ge;
+  return FG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -137,73 +283,53 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
 fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   if (!c || iters < 0) return cfail(FG_EINVAL, "bad arguments");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int n = c->n;
-  const fg_chain_cfg& cf = c->cfg;
-  double* v0 = c->vecs;
-  double* v1 = v0 + n;
-  double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, tau y]
-  double* v3 = v2 + n;
   for (int it = 0; it < iters; ++it) {
-    const uint64_t t = (uint64_t)c->iter;
-    const int cur = c->cur, oth = 1 - cur;
-    fg::launch_sweep_begin(c->st, s);
-    // f | -  (Algorithm 1)
-    c->WM.H = &c->H[cur];
-    c->WM.alpha = 0.0;  // taken from the device scalar
-    c->WM.beta = 1.0;
-    fg::launch_factor(c->WM, &c->st->alphaM, nullptr, nullptr, s);
-    hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-    fg::launch_normals(cf.seed, 1, t, cf.stream_id, n, v0, s);
-    fg::launch_normals(cf.seed, 2, t, cf.stream_id, n, v1, s);
-    fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
-    fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
-    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
-    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
-    fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
-    fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
-    fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
-                      c->H[cur].work, s);
-    fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
-    hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-    fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
-    fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
-    // tau | -
-    fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, t, cf.stream_id, s);
-    // sigma_f^-2 | -
-    hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-    fg::launch_apply_w(c->W[cur], 2, v0, 1, n, c->W[cur].work, s);
-    fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
-    fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, t, cf.stream_id, s);
-    // length-scale | -  (Metropolis on the grid; the proposal uniform is known on the host)
-    uint64_t w[4];
-    fg::philox4x64_10(0, 5, t, cf.stream_id, cf.seed, 0, w);
-    const int kp = c->k + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
-    const int ongrid = (kp >= 0 && kp < cf.grid_size) ? 1 : 0;
-    if (ongrid) {
-      fg::launch_zero_int(c->H[oth].status, 1, s);
-      fg::launch_zero_int(c->W[oth].status, 1, s);
-      c->H[oth].pk = c->packs[kp];
-      fg::launch_build(c->H[oth], s);
-      c->W[oth].H = &c->H[oth];
-      c->W[oth].alpha = 1.0;
-      c->W[oth].beta = 0.0;
-      fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, s);
-      hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-      hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-      fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
-      fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
-    }
-    fg::launch_mh_step(c->st, kp, ongrid, cf.seed, t, cf.stream_id,
-                       ongrid ? c->H[oth].status : nullptr, ongrid ? c->W[oth].status : nullptr, s);
-    hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+    const Proposal pr = propose(c);
+    enqueue_sweep(c, pr, s);
     if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
-    if (c->st_host->accept) {
-      c->cur = oth;
-      c->k = kp;
+    finish_sweep(c, pr);
+  }
+  return FG_OK;
+}
+
+fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int32_t nstreams,
+                           int32_t use_graphs, fg_stream stream) {
+  if (!chains || nchains < 0 || iters < 0 || nstreams < 1 || nstreams > BATCH_STREAMS)
+    return cfail(FG_EINVAL, "bad arguments");
+  for (int i = 0; i < nchains; ++i) {
+    if (!chains[i]) return cfail(FG_EINVAL, "NULL chain");
+    for (int j = 0; j < i; ++j)
+      if (chains[j] == chains[i]) return cfail(FG_EINVAL, "a chain appears twice");
+  }
+  hipStream_t caller = reinterpret_cast<hipStream_t>(stream);
+  fg_status st = batch_streams_init();
+  if (st != FG_OK) return st;
+  const bool graphs = use_graphs && !fg::timer_active();
+  // the batch starts after the work already queued on the caller's stream
+  if (hipEventRecord(g_batch.ev_in, caller) != hipSuccess) return cfail(FG_EDEVICE, "event record failed");
+  for (int q = 0; q < nstreams; ++q) hipStreamWaitEvent(g_batch.s[q], g_batch.ev_in, 0);
+  std::vector<Proposal> pr(nchains);
+  for (int it = 0; it < iters; ++it) {
+    for (int i = 0; i < nchains; ++i) {
+      fg_chain c = chains[i];
+      hipStream_t q = g_batch.s[i % nstreams];
+      pr[i] = propose(c);
+      if (!graphs) {
+        enqueue_sweep(c, pr[i], q);
+        continue;
+      }
+      hipGraphExec_t ge = nullptr;
+      if ((st = sweep_graph(c, pr[i], q, ge)) != FG_OK) return st;
+      if (hipGraphLaunch(ge, q) != hipSuccess) return cfail(FG_EDEVICE, "graph launch failed");
     }
-    c->iter += 1;
+    for (int q = 0; q < nstreams; ++q)
+      if (hipStreamSynchronize(g_batch.s[q]) != hipSuccess)
+        return cfail(FG_EDEVICE, "batched sweep failed on the device");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("batched sweep: ") + hipGetErrorString(e));
+    for (int i = 0; i < nchains; ++i) finish_sweep(chains[i], pr[i]);
   }
   return FG_OK;
 }

@@ -172,8 +172,9 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
                    double* work, hipStream_t s);
 void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int64_t count,
                     double* out, hipStream_t s);
+// iteration word from iter_dev (device) when given, else `iter`
 void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
-                    double* out, hipStream_t s);
+                    double* out, hipStream_t s, const uint64_t* iter_dev = nullptr);
 // out = scale * sum (a-b)^2 or sum a*b etc (deterministic two-stage)
 void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
                 hipStream_t s);

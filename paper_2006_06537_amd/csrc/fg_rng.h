@@ -73,17 +73,20 @@ struct DevState {
   double sse, q, qprop, yr;
   double logdetM, logdet1, logdet1p;
   double logdet_sigma, loglik, mh;
+  uint64_t iter;              // sweeps completed (the Philox iteration word)
   int k, kprop, accept, accepts, status, pad;
 };
 
 void launch_sweep_begin(DevState* st, hipStream_t s);
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s);
-void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
-                     uint64_t strm, hipStream_t s);
-void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t iter,
-                      uint64_t strm, hipStream_t s);
-void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t iter,
-                    uint64_t strm, const int* pst_a, const int* pst_b, hipStream_t s);
+// the steps below take the iteration word from st->iter; the Metropolis step ends the
+// sweep and advances it
+void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t strm,
+                     hipStream_t s);
+void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t strm,
+                      hipStream_t s);
+void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t strm,
+                    const int* pst_a, const int* pst_b, hipStream_t s);
 void launch_zero_int(int* p, int n, hipStream_t s);
 
 }  // namespace fg

@@ -6,6 +6,7 @@
 
 namespace fg {
 bool timer_wants(int kid);
+bool timer_active();  // a kernel is being timed (launches must stay eager)
 void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const int* kmax_dev,
                   int ntask);
 void timer_after(int kid, hipStream_t s);

@@ -469,9 +469,13 @@ void launch_build(HodlrData& H, hipStream_t s) {
     k_moments<<<nm, NTHREADS, 0, s>>>(D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
   const int pm = std::max(P.pmax, 1);
   const size_t lds = sizeof(double) * 5 * pm * pm;
-  if (lds > 65536)
+  static bool lds_set = false;  // raised once to the largest size any plan can ask for
+  if (!lds_set) {
     (void)hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(lds));
+                              int(sizeof(double) * 5 * PMAX * PMAX));
+    lds_set = true;
+  }
+
   k_compress<<<P.nint, NTHREADS, lds, s>>>(D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart,
                                            P.mpart_stride, D.mtask_off, D.kcap, H.tbuf, H.sv,
                                            H.rank, H.status, pm);

@@ -761,9 +761,14 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
   timer_after(KID_LEAF, s);
   const int kcm = std::max(P.kcapmax, 1);
   const size_t lds_max = sizeof(double) * 5 * (size_t)kcm * kcm;
-  if (lds_max > 65536)
+  static bool lds_set = false;  // raised once to the largest size any plan can ask for
+  if (!lds_set) {
     (void)hipFuncSetAttribute((const void*)k_node_factor,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_max));
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(sizeof(double) * 5 * PMAX * PMAX));
+    lds_set = true;
+  }
+
   for (int l = P.L - 1; l >= 0; --l) {
     const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
     const int Wcap = P.coff[l + 1];  // columns of levels <= l (capacity)

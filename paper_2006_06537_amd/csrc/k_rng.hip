@@ -12,11 +12,12 @@
 
 namespace fg {
 
-__global__ void k_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
-                          double* __restrict__ out) {
+__global__ void k_normals(uint64_t seed, uint64_t tag, uint64_t iter, const uint64_t* iter_p,
+                          uint64_t strm, int64_t n, double* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nb = (n + 3) / 4;
   if (j >= nb) return;
+  if (iter_p) iter = *iter_p;
   uint64_t w[4];
   philox4x64_10((uint64_t)j, tag, iter, strm, seed, 0, w);
   const double u0 = to_unit(w[0]), u1 = to_unit(w[1]), u2 = to_unit(w[2]), u3 = to_unit(w[3]);
@@ -99,10 +100,10 @@ void launch_axpby(int n, const double* x, const double* y, double* out, const do
 }
 
 void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, int64_t n,
-                    double* out, hipStream_t s) {
+                    double* out, hipStream_t s, const uint64_t* iter_dev) {
   const int64_t nb = (n + 3) / 4;
   if (nb <= 0) return;
-  k_normals<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(seed, tag, iter, strm, n, out);
+  k_normals<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(seed, tag, iter, iter_dev, strm, n, out);
 }
 
 // ---------------------------------------------------------------------------------
@@ -126,8 +127,9 @@ __global__ void k_set_draw_scalars(DevState* st, double tau, double sigf2) {
 }
 
 // log-likelihood bookkeeping of the f draw and the tau update
-__global__ void k_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
+__global__ void k_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed,
                            uint64_t strm) {
+  const uint64_t iter = st->iter;
   const double tau0 = st->tau_draw;
   st->logdet_sigma = st->logdetM - n * log(tau0);
   st->loglik = -0.5 * n * log(2.0 * M_PI) - 0.5 * st->logdet_sigma - 0.5 * st->yr;
@@ -136,13 +138,16 @@ __global__ void k_tau_step(DevState* st, int n, double a1, double b1, uint64_t s
 }
 
 __global__ void k_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed,
-                            uint64_t iter, uint64_t strm) {
+                            uint64_t strm) {
+  const uint64_t iter = st->iter;
   const double g = gamma_mt(0.5 * (a2 + n), seed, 4, iter, strm, &st->status);
   st->sigf2 = 1.0 / (g / (0.5 * (b2 + st->q)));
 }
 
-__global__ void k_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t iter,
-                          uint64_t strm, const int* pst_a, const int* pst_b) {
+__global__ void k_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t strm,
+                          const int* pst_a, const int* pst_b) {
+  const uint64_t iter = st->iter;
+  st->iter = iter + 1;  // this step ends the sweep
   st->kprop = kprop;
   st->accept = 0;
   st->mh = 0.0;
@@ -167,17 +172,17 @@ void launch_sweep_begin(DevState* st, hipStream_t s) { k_sweep_begin<<<1, 1, 0, 
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s) {
   k_set_draw_scalars<<<1, 1, 0, s>>>(st, tau, sigf2);
 }
-void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
-                     uint64_t strm, hipStream_t s) {
-  k_tau_step<<<1, 1, 0, s>>>(st, n, a1, b1, seed, iter, strm);
+void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t strm,
+                     hipStream_t s) {
+  k_tau_step<<<1, 1, 0, s>>>(st, n, a1, b1, seed, strm);
 }
-void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t iter,
-                      uint64_t strm, hipStream_t s) {
-  k_sigf_step<<<1, 1, 0, s>>>(st, n, a2, b2, seed, iter, strm);
+void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t strm,
+                      hipStream_t s) {
+  k_sigf_step<<<1, 1, 0, s>>>(st, n, a2, b2, seed, strm);
 }
-void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t iter,
-                    uint64_t strm, const int* pst_a, const int* pst_b, hipStream_t s) {
-  k_mh_step<<<1, 1, 0, s>>>(st, kprop, ongrid, seed, iter, strm, pst_a, pst_b);
+void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t strm,
+                    const int* pst_a, const int* pst_b, hipStream_t s) {
+  k_mh_step<<<1, 1, 0, s>>>(st, kprop, ongrid, seed, strm, pst_a, pst_b);
 }
 
 __global__ void k_zero_int(int* p, int n) {

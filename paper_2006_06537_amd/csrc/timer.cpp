@@ -32,6 +32,8 @@ __global__ void k_snapshot(const int* __restrict__ src, int count, int* __restri
   if (i < count) dst[i] = src[i];
 }
 
+bool timer_active() { return g_t.on; }
+
 bool timer_wants(int kid) { return g_t.on && g_t.kid == kid && (int)g_t.recs.size() < MAX_REC; }
 
 void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const int* kmax_dev,
