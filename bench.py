@@ -8,6 +8,13 @@ in HBM before the timed region.
 
 Prints one JSON line (metric, value, roofline of the dominant kernel, CPU oracle
 baseline).  Only one GPU is used: --gpus above 1 exits with a message.
+
+Other workloads (--workload), each printing its own JSON line:
+  batch   64 independent chains, n = 32,768 each (the large-workload generator with
+          seeds 1000 + c), stepped together by gibbs_step_batch with captured sweep
+          graphs; value = chain sweeps per second over all chains.  The same chains
+          stepped one after the other (gibbs_step) are timed beside it.
+  tensor  the d = 4, n = 65,536 tensor-product surface chain; value = sweeps/s.
 """
 from __future__ import annotations
 
@@ -31,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
+    ap.add_argument("--workload", default="large_1d", choices=["large_1d", "batch", "tensor"])
+    ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
     ap.add_argument("--kernel", type=int, default=1,
                     help="kernel timed for the roofline: 1 leaf, 2 level reduce, 3 level update")
     return ap.parse_args()
@@ -53,12 +62,116 @@ def cpu_baseline(x, y, cfg):
                       f"{dt:.1f} s"}
 
 
+def _line(metric, value, unit, args, dt, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import LARGE_1D, sinusoid_1d
+    cfg = dict(LARGE_1D)
+    n = args.n or 32768
+    dev = torch.device("cuda:0")
+
+    def make():
+        out = []
+        for c in range(args.chains):
+            x, y = sinusoid_1d(n, seed=1000 + c)
+            out.append(fg.Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev),
+                                ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
+                                nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"],
+                                seed=1000 + c, stream_id=c))
+        return out
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    chains = make()
+    print(f"bench: {args.chains} chains ready (n={n})", file=sys.stderr, flush=True)
+    fg.step_batch(chains, args.warmup, nstreams=4, graphs=True)
+    dt = timed(lambda: fg.step_batch(chains, args.steps, nstreams=4, graphs=True))
+    print(f"bench: batched with graphs {dt:.3f} s", file=sys.stderr, flush=True)
+    dt_eager = timed(lambda: fg.step_batch(chains, args.steps, nstreams=4, graphs=False))
+    print(f"bench: batched eager {dt_eager:.3f} s", file=sys.stderr, flush=True)
+
+    def seq():
+        for c in chains:
+            c.step(args.steps)
+    dt_seq = timed(seq)
+    print(f"bench: sequential {dt_seq:.3f} s", file=sys.stderr, flush=True)
+    tot = args.chains * args.steps
+    _line(f"chain Gibbs iters/s, {args.chains} chains x n={n} (FP64)", tot / dt,
+          "chain Gibbs iters/s", args, dt, "f64",
+          {"workload": f"batch: {args.chains} independent FP64 chains, n={n} each (5-sinusoid y, "
+                       "seeds 1000+c), SE kernel ell0=0.02, leaf 128, tol 1e-10; "
+                       "gibbs_step_batch, 4 streams, captured sweep graphs",
+           "chains": args.chains, "n": n},
+          batch_eager_value=tot / dt_eager, sequential_value=tot / dt_seq)
+
+
+def bench_tensor(args):
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import TENSOR_4D, tensor_surface
+    T = dict(TENSOR_4D)
+    n = args.n or T["n"]
+    x, y = tensor_surface(T["d"], n, seed=T["seed"])
+    dev = torch.device("cuda:0")
+    ch = fg.TensorChain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), T["ell0"],
+                        tau0=T["tau0"], beta0=T["beta0"], nugget=T["nugget"], leaf=T["leaf"],
+                        tol=T["tol"], seed=T["seed"])
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ch.state()
+    print(f"bench: tensor status {st['status']} tau {st['tau']:.4g} beta {st['beta']:.4g} "
+          f"k {st['k']}", file=sys.stderr, flush=True)
+    extra = {}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import kernels, tensor
+        oc = tensor.TensorChain(x, y, kernels.SE, T["ell0"], T["nugget"], T["leaf"], T["tol"],
+                                T["tau0"], T["beta0"], T["seed"])
+        t1 = time.perf_counter()
+        oc.step()
+        dto = time.perf_counter() - t1
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        extra["cpu_baseline"] = {"value": 1.0 / dto, "unit": "tensor sweeps/s", "cores": threads,
+                                 "kind": "oracle",
+                                 "sample": f"one sweep of the same chain (set-up untimed), {dto:.1f} s"}
+    _line(f"tensor-product sweeps/s, d={T['d']} x n={n} (FP64)", args.steps / dt, "sweeps/s",
+          args, dt, "f64",
+          {"workload": f"tensor: y = beta prod_h f_h(x_h) + noise, d={T['d']}, n={n}, x ~ U[0,1]^d, "
+                       "s(x)=sin(4x)sqrt(4x) per factor, Algorithm 1.h per factor, leaf 128, "
+                       "tol 1e-10", "d": T["d"], "n": n}, **extra)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU layout is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "tensor":
+        return bench_tensor(args)
     import numpy as np
     import torch
 
