@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--workload", default="large_1d", choices=["large_1d", "batch", "tensor"])
     ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: M~ factored in FP32, its solves refined by PCG to 1e-10")
     ap.add_argument("--kernel", type=int, default=1,
                     help="kernel timed for the roofline: 1 leaf, 2 level reduce, 3 level update")
     return ap.parse_args()
@@ -79,6 +81,7 @@ def bench_batch(args):
     cfg = dict(LARGE_1D)
     n = args.n or 32768
     dev = torch.device("cuda:0")
+    prec = fg.MIXED if args.precision == "mixed" else fg.FP64
 
     def make():
         out = []
@@ -87,7 +90,7 @@ def bench_batch(args):
             out.append(fg.Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev),
                                 ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
                                 nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"],
-                                seed=1000 + c, stream_id=c))
+                                seed=1000 + c, stream_id=c, precision=prec))
         return out
 
     def timed(fn):
@@ -111,9 +114,11 @@ def bench_batch(args):
     dt_seq = timed(seq)
     print(f"bench: sequential {dt_seq:.3f} s", file=sys.stderr, flush=True)
     tot = args.chains * args.steps
-    _line(f"chain Gibbs iters/s, {args.chains} chains x n={n} (FP64)", tot / dt,
-          "chain Gibbs iters/s", args, dt, "f64",
-          {"workload": f"batch: {args.chains} independent FP64 chains, n={n} each (5-sinusoid y, "
+    pname = "mixed" if prec == fg.MIXED else "FP64"
+    dname = "f32+f64" if prec == fg.MIXED else "f64"
+    _line(f"chain Gibbs iters/s, {args.chains} chains x n={n} ({pname})", tot / dt,
+          "chain Gibbs iters/s", args, dt, dname,
+          {"workload": f"batch: {args.chains} independent {pname} chains, n={n} each (5-sinusoid y, "
                        "seeds 1000+c), SE kernel ell0=0.02, leaf 128, tol 1e-10; "
                        "gibbs_step_batch, 4 streams, captured sweep graphs",
            "chains": args.chains, "n": n},
@@ -186,8 +191,10 @@ def main():
         x, y = large_1d(cfg["n"], cfg["seed"])
     dev = torch.device("cuda:0")
     xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    mixed = args.precision == "mixed"
     chain = fg.Chain(xt, yt, ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
-                     nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"])
+                     nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"],
+                     precision=fg.MIXED if mixed else fg.FP64)
     print(f"bench: chain ready (n={cfg['n']})", file=sys.stderr, flush=True)
     chain.step(args.warmup)
     torch.cuda.synchronize()
@@ -212,8 +219,24 @@ def main():
                 "traffic": None, "launches": launches,
                 "avg_launch_us": 1e3 * ktime_ms / launches,
                 "algorithmic_bytes_per_launch": kbytes / launches}
+    extra = {}
+    if mixed:
+        # the same chain in FP64 (itself held to the oracle at 1e-9), run to the same sweep
+        ref = fg.Chain(xt, yt, ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
+                       nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"])
+        ref.step(args.warmup + args.steps)
+        a, b = chain.state(with_vectors=True), ref.state(with_vectors=True)
+        fe = float(torch.linalg.norm(a["f"] - b["f"]) / torch.linalg.norm(b["f"]))
+        extra["vs_fp64_path"] = {
+            "sweeps": args.warmup + args.steps, "same_grid_index": a["k"] == b["k"],
+            "same_accepts": a["accepts"] == b["accepts"],
+            "tau_rel": abs(a["tau"] - b["tau"]) / abs(b["tau"]),
+            "sigf2_rel": abs(a["sigf2"] - b["sigf2"]) / abs(b["sigf2"]), "f_rel": fe,
+            "loglik_abs": abs(a["loglik"] - b["loglik"]), "pcg_iters": a["pcg_iters"],
+            "pcg_relres": a["pcg_relres"]}
+        print(f"bench: mixed vs FP64 path {extra['vs_fp64_path']}", file=sys.stderr, flush=True)
     out = {
-        "metric": "Gibbs iters/s at n=2^20 (FP64)",
+        "metric": "Gibbs iters/s at n=2^20 (mixed)" if mixed else "Gibbs iters/s at n=2^20 (FP64)",
         "value": args.steps / dt,
         "unit": "Gibbs iters/s",
         "n_gpus": 1,
@@ -223,14 +246,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "large_1d: single FP64 chain, n=2^20 sorted U[0,1], 5-sinusoid y "
+        "config": {"workload": ("large_1d: single chain, M~ factored in FP32 (leaf Cholesky, "
+                                "FP32 MFMA panel Grams) with PCG to 1e-10 on the FP64 HODLR, "
+                                "W_1 FP64;" if mixed else "large_1d: single FP64 chain,") + " "
+                               "n=2^20 sorted U[0,1], 5-sinusoid y "
                                "+ N(0,0.05^2), SE kernel ell0=0.02 (100-point grid), leaf 128, "
                                "tol 1e-10, nugget 1e-6",
                    "n": cfg["n"], "leaf": cfg["leaf"], "tol": cfg["tol"], "ell0": cfg["ell0"]},
         "roofline": roof,
     }
+    out.update(extra)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, y, cfg)

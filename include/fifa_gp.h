@@ -113,6 +113,33 @@ fg_status hodlr_matvec(fg_hodlr A, double alpha, double beta, const double* v, d
 fg_status hodlr_factor(fg_hodlr A, double alpha, double beta, const double* diag,
                        fg_stream stream, fg_factor* out);
 
+/* ---------------------------------------------------------------------------
+ * Precision of a factor.  FG_MIXED holds the leaf Cholesky factors, their inverses and
+ * the whitened panels in FP32 and computes them in FP32 (leaf Cholesky / whitening,
+ * panel Gram products on FP32 MFMA, panel updates); node capacitance factors, log-det
+ * accumulation and every vector operation stay FP64.  Meant as a preconditioner
+ * (hodlr_solve_refined); its W-products and log-det carry FP32-level error, and a node
+ * whose 1 - s^2 falls below 16 FP32 ulps (kappa u32 ~ 1) is floored there instead of
+ * being reported as not positive definite.
+ * ------------------------------------------------------------------------- */
+#define FG_FP64 0
+#define FG_MIXED 1
+/* hodlr_factor with a precision (FG_FP64 is hodlr_factor itself). */
+fg_status hodlr_factor_prec(fg_hodlr A, double alpha, double beta, const double* diag,
+                            int32_t precision, fg_stream stream, fg_factor* out);
+/* ---------------------------------------------------------------------------
+ * hodlr_solve_refined -- x = (alpha K~_1 + beta I)^-1 b by preconditioned conjugate
+ * gradients: products with the FP64 HODLR matrix A, preconditioner z = W^-T W^-1 r from
+ * F (a factor of the same matrix, any precision), FP64 residuals and inner products.
+ * Stops when |b - A x|_2 <= rtol |b|_2 for every column (rtol > 0) or after maxit
+ * iterations.  nrhs <= 4 columns, ld >= n; b and x must not overlap.
+ * *iters (host, may be NULL): iterations used; *relres (host, may be NULL): the largest
+ * final relative residual.  Synchronises the stream once per iteration.
+ * Errors: FG_EINVAL, FG_ENOMEM (workspace), FG_ENOTCONV (rtol not reached).
+ * ------------------------------------------------------------------------- */
+fg_status hodlr_solve_refined(fg_hodlr A, fg_factor F, double alpha, double beta,
+                              const double* b, double* x, int32_t nrhs, int64_t ld, double rtol,
+                              int32_t maxit, int32_t* iters, double* relres, fg_stream stream);
 /* x = (W W')^-1 b = W^-T W^-1 b for nrhs columns.  b and x may be the same. */
 fg_status hodlr_solve(fg_factor F, const double* b, double* x, int32_t nrhs, int64_t ld,
                       fg_stream stream);
@@ -190,6 +217,10 @@ typedef struct {
   int32_t grid_center;   /* starting index (e.g. 50) */
   uint64_t seed;
   uint64_t stream_id;    /* chain id in the Philox counter */
+  int32_t precision;     /* FG_FP64, or FG_MIXED: M~ = tau sigf2 K~_1 + I factored in
+                            FP32 and its two solves refined by PCG to a relative residual
+                            of 1e-10 (W_1 and everything else stay FP64); falls back to
+                            FP64 for good if the FP32 factor fails (see precision_used) */
 } fg_chain_cfg;
 
 typedef struct {
@@ -207,6 +238,11 @@ typedef struct {
   double logdet1;        /* log|K~_1| at the current length-scale */
   double mh_log_ratio;   /* D of the last Metropolis step (0 if off grid) */
   int32_t status;        /* device status word (FG_OK or a negative code) */
+  int32_t pcg_iters;     /* FG_MIXED: PCG iterations of the last f-draw (0 in FP64) */
+  double pcg_relres;     /* FG_MIXED: its final relative residual */
+  int32_t precision_used;/* precision of M~'s factor now: an FG_MIXED chain moves to FG_FP64
+                            for good when the FP32 factor fails as a preconditioner
+                            (kappa(M~) u32 ~ 1: non-finite or no convergence in 30 steps) */
 } fg_chain_snapshot;
 
 /* x, y: device n-vectors (x sorted); copied.  Builds and factors K~_1 at ell0. */

@@ -10,11 +10,11 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, TpCfg,
+from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, TpCfg,
                    TpSnapshot, check, lib)
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
-           "draw_f_hetero", "step_batch", "KERNEL_SE",
+           "draw_f_hetero", "step_batch", "solve_refined", "FP64", "MIXED", "KERNEL_SE",
            "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE"]
 
 KID_LEAF, KID_REDUCE, KID_UPDATE = 1, 2, 3
@@ -128,11 +128,12 @@ class Hodlr:
 class Factor:
     """W W' = alpha K~_1 + beta I + diag(d) (hodlr_factor)."""
 
-    def __init__(self, H: Hodlr, alpha=1.0, beta=0.0, diag=None):
+    def __init__(self, H: Hodlr, alpha=1.0, beta=0.0, diag=None, precision=FP64):
         self.H = H  # keep the matrix alive
         f = C.c_void_p()
-        check(lib().hodlr_factor(H.handle, alpha, beta, _dev(diag) if diag is not None else None,
-                                 _stream(), C.byref(f)))
+        check(lib().hodlr_factor_prec(H.handle, alpha, beta,
+                                      _dev(diag) if diag is not None else None, precision,
+                                      _stream(), C.byref(f)))
         self._f = f
 
     @property
@@ -171,6 +172,17 @@ class Factor:
         except Exception:  # interpreter shutdown
             pass
         self._f = None
+
+
+def solve_refined(A: Hodlr, F: Factor, alpha, beta, b, rtol=1e-10, maxit=50):
+    """PCG on (alpha K~_1 + beta I) x = b preconditioned by F; returns (x, iters, relres)."""
+    torch = _torch()
+    x = torch.empty_like(b)
+    nrhs, ld = _cols(b)
+    it, rr = C.c_int32(), C.c_double()
+    check(lib().hodlr_solve_refined(A.handle, F.handle, alpha, beta, _dev(b), _dev(x), nrhs, ld,
+                                    rtol, maxit, C.byref(it), C.byref(rr), _stream()))
+    return x, it.value, rr.value
 
 
 def normals(n, seed, tag, iteration, stream_id):
@@ -258,10 +270,10 @@ class Chain:
 
     def __init__(self, x, y, ell0, tau0, sigf2_0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
                  seed=0, stream_id=0, kind=KERNEL_SE, priors=(1.0, 1.0, 1.0, 1.0),
-                 grid_size=100, grid_center=50):
+                 grid_size=100, grid_center=50, precision=FP64):
         self.n = int(x.shape[0])
         cfg = ChainCfg(kind, ell0, nugget, leaf, tol, tau0, sigf2_0, priors[0], priors[1],
-                       priors[2], priors[3], grid_size, grid_center, seed, stream_id)
+                       priors[2], priors[3], grid_size, grid_center, seed, stream_id, precision)
         c = C.c_void_p()
         check(lib().gibbs_chain_create(C.byref(cfg), _dev(x, self.n), _dev(y, self.n), self.n,
                                        _stream(), C.byref(c)))

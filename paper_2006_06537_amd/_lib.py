@@ -12,6 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfifagp.so")
 
+FP64, MIXED = 0, 1
 FG_OK, FG_EINVAL, FG_ENOMEM, FG_ENOTSPD, FG_ETOL, FG_ENOTCONV, FG_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 KERNEL_SE, KERNEL_EXP = 0, 1
 STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", -4: "FG_ETOL",
@@ -19,7 +20,8 @@ STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", 
 
 # names declared in include/fifa_gp.h, in declaration order
 EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", "hodlr_entries",
-           "hodlr_matvec", "hodlr_factor", "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
+           "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
+           "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
            "gibbs_step_batch", "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state", "fg_timer_start",
            "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
@@ -41,7 +43,8 @@ class ChainCfg(C.Structure):
                 ("leaf", C.c_int32), ("tol", C.c_double), ("tau0", C.c_double),
                 ("sigf2_0", C.c_double), ("a1", C.c_double), ("b1", C.c_double),
                 ("a2", C.c_double), ("b2", C.c_double), ("grid_size", C.c_int32),
-                ("grid_center", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64)]
+                ("grid_center", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("precision", C.c_int32)]
 
 
 class ChainSnapshot(C.Structure):
@@ -50,7 +53,8 @@ class ChainSnapshot(C.Structure):
                 ("last_accept", C.c_int32), ("accepts", C.c_int32), ("logdet_sigma", C.c_double),
                 ("yr", C.c_double), ("loglik", C.c_double), ("sse", C.c_double),
                 ("q", C.c_double), ("logdet1", C.c_double), ("mh_log_ratio", C.c_double),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("pcg_iters", C.c_int32), ("pcg_relres", C.c_double),
+                ("precision_used", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,6 +108,9 @@ def lib():
         "hodlr_entries": ([P, DP, DP, I64, DP, P], I32),
         "hodlr_matvec": ([P, D, D, DP, DP, I32, I64, P], I32),
         "hodlr_factor": ([P, D, D, DP, P, C.POINTER(P)], I32),
+        "hodlr_factor_prec": ([P, D, D, DP, I32, P, C.POINTER(P)], I32),
+        "hodlr_solve_refined": ([P, P, D, D, DP, DP, I32, I64, D, I32, C.POINTER(I32),
+                                 C.POINTER(D), P], I32),
         "hodlr_solve": ([P, DP, DP, I32, I64, P], I32),
         "hodlr_logdet": ([P, DP, P], I32),
         "hodlr_apply_w": ([P, I32, I32, DP, DP, I32, I64, P], I32),

@@ -6,6 +6,7 @@
 #include "fg_internal.h"
 #include "fg_rng.h"
 #include "fg_tensor.h"
+#include "fg_pcg.h"
 
 namespace fg {
 static thread_local std::string g_err;
@@ -152,16 +153,17 @@ fg_status hodlr_matvec(fg_hodlr A, double alpha, double beta, const double* v, d
   return check_launch("hodlr_matvec");
 }
 
-fg_status hodlr_factor(fg_hodlr A, double alpha, double beta, const double* diag,
-                       fg_stream stream, fg_factor* out) {
+fg_status hodlr_factor_prec(fg_hodlr A, double alpha, double beta, const double* diag,
+                            int32_t precision, fg_stream stream, fg_factor* out) {
   if (!out) return fail(FG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!A) return fail(FG_EINVAL, "NULL handle");
+  if (precision != FG_FP64 && precision != FG_MIXED) return fail(FG_EINVAL, "bad precision");
   if (!(alpha > 0.0) || !(beta >= 0.0) || !std::isfinite(alpha) || !std::isfinite(beta))
     return fail(FG_EINVAL, "alpha must be > 0 and beta >= 0");
   std::string err;
   fg_factor_s* F = new fg_factor_s();
-  fg_status st = fg::factor_alloc(F->d, A->caps, err);
+  fg_status st = fg::factor_alloc(F->d, A->caps, err, precision == FG_MIXED);
   if (st != FG_OK) { delete F; return fail(st, err); }
   F->n = A->pk->P.n;
   if (hipMalloc(reinterpret_cast<void**>(&F->vecs), sizeof(double) * 4 * (size_t)F->n) != hipSuccess) {
@@ -175,6 +177,33 @@ fg_status hodlr_factor(fg_hodlr A, double alpha, double beta, const double* diag
   if ((st = check_launch("hodlr_factor")) != FG_OK) { factor_destroy(F); return st; }
   *out = F;
   return FG_OK;
+}
+
+fg_status hodlr_factor(fg_hodlr A, double alpha, double beta, const double* diag,
+                       fg_stream stream, fg_factor* out) {
+  return hodlr_factor_prec(A, alpha, beta, diag, FG_FP64, stream, out);
+}
+
+fg_status hodlr_solve_refined(fg_hodlr A, fg_factor F, double alpha, double beta,
+                              const double* b, double* x, int32_t nrhs, int64_t ld, double rtol,
+                              int32_t maxit, int32_t* iters, double* relres, fg_stream stream) {
+  if (!A || !F || !b || !x) return fail(FG_EINVAL, "NULL argument");
+  const int n = A->pk->P.n;
+  if (F->n != n || F->d.H != &A->d) return fail(FG_EINVAL, "F is not a factor of A");
+  if (nrhs < 1 || nrhs > fg::NRHS_PCG || ld < n) return fail(FG_EINVAL, "bad nrhs or ld");
+  if (!(rtol > 0.0) || maxit < 1) return fail(FG_EINVAL, "rtol must be > 0 and maxit >= 1");
+  if (!(alpha > 0.0) || !(beta >= 0.0)) return fail(FG_EINVAL, "alpha must be > 0, beta >= 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  fg::PcgWork w;
+  std::string err;
+  fg_status st = fg::pcg_alloc(w, n, err);
+  if (st != FG_OK) return fail(st, err);
+  st = fg::pcg_solve(A->d, alpha, nullptr, beta, F->d, b, x, nrhs, int(ld), rtol, maxit, w, s,
+                     iters, relres, err);
+  (void)hipStreamSynchronize(s);
+  fg::pcg_free(w);
+  if (st != FG_OK) return fail(st, err);
+  return check_launch("hodlr_solve_refined");
 }
 
 fg_status hodlr_solve(fg_factor F, const double* b, double* x, int32_t nrhs, int64_t ld,

@@ -4,6 +4,7 @@
 // suggests).  The chain keeps two slots of (K~_1, W_1) -- the current length-scale and
 // the proposal -- and swaps them on acceptance; all plans of the grid are made and
 // uploaded once, so a sweep only enqueues kernels and synchronises once at its end.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <string>
@@ -11,6 +12,7 @@
 
 #include "fg_internal.h"
 #include "fg_rng.h"
+#include "fg_pcg.h"
 #include "fg_timer.h"
 
 struct fg_chain_s {
@@ -30,11 +32,20 @@ struct fg_chain_s {
   double* dotwork = nullptr;  // reduction partials
   fg::DevState* st = nullptr;
   fg::DevState* st_host = nullptr;  // pinned
+  bool mixed = false;                         // FP32 factor of M~ + PCG refinement
+  bool fell_back = false;                     // M~ moved to FP64 after an FP32 failure
+  fg::FactorData WM64;                        // FP64 factor of M~ used after the fallback
+  fg::PcgWork pcg;
+  int pcg_iters = 0;
+  double pcg_relres = 0.0;
+  bool pcg_failed = false;
   std::map<uint64_t, hipGraphExec_t> graphs;  // captured sweeps by (cur, k, proposal)
   std::vector<uint64_t> graph_order;          // insertion order, for eviction
 };
 
 constexpr size_t GRAPH_CACHE = 48;  // captured sweeps kept per chain
+constexpr double PCG_RTOL = 1e-10;  // relative residual of the mixed-precision solves
+constexpr int PCG_MAXIT = 30;
 
 using fg::set_error;
 
@@ -47,8 +58,10 @@ static void chain_free(fg_chain c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   fg::factor_free(c->WM);
+  fg::factor_free(c->WM64);
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
   double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork};
   for (double* b : bufs)
@@ -89,19 +102,53 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   const int cur = c->cur, oth = 1 - cur;
   fg::launch_sweep_begin(c->st, s);
   // f | -  (Algorithm 1)
-  c->WM.H = &c->H[cur];
-  c->WM.alpha = 0.0;  // taken from the device scalar
-  c->WM.beta = 1.0;
-  fg::launch_factor(c->WM, &c->st->alphaM, nullptr, nullptr, s);
-  hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
+  WM.H = &c->H[cur];
+  WM.alpha = 0.0;  // taken from the device scalar
+  WM.beta = 1.0;
+  fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
+  hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
   fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
   fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
   fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
   fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
   fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
   fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
-  fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
-  fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
+  if (c->mixed && !c->fell_back) {
+    // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
+    // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
+    // residual test comes after as many iterations as the last draw needed.
+    std::string err;
+    const int min_it = std::max(1, c->pcg_iters);
+    const fg_status st = fg::pcg_solve(c->H[cur], 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
+                                       PCG_RTOL, PCG_MAXIT, c->pcg, s, &c->pcg_iters,
+                                       &c->pcg_relres, err, min_it);
+    if (st == FG_OK) {
+      hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    } else {
+      // kappa(M~) u32 ~ 1: the FP32 factor is no preconditioner.  M~ is factored in FP64
+      // from now on (this draw included); the right-hand sides in v2, v3 are intact.
+      c->fell_back = true;
+      c->pcg_iters = 0;
+      c->pcg_relres = 0.0;
+      (void)hipStreamSynchronize(s);
+      std::string e2;
+      if (fg::factor_alloc(c->WM64, c->caps, e2) != FG_OK) {
+        c->pcg_failed = true;
+      } else {
+        c->WM64.H = &c->H[cur];
+        c->WM64.alpha = 0.0;
+        c->WM64.beta = 1.0;
+        fg::launch_factor(c->WM64, &c->st->alphaM, nullptr, nullptr, s);
+        hipMemcpyAsync(&c->st->logdetM, c->WM64.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+        fg::launch_apply_w(c->WM64, 2, v2, 2, n, c->WM64.work, s);
+        fg::launch_apply_w(c->WM64, 3, v2, 2, n, c->WM64.work, s);
+      }
+    }
+  } else {
+    fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
+    fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
+  }
   fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
                     c->H[cur].work, s);
   fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
@@ -238,7 +285,13 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
       return cfail(st, err);
     }
   }
-  if ((st = fg::factor_alloc(c->WM, c->caps, err)) != FG_OK) { chain_free(c); return cfail(st, err); }
+  if (cfg->precision != FG_FP64 && cfg->precision != FG_MIXED) {
+    chain_free(c);
+    return cfail(FG_EINVAL, "bad precision");
+  }
+  c->mixed = cfg->precision == FG_MIXED;
+  if ((st = fg::factor_alloc(c->WM, c->caps, err, c->mixed)) != FG_OK) { chain_free(c); return cfail(st, err); }
+  if (c->mixed && (st = fg::pcg_alloc(c->pcg, int(n), err)) != FG_OK) { chain_free(c); return cfail(st, err); }
   const size_t nb = sizeof(double) * (size_t)n;
   if (hipMalloc(reinterpret_cast<void**>(&c->x), nb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
@@ -316,7 +369,7 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
       fg_chain c = chains[i];
       hipStream_t q = g_batch.s[i % nstreams];
       pr[i] = propose(c);
-      if (!graphs) {
+      if (!graphs || c->mixed) {
         enqueue_sweep(c, pr[i], q);
         continue;
       }
@@ -348,7 +401,7 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
   int hs = 0, ws = 0, ms = 0;
   hipMemcpy(&hs, c->H[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
   hipMemcpy(&ws, c->W[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
-  hipMemcpy(&ms, c->WM.status, sizeof(int), hipMemcpyDeviceToHost);
+  hipMemcpy(&ms, (c->fell_back ? c->WM64 : c->WM).status, sizeof(int), hipMemcpyDeviceToHost);
   fst = c->st_host->status | hs | ws | ms;
   const fg::DevState& d = *c->st_host;
   host_out->iteration = c->iter;
@@ -367,6 +420,10 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
   host_out->logdet1 = d.logdet1;
   host_out->mh_log_ratio = d.mh;
   host_out->status = (fst & fg::ST_NOTSPD) ? FG_ENOTSPD : (fst & fg::ST_NOTCONV) ? FG_ENOTCONV : FG_OK;
+  if (host_out->status == FG_OK && c->pcg_failed) host_out->status = FG_ENOTCONV;
+  host_out->pcg_iters = c->pcg_iters;
+  host_out->pcg_relres = c->pcg_relres;
+  host_out->precision_used = (c->mixed && !c->fell_back) ? FG_MIXED : FG_FP64;
   return FG_OK;
 }
 

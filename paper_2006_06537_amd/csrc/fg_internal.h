@@ -132,6 +132,10 @@ struct HodlrData {
 struct FactorData {
   const HodlrData* H = nullptr;
   double alpha = 1, beta = 0;
+  bool fp32 = false;           // leaf factors and whitened panels held in FP32
+  float* leafLf = nullptr;     // FP32 copies of leafL / leafLinv / panel (fp32 only)
+  float* leafLinvf = nullptr;
+  float* panelf = nullptr;
   double* leafL = nullptr;     // nleaf x B x B
   double* leafLinv = nullptr;  // nleaf x B x B
   double* leaf_ld = nullptr;   // nleaf
@@ -155,7 +159,7 @@ struct Caps {
 };
 fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err);
 void hodlr_free(HodlrData& H);
-fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err);
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32 = false);
 void factor_free(FactorData& F);
 
 // -------- kernels' host launchers (stream-ordered) --------

@@ -27,8 +27,10 @@ __device__ __forceinline__ double wave_red(double v) {
 }
 
 // leaf block operator, in place on v: op 0 L, 1 L', 2 Linv, 3 Linv'
+// (factor data of precision T; vectors and arithmetic in FP64)
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
-                                                         const double* __restrict__ M, int Bc,
+                                                         const T* __restrict__ M, int Bc,
                                                          int trans, double* __restrict__ v,
                                                          int nrhs, int ld) {
   const int b = blockIdx.x;
@@ -38,23 +40,24 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__
   for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
     vs[idx / m][idx % m] = v[(size_t)(idx / m) * ld + lo + idx % m];
   __syncthreads();
-  const double* Mb = M + (size_t)b * Bc * Bc;
+  const T* Mb = M + (size_t)b * Bc * Bc;
   for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS) {
     const int r = idx % m, c = idx / m;
     double acc = 0.0;
     if (!trans) {
-      for (int s = 0; s <= r; ++s) acc += Mb[r + s * Bc] * vs[c][s];
+      for (int s = 0; s <= r; ++s) acc += (double)Mb[r + s * Bc] * vs[c][s];
     } else {
-      for (int s = r; s < m; ++s) acc += Mb[s + r * Bc] * vs[c][s];
+      for (int s = r; s < m; ++s) acc += (double)Mb[s + r * Bc] * vs[c][s];
     }
     v[(size_t)c * ld + lo + r] = acc;
   }
 }
 
 // level reduce with a vector right operand: z[t][a][c] = sum_rows P[i, coff + a] v[i, c]
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
-    const int* __restrict__ coff, const int* __restrict__ kmax, const double* __restrict__ P,
+    const int* __restrict__ coff, const int* __restrict__ kmax, const T* __restrict__ P,
     int K, const double* __restrict__ v, int nrhs, int ldv, double* __restrict__ zpart,
     int zs_task) {
   const int t = blockIdx.x;
@@ -71,7 +74,7 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
   for (int a = wv; a < kl; a += NTHREADS / 64) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
     for (int i = lane; i < rw; i += 64) {
-      const double pv = P[pix(tk.r0 + i, c0 + a, K)];
+      const double pv = (double)P[pix(tk.r0 + i, c0 + a, K)];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * vs[c][i];
     }
     for (int c = 0; c < nrhs; ++c) {
@@ -166,10 +169,11 @@ __global__ void __launch_bounds__(64) k_node_coef(
 }
 
 // v[rows of side] += P[rows, coff + a] coef_side[a][c]
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_update_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
     int hbase, const int* __restrict__ rank, const int* __restrict__ coff,
-    const double* __restrict__ P, int K, double* __restrict__ v, int nrhs, int ldv,
+    const T* __restrict__ P, int K, double* __restrict__ v, int nrhs, int ldv,
     const double* __restrict__ coef, int cs_node, int skip_left) {
   const int t = blockIdx.x;
   if (t >= ntask) return;
@@ -186,7 +190,7 @@ __global__ void __launch_bounds__(NTHREADS) k_update_vec(
   for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
     for (int a = 0; a < k; ++a) {
-      const double pv = P[pix(r, cb + a, K)];
+      const double pv = (double)P[pix(r, cb + a, K)];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * cs[a * nrhs + c];
     }
     for (int c = 0; c < nrhs; ++c) v[(size_t)c * ldv + r] += acc[c];
@@ -257,8 +261,9 @@ size_t matvec_work_doubles(const HostPlan& P, int nrhs) {
   return zp + 2 * cf;
 }
 
-static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int ld, double* work,
-                        hipStream_t s) {
+template <typename T>
+static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v, int nrhs, int ld,
+                        double* work, hipStream_t s) {
   const HodlrData& H = *F.H;
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
@@ -268,8 +273,8 @@ static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int l
   double* coef = work + (size_t)std::max(P.max_ltasks, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   const int hbase = (1 << l) - 1;
-  k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, F.panel,
-                                       P.Ktot, v, nrhs, ld, zpart, zs_task);
+  k_reduce_vec<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, panel,
+                                          P.Ktot, v, nrhs, ld, zpart, zs_task);
   double* zs = nullptr;
   if (P.max_tps[l] > 1) {
     zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
@@ -279,30 +284,37 @@ static void sweep_level(FactorData& F, int op, int l, double* v, int nrhs, int l
                                     zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr, coef,
                                     cs_node, zs);
   const int skip_left = (op == 0 || op == 2) ? 1 : 0;
-  k_update_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
-                                       F.panel, P.Ktot, v, nrhs, ld, coef, cs_node, skip_left);
+  k_update_vec<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
+                                          panel, P.Ktot, v, nrhs, ld, coef, cs_node, skip_left);
 }
 
-void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
-                    hipStream_t s) {
+template <typename T>
+static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const T* panel, int op,
+                    double* v, int nrhs, int ld, double* work, hipStream_t s) {
   const HostPlan& P = F.H->pk->P;
   const int* leaf_lo = F.H->pk->D.leaf_lo;
   // W = L_D W_(L-1) ... W_(0)
   if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
-    for (int l = 0; l < P.L; ++l) sweep_level(F, 0, l, v, nrhs, ld, work, s);
-    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafL, P.B, 0, v, nrhs, ld);
+    for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 0, l, v, nrhs, ld, work, s);
+    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, P.B, 0, v, nrhs, ld);
   } else if (op == 1) {   // W' v = W_(0)' ... W_(L-1)' L_D' v
-    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafL, P.B, 1, v, nrhs, ld);
-    for (int l = P.L - 1; l >= 0; --l) sweep_level(F, 1, l, v, nrhs, ld, work, s);
+    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, P.B, 1, v, nrhs, ld);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 1, l, v, nrhs, ld, work, s);
   } else if (op == 2) {   // W^-1 v = W_(0)^-1 ... W_(L-1)^-1 L_D^-1 v
-    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafLinv, P.B, 0, v, nrhs,
-                                             ld);
-    for (int l = P.L - 1; l >= 0; --l) sweep_level(F, 2, l, v, nrhs, ld, work, s);
+    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafLinv, P.B, 0, v, nrhs, ld);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 2, l, v, nrhs, ld, work, s);
   } else {                // W^-T v = L_D^-T W_(L-1)^-T ... W_(0)^-T v
-    for (int l = 0; l < P.L; ++l) sweep_level(F, 3, l, v, nrhs, ld, work, s);
-    k_leaf_apply<<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, F.leafLinv, P.B, 1, v, nrhs,
-                                             ld);
+    for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 3, l, v, nrhs, ld, work, s);
+    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafLinv, P.B, 1, v, nrhs, ld);
   }
+}
+
+void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
+                    hipStream_t s) {
+  if (F.fp32)
+    apply_w<float>(F, F.leafLf, F.leafLinvf, F.panelf, op, v, nrhs, ld, work, s);
+  else
+    apply_w<double>(F, F.leafL, F.leafLinv, F.panel, op, v, nrhs, ld, work, s);
 }
 
 void launch_matvec(const HodlrData& H, double alpha, double beta, const double* alpha_dev,
@@ -316,7 +328,7 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
   double* coef = work + (size_t)std::max(nt, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   if (P.L > 0) {
-    k_reduce_vec<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel,
+    k_reduce_vec<double><<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel,
                                          P.Ktot, v, nrhs, ld, zpart, zs_task);
     double* zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
     launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task, s);

@@ -48,40 +48,41 @@ constexpr int LPD = 17;       // LDS pitch of 16-wide rows
 // wave 0: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD); writes L into
 // Lk and L^-1 into Lik (LDS, pitch LPD, zero upper triangles); returns the sum of the
 // log pivots (all lanes) and flags a non-positive pivot.
-__device__ double diag_factor16(const double* Dk, double* Lk, double* Lik, bool& bad) {
+template <typename T>
+__device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  double d[4], x[4];
+  T d[4], x[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     d[v] = Dk[r * LPD + 4 * g + v];
-    x[v] = (r == 4 * g + v) ? 1.0 : 0.0;
+    x[v] = (r == 4 * g + v) ? T(1) : T(0);
   }
   double ls = 0.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int gj = j >> 2, vj = j & 3;
-    const double colv = d[vj];
-    const double piv = __shfl(colv, j + 16 * gj, 64);
-    const bool ok = piv > 0.0;
+    const T colv = d[vj];
+    const T piv = __shfl(colv, j + 16 * gj, 64);
+    const bool ok = piv > T(0);
     bad |= !ok;
-    const double inv = ok ? 1.0 / sqrt(piv) : 1.0;
-    ls += ok ? log(piv) : 0.0;
-    const double lrj = __shfl(colv, r + 16 * gj, 64) * inv;
-    double lcj[4];
+    const T inv = ok ? T(1) / sqrt(piv) : T(1);
+    ls += ok ? log((double)piv) : 0.0;
+    const T lrj = __shfl(colv, r + 16 * gj, 64) * inv;
+    T lcj[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) lcj[v] = __shfl(colv, 4 * g + v + 16 * gj, 64) * inv;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       if (r > j && 4 * g + v > j) d[v] -= lrj * lcj[v];
-    if (g == gj) d[vj] = (r >= j) ? lrj : 0.0;
+    if (g == gj) d[vj] = (r >= j) ? lrj : T(0);
   }
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int gj = j >> 2, vj = j & 3;
-    const double ljj = __shfl(d[vj], j + 16 * gj, 64);
-    const double lrj = __shfl(d[vj], r + 16 * gj, 64);
-    double xj[4];
+    const T ljj = __shfl(d[vj], j + 16 * gj, 64);
+    const T lrj = __shfl(d[vj], r + 16 * gj, 64);
+    T xj[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) xj[v] = __shfl(x[v], j + 16 * g, 64) / ljj;
 #pragma unroll
@@ -93,19 +94,20 @@ __device__ double diag_factor16(const double* Dk, double* Lk, double* Lik, bool&
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = 4 * g + v;
-    Lk[r * LPD + c] = (c <= r) ? d[v] : 0.0;
-    Lik[r * LPD + c] = (c <= r) ? x[v] : 0.0;
+    Lk[r * LPD + c] = (c <= r) ? d[v] : T(0);
+    Lik[r * LPD + c] = (c <= r) ? x[v] : T(0);
   }
   return ls;
 }
 
 // y (rows 16 i + tr, columns tc + 16 q of a 64-column block) <- L^-1 y, blocks kb0..nb-1.
 // Likk: the 8 inverted diagonal blocks; Lp: 2 x 128 x LPD scratch; Yk, Yh: 16 x 65 each.
-__device__ __forceinline__ void leaf_trsm_blk(const double (&a)[LE][LE], double (&y)[LE][YQ],
-                                              int nb, int kb0, const double* Likk, double* Lp,
-                                              double* Yk, double* Yh, int tr, int tc) {
+template <typename T>
+__device__ __forceinline__ void leaf_trsm_blk(const T (&a)[LE][LE], T (&y)[LE][YQ], int nb,
+                                              int kb0, const T* Likk, T* Lp, T* Yk, T* Yh, int tr,
+                                              int tc) {
   for (int kb = kb0; kb < nb; ++kb) {
-    double* L2 = Lp + (kb & 1) * (BMAX * LPD);
+    T* L2 = Lp + (kb & 1) * (BMAX * LPD);
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       if (i == kb) {
@@ -119,13 +121,13 @@ __device__ __forceinline__ void leaf_trsm_blk(const double (&a)[LE][LE], double 
       }
     }
     __syncthreads();
-    const double* Li = Likk + kb * (16 * LPD);
-    double yh[YQ];
+    const T* Li = Likk + kb * (16 * LPD);
+    T yh[YQ];
 #pragma unroll
-    for (int q = 0; q < YQ; ++q) yh[q] = 0.0;
+    for (int q = 0; q < YQ; ++q) yh[q] = T(0);
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      const double lv = Li[tr * LPD + t];
+      const T lv = Li[tr * LPD + t];
 #pragma unroll
       for (int q = 0; q < YQ; ++q) yh[q] += lv * Yk[t * 65 + tc + LG * q];
     }
@@ -143,7 +145,7 @@ __device__ __forceinline__ void leaf_trsm_blk(const double (&a)[LE][LE], double 
       if (i > kb && i < nb) {
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-          const double lr = L2[(LG * i + tr) * LPD + t];
+          const T lr = L2[(LG * i + tr) * LPD + t];
 #pragma unroll
           for (int q = 0; q < YQ; ++q) y[i][q] -= lr * Yh[t * 65 + tc + LG * q];
         }
@@ -152,12 +154,13 @@ __device__ __forceinline__ void leaf_trsm_blk(const double (&a)[LE][LE], double 
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
     double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
-    double* __restrict__ leafL, double* __restrict__ leafLinv, double* __restrict__ leaf_ld,
-    int* __restrict__ status, const double* __restrict__ src, double* __restrict__ dst, int K,
+    T* __restrict__ leafL, T* __restrict__ leafLinv, double* __restrict__ leaf_ld,
+    int* __restrict__ status, const double* __restrict__ src, T* __restrict__ dst, int K,
     const int* __restrict__ coff, const int* __restrict__ kmax, int L) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
@@ -168,20 +171,20 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   // LDS: Likk 8 blocks | Lk | Dk | Lp (2 x 128 rows) | union{ Pp 128 rows ; Yk + Yh }
   __shared__ double xs[BMAX];
-  __shared__ double Likk[LE * 16 * LPD];
-  __shared__ double Lk[16 * LPD];
-  __shared__ double Dk[16 * LPD];
-  __shared__ double Lp[2 * BMAX * LPD];
-  __shared__ double U[BMAX * LPD];  // Pp during the factorization, Yk | Yh afterwards
-  double* Pp = U;
-  double* Yk = U;
-  double* Yh = U + 16 * 65;
+  __shared__ T Likk[LE * 16 * LPD];
+  __shared__ T Lk[16 * LPD];
+  __shared__ T Dk[16 * LPD];
+  __shared__ T Lp[2 * BMAX * LPD];
+  __shared__ T U[BMAX * LPD];  // Pp during the factorization, Yk | Yh afterwards
+  T* Pp = U;
+  T* Yk = U;
+  T* Yh = U + 16 * 65;
   __shared__ int bad;
   __shared__ double ldsum;
   if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
   for (int r = threadIdx.x; r < m; r += NTHREADS) xs[r] = x[lo + r];
   __syncthreads();
-  double a[LE][LE];
+  T a[LE][LE];
 #pragma unroll
   for (int i = 0; i < LE; ++i) {
     const int r = LG * i + tr;
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
         v = alpha * kern1(kind, ell, xs[r], xs[c]);
         if (r == c) v += alpha * nugget + beta + (diag ? diag[lo + r] : 0.0);
       }
-      a[i][jj] = v;
+      a[i][jj] = (T)v;  // entries are formed in FP64 and stored in T
     }
   }
   // blocked Cholesky
@@ -217,8 +220,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       if (wb) bad = 1;
     }
     __syncthreads();
-    const double* Li = Likk + kb * (16 * LPD);
-    double* L1 = Lp;
+    const T* Li = Likk + kb * (16 * LPD);
+    T* L1 = Lp;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       if (i == kb) {
@@ -228,7 +231,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       }
       if (i > kb && i < nb) {
         // L[i][kb] = A[i][kb] L_kk^-T : row (16 i + tr) of the panel times column tc of Li'
-        double s = 0.0;
+        T s = T(0);
 #pragma unroll
         for (int t = 0; t < 16; ++t) s += Pp[(LG * i + tr) * LPD + t] * Li[tc * LPD + t];
 #pragma unroll
@@ -240,11 +243,11 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      double lr[LE], lc[LE];
+      T lr[LE], lc[LE];
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
-        lr[i] = (i > kb && i < nb) ? L1[(LG * i + tr) * LPD + t] : 0.0;
-        lc[i] = (i > kb && i < nb) ? L1[(LG * i + tc) * LPD + t] : 0.0;
+        lr[i] = (i > kb && i < nb) ? L1[(LG * i + tr) * LPD + t] : T(0);
+        lc[i] = (i > kb && i < nb) ? L1[(LG * i + tc) * LPD + t] : T(0);
       }
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
@@ -263,24 +266,24 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   }
   (void)mybad;
   // L to global (lower triangle, column-major, ld = Bc); rows/cols beyond m untouched
-  double* Lg = leafL + (size_t)b * Bc * Bc;
+  T* Lg = leafL + (size_t)b * Bc * Bc;
 #pragma unroll
   for (int jj = 0; jj < LE; ++jj) {
     const int c = LG * jj + tc;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       const int r = LG * i + tr;
-      if (r < m && c < m) Lg[r + (size_t)c * Bc] = (c <= r) ? a[i][jj] : 0.0;
+      if (r < m && c < m) Lg[r + (size_t)c * Bc] = (c <= r) ? a[i][jj] : T(0);
     }
   }
   // L^-1 by blocked substitution on identity columns, 64 columns per pass
-  double* Lig = leafLinv + (size_t)b * Bc * Bc;
+  T* Lig = leafLinv + (size_t)b * Bc * Bc;
   for (int c0 = 0; c0 < m; c0 += 64) {
-    double y[LE][YQ];
+    T y[LE][YQ];
 #pragma unroll
     for (int i = 0; i < LE; ++i)
 #pragma unroll
-      for (int q = 0; q < YQ; ++q) y[i][q] = (LG * i + tr == c0 + tc + LG * q) ? 1.0 : 0.0;
+      for (int q = 0; q < YQ; ++q) y[i][q] = (LG * i + tr == c0 + tc + LG * q) ? T(1) : T(0);
     __syncthreads();
     leaf_trsm_blk(a, y, nb, c0 >> 4, Likk, Lp, Yk, Yh, tr, tc);
 #pragma unroll
@@ -289,13 +292,13 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         const int r = LG * i + tr;
-        if (r < m && c < m) Lig[r + (size_t)c * Bc] = (c <= r) ? y[i][q] : 0.0;
+        if (r < m && c < m) Lig[r + (size_t)c * Bc] = (c <= r) ? y[i][q] : T(0);
       }
     }
   }
   // whitening of all panel rows of this leaf: dst = sqrt(alpha) L^-1 src.  The active
   // columns of all levels are numbered 0..total-1 and handled 64 per pass.
-  const double sa = sqrt(alpha);
+  const T sa = (T)sqrt(alpha);
   int total = 0;
   for (int l = 0; l < L; ++l) total += kmax[l];
   for (int p0 = 0; p0 < total; p0 += 64) {
@@ -312,13 +315,13 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
         }
       }
     }
-    double y[LE][YQ];
+    T y[LE][YQ];
 #pragma unroll
     for (int q = 0; q < YQ; ++q) {
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         const int r = LG * i + tr;
-        y[i][q] = (gcq[q] >= 0 && r < m) ? src[pix(lo + r, gcq[q], K)] : 0.0;
+        y[i][q] = (gcq[q] >= 0 && r < m) ? (T)src[pix(lo + r, gcq[q], K)] : T(0);
       }
     }
     __syncthreads();
@@ -346,16 +349,38 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 // (coalesced along rows); each wave owns 16 right columns and all left tiles.
 // ---------------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// one 16 x 16 x 4 MFMA step in the precision of the panel, and the accumulator row of
+// (lane group kg, register v): f64 puts row kg + 4 v in register v, f32 row 4 kg + v
+// (both layouts checked on gfx950)
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kg, int v) { return kg + 4 * v; }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kg, int v) { return 4 * kg + v; }
+};
 
 // Each wave owns 16 right columns of one task and every 16-column left tile; it walks
 // the task's rows 16 at a time with no LDS and no barrier.  For step s (0..3) of a
 // 16-row group, K-slot k holds row base + 4k + s, so lane l reads rows base + 4 (l/16)
 // .. +3 of its column: 32 contiguous bytes, and the four steps use each 128-byte line
 // of the 16-row tile completely.
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
     const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ coff,
     const int* __restrict__ kmax, const int* __restrict__ rcols, const int* __restrict__ rcount,
-    int K, const double* __restrict__ P, double* __restrict__ zpart, int zs_a, int zs_task) {
+    int K, const T* __restrict__ P, double* __restrict__ zpart, int zs_a, int zs_task) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const int t = blockIdx.x;
   if (t >= ntask) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -370,41 +395,40 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
   int acol[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acol[q] = (q * 16 + cl < kl) ? c0 + q * 16 + cl : -1;
-  d4 acc[4];
+  acc_t acc[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 4; ++q) acc[q] = acc_t{T(0), T(0), T(0), T(0)};
   const bool aligned = ((tk.r0 | tk.r1) & 15) == 0;
   for (int base = tk.r0; base < tk.r1; base += 16) {
-    double bv[4];
+    T bv[4];
     if (aligned) {
-      const double* pb = P + pix(base + 4 * kg, gcb < 0 ? 0 : gcb, K);
+      const T* pb = P + pix(base + 4 * kg, gcb < 0 ? 0 : gcb, K);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) bv[s] = gcb >= 0 ? pb[s] : 0.0;
+      for (int s = 0; s < 4; ++s) bv[s] = gcb >= 0 ? pb[s] : T(0);
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int row = base + 4 * kg + s;
-        bv[s] = (gcb >= 0 && row < tk.r1) ? P[pix(row, gcb, K)] : 0.0;
+        bv[s] = (gcb >= 0 && row < tk.r1) ? P[pix(row, gcb, K)] : T(0);
       }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (q < na) {
-        double av[4];
+        T av[4];
         if (aligned) {
-          const double* pa = P + pix(base + 4 * kg, acol[q] < 0 ? 0 : acol[q], K);
+          const T* pa = P + pix(base + 4 * kg, acol[q] < 0 ? 0 : acol[q], K);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) av[s] = acol[q] >= 0 ? pa[s] : 0.0;
+          for (int s = 0; s < 4; ++s) av[s] = acol[q] >= 0 ? pa[s] : T(0);
         } else {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int row = base + 4 * kg + s;
-            av[s] = (acol[q] >= 0 && row < tk.r1) ? P[pix(row, acol[q], K)] : 0.0;
+            av[s] = (acol[q] >= 0 && row < tk.r1) ? P[pix(row, acol[q], K)] : T(0);
           }
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc[q], 0, 0, 0);
+        for (int s = 0; s < 4; ++s) acc[q] = Mfma<T>::step(av[s], bv[s], acc[q]);
       }
     }
   }
@@ -414,8 +438,8 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
       if (q < na) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int a = q * 16 + kg + 4 * v;
-          if (a < kl) zpart[(size_t)t * zs_task + (size_t)a * zs_a + bcol] = acc[q][v];
+          const int a = q * 16 + Mfma<T>::row(kg, v);
+          if (a < kl) zpart[(size_t)t * zs_task + (size_t)a * zs_a + bcol] = (double)acc[q][v];
         }
       }
     }
@@ -553,7 +577,7 @@ __global__ void __launch_bounds__(64) k_node_factor(
     const double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
     int zf_side, double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
     double* __restrict__ node_ld, double* __restrict__ coef, int cs_node, int cs_a,
-    int* __restrict__ status, int kc) {
+    int* __restrict__ status, int kc, double gap_floor) {
   const int j = blockIdx.x;
   const int h = (1 << l) - 1 + j;
   const int k = rank[h], kl = kmax[l], W = rcount[l], Wc = W - kl;
@@ -617,7 +641,14 @@ __global__ void __launch_bounds__(64) k_node_factor(
     bool spd = true;
     for (int a = 0; a < k; ++a) {
       double s2 = fmax(Hm[a + a * kc], 0.0);
-      if (!(s2 < 1.0)) { spd = false; s2 = 1.0 - DBL_EPSILON; }
+      if (gap_floor > 0.0) {
+        // FP32 panels: 1 - s^2 below their resolution is noise; the floor keeps the
+        // (preconditioner) factor SPD
+        s2 = fmin(s2, 1.0 - gap_floor);
+      } else if (!(s2 < 1.0)) {
+        spd = false;
+        s2 = 1.0 - DBL_EPSILON;
+      }
       const double d = sqrt(1.0 - s2);
       g1[a] = -1.0 / (1.0 + d);
       g2[a] = 1.0 / (d * (1.0 + d));
@@ -679,10 +710,11 @@ __global__ void __launch_bounds__(64) k_node_factor(
 // tile (k x 64 columns) is broadcast from LDS, and every coarser column is read and
 // written once, coalesced along rows.
 // ---------------------------------------------------------------------------------
+template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_update_panel(
     const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ rank,
     const int* __restrict__ coff, const int* __restrict__ kmax, const int* __restrict__ rcols,
-    const int* __restrict__ rcount, int K, double* __restrict__ P, int unused_ld,
+    const int* __restrict__ rcount, int K, T* __restrict__ P, int unused_ld,
     const double* __restrict__ coef, int cs_node, int cs_a) {
   const int Ktot = K;
   (void)unused_ld;
@@ -697,7 +729,7 @@ __global__ void __launch_bounds__(NTHREADS) k_update_panel(
   const int j = tk.h - ((1 << l) - 1);
   const int* yc = rcols + (size_t)l * Ktot + kl;
   const double* cf = coef + (size_t)j * cs_node;
-  __shared__ double As[64][64];
+  __shared__ T As[64][64];
   __shared__ int ycol[64];
   for (int bt = 0; bt < Wc; bt += 64) {
     const int bw = min(64, Wc - bt);
@@ -705,17 +737,17 @@ __global__ void __launch_bounds__(NTHREADS) k_update_panel(
     const int k16 = (k + 15) & ~15;  // rows read by the 16-wide register blocks
     for (int idx = threadIdx.x; idx < k16 * 64; idx += NTHREADS) {
       const int a = idx >> 6, b = idx & 63;
-      As[a][b] = (a < k && b < bw) ? cf[(size_t)a * cs_a + bt + b] : 0.0;
+      As[a][b] = (a < k && b < bw) ? (T)cf[(size_t)a * cs_a + bt + b] : T(0);
     }
     if (threadIdx.x < 64) ycol[threadIdx.x] = threadIdx.x < bw ? yc[bt + threadIdx.x] : 0;
     __syncthreads();
     for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
       for (int a0 = 0; a0 < k; a0 += 16) {
-        double v[16];
+        T v[16];
 #pragma unroll
-        for (int a = 0; a < 16; ++a) v[a] = (a0 + a < k) ? P[pix(r, c0 + a0 + a, K)] : 0.0;
+        for (int a = 0; a < 16; ++a) v[a] = (a0 + a < k) ? P[pix(r, c0 + a0 + a, K)] : T(0);
         for (int b = 0; b < bw; ++b) {
-          double acc = 0.0;
+          T acc = T(0);
 #pragma unroll
           for (int a = 0; a < 16; ++a) acc += v[a] * As[a0 + a][b];
           P[pix(r, ycol[b], K)] += acc;
@@ -747,20 +779,22 @@ __global__ void k_logdet_sum(const double* __restrict__ leaf_ld, int nleaf,
 // ---------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------
-void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
-                   const double* diag, hipStream_t s) {
+// floor on 1 - s^2 of a node whose panels are held in FP32 (16 FP32 ulps of 1)
+constexpr double GAP_FLOOR_FP32 = 16.0 * 5.9604644775390625e-08;
+
+template <typename T>
+static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const double* alpha_dev,
+                          const double* beta_dev, const double* diag, hipStream_t s) {
   const HodlrData& H = *F.H;
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
   const int Bc = P.B;
   timer_before(KID_LEAF, s, -1, P, H.kmax, 0);
-  k_leaf<<<P.nleaf, NTHREADS, 0, s>>>(
+  k_leaf<T><<<P.nleaf, NTHREADS, 0, s>>>(
       D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
-      diag, Bc, F.leafL, F.leafLinv, F.leaf_ld, F.status, H.panel, F.panel, P.Ktot, D.coff, H.kmax,
+      diag, Bc, leafL, leafLinv, F.leaf_ld, F.status, H.panel, panel, P.Ktot, D.coff, H.kmax,
       P.L);
   timer_after(KID_LEAF, s);
-  const int kcm = std::max(P.kcapmax, 1);
-  const size_t lds_max = sizeof(double) * 5 * (size_t)kcm * kcm;
   static bool lds_set = false;  // raised once to the largest size any plan can ask for
   if (!lds_set) {
     (void)hipFuncSetAttribute((const void*)k_node_factor,
@@ -768,15 +802,14 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
                               int(sizeof(double) * 5 * PMAX * PMAX));
     lds_set = true;
   }
-
   for (int l = P.L - 1; l >= 0; --l) {
     const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
     const int Wcap = P.coff[l + 1];  // columns of levels <= l (capacity)
     const int zs_a = Wcap, zs_task = P.kcap[l] * Wcap;
     timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
     const dim3 grid_r(nt, (Wcap + 63) / 64);
-    k_reduce_panel<<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
-                                               H.rcount, P.Ktot, F.panel, F.zpart, zs_a, zs_task);
+    k_reduce_panel<T><<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
+                                                  H.rcount, P.Ktot, panel, F.zpart, zs_a, zs_task);
     timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
     launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
@@ -786,16 +819,24 @@ void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_de
     k_node_factor<<<1 << l, 64, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
-        kc);
+        kc, sizeof(T) == 4 ? GAP_FLOOR_FP32 : 0.0);
     if (l > 0) {
       timer_before(KID_UPDATE, s, l, P, H.kmax, nt);
-      k_update_panel<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
-                                             H.rcols, H.rcount, P.Ktot, F.panel, H.ld, F.coef,
-                                             cs_node, cs_a);
+      k_update_panel<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
+                                                H.rcols, H.rcount, P.Ktot, panel, H.ld, F.coef,
+                                                cs_node, cs_a);
       timer_after(KID_UPDATE, s);
     }
   }
   launch_logdet_sum(F, s);
+}
+
+void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
+                   const double* diag, hipStream_t s) {
+  if (F.fp32)
+    factor_levels<float>(F, F.leafLf, F.leafLinvf, F.panelf, alpha_dev, beta_dev, diag, s);
+  else
+    factor_levels<double>(F, F.leafL, F.leafLinv, F.panel, alpha_dev, beta_dev, diag, s);
 }
 
 void launch_logdet_sum(FactorData& F, hipStream_t s) {

@@ -9,6 +9,7 @@
 // cosine branch, acceptance uniform u2), at most 64 tries.
 #include "fg_internal.h"
 #include "fg_rng.h"
+#include "fg_pcg.h"
 
 namespace fg {
 
@@ -191,6 +192,75 @@ __global__ void k_zero_int(int* p, int n) {
 }
 void launch_zero_int(int* p, int n, hipStream_t s) {
   if (n > 0) k_zero_int<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+}
+
+}  // namespace fg
+
+// ---------------------------------------------------------------------------------
+// PCG vector steps (one thread per row, all right-hand sides)
+// ---------------------------------------------------------------------------------
+namespace fg {
+
+__global__ void k_pcg_init(int n, int nrhs, const double* __restrict__ b, int ld,
+                           double* __restrict__ x, double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nrhs; ++c) {
+    r[(size_t)c * n + i] = b[(size_t)c * ld + i];
+    x[(size_t)c * ld + i] = 0.0;
+  }
+}
+
+__global__ void k_pcg_copy(int n, int nrhs, const double* __restrict__ a, double* __restrict__ o) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nrhs; ++c) o[(size_t)c * n + i] = a[(size_t)c * n + i];
+}
+
+__global__ void k_pcg_xr(int n, int nrhs, double* __restrict__ x, int ld, double* __restrict__ r,
+                         const double* __restrict__ p, const double* __restrict__ q,
+                         const PcgScalars* __restrict__ sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nrhs; ++c) {
+    const double a = sc->pq[c] != 0.0 ? sc->rz[c] / sc->pq[c] : 0.0;
+    x[(size_t)c * ld + i] += a * p[(size_t)c * n + i];
+    r[(size_t)c * n + i] -= a * q[(size_t)c * n + i];
+  }
+}
+
+// p = z + (rz_new / rz) p; the ratio is formed before any thread can update rz, which
+// is done by a second kernel
+__global__ void k_pcg_p(int n, int nrhs, double* __restrict__ p, const double* __restrict__ z,
+                        const PcgScalars* __restrict__ sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < nrhs; ++c) {
+    const double bt = sc->rz[c] != 0.0 ? sc->rz_new[c] / sc->rz[c] : 0.0;
+    p[(size_t)c * n + i] = z[(size_t)c * n + i] + bt * p[(size_t)c * n + i];
+  }
+}
+
+__global__ void k_pcg_rz(int nrhs, PcgScalars* sc) {
+  const int c = threadIdx.x;
+  if (c < nrhs) sc->rz[c] = sc->rz_new[c];
+}
+
+static inline unsigned pblk(int n) { return (unsigned)((n + 255) / 256); }
+
+void launch_pcg_init(int n, int nrhs, const double* b, int ld, double* x, double* r, hipStream_t s) {
+  if (n > 0) k_pcg_init<<<pblk(n), 256, 0, s>>>(n, nrhs, b, ld, x, r);
+}
+void launch_pcg_copy(int n, int nrhs, const double* a, double* out, hipStream_t s) {
+  if (n > 0) k_pcg_copy<<<pblk(n), 256, 0, s>>>(n, nrhs, a, out);
+}
+void launch_pcg_xr(int n, int nrhs, double* x, int ld, double* r, const double* p, const double* q,
+                   const PcgScalars* sc, hipStream_t s) {
+  if (n > 0) k_pcg_xr<<<pblk(n), 256, 0, s>>>(n, nrhs, x, ld, r, p, q, sc);
+}
+void launch_pcg_p(int n, int nrhs, double* p, const double* z, PcgScalars* sc, hipStream_t s) {
+  if (n > 0) k_pcg_p<<<pblk(n), 256, 0, s>>>(n, nrhs, p, z, sc);
+  k_pcg_rz<<<1, 64, 0, s>>>(nrhs, sc);
 }
 
 }  // namespace fg

@@ -140,13 +140,22 @@ void hodlr_free(HodlrData& H) {
   dfree(H.rcols); dfree(H.rcount); dfree(H.panel); dfree(H.status); dfree(H.work);
 }
 
-fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err) {
-  fg_status st;
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32) {
+  fg_status st = FG_OK;
   const size_t ld = round_ld(c.n);
   const size_t bb = (size_t)c.nleaf * c.B * c.B;
-  if ((st = dalloc(&F.leafL, bb, err)) != FG_OK || (st = dalloc(&F.leafLinv, bb, err)) != FG_OK ||
-      (st = dalloc(&F.leaf_ld, c.nleaf, err)) != FG_OK ||
-      (st = dalloc(&F.panel, ld * c.Ktot, err)) != FG_OK ||
+  F.fp32 = fp32;
+  const bool ok64 = fp32 || ((st = dalloc(&F.leafL, bb, err)) == FG_OK &&
+                             (st = dalloc(&F.leafLinv, bb, err)) == FG_OK &&
+                             (st = dalloc(&F.panel, ld * c.Ktot, err)) == FG_OK);
+  const bool ok32 = !fp32 || ((st = dalloc(&F.leafLf, bb, err)) == FG_OK &&
+                              (st = dalloc(&F.leafLinvf, bb, err)) == FG_OK &&
+                              (st = dalloc(&F.panelf, ld * c.Ktot, err)) == FG_OK);
+  if (!ok64 || !ok32) {
+    factor_free(F);
+    return st;
+  }
+  if ((st = dalloc(&F.leaf_ld, c.nleaf, err)) != FG_OK ||
       (st = dalloc(&F.nodemat, c.nodemat, err)) != FG_OK ||
       (st = dalloc(&F.node_ld, std::max(c.nint, 1), err)) != FG_OK ||
       (st = dalloc(&F.zpart, c.zpart, err)) != FG_OK ||
@@ -163,6 +172,7 @@ fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err) {
 
 void factor_free(FactorData& F) {
   dfree(F.leafL); dfree(F.leafLinv); dfree(F.leaf_ld); dfree(F.panel); dfree(F.nodemat);
+  dfree(F.leafLf); dfree(F.leafLinvf); dfree(F.panelf);
   dfree(F.node_ld); dfree(F.zpart); dfree(F.zfin); dfree(F.coef); dfree(F.logdet);
   dfree(F.status); dfree(F.work);
 }
