@@ -327,6 +327,65 @@ fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream);
 fg_status tp_chain_state(fg_tp_chain c, fg_tp_snapshot* host_out, double* F_out,
                          fg_stream stream);
 
+/* Host-only count of the device bytes gibbs_chain_create(cfg) takes for these inputs
+ * (x host, sorted): every grid point is planned on the host and the buffers are sized
+ * for the largest, as the chain does.  No device call. */
+fg_status fg_footprint_bytes(const fg_chain_cfg* cfg, const double* x_host, int64_t n,
+                             uint64_t* bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving (a request loop for GP-regression jobs).  A job is one Gibbs chain on
+ * (x, y) run for `iters` sweeps.  A worker thread admits submitted jobs in arrival
+ * order while the footprint estimate (fg_footprint_bytes) fits within mem_budget minus
+ * the bytes held by running jobs (a job is always admitted into an empty server) and
+ * fewer than max_active run; it then advances every running job by one sweep
+ * (gibbs_step_batch on its own stream) and retires the jobs that are done, releasing
+ * their memory before the next admission.  Each job's result is the result of the
+ * same chain run alone.  Times are seconds since serve_create (steady clock).
+ * ------------------------------------------------------------------------- */
+typedef struct fg_server_s* fg_server;
+typedef struct {
+  uint64_t mem_budget;   /* device bytes for running jobs (> 0) */
+  int32_t max_active;    /* most jobs in one batched sweep (>= 1) */
+  int32_t nstreams;      /* library streams of the batched sweep (1..4) */
+  int32_t use_graphs;    /* capture and replay sweep graphs (gibbs_step_batch) */
+} fg_serve_cfg;
+typedef struct {
+  const double* x;       /* host, n sorted inputs (copied at submission) */
+  const double* y;       /* host, n observations (copied) */
+  int64_t n;
+  int32_t kind;
+  double ell0, nugget;
+  int32_t leaf;
+  double tol, tau0, sigf2_0;
+  int32_t iters;         /* sweeps to run */
+  uint64_t seed, stream_id;
+  int32_t precision;     /* FG_FP64 / FG_MIXED */
+  double* f_out;         /* host, n doubles or NULL: the last draw of f; must stay valid
+                            until the job's result has been polled */
+} fg_job;
+typedef struct {
+  uint64_t id;
+  int32_t status;        /* FG_OK or the job's error */
+  fg_chain_snapshot snap;
+  double t_submit, t_admit, t_done;
+  uint64_t bytes;        /* device bytes the job held */
+} fg_result;
+typedef struct {
+  int64_t pending, outstanding, sweeps;
+  uint64_t peak_bytes;   /* most bytes held by running jobs at once */
+} fg_serve_stats;
+fg_status serve_create(const fg_serve_cfg* cfg, fg_server* out);
+/* Copies the request and queues it; *id (may be NULL) receives its id. */
+fg_status serve_submit(fg_server s, const fg_job* job, uint64_t* id);
+/* Moves up to `max` finished results into out (host); *got = how many. */
+fg_status serve_poll(fg_server s, fg_result* out, int32_t max, int32_t* got);
+/* Blocks until every submitted job has finished (FG_ENOTCONV after timeout_s). */
+fg_status serve_drain(fg_server s, double timeout_s);
+fg_status serve_stats(fg_server s, fg_serve_stats* out);
+/* Stops the worker after its current sweep and frees every running job. */
+void serve_destroy(fg_server s);
+
 /* ---------------------------------------------------------------------------
  * Live kernel timing (diagnostics).  fg_timer_start(id) makes the library record
  * HIP events, on the launch stream, around every following launch of kernel `id`

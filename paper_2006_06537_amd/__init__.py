@@ -10,11 +10,11 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Kernel, TpCfg,
-                   TpSnapshot, check, lib)
+from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Job,
+                   Kernel, Result, ServeCfg, ServeStats, TpCfg, TpSnapshot, check, lib)
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
-           "draw_f_hetero", "step_batch", "solve_refined", "FP64", "MIXED", "KERNEL_SE",
+           "draw_f_hetero", "step_batch", "solve_refined", "Server", "footprint_bytes", "FP64", "MIXED", "KERNEL_SE",
            "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE"]
 
 KID_LEAF, KID_REDUCE, KID_UPDATE = 1, 2, 3
@@ -263,6 +263,79 @@ def step_batch(chains, iters=1, nstreams=4, graphs=True):
     """gibbs_step_batch over a list of Chain objects."""
     arr = (C.c_void_p * max(len(chains), 1))(*[c._c for c in chains])
     check(lib().gibbs_step_batch(arr, len(chains), iters, nstreams, int(graphs), _stream()))
+
+
+def footprint_bytes(x, ell0, leaf=128, tol=1e-10, nugget=1e-6, kind=KERNEL_SE, precision=FP64,
+                    grid_size=100, grid_center=50):
+    """fg_footprint_bytes for host inputs x (numpy, sorted): device bytes of a chain."""
+    import numpy as np
+    xh = np.ascontiguousarray(x, dtype=np.float64)
+    cfg = ChainCfg(kind, ell0, nugget, leaf, tol, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, grid_size,
+                   grid_center, 0, 0, precision)
+    out = C.c_uint64()
+    check(lib().fg_footprint_bytes(C.byref(cfg), C.c_void_p(xh.ctypes.data), xh.size,
+                                   C.byref(out)))
+    return out.value
+
+
+class Server:
+    """Serving loop (serve_create / serve_submit / serve_poll / serve_drain).  Jobs are
+    host numpy arrays; the server copies them at submission."""
+
+    def __init__(self, mem_budget, max_active=64, nstreams=4, graphs=True):
+        cfg = ServeCfg(int(mem_budget), max_active, nstreams, int(graphs))
+        s = C.c_void_p()
+        check(lib().serve_create(C.byref(cfg), C.byref(s)))
+        self._s = s
+        self._keep = {}  # f buffers of jobs not yet polled
+
+    def submit(self, x, y, ell0, iters, tau0=100.0, sigf2_0=1.0, nugget=1e-6, leaf=128,
+               tol=1e-10, seed=0, stream_id=0, kind=KERNEL_SE, precision=FP64, want_f=True):
+        import numpy as np
+        xh = np.ascontiguousarray(x, dtype=np.float64)
+        yh = np.ascontiguousarray(y, dtype=np.float64)
+        f = np.empty_like(xh) if want_f else None
+        job = Job(C.c_void_p(xh.ctypes.data), C.c_void_p(yh.ctypes.data), xh.size, kind, ell0,
+                  nugget, leaf, tol, tau0, sigf2_0, iters, seed, stream_id, precision,
+                  C.c_void_p(f.ctypes.data) if f is not None else None)
+        jid = C.c_uint64()
+        check(lib().serve_submit(self._s, C.byref(job), C.byref(jid)))
+        self._keep[jid.value] = f
+        return jid.value
+
+    def poll(self, max_results=1024):
+        buf = (Result * max_results)()
+        got = C.c_int32()
+        check(lib().serve_poll(self._s, buf, max_results, C.byref(got)))
+        out = []
+        for i in range(got.value):
+            r = buf[i]
+            d = {"id": r.id, "status": r.status, "t_submit": r.t_submit, "t_admit": r.t_admit,
+                 "t_done": r.t_done, "bytes": r.bytes}
+            d.update(r.snap.as_dict())
+            d["f"] = self._keep.pop(r.id, None)
+            out.append(d)
+        return out
+
+    def drain(self, timeout=600.0):
+        check(lib().serve_drain(self._s, timeout))
+
+    def stats(self):
+        st = ServeStats()
+        check(lib().serve_stats(self._s, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        s = getattr(self, "_s", None)
+        try:
+            if s is not None and s.value and _lib._lib is not None:
+                _lib._lib.serve_destroy(s)
+        except Exception:  # interpreter shutdown
+            pass
+        self._s = None
+
+    def __del__(self):
+        self.close()
 
 
 class Chain:

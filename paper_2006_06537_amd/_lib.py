@@ -23,8 +23,9 @@ EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", 
            "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
            "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
-           "gibbs_step_batch", "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state", "fg_timer_start",
-           "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
+           "gibbs_step_batch", "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state",
+           "fg_footprint_bytes", "serve_create", "serve_submit", "serve_poll", "serve_drain",
+           "serve_stats", "serve_destroy", "fg_timer_start", "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
            "factor_destroy", "gibbs_chain_destroy", "tp_chain_destroy"]
 
 
@@ -84,6 +85,30 @@ class TpSnapshot(C.Structure):
         return out
 
 
+class ServeCfg(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int32), ("nstreams", C.c_int32),
+                ("use_graphs", C.c_int32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("n", C.c_int64), ("kind", C.c_int32),
+                ("ell0", C.c_double), ("nugget", C.c_double), ("leaf", C.c_int32),
+                ("tol", C.c_double), ("tau0", C.c_double), ("sigf2_0", C.c_double),
+                ("iters", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("precision", C.c_int32), ("f_out", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("snap", ChainSnapshot),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("bytes", C.c_uint64)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("pending", C.c_int64), ("outstanding", C.c_int64), ("sweeps", C.c_int64),
+                ("peak_bytes", C.c_uint64)]
+
+
 _lib = None
 
 P = C.c_void_p
@@ -125,6 +150,13 @@ def lib():
         "gibbs_step": ([P, I32, P], I32),
         "gibbs_step_batch": ([C.POINTER(P), I32, I32, I32, I32, P], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),
+        "fg_footprint_bytes": ([C.POINTER(ChainCfg), P, I64, C.POINTER(U64)], I32),
+        "serve_create": ([C.POINTER(ServeCfg), C.POINTER(P)], I32),
+        "serve_submit": ([P, C.POINTER(Job), C.POINTER(U64)], I32),
+        "serve_poll": ([P, C.POINTER(Result), I32, C.POINTER(I32)], I32),
+        "serve_drain": ([P, D], I32),
+        "serve_stats": ([P, C.POINTER(ServeStats)], I32),
+        "serve_destroy": ([P], None),
         "fg_timer_start": ([I32], I32),
         "fg_timer_stop": ([C.POINTER(D), C.POINTER(I64), C.POINTER(D)], I32),
         "hodlr_status": ([P, P], I32),

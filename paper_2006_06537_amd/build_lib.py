@@ -15,7 +15,8 @@ OUT = os.path.join(HERE, "libfifagp.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["plan.cpp", "resources.cpp", "abi.cpp", "chain.cpp", "chain_tp.cpp",
            "timer.cpp", "k_build.hip", "k_factor.hip", "k_apply.hip", "k_rng.hip",
-           "k_tensor.hip", "pcg.cpp"]
+           "k_tensor.hip", "pcg.cpp",
+           "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in the device code
@@ -40,7 +41,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -91,6 +91,23 @@ Proposal propose(fg_chain c) {
 // Enqueues one sweep on s.  Every argument is fixed by (cur, k, proposal): the
 // iteration word lives in device memory, so the sequence can be captured once and
 // replayed.  Ends with the copy of the device state to pinned host memory.
+// Host-side state of the sweep about to run: which plan and matrix each slot's
+// launches refer to.  Runs before every sweep, captured or replayed, so that the host
+// view always matches what the device holds.
+void prepare_sweep(fg_chain c, const Proposal& pr) {
+  const int cur = c->cur, oth = 1 - cur;
+  fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
+  WM.H = &c->H[cur];
+  WM.alpha = 0.0;  // taken from the device scalar
+  WM.beta = 1.0;
+  if (pr.ongrid) {
+    c->H[oth].pk = c->packs[pr.kp];
+    c->W[oth].H = &c->H[oth];
+    c->W[oth].alpha = 1.0;
+    c->W[oth].beta = 0.0;
+  }
+}
+
 void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   const int n = c->n;
   const fg_chain_cfg& cf = c->cfg;
@@ -103,9 +120,6 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   fg::launch_sweep_begin(c->st, s);
   // f | -  (Algorithm 1)
   fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
-  WM.H = &c->H[cur];
-  WM.alpha = 0.0;  // taken from the device scalar
-  WM.beta = 1.0;
   fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
   hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
   fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
@@ -166,11 +180,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   if (pr.ongrid) {
     fg::launch_zero_int(c->H[oth].status, 1, s);
     fg::launch_zero_int(c->W[oth].status, 1, s);
-    c->H[oth].pk = c->packs[pr.kp];
     fg::launch_build(c->H[oth], s);
-    c->W[oth].H = &c->H[oth];
-    c->W[oth].alpha = 1.0;
-    c->W[oth].beta = 0.0;
     fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, s);
     hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
     hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
@@ -242,9 +252,54 @@ fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExe
   return FG_OK;
 }
 
+// device bytes of a chain of capacity `caps` with `plan_bytes` of uploaded plans
+size_t chain_bytes_from(const fg::Caps& caps, size_t plan_bytes, int n, bool mixed) {
+  size_t b = plan_bytes + 2 * fg::hodlr_bytes(caps) + 2 * fg::factor_bytes(caps, false) +
+             fg::factor_bytes(caps, mixed);
+  b += sizeof(double) * ((size_t)9 * n + 2048) + 2 * sizeof(fg::DevState);
+  if (mixed) b += sizeof(double) * ((size_t)4 * fg::NRHS_PCG * n + 4096);
+  return b;
+}
+
 }  // namespace
 
+namespace fg {
+size_t chain_device_bytes(fg_chain c) {
+  size_t pb = 0;
+  for (auto* p : c->packs) pb += plan_device_bytes(*p);
+  size_t b = chain_bytes_from(c->caps, pb, c->n, c->mixed);
+  if (c->fell_back) b += factor_bytes(c->caps, false);
+  return b;
+}
+int64_t chain_iteration(fg_chain c) { return c->iter; }
+}  // namespace fg
+
 extern "C" {
+
+fg_status fg_footprint_bytes(const fg_chain_cfg* cfg, const double* x_host, int64_t n,
+                             uint64_t* bytes) {
+  if (!cfg || !x_host || !bytes) return cfail(FG_EINVAL, "NULL argument");
+  if (n < 1 || n >= (int64_t(1) << 31)) return cfail(FG_EINVAL, "n out of range");
+  if (cfg->grid_size < 1 || cfg->grid_center < 0 || cfg->grid_center >= cfg->grid_size)
+    return cfail(FG_EINVAL, "bad grid");
+  // the capacity the chain takes is the largest over every plan of its grid
+  fg::Caps caps;
+  size_t plan_sum = 0;
+  for (int g = 0; g < cfg->grid_size; ++g) {
+    fg::PlanPack pk;
+    std::string err;
+    const double ell = cfg->ell0 * std::pow(10.0, (g - cfg->grid_center) / 50.0);
+    const fg_status st = fg::make_plan(x_host, int(n), cfg->kind, ell, cfg->nugget, cfg->leaf,
+                                       cfg->tol, pk.P, err);
+    if (st != FG_OK) return cfail(st, err);
+    fg::plan_pack_sizes(&pk);
+    caps.add(pk);
+    plan_sum += fg::plan_device_bytes(pk);
+  }
+  *bytes = chain_bytes_from(caps, plan_sum, int(n), cfg->precision == FG_MIXED);
+  return FG_OK;
+}
+
 
 fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const double* y, int64_t n,
                              fg_stream stream, fg_chain* out) {
@@ -338,6 +393,7 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int it = 0; it < iters; ++it) {
     const Proposal pr = propose(c);
+    prepare_sweep(c, pr);
     enqueue_sweep(c, pr, s);
     if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
     const hipError_t e = hipGetLastError();
@@ -369,6 +425,7 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
       fg_chain c = chains[i];
       hipStream_t q = g_batch.s[i % nstreams];
       pr[i] = propose(c);
+      prepare_sweep(c, pr[i]);
       if (!graphs || c->mixed) {
         enqueue_sweep(c, pr[i], q);
         continue;

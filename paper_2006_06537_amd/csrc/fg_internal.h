@@ -111,6 +111,7 @@ struct PlanPack {
 PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
                            double tol, hipStream_t s, fg_status& st, std::string& err);
 void plan_pack_destroy(PlanPack* pk);
+void plan_pack_sizes(PlanPack* pk);  // buffer sizes of pk->P (host only)
 
 // Buffers of one compressed matrix, sized for `cap` (>= the plan it currently holds).
 struct HodlrData {
@@ -161,6 +162,10 @@ fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err);
 void hodlr_free(HodlrData& H);
 fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32 = false);
 void factor_free(FactorData& F);
+// device bytes held by a plan upload, a compressed matrix and a factor of capacity c
+size_t plan_device_bytes(const PlanPack& pk);
+size_t hodlr_bytes(const Caps& c);
+size_t factor_bytes(const Caps& c, bool fp32);
 
 // -------- kernels' host launchers (stream-ordered) --------
 void launch_build(HodlrData& H, hipStream_t s);

@@ -36,11 +36,8 @@ static fg_status upload(T** dst, const std::vector<T>& v, hipStream_t s, std::st
   return FG_OK;
 }
 
-PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
-                           double tol, hipStream_t s, fg_status& st, std::string& err) {
-  PlanPack* pk = new PlanPack();
-  st = make_plan(xh, n, kind, ell, nugget, leaf, tol, pk->P, err);
-  if (st != FG_OK) { delete pk; return nullptr; }
+// buffer sizes of a plan (host only)
+void plan_pack_sizes(PlanPack* pk) {
   HostPlan& P = pk->P;
   // per node offsets of (G_V, F1, F2) and factor scratch sizes
   pk->nodemat_off.resize(std::max(P.nint, 1));
@@ -62,6 +59,15 @@ PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double
   pk->mpart_size = (size_t)std::max(P.nmt, 1) * P.mpart_stride;
   pk->mv_work = matvec_work_doubles(P, 4);
   pk->ap_work = apply_work_doubles(P, 4);
+}
+
+PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                           double tol, hipStream_t s, fg_status& st, std::string& err) {
+  PlanPack* pk = new PlanPack();
+  st = make_plan(xh, n, kind, ell, nugget, leaf, tol, pk->P, err);
+  if (st != FG_OK) { delete pk; return nullptr; }
+  plan_pack_sizes(pk);
+  HostPlan& P = pk->P;
   DevPlan& D = pk->D;
   std::vector<int> kc(P.kcap), co(P.coff);
   if (kc.empty()) kc.push_back(0);
@@ -113,6 +119,26 @@ void Caps::add(const PlanPack& pk) {
 }
 
 static int round_ld(int n) { return (n + 63) / 64 * 64; }
+
+size_t plan_device_bytes(const PlanPack& pk) {
+  const HostPlan& P = pk.P;
+  return sizeof(NodePlan) * std::max(P.nint, 1) + sizeof(int) * (P.nleaf + 1) +
+         sizeof(Task) * ((size_t)P.nmt + P.ngt + P.nlt) + sizeof(int) * 2 * (2 * P.nint + 1) +
+         sizeof(int) * 2 * std::max(P.L, 1) + sizeof(int) * std::max(P.nint, 1);
+}
+
+size_t hodlr_bytes(const Caps& c) {
+  const size_t ld = round_ld(c.n), Lm = std::max(c.L, 1), ni = std::max(c.nint, 1);
+  return 8 * ((size_t)c.n + c.tbuf + c.mpart + ni * PMAX + ld * c.Ktot + c.mv_work) +
+         4 * (ni + 2 * Lm + Lm * c.Ktot + 1);
+}
+
+size_t factor_bytes(const Caps& c, bool fp32) {
+  const size_t ld = round_ld(c.n), ni = std::max(c.nint, 1);
+  const size_t big = 2 * (size_t)c.nleaf * c.B * c.B + ld * c.Ktot;
+  return (fp32 ? 4 : 8) * big +
+         8 * ((size_t)c.nleaf + c.nodemat + ni + c.zpart + c.zfin + c.coef + 1 + c.ap_work) + 4;
+}
 
 fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err) {
   fg_status st;

@@ -58,3 +58,21 @@ def test_argument_errors_without_device(L):
     assert L.gibbs_chain_create(C.byref(cfg), C.c_void_p(8), C.c_void_p(8), 10, None,
                                 C.byref(ch)) == _lib.FG_EINVAL
     assert b"grid" in L.fg_last_error()
+
+
+def test_footprint_estimate_host_only():
+    """fg_footprint_bytes plans on the host only (no device call): positive, growing
+    with n, and smaller for the FP32 factor of M~."""
+    import numpy as np
+    import paper_2006_06537_amd as fg
+    from workloads import sinusoid_1d
+    sizes = []
+    for n in (2000, 8000, 32000):
+        x, _ = sinusoid_1d(n, seed=2)
+        sizes.append(fg.footprint_bytes(x, 0.05, leaf=128))
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    assert sizes[2] / sizes[1] > 3.0  # at least linear in n
+    x, _ = sinusoid_1d(8000, seed=2)
+    assert fg.footprint_bytes(x, 0.05, precision=fg.MIXED) < sizes[1]
+    with pytest.raises(fg.FgError):
+        fg.footprint_bytes(x, 0.05, leaf=1)

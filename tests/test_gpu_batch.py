@@ -47,7 +47,8 @@ def same(a, b):
 def test_batch_equals_sequential(graphs, nstreams):
     eager = [make(s) for s in SPECS]
     batch = [make(s) for s in SPECS]
-    for rnd, iters in enumerate([3, 2, 4]):  # later rounds replay captured sweeps
+    # later rounds replay captured sweeps, interleaved with acceptances that swap slots
+    for rnd, iters in enumerate([3, 2, 4, 6, 5]):
         for c in eager:
             c.step(iters)
         fg().step_batch(batch, iters, nstreams=nstreams, graphs=graphs)
