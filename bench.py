@@ -15,6 +15,10 @@ Other workloads (--workload), each printing its own JSON line:
           graphs; value = chain sweeps per second over all chains.  The same chains
           stepped one after the other (gibbs_step) are timed beside it.
   tensor  the d = 4, n = 65,536 tensor-product surface chain; value = sweeps/s.
+  serve   GP-regression jobs of mixed n (workloads.served_jobs) through the serving
+          loop: first all at once (saturation throughput), then Poisson arrivals at
+          0.7 x that rate; value = p50 latency (s), with p99 and the same arrival list
+          run as a sequential FIFO of plain FP64 chains beside it.
 """
 from __future__ import annotations
 
@@ -38,7 +42,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
-    ap.add_argument("--workload", default="large_1d", choices=["large_1d", "batch", "tensor"])
+    ap.add_argument("--workload", default="large_1d",
+                    choices=["large_1d", "batch", "tensor", "serve"])
+    ap.add_argument("--jobs", type=int, default=64, help="serve workload: number of jobs")
+    ap.add_argument("--job-iters", type=int, default=20, help="serve workload: sweeps per job")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturation")
     ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: M~ factored in FP32, its solves refined by PCG to 1e-10")
@@ -167,6 +175,94 @@ def bench_tensor(args):
                        "tol 1e-10", "d": T["d"], "n": n}, **extra)
 
 
+def bench_serve(args):
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import served_jobs
+    jobs = served_jobs(args.jobs, seed=5)
+    prec = fg.MIXED if args.precision == "mixed" else fg.FP64
+    budget = 96 << 30
+    common = dict(tau0=400.0, leaf=128, tol=1e-10, precision=prec, want_f=False)
+
+    def run(arrivals):
+        srv = fg.Server(budget, max_active=48, nstreams=4, graphs=True)
+        t0 = time.perf_counter()
+
+        def feeder():
+            for j, job in enumerate(jobs):
+                dt = arrivals[j] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                srv.submit(job["x"], job["y"], job["ell0"], args.job_iters, seed=job["seed"],
+                           stream_id=j, **common)
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        srv.drain(1200.0)
+        span = time.perf_counter() - t0
+        res = srv.poll(4096)
+        st = srv.stats()
+        srv.close()
+        bad = [r for r in res if r["status"] != 0]
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        return span, lat, st, len(bad)
+
+    # saturation: every job at t = 0
+    span0, lat0, st0, bad0 = run([0.0] * len(jobs))
+    sat = len(jobs) / span0
+    print(f"bench: saturation {sat:.3f} jobs/s ({span0:.1f} s, peak {st0['peak_bytes'] / 2**30:.1f} GiB,"
+          f" {bad0} failed)", file=sys.stderr, flush=True)
+    lam = args.load * sat
+    gaps = np.random.default_rng(55).exponential(1.0 / lam, len(jobs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    span, lat, st, bad = run(list(arrivals))
+    print(f"bench: served at {lam:.3f} jobs/s in {span:.1f} s, {bad} failed", file=sys.stderr,
+          flush=True)
+    # sequential FIFO of plain FP64 chains on the same arrivals: service times measured
+    # one job at a time, queue replayed on the host
+    dev = torch.device("cuda:0")
+    svc = []
+    for j, job in enumerate(jobs):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c = fg.Chain(torch.tensor(job["x"], device=dev), torch.tensor(job["y"], device=dev),
+                     ell0=job["ell0"], tau0=400.0, leaf=128, tol=1e-10, seed=job["seed"],
+                     stream_id=j)
+        c.step(args.job_iters)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t1)
+        del c
+    fin, seq_lat = 0.0, []
+    for j in range(len(jobs)):
+        fin = max(fin, arrivals[j]) + svc[j]
+        seq_lat.append(fin - arrivals[j])
+    seq_lat = np.array(seq_lat)
+    q = lambda a, p: float(np.percentile(a, p))
+    print(f"bench: sequential FIFO p50 {q(seq_lat, 50):.2f} s p99 {q(seq_lat, 99):.2f} s",
+          file=sys.stderr, flush=True)
+    ns = [j["n"] for j in jobs]
+    out = {"metric": "p50 latency of served GP-regression jobs", "value": q(lat, 50), "unit": "s",
+           "n_gpus": 1, "steps": args.job_iters, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if prec == fg.MIXED else "f64", "data": "synthetic",
+           "config": {"workload": f"serve: {len(jobs)} jobs, n log-uniform [1e3, 2e5] (mean "
+                                  f"{np.mean(ns):.0f}), 5-sinusoid y, noise U[0.02,0.2], ell0 "
+                                  f"LogU[0.01,0.3], {args.job_iters} sweeps each, Poisson "
+                                  f"arrivals at {args.load} x saturation; budget 96 GiB, "
+                                  "48 slots", "jobs": len(jobs), "sweeps_per_job": args.job_iters},
+           "p99": q(lat, 99), "throughput_jobs_per_s": len(jobs) / span,
+           "saturation_jobs_per_s": sat, "arrival_rate": lam,
+           "peak_bytes": st["peak_bytes"], "failed_jobs": bad,
+           "sequential_fp64_fifo": {"p50": q(seq_lat, 50), "p99": q(seq_lat, 99),
+                                    "throughput_jobs_per_s": len(jobs) / fin,
+                                    "mean_service_s": float(np.mean(svc))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -177,6 +273,8 @@ def main():
         return bench_batch(args)
     if args.workload == "tensor":
         return bench_tensor(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     import numpy as np
     import torch
 

@@ -74,3 +74,20 @@ def tensor_surface(d: int = 4, n: int = 65536, seed: int = 3, noise: float = 0.1
 # every f_h = 1, beta = 1, tau = tau0; grid centre ell0[h] per factor.
 TENSOR_4D = dict(d=4, n=65536, leaf=128, tol=1e-10, ell0=(0.05, 0.1333, 0.2167, 0.3),
                  tau0=100.0, beta0=1.0, nugget=1e-6, iters=200, seed=3)
+
+
+def served_jobs(count: int = 512, seed: int = 5):
+    """GP-regression jobs for the serving workload, in arrival order: n log-uniform on
+    [1e3, 2e5], sorted x ~ U[0,1], y = 5-sinusoid mixture (the large_1d generator's
+    recipe) + N(0, s^2) with s ~ U[0.02, 0.2], grid centre ell0 log-uniform on
+    [0.01, 0.3].  Returns a list of dicts (x, y, ell0, noise, seed)."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for j in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(1e3), math.log(2e5)))))
+        noise = float(rng.uniform(0.02, 0.2))
+        ell0 = float(math.exp(rng.uniform(math.log(0.01), math.log(0.3))))
+        jseed = int(rng.integers(1, 2 ** 31))
+        x, y = sinusoid_1d(n, seed=jseed, noise=noise)
+        jobs.append(dict(x=x, y=y, ell0=ell0, noise=noise, seed=jseed, n=n))
+    return jobs
