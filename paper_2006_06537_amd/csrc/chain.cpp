@@ -39,6 +39,8 @@ struct fg_chain_s {
   int pcg_iters = 0;
   double pcg_relres = 0.0;
   bool pcg_failed = false;
+  hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::map<uint64_t, hipGraphExec_t> graphs;  // captured sweeps by (cur, k, proposal)
   std::vector<uint64_t> graph_order;          // insertion order, for eviction
 };
@@ -58,6 +60,9 @@ static void chain_free(fg_chain c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   fg::factor_free(c->WM);
@@ -118,6 +123,19 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   const uint64_t* itp = &c->st->iter;
   const int cur = c->cur, oth = 1 - cur;
   fg::launch_sweep_begin(c->st, s);
+  // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
+  // the chain's second stream while this stream factors M~ and draws f.
+  hipEventRecord(c->ev_fork, s);
+  hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+  if (pr.ongrid) {
+    fg::launch_zero_int(c->H[oth].status, 1, c->aux);
+    fg::launch_zero_int(c->W[oth].status, 1, c->aux);
+    fg::launch_build(c->H[oth], c->aux);
+    fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, c->aux);
+    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
+                   c->aux);
+  }
+  hipEventRecord(c->ev_join, c->aux);
   // f | -  (Algorithm 1)
   fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
   fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
@@ -177,12 +195,8 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
   fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
   // length-scale | -  (Metropolis on the grid)
+  hipStreamWaitEvent(s, c->ev_join, 0);
   if (pr.ongrid) {
-    fg::launch_zero_int(c->H[oth].status, 1, s);
-    fg::launch_zero_int(c->W[oth].status, 1, s);
-    fg::launch_build(c->H[oth], s);
-    fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, s);
-    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
     hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
     fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
@@ -359,6 +373,12 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
       hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::DevState)) != hipSuccess) {
     chain_free(c);
     return cfail(FG_ENOMEM, "chain allocation failed");
+  }
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_EDEVICE, "stream or event creation failed");
   }
   hipMemcpyAsync(c->x, x, nb, hipMemcpyDeviceToDevice, s);
   hipMemcpyAsync(c->y, y, nb, hipMemcpyDeviceToDevice, s);

@@ -34,6 +34,8 @@ struct fg_tp_chain_s {
   double* dotwork = nullptr;
   fg::TpState* st = nullptr;
   fg::TpState* st_host = nullptr;
+  hipStream_t aux = nullptr;  // proposals' builds and factors, beside the draws
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 using fg::set_error;
@@ -55,6 +57,9 @@ static void tp_free(fg_tp_chain c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 
@@ -131,6 +136,12 @@ fg_status tp_chain_create(const fg_tp_cfg* cfg, const double* x, const double* y
     tp_free(c);
     return tfail(FG_ENOMEM, "tensor chain allocation failed");
   }
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    tp_free(c);
+    return tfail(FG_EDEVICE, "stream or event creation failed");
+  }
   hipMemcpyAsync(c->perm, permh.data(), sizeof(int) * permh.size(), hipMemcpyHostToDevice, s);
   hipMemcpyAsync(c->y, y, nb, hipMemcpyDeviceToDevice, s);
   std::vector<double> ones((size_t)d * nn, 1.0);
@@ -179,6 +190,30 @@ fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream) {
   double* v3 = v2 + n;
   for (int it = 0; it < iters; ++it) {
     const uint64_t t = (uint64_t)c->iter;
+    // Every factor's length-scale proposal is known on the host: build and factor the
+    // proposals on the second stream while this one draws f_1..f_d, beta and tau.
+    int kp[fg::TP_DMAX], ong[fg::TP_DMAX];
+    hipEventRecord(c->ev_fork, s);
+    hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+    for (int h = 0; h < d; ++h) {
+      uint64_t w[4];
+      fg::philox4x64_10(0, fg::tp_factor_tag(5, h), t, cf.stream_id, cf.seed, 0, w);
+      kp[h] = c->k[h] + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
+      ong[h] = (kp[h] >= 0 && kp[h] < cf.grid_size) ? 1 : 0;
+      if (!ong[h]) continue;
+      const int oth = 1 - c->cur[h];
+      fg::launch_zero_int(c->H[h][oth].status, 1, c->aux);
+      fg::launch_zero_int(c->W[h][oth].status, 1, c->aux);
+      c->H[h][oth].pk = c->packs[h][kp[h]];
+      fg::launch_build(c->H[h][oth], c->aux);
+      c->W[h][oth].H = &c->H[h][oth];
+      c->W[h][oth].alpha = 1.0;
+      c->W[h][oth].beta = 0.0;
+      fg::launch_factor(c->W[h][oth], nullptr, nullptr, nullptr, c->aux);
+      hipMemcpyAsync(&c->st->logdetp[h], c->W[h][oth].logdet, sizeof(double),
+                     hipMemcpyDeviceToDevice, c->aux);
+    }
+    hipEventRecord(c->ev_join, c->aux);
     // f_h | -  for h = 1..d in turn (Algorithm 1.h)
     for (int h = 0; h < d; ++h) {
       fg::HodlrData& H = c->H[h][c->cur[h]];
@@ -210,29 +245,15 @@ fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream) {
     fg::launch_axpby(n, G, nullptr, v0, &c->st->beta, 0.0, nullptr, 0.0, s);
     fg::launch_dot(c->y, v0, n, 1, &c->st->sse, c->dotwork, s);
     fg::launch_tp_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, t, cf.stream_id, s);
-    // ell_h | -  (grid Metropolis per factor; proposals are known on the host)
-    int kp[fg::TP_DMAX], ong[fg::TP_DMAX];
+    // ell_h | -  (grid Metropolis per factor)
+    hipStreamWaitEvent(s, c->ev_join, 0);
     for (int h = 0; h < d; ++h) {
       const int cur = c->cur[h], oth = 1 - cur;
       const double* fh = c->fs + (size_t)h * n;
       hipMemcpyAsync(v1, fh, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
       fg::launch_apply_w(c->W[h][cur], 2, v1, 1, n, c->W[h][cur].work, s);
       fg::launch_dot(v1, v1, n, 0, &c->st->q[h], c->dotwork, s);
-      uint64_t w[4];
-      fg::philox4x64_10(0, fg::tp_factor_tag(5, h), t, cf.stream_id, cf.seed, 0, w);
-      kp[h] = c->k[h] + (fg::to_unit(w[0]) < 0.5 ? 1 : -1);
-      ong[h] = (kp[h] >= 0 && kp[h] < cf.grid_size) ? 1 : 0;
       if (ong[h]) {
-        fg::launch_zero_int(c->H[h][oth].status, 1, s);
-        fg::launch_zero_int(c->W[h][oth].status, 1, s);
-        c->H[h][oth].pk = c->packs[h][kp[h]];
-        fg::launch_build(c->H[h][oth], s);
-        c->W[h][oth].H = &c->H[h][oth];
-        c->W[h][oth].alpha = 1.0;
-        c->W[h][oth].beta = 0.0;
-        fg::launch_factor(c->W[h][oth], nullptr, nullptr, nullptr, s);
-        hipMemcpyAsync(&c->st->logdetp[h], c->W[h][oth].logdet, sizeof(double),
-                       hipMemcpyDeviceToDevice, s);
         hipMemcpyAsync(v1, fh, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
         fg::launch_apply_w(c->W[h][oth], 2, v1, 1, n, c->W[h][oth].work, s);
         fg::launch_dot(v1, v1, n, 0, &c->st->qp[h], c->dotwork, s);

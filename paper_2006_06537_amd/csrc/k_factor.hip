@@ -265,7 +265,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     if (bad) atomicOr(status, ST_NOTSPD);
   }
   (void)mybad;
-  // L to global (lower triangle, column-major, ld = Bc); rows/cols beyond m untouched
+  // L to global (lower triangle, column-major, ld = Bc); the upper triangle and rows/cols
+  // beyond m are never written (no reader touches them)
   T* Lg = leafL + (size_t)b * Bc * Bc;
 #pragma unroll
   for (int jj = 0; jj < LE; ++jj) {
@@ -273,7 +274,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
       const int r = LG * i + tr;
-      if (r < m && c < m) Lg[r + (size_t)c * Bc] = (c <= r) ? a[i][jj] : T(0);
+      if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[i][jj];  // lower triangle only
     }
   }
   // L^-1 by blocked substitution on identity columns, 64 columns per pass
@@ -292,7 +293,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         const int r = LG * i + tr;
-        if (r < m && c < m) Lig[r + (size_t)c * Bc] = (c <= r) ? y[i][q] : T(0);
+        if (r < m && c <= r) Lig[r + (size_t)c * Bc] = y[i][q];
       }
     }
   }
