@@ -389,8 +389,9 @@ void serve_destroy(fg_server s);
 /* ---------------------------------------------------------------------------
  * Live kernel timing (diagnostics).  fg_timer_start(id) makes the library record
  * HIP events, on the launch stream, around every following launch of kernel `id`
- * (FG_KID_LEAF: leaf Cholesky + whitening of the panels; FG_KID_REDUCE: level Gram
- * reduction; FG_KID_UPDATE: level update of the coarser panels).  fg_timer_stop
+ * (FG_KID_LEAF: leaf Cholesky and inverse; FG_KID_REDUCE: level Gram reduction;
+ * FG_KID_UPDATE: level update of the coarser panels; FG_KID_WHITEN: whitening of every
+ * panel row by the leaf inverses, on matrix cores).  fg_timer_stop
  * synchronises the device and returns the summed kernel time (ms), the launch count
  * and the algorithmic HBM bytes of those launches (each kernel's minimum traffic:
  * every operand read once and every result written once).  Not thread-safe.
@@ -398,6 +399,7 @@ void serve_destroy(fg_server s);
 #define FG_KID_LEAF 1
 #define FG_KID_REDUCE 2
 #define FG_KID_UPDATE 3
+#define FG_KID_WHITEN 4
 fg_status fg_timer_start(int32_t kernel_id);
 fg_status fg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
 

@@ -21,6 +21,7 @@ constexpr double KAPPA_H = 1.086435;  // Cramer: |H_n(x)| e^{-x^2/2} <= KAPPA_H 
 constexpr int KID_LEAF = 1;
 constexpr int KID_REDUCE = 2;
 constexpr int KID_UPDATE = 3;
+constexpr int KID_WHITEN = 4;
 
 // status bits written by kernels (device word, OR-ed)
 constexpr int ST_NOTSPD = 1;
@@ -138,7 +139,7 @@ struct FactorData {
   float* leafLinvf = nullptr;
   float* panelf = nullptr;
   double* leafL = nullptr;     // nleaf x B x B
-  double* leafLinv = nullptr;  // nleaf x B x B
+  double* leafLinv = nullptr;  // nleaf x B x B: inverses of L's 16 x 16 diagonal blocks
   double* leaf_ld = nullptr;   // nleaf
   double* panel = nullptr;     // whitened panels, same layout as H->panel
   double* nodemat = nullptr;   // per node: G_V, F1, F2 (k x k each)

@@ -26,31 +26,76 @@ __device__ __forceinline__ double wave_red(double v) {
   return v;
 }
 
-// leaf block operator, in place on v: op 0 L, 1 L', 2 Linv, 3 Linv'
+// leaf block operator, in place on v: op 0 L, 1 L', 2 L^-1, 3 L^-T.  L is the leaf's lower
+// triangle; Dinv holds the inverses of its 16 x 16 diagonal blocks (in the diagonal
+// blocks of the slot).  L^-1 and L^-T are blocked substitutions:
+//   forward:  v_i <- D_i^-1 (v_i - sum_{j<i} L_ij v_j),   i = 0, 1, ...
+//   backward: v_i <- D_i^-T (v_i - sum_{j>i} L_ji' v_j),  i = nb-1, ..., 0
 // (factor data of precision T; vectors and arithmetic in FP64)
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
-                                                         const T* __restrict__ M, int Bc,
-                                                         int trans, double* __restrict__ v,
+                                                         const T* __restrict__ Lm,
+                                                         const T* __restrict__ Dinv, int Bc,
+                                                         int op, double* __restrict__ v,
                                                          int nrhs, int ld) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   __shared__ double vs[NRHS_MAX][BMAX];
+  __shared__ double ts[NRHS_MAX][16];
   for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
     vs[idx / m][idx % m] = v[(size_t)(idx / m) * ld + lo + idx % m];
   __syncthreads();
-  const T* Mb = M + (size_t)b * Bc * Bc;
-  for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS) {
-    const int r = idx % m, c = idx / m;
-    double acc = 0.0;
-    if (!trans) {
-      for (int s = 0; s <= r; ++s) acc += (double)Mb[r + s * Bc] * vs[c][s];
-    } else {
-      for (int s = r; s < m; ++s) acc += (double)Mb[s + r * Bc] * vs[c][s];
+  const T* Mb = Lm + (size_t)b * Bc * Bc;
+  if (op < 2) {
+    for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS) {
+      const int r = idx % m, c = idx / m;
+      double acc = 0.0;
+      if (op == 0) {
+        for (int s = 0; s <= r; ++s) acc += (double)Mb[r + s * Bc] * vs[c][s];
+      } else {
+        for (int s = r; s < m; ++s) acc += (double)Mb[s + r * Bc] * vs[c][s];
+      }
+      v[(size_t)c * ld + lo + r] = acc;
     }
-    v[(size_t)c * ld + lo + r] = acc;
+    return;
   }
+  const T* Db = Dinv + (size_t)b * Bc * Bc;
+  const int nb = (m + 15) >> 4;
+  // 4 threads per (row of the block, column): partial sums combined by shuffles
+  const int q = threadIdx.x & 3, e = threadIdx.x >> 2;  // e: 0..63 = row r (16) x column c (4)
+  const int rr = e & 15, c = e >> 4;
+  for (int step = 0; step < nb; ++step) {
+    const int i = (op == 2) ? step : nb - 1 - step;
+    const int r = i * 16 + rr;
+    double t = 0.0;
+    if (c < nrhs && r < m) {
+      if (op == 2) {
+        for (int s = q; s < i * 16; s += 4) t += (double)Mb[r + (size_t)s * Bc] * vs[c][s];
+      } else {
+        for (int s = (i + 1) * 16 + q; s < m; s += 4) t += (double)Mb[s + (size_t)r * Bc] * vs[c][s];
+      }
+    }
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    if (q == 0 && c < nrhs) ts[c][rr] = (r < m) ? vs[c][r] - t : 0.0;
+    __syncthreads();
+    // v_i = D_i^-1 t (forward) or D_i^-T t (backward); D_i^-1 is lower triangular
+    if (q == 0 && c < nrhs && r < m) {
+      double u = 0.0;
+      const int r0 = i * 16;
+      const int mi = min(16, m - r0);
+      if (op == 2) {
+        for (int s2 = 0; s2 <= rr; ++s2) u += (double)Db[(r0 + rr) + (size_t)(r0 + s2) * Bc] * ts[c][s2];
+      } else {
+        for (int s2 = rr; s2 < mi; ++s2) u += (double)Db[(r0 + s2) + (size_t)(r0 + rr) * Bc] * ts[c][s2];
+      }
+      vs[c][r] = u;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
+    v[(size_t)(idx / m) * ld + lo + idx % m] = vs[idx / m][idx % m];
 }
 
 // level reduce with a vector right operand: z[t][a][c] = sum_rows P[i, coff + a] v[i, c]
@@ -294,18 +339,22 @@ static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const T* p
   const HostPlan& P = F.H->pk->P;
   const int* leaf_lo = F.H->pk->D.leaf_lo;
   // W = L_D W_(L-1) ... W_(0)
+  auto leaf = [&](int lop) {
+    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop, v,
+                                                 nrhs, ld);
+  };
   if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
     for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 0, l, v, nrhs, ld, work, s);
-    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, P.B, 0, v, nrhs, ld);
+    leaf(0);
   } else if (op == 1) {   // W' v = W_(0)' ... W_(L-1)' L_D' v
-    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, P.B, 1, v, nrhs, ld);
+    leaf(1);
     for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 1, l, v, nrhs, ld, work, s);
   } else if (op == 2) {   // W^-1 v = W_(0)^-1 ... W_(L-1)^-1 L_D^-1 v
-    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafLinv, P.B, 0, v, nrhs, ld);
+    leaf(2);
     for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 2, l, v, nrhs, ld, work, s);
   } else {                // W^-T v = L_D^-T W_(L-1)^-T ... W_(0)^-T v
     for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 3, l, v, nrhs, ld, work, s);
-    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafLinv, P.B, 1, v, nrhs, ld);
+    leaf(3);
   }
 }
 

@@ -29,20 +29,20 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // ---------------------------------------------------------------------------------
-// leaves: Cholesky, its inverse, log-det and the whitening of every panel row
+// leaves: Cholesky and the log-det (the panel rows are whitened by k_whiten on matrix
+// cores)
 //
 // One work-group of 256 threads per leaf (m <= 128 rows).  The leaf matrix lives in
 // registers in a 16 x 16 thread grid: thread (tr, tc) holds the 8 x 8 elements
 // (16 i + tr, 16 j + tc), so diagonal block kb of a 16 x 16 blocking is element
 // [kb][kb] of every thread.  Blocked right-looking Cholesky: wave 0 factors the 16 x 16
 // diagonal block (and inverts it) with cross-lane shuffles, the block column below is
-// multiplied by that inverse, and the trailing matrix takes a rank-16 update.  Forward
-// substitution on the panels (and on identity columns, for L^-1) runs by 16-row blocks
-// the same way.  Three barriers per block step.
+// multiplied by that inverse, and the trailing matrix takes a rank-16 update.  Three
+// barriers per block step.  Output: L (lower triangle), the inverses of its 16 x 16
+// diagonal blocks, and the log-det.
 // ---------------------------------------------------------------------------------
 constexpr int LG = 16;        // thread grid side
 constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
-constexpr int YQ = 4;         // right-hand-side columns per thread (64 per pass)
 constexpr int LPD = 17;       // LDS pitch of 16-wide rows
 
 // wave 0: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD); writes L into
@@ -100,68 +100,13 @@ __device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
   return ls;
 }
 
-// y (rows 16 i + tr, columns tc + 16 q of a 64-column block) <- L^-1 y, blocks kb0..nb-1.
-// Likk: the 8 inverted diagonal blocks; Lp: 2 x 128 x LPD scratch; Yk, Yh: 16 x 65 each.
-template <typename T>
-__device__ __forceinline__ void leaf_trsm_blk(const T (&a)[LE][LE], T (&y)[LE][YQ], int nb,
-                                              int kb0, const T* Likk, T* Lp, T* Yk, T* Yh, int tr,
-                                              int tc) {
-  for (int kb = kb0; kb < nb; ++kb) {
-    T* L2 = Lp + (kb & 1) * (BMAX * LPD);
-#pragma unroll
-    for (int i = 0; i < LE; ++i) {
-      if (i == kb) {
-#pragma unroll
-        for (int q = 0; q < YQ; ++q) Yk[tr * 65 + tc + LG * q] = y[i][q];
-      }
-      if (i > kb && i < nb) {
-#pragma unroll
-        for (int jj = 0; jj < LE; ++jj)
-          if (jj == kb) L2[(LG * i + tr) * LPD + tc] = a[i][jj];
-      }
-    }
-    __syncthreads();
-    const T* Li = Likk + kb * (16 * LPD);
-    T yh[YQ];
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) yh[q] = T(0);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const T lv = Li[tr * LPD + t];
-#pragma unroll
-      for (int q = 0; q < YQ; ++q) yh[q] += lv * Yk[t * 65 + tc + LG * q];
-    }
-#pragma unroll
-    for (int i = 0; i < LE; ++i)
-      if (i == kb) {
-#pragma unroll
-        for (int q = 0; q < YQ; ++q) y[i][q] = yh[q];
-      }
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) Yh[tr * 65 + tc + LG * q] = yh[q];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < LE; ++i) {
-      if (i > kb && i < nb) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const T lr = L2[(LG * i + tr) * LPD + t];
-#pragma unroll
-          for (int q = 0; q < YQ; ++q) y[i][q] -= lr * Yh[t * 65 + tc + LG * q];
-        }
-      }
-    }
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
     double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
     T* __restrict__ leafL, T* __restrict__ leafLinv, double* __restrict__ leaf_ld,
-    int* __restrict__ status, const double* __restrict__ src, T* __restrict__ dst, int K,
-    const int* __restrict__ coff, const int* __restrict__ kmax, int L) {
+    int* __restrict__ status) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
@@ -169,16 +114,13 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   const double alpha = alpha_p ? *alpha_p : alpha_v;
   const double beta = beta_p ? *beta_p : beta_v;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  // LDS: Likk 8 blocks | Lk | Dk | Lp (2 x 128 rows) | union{ Pp 128 rows ; Yk + Yh }
+  // LDS: Likk 8 blocks | Lk | Dk | Lp (2 x 128 rows) | Pp 128 rows
   __shared__ double xs[BMAX];
   __shared__ T Likk[LE * 16 * LPD];
   __shared__ T Lk[16 * LPD];
   __shared__ T Dk[16 * LPD];
   __shared__ T Lp[2 * BMAX * LPD];
-  __shared__ T U[BMAX * LPD];  // Pp during the factorization, Yk | Yh afterwards
-  T* Pp = U;
-  T* Yk = U;
-  T* Yh = U + 16 * 65;
+  __shared__ T Pp[BMAX * LPD];
   __shared__ int bad;
   __shared__ double ldsum;
   if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
@@ -277,65 +219,14 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[i][jj];  // lower triangle only
     }
   }
-  // L^-1 by blocked substitution on identity columns, 64 columns per pass
+  // the inverses of the 16 x 16 diagonal blocks (from the diagonal factorizations) go to
+  // the diagonal blocks of the leaf's L^-1 slot; L^-1 itself is never formed (its
+  // products are blocked substitutions: k_whiten, k_leaf_apply)
   T* Lig = leafLinv + (size_t)b * Bc * Bc;
-  for (int c0 = 0; c0 < m; c0 += 64) {
-    T y[LE][YQ];
-#pragma unroll
-    for (int i = 0; i < LE; ++i)
-#pragma unroll
-      for (int q = 0; q < YQ; ++q) y[i][q] = (LG * i + tr == c0 + tc + LG * q) ? T(1) : T(0);
-    __syncthreads();
-    leaf_trsm_blk(a, y, nb, c0 >> 4, Likk, Lp, Yk, Yh, tr, tc);
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) {
-      const int c = c0 + tc + LG * q;
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = LG * i + tr;
-        if (r < m && c <= r) Lig[r + (size_t)c * Bc] = y[i][q];
-      }
-    }
-  }
-  // whitening of all panel rows of this leaf: dst = sqrt(alpha) L^-1 src.  The active
-  // columns of all levels are numbered 0..total-1 and handled 64 per pass.
-  const T sa = (T)sqrt(alpha);
-  int total = 0;
-  for (int l = 0; l < L; ++l) total += kmax[l];
-  for (int p0 = 0; p0 < total; p0 += 64) {
-    int gcq[YQ];
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) {
-      int f = p0 + tc + LG * q;
-      gcq[q] = -1;
-      if (f < total) {
-        for (int l = 0; l < L; ++l) {
-          const int km = kmax[l];
-          if (f < km) { gcq[q] = coff[l] + f; break; }
-          f -= km;
-        }
-      }
-    }
-    T y[LE][YQ];
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) {
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = LG * i + tr;
-        y[i][q] = (gcq[q] >= 0 && r < m) ? (T)src[pix(lo + r, gcq[q], K)] : T(0);
-      }
-    }
-    __syncthreads();
-    leaf_trsm_blk(a, y, nb, 0, Likk, Lp, Yk, Yh, tr, tc);
-#pragma unroll
-    for (int q = 0; q < YQ; ++q) {
-      if (gcq[q] < 0) continue;
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        const int r = LG * i + tr;
-        if (r < m) dst[pix(lo + r, gcq[q], K)] = sa * y[i][q];
-      }
-    }
+  for (int kb = 0; kb < nb; ++kb) {
+    const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
+    if (kb * 16 + r < m && c <= r)
+      Lig[(kb * 16 + r) + (size_t)(kb * 16 + c) * Bc] = Likk[kb * (16 * LPD) + r * LPD + c];
   }
 }
 
@@ -362,6 +253,9 @@ template <> struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int kg, int v) { return kg + 4 * v; }
+  // row of a 16-row block that lane group kg feeds into K-step s; equal to row(kg, s), so
+  // accumulator register s of a finished block is the B operand of step s
+  static __device__ __forceinline__ int kcol(int kg, int s) { return 4 * s + kg; }
 };
 template <> struct Mfma<float> {
   typedef f4 acc_t;
@@ -369,6 +263,7 @@ template <> struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int kg, int v) { return 4 * kg + v; }
+  static __device__ __forceinline__ int kcol(int kg, int s) { return 4 * kg + s; }
 };
 
 // Each wave owns 16 right columns of one task and every 16-column left tile; it walks
@@ -441,6 +336,111 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
         for (int v = 0; v < 4; ++v) {
           const int a = q * 16 + Mfma<T>::row(kg, v);
           if (a < kl) zpart[(size_t)t * zs_task + (size_t)a * zs_a + bcol] = (double)acc[q][v];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// leaf whitening on matrix cores: dst = sqrt(alpha) L^-1 src for every active panel
+// column of every level, rows of one leaf per work-group, by blocked forward
+// substitution in 16-row blocks:  Y_j = D_j^-1 Y_j;  Y_i -= L_ij Y_j (i > j).
+//
+// The 28 strictly lower 16 x 16 blocks of L (negated) and the 8 diagonal-block inverses
+// D_j^-1 are staged in LDS once (pitch 17).  Each wave owns 16 panel columns at a time
+// and keeps the leaf's 8 row blocks in MFMA accumulators; a finished block's register s
+// is exactly the B operand of K-step s (rows Mfma::kcol), so results feed the next
+// products without moving.  Every column is read once and written once.
+// ---------------------------------------------------------------------------------
+constexpr int WB = BMAX / 16;          // 16-row blocks per leaf (8)
+constexpr int WTRI = WB * (WB + 1) / 2;  // lower blocks (36)
+constexpr int WPD = 17;                // LDS pitch of a staged block
+
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
+    const int* __restrict__ leaf_lo, int nleaf, const T* __restrict__ leafL,
+    const T* __restrict__ leafLinv, int Bc, double alpha_v, const double* __restrict__ alpha_p,
+    const double* __restrict__ src, T* __restrict__ dst, int K, const int* __restrict__ coff,
+    const int* __restrict__ kmax, int L) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int b = blockIdx.x;
+  if (b >= nleaf) return;
+  const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  const int nb = (m + 15) >> 4;
+  __shared__ T Ls[WTRI * 16 * WPD];
+  const T* Lg = leafL + (size_t)b * Bc * Bc;
+  const T* Dg = leafLinv + (size_t)b * Bc * Bc;
+  // stage: element (r, c) of block t = (bi, bj) at Ls[t*16*WPD + r*WPD + c]; r runs
+  // fastest so that reads of the column-major factors are contiguous
+  for (int idx = threadIdx.x; idx < WTRI * 256; idx += NTHREADS) {
+    const int t = idx >> 8, e = idx & 255, r = e & 15, c = e >> 4;
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int gr = bi * 16 + r, gcol = bj * 16 + c;
+    T v = T(0);
+    if (bi == bj) {
+      if (gr < m && c <= r) v = Dg[gr + (size_t)gcol * Bc];
+    } else if (bi < nb && gr < m) {
+      v = -Lg[gr + (size_t)gcol * Bc];
+    }
+    Ls[t * 16 * WPD + r * WPD + c] = v;
+  }
+  __syncthreads();
+  const double alpha = alpha_p ? *alpha_p : alpha_v;
+  const T sa = (T)sqrt(alpha);
+  int total = 0;
+  for (int l = 0; l < L; ++l) total += kmax[l];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cl = lane & 15, kg = lane >> 4;
+  for (int p0 = 16 * w; p0 < total; p0 += 64) {
+    int f = p0 + cl, gc = -1;
+    if (f < total) {
+      for (int l = 0; l < L; ++l) {
+        const int km = kmax[l];
+        if (f < km) { gc = coff[l] + f; break; }
+        f -= km;
+      }
+    }
+    acc_t acc[WB];
+#pragma unroll
+    for (int i = 0; i < WB; ++i) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + Mfma<T>::row(kg, v);
+        acc[i][v] = (gc >= 0 && row < m) ? (T)src[pix(lo + row, gc, K)] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WB; ++j) {
+      if (j < nb) {
+        const T* Dj = Ls + (j * (j + 1) / 2 + j) * 16 * WPD + cl * WPD;
+        acc_t y = acc_t{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          y = Mfma<T>::step(Dj[Mfma<T>::kcol(kg, s4)], acc[j][s4], y);
+        acc[j] = y;
+#pragma unroll
+        for (int i = 0; i < WB; ++i) {
+          if (i > j && i < nb) {
+            const T* A = Ls + (i * (i + 1) / 2 + j) * 16 * WPD + cl * WPD;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+              acc[i] = Mfma<T>::step(A[Mfma<T>::kcol(kg, s4)], acc[j][s4], acc[i]);
+          }
+        }
+      }
+    }
+    if (gc >= 0) {
+#pragma unroll
+      for (int bi = 0; bi < WB; ++bi) {
+        if (bi < nb) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = bi * 16 + Mfma<T>::row(kg, v);
+            if (row < m) dst[pix(lo + row, gc, K)] = sa * acc[bi][v];
+          }
         }
       }
     }
@@ -793,9 +793,15 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
   timer_before(KID_LEAF, s, -1, P, H.kmax, 0);
   k_leaf<T><<<P.nleaf, NTHREADS, 0, s>>>(
       D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
-      diag, Bc, leafL, leafLinv, F.leaf_ld, F.status, H.panel, panel, P.Ktot, D.coff, H.kmax,
-      P.L);
+      diag, Bc, leafL, leafLinv, F.leaf_ld, F.status);
   timer_after(KID_LEAF, s);
+  if (P.L > 0) {
+    timer_before(KID_WHITEN, s, -1, P, H.kmax, 0);
+    k_whiten<T><<<P.nleaf, NTHREADS, 0, s>>>(D.leaf_lo, P.nleaf, leafL, leafLinv, Bc, F.alpha,
+                                             alpha_dev, H.panel, panel, P.Ktot, D.coff, H.kmax,
+                                             P.L);
+    timer_after(KID_WHITEN, s);
+  }
   static bool lds_set = false;  // raised once to the largest size any plan can ask for
   if (!lds_set) {
     (void)hipFuncSetAttribute((const void*)k_node_factor,

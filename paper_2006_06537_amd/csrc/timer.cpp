@@ -74,8 +74,10 @@ static double launch_bytes(const Rec& r, const std::vector<int>& km) {
   double K = 0;
   for (int l = 0; l < r.L; ++l) K += km[l];
   switch (r.kid) {
-    case KID_LEAF:  // x, panel rows in and out, L and L^-1 (lower triangles)
-      return 8.0 * (n + 2.0 * n * K + 2.0 * r.sum_leaf_tri);
+    case KID_LEAF:  // x in; L (lower triangle) and its 16 x 16 diagonal-block inverses out
+      return 8.0 * (n + r.sum_leaf_tri + 8.5 * n);
+    case KID_WHITEN:  // L, the diagonal-block inverses and every active panel row in, rows out
+      return 8.0 * (2.0 * n * K + r.sum_leaf_tri + 8.5 * n);
     case KID_REDUCE: {  // every right column of the level read once + partial sums
       double W = 0;
       for (int l = 0; l <= r.level; ++l) W += km[l];
@@ -97,7 +99,7 @@ extern "C" {
 
 fg_status fg_timer_start(int32_t kernel_id) {
   using namespace fg;
-  if (kernel_id < KID_LEAF || kernel_id > KID_UPDATE) return FG_EINVAL;
+  if (kernel_id < KID_LEAF || kernel_id > KID_WHITEN) return FG_EINVAL;
   for (auto e : g_t.ev) hipEventDestroy(e);
   g_t.ev.clear();
   g_t.recs.clear();
