@@ -100,6 +100,7 @@ __device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
   return ls;
 }
 
+#define LT(i, j) ((i) * ((i) + 1) / 2 + (j))
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
@@ -126,19 +127,20 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
   for (int r = threadIdx.x; r < m; r += NTHREADS) xs[r] = x[lo + r];
   __syncthreads();
-  T a[LE][LE];
+  // block-lower part only: element (16 i + tr, 16 jj + tc), jj <= i, at a[LT(i, jj)]
+  T a[LE * (LE + 1) / 2];
 #pragma unroll
   for (int i = 0; i < LE; ++i) {
     const int r = LG * i + tr;
 #pragma unroll
-    for (int jj = 0; jj < LE; ++jj) {
+    for (int jj = 0; jj <= i; ++jj) {
       const int c = LG * jj + tc;
       double v = (r == c) ? 1.0 : 0.0;
       if (r < m && c < m) {
         v = alpha * kern1(kind, ell, xs[r], xs[c]);
         if (r == c) v += alpha * nugget + beta + (diag ? diag[lo + r] : 0.0);
       }
-      a[i][jj] = (T)v;  // entries are formed in FP64 and stored in T
+      a[LT(i, jj)] = (T)v;  // entries are formed in FP64 and stored in T
     }
   }
   // blocked Cholesky
@@ -147,10 +149,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
 #pragma unroll
-      for (int jj = 0; jj < LE; ++jj) {
+      for (int jj = 0; jj <= i; ++jj) {
         if (jj == kb) {
-          if (i == kb) Dk[tr * LPD + tc] = a[i][jj];
-          if (i > kb && i < nb) Pp[(LG * i + tr) * LPD + tc] = a[i][jj];
+          if (i == kb) Dk[tr * LPD + tc] = a[LT(i, jj)];
+          if (i > kb && i < nb) Pp[(LG * i + tr) * LPD + tc] = a[LT(i, jj)];
         }
       }
     }
@@ -166,24 +168,20 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     T* L1 = Lp;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
-      if (i == kb) {
-#pragma unroll
-        for (int jj = 0; jj < LE; ++jj)
-          if (jj == kb) a[i][jj] = Lk[tr * LPD + tc];
-      }
+      if (i == kb) a[LT(i, i)] = Lk[tr * LPD + tc];
       if (i > kb && i < nb) {
         // L[i][kb] = A[i][kb] L_kk^-T : row (16 i + tr) of the panel times column tc of Li'
         T s = T(0);
 #pragma unroll
         for (int t = 0; t < 16; ++t) s += Pp[(LG * i + tr) * LPD + t] * Li[tc * LPD + t];
 #pragma unroll
-        for (int jj = 0; jj < LE; ++jj)
-          if (jj == kb) a[i][jj] = s;
+        for (int jj = 0; jj < i; ++jj)
+          if (jj == kb) a[LT(i, jj)] = s;
         L1[(LG * i + tr) * LPD + tc] = s;
       }
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 2
     for (int t = 0; t < 16; ++t) {
       T lr[LE], lc[LE];
 #pragma unroll
@@ -195,8 +193,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       for (int i = 0; i < LE; ++i) {
         if (i > kb && i < nb) {
 #pragma unroll
-          for (int jj = 0; jj < LE; ++jj)
-            if (jj > kb && jj <= i) a[i][jj] -= lr[i] * lc[jj];
+          for (int jj = 0; jj <= i; ++jj)
+            if (jj > kb) a[LT(i, jj)] -= lr[i] * lc[jj];
         }
       }
     }
@@ -214,9 +212,9 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   for (int jj = 0; jj < LE; ++jj) {
     const int c = LG * jj + tc;
 #pragma unroll
-    for (int i = 0; i < LE; ++i) {
+    for (int i = jj; i < LE; ++i) {
       const int r = LG * i + tr;
-      if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[i][jj];  // lower triangle only
+      if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[LT(i, jj)];  // lower triangle only
     }
   }
   // the inverses of the 16 x 16 diagonal blocks (from the diagonal factorizations) go to
@@ -229,6 +227,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       Lig[(kb * 16 + r) + (size_t)(kb * 16 + c) * Bc] = Likk[kb * (16 * LPD) + r * LPD + c];
   }
 }
+
+#undef LT
 
 // ---------------------------------------------------------------------------------
 // level reduce (panel x panel): Z[a][b] = sum_i P[i, coff_l + a] P[i, rcols_l[b]]
