@@ -45,57 +45,75 @@ constexpr int LG = 16;        // thread grid side
 constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
 constexpr int LPD = 17;       // LDS pitch of 16-wide rows
 
-// wave 0: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD); writes L into
-// Lk and L^-1 into Lik (LDS, pitch LPD, zero upper triangles); returns the sum of the
-// log pivots (all lanes) and flags a non-positive pivot.
+// broadcast of lane `l`'s value to the whole wave (a register read, no LDS round trip)
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// One wave: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD).  Lane r (and its
+// copies r + 16, r + 32, r + 48) owns row r; pivots and finished rows travel by register
+// broadcast.  Writes L into Lk and L^-1 into Lik (LDS, pitch LPD, zero upper triangles);
+// returns the sum of the log pivots (every lane) and flags a non-positive pivot.
 template <typename T>
 __device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
   const int lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
-  T d[4], x[4];
+  const int r = lane & 15;
+  T row[16], x[16], inv[16];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    d[v] = Dk[r * LPD + 4 * g + v];
-    x[v] = (r == 4 * g + v) ? T(1) : T(0);
-  }
-  double ls = 0.0;
+  for (int c = 0; c < 16; ++c) row[c] = Dk[r * LPD + c];
+  // right-looking Cholesky on rows: column j scaled by 1/sqrt(pivot), then the rows
+  // below take the rank-one update with row j's finished column entries
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int gj = j >> 2, vj = j & 3;
-    const T colv = d[vj];
-    const T piv = __shfl(colv, j + 16 * gj, 64);
+    const T piv = bcast(row[j], j);
     const bool ok = piv > T(0);
     bad |= !ok;
-    const T inv = ok ? T(1) / sqrt(piv) : T(1);
-    ls += ok ? log((double)piv) : 0.0;
-    const T lrj = __shfl(colv, r + 16 * gj, 64) * inv;
-    T lcj[4];
+    const T sq = ok ? sqrt(piv) : T(1);
+    inv[j] = T(1) / sq;
+    const T lrj = (r > j) ? row[j] * inv[j] : ((r == j) ? sq : T(0));
+    row[j] = lrj;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) lcj[v] = __shfl(colv, 4 * g + v + 16 * gj, 64) * inv;
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (r > j && 4 * g + v > j) d[v] -= lrj * lcj[v];
-    if (g == gj) d[vj] = (r >= j) ? lrj : T(0);
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int gj = j >> 2, vj = j & 3;
-    const T ljj = __shfl(d[vj], j + 16 * gj, 64);
-    const T lrj = __shfl(d[vj], r + 16 * gj, 64);
-    T xj[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) xj[v] = __shfl(x[v], j + 16 * g, 64) / ljj;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (r > j) x[v] -= lrj * xj[v];
-      else if (r == j) x[v] = xj[v];
+    for (int c = j + 1; c < 16; ++c) {
+      const T lcj = bcast(row[j], c);
+      if (c <= r) row[c] -= lrj * lcj;
     }
   }
+  // L^-1 by rows: x = e_r, then for k = 0..15 row k is finished by lane k and
+  // broadcast to the rows below it
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int c = 4 * g + v;
-    Lk[r * LPD + c] = (c <= r) ? d[v] : T(0);
-    Lik[r * LPD + c] = (c <= r) ? x[v] : T(0);
+  for (int c = 0; c < 16; ++c) x[c] = (c == r) ? T(1) : T(0);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (r == k) {
+#pragma unroll
+      for (int c = 0; c <= k; ++c) x[c] *= inv[k];
+    }
+    const T lrk = row[k];
+#pragma unroll
+    for (int c = 0; c <= k; ++c) {
+      const T xk = bcast(x[c], k);
+      if (r > k) x[c] -= lrk * xk;
+    }
+  }
+  // log pivots: lane r takes 2 log L[r][r], summed over the 16 rows
+  T dr = T(1);
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (c == r) dr = row[c];
+  double ls = (dr > T(0)) ? 2.0 * log((double)dr) : 0.0;
+  for (int o = 8; o > 0; o >>= 1) ls += __shfl_xor(ls, o, 16);
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      Lk[r * LPD + c] = (c <= r) ? row[c] : T(0);
+      Lik[r * LPD + c] = (c <= r) ? x[c] : T(0);
+    }
   }
   return ls;
 }
@@ -157,10 +175,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if ((threadIdx.x >> 6) == (kb & 3)) {  // the factoring wave rotates over the SIMDs
       bool wb = false;
       const double ls = diag_factor16(Dk, Lk, Likk + kb * (16 * LPD), wb);
-      if (threadIdx.x == 0) ldsum += ls;
+      if ((threadIdx.x & 63) == 0) ldsum += ls;
       if (wb) bad = 1;
     }
     __syncthreads();
