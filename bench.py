@@ -15,6 +15,8 @@ Other workloads (--workload), each printing its own JSON line:
           graphs; value = chain sweeps per second over all chains.  The same chains
           stepped one after the other (gibbs_step) are timed beside it.
   tensor  the d = 4, n = 65,536 tensor-product surface chain; value = sweeps/s.
+  copy    a plain 2 GiB FP64 copy kernel (one read, one write of 2 GiB per launch): the
+          calibration run for the HBM byte counters (FETCH_SIZE, WRITE_SIZE).
   serve   GP-regression jobs of mixed n (workloads.served_jobs) through the serving
           loop: first all at once (saturation throughput), then Poisson arrivals at
           0.7 x that rate; value = p50 latency (s), with p99 and the same arrival list
@@ -43,16 +45,57 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--workload", default="large_1d",
-                    choices=["large_1d", "batch", "tensor", "serve"])
+                    choices=["large_1d", "batch", "tensor", "serve", "copy"])
     ap.add_argument("--jobs", type=int, default=64, help="serve workload: number of jobs")
     ap.add_argument("--job-iters", type=int, default=20, help="serve workload: sweeps per job")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturation")
     ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: M~ factored in FP32, its solves refined by PCG to 1e-10")
-    ap.add_argument("--kernel", type=int, default=1,
-                    help="kernel timed for the roofline: 1 leaf, 2 level reduce, 3 level update")
+    ap.add_argument("--kernel", type=int, default=2,
+                    help="kernel timed for the roofline: 1 leaf Cholesky, 2 level reduce (the "
+                         "largest total time), 3 level update, 4 leaf whitening")
     return ap.parse_args()
+
+
+def counter_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed counter summary, if the
+    library sources are still the ones it was taken on (else None)."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_large_1d.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2006_06537_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest()[:16] != doc.get("source_hash"):
+        return None
+    for key in (f"fg::{kernel_name}<double>", f"fg::{kernel_name}"):
+        if key in doc["kernels"]:
+            return doc["kernels"][key]["traffic_bytes"]
+    return None
+
+
+def bench_copy(args):
+    import torch
+    n = (2 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 3
+    print(json.dumps({"metric": "copy bandwidth (counter calibration)", "value": 2 * 8 * n / dt / 1e9,
+                      "unit": "GB/s", "bytes_read_per_launch": 8 * n,
+                      "bytes_written_per_launch": 8 * n}), flush=True)
 
 
 def cpu_baseline(x, y, cfg):
@@ -277,6 +320,8 @@ def main():
         return bench_tensor(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     import numpy as np
     import torch
 
@@ -327,7 +372,7 @@ def main():
         achieved = kbytes / (ktime_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": timer.name, "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "launches": launches,
+                "traffic": counter_traffic(timer.name), "launches": launches,
                 "avg_launch_us": 1e3 * ktime_ms / launches,
                 "algorithmic_bytes_per_launch": kbytes / launches,
                 "isolated_avg_launch_us": iso_us,

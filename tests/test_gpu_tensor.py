@@ -1,8 +1,11 @@
 """Parity of the tensor-product path (Algorithm 1.h and the tensor sweep, through the
 C ABI) with the oracle, on the same seeded inputs.
 
-Tolerance: relative 1e-9 (2-norm) for vectors and scalars, exact for grid indices,
-proposals and accept flags -- the bar used for the 1-D sampler's draws.  The
+Tolerance: relative 1e-9 (2-norm) for scalars, exact for grid indices, proposals and
+accept flags -- the bar used for the 1-D sampler's draws.  The factors f_h contain
+W_h b, a product with the symmetric factor of K~_h (nugget 1e-6), which the factor
+parity tests hold to max(1e-9, 2 u kappa(leaf)) (leaf Cholesky forward error); each f_h
+is held to that same bar.  The
 quadratic forms q = |W_h^-1 f_h|^2 carry twice the bar of a W^-1 product of K~_h,
 max(1e-9, 2 u kappa(leaf)) -- the leaf Cholesky forward-error bound of the factor
 parity tests -- and the Metropolis log ratio D = -1/2 (l' - l) - (q' - q)/2, a
@@ -83,6 +86,12 @@ def _tw(o, h, k):
     return max(1e-9, 2.0 * 2.0 ** -53 * kap)
 
 
+def _check_factors(F, o, ks):
+    for h in range(o.d):
+        bar = max(_tw(o, h, k) for k in ks[h])
+        assert rel(F[h], o.F[h]) <= bar, (h, rel(F[h], o.F[h]), bar)
+
+
 def _compare(s, r, o, it, kb):
     d = o.d
     assert s["k"] == r["k"], (it, s["k"], r["k"])
@@ -108,23 +117,28 @@ def _compare(s, r, o, it, kb):
 @pytest.mark.parametrize("positive", [False, True], ids=["sin-sqrt", "positive"])
 def test_tensor_chain_matches_oracle(positive):
     g, o = _pair(3, 2000, 64, 1e-10, (0.05, 0.1, 0.2), 3, positive=positive)
+    seen = [set() for _ in range(o.d)]
     for it in range(4):
         g.step(1)
         s = g.state(with_factors=(it == 3))
         kb = list(o.k)
+        for h in range(o.d):
+            seen[h].add(kb[h])
         r = o.step()
         _compare(s, r, o, it, kb)
-    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+    _check_factors(s["F"].cpu().numpy(), o, seen)
 
 
 def test_tensor_chain_one_factor_ragged():
     g, o = _pair(1, 777, 32, 1e-10, (0.07,), 8)
+    seen = [set()]
     for it in range(3):
         g.step(1)
         s = g.state(with_factors=True)
         kb = list(o.k)
+        seen[0].add(kb[0])
         _compare(s, o.step(), o, it, kb)
-    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+    _check_factors(s["F"].cpu().numpy(), o, seen)
 
 
 def test_tensor_chain_full_size_first_sweep():
@@ -135,7 +149,7 @@ def test_tensor_chain_full_size_first_sweep():
     s = g.state(with_factors=True)
     kb = list(o.k)
     _compare(s, o.step(), o, 0, kb)
-    assert rel(s["F"].cpu().numpy(), o.F) <= 1e-9
+    _check_factors(s["F"].cpu().numpy(), o, [{k} for k in kb])
 
 
 def test_tensor_chain_deterministic():
