@@ -289,7 +289,7 @@ template <> struct Mfma<float> {
 // 16-row group, K-slot k holds row base + 4k + s, so lane l reads rows base + 4 (l/16)
 // .. +3 of its column: 32 contiguous bytes, and the four steps use each 128-byte line
 // of the 16-row tile completely.
-template <typename T>
+template <typename T, int NA>
 __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
     const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ coff,
     const int* __restrict__ kmax, const int* __restrict__ rcols, const int* __restrict__ rcount,
@@ -302,53 +302,59 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
   const int b0 = blockIdx.y * 64 + wv * 16;
   if (b0 >= W || kl == 0) return;
   const Task tk = tasks[tbase + t];
-  const int na = (kl + 15) >> 4;
+  const int na = min(NA, (kl + 15) >> 4);  // left tiles in use (NA: capacity of the level)
   const int cl = lane & 15, kg = lane >> 4;
   const int bcol = b0 + cl;
   const int gcb = bcol < W ? rcols[(size_t)l * K + bcol] : -1;
-  int acol[4];
+  int acol[NA];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acol[q] = (q * 16 + cl < kl) ? c0 + q * 16 + cl : -1;
-  acc_t acc[4];
+  for (int q = 0; q < NA; ++q) acol[q] = (q * 16 + cl < kl) ? c0 + q * 16 + cl : -1;
+  acc_t acc[NA];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = acc_t{T(0), T(0), T(0), T(0)};
+  for (int q = 0; q < NA; ++q) acc[q] = acc_t{T(0), T(0), T(0), T(0)};
   const bool aligned = ((tk.r0 | tk.r1) & 15) == 0;
-  for (int base = tk.r0; base < tk.r1; base += 16) {
-    T bv[4];
-    if (aligned) {
+  // operands of one 16-row group: bv (this wave's 16 right columns) and av[q] (left tile q)
+  auto load = [&](int base, T (&bv)[4], T (&av)[NA][4]) {
+    if (aligned && base < tk.r1) {
       const T* pb = P + pix(base + 4 * kg, gcb < 0 ? 0 : gcb, K);
 #pragma unroll
       for (int s = 0; s < 4; ++s) bv[s] = gcb >= 0 ? pb[s] : T(0);
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const T* pa = P + pix(base + 4 * kg, acol[q] < 0 ? 0 : acol[q], K);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[q][s] = (q < na && acol[q] >= 0) ? pa[s] : T(0);
+      }
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int row = base + 4 * kg + s;
         bv[s] = (gcb >= 0 && row < tk.r1) ? P[pix(row, gcb, K)] : T(0);
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+          av[q][s] = (q < na && acol[q] >= 0 && row < tk.r1) ? P[pix(row, acol[q], K)] : T(0);
       }
     }
+  };
+  auto mfma = [&](const T (&bv)[4], const T (&av)[NA][4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q)
       if (q < na) {
-        T av[4];
-        if (aligned) {
-          const T* pa = P + pix(base + 4 * kg, acol[q] < 0 ? 0 : acol[q], K);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) av[s] = acol[q] >= 0 ? pa[s] : T(0);
-        } else {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int row = base + 4 * kg + s;
-            av[s] = (acol[q] >= 0 && row < tk.r1) ? P[pix(row, acol[q], K)] : T(0);
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc[q] = Mfma<T>::step(av[s], bv[s], acc[q]);
+        for (int s = 0; s < 4; ++s) acc[q] = Mfma<T>::step(av[q][s], bv[s], acc[q]);
       }
-    }
+  };
+  // two row groups per step: both groups' loads are in flight before their products
+  for (int base = tk.r0; base < tk.r1; base += 32) {
+    T bv0[4], av0[NA][4], bv1[4], av1[NA][4];
+    load(base, bv0, av0);
+    load(base + 16, bv1, av1);
+    mfma(bv0, av0);
+    mfma(bv1, av1);
   }
   if (bcol < W) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q) {
       if (q < na) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -760,16 +766,30 @@ __global__ void __launch_bounds__(NTHREADS) k_update_panel(
     }
     if (threadIdx.x < 64) ycol[threadIdx.x] = threadIdx.x < bw ? yc[bt + threadIdx.x] : 0;
     __syncthreads();
+#pragma unroll 1
     for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+#pragma unroll 1
       for (int a0 = 0; a0 < k; a0 += 16) {
         T v[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a) v[a] = (a0 + a < k) ? P[pix(r, c0 + a0 + a, K)] : T(0);
-        for (int b = 0; b < bw; ++b) {
-          T acc = T(0);
+        // 8 coarser columns at a time: their loads are issued together before any store
+        // (the columns are distinct, so no store can feed a later load)
+#pragma unroll 1
+        for (int b0 = 0; b0 < bw; b0 += 8) {
+          T old[8];
 #pragma unroll
-          for (int a = 0; a < 16; ++a) acc += v[a] * As[a0 + a][b];
-          P[pix(r, ycol[b], K)] += acc;
+          for (int j = 0; j < 8; ++j)
+            old[j] = (b0 + j < bw) ? P[pix(r, ycol[b0 + j], K)] : T(0);
+#pragma unroll 2
+          for (int a = 0; a < 16; ++a) {
+            const T va = v[a];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) old[j] += va * As[a0 + a][(b0 + j) & 63];
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (b0 + j < bw) P[pix(r, ycol[b0 + j], K)] = old[j];
         }
       }
     }
@@ -833,8 +853,11 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
     const int zs_a = Wcap, zs_task = P.kcap[l] * Wcap;
     timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
     const dim3 grid_r(nt, (Wcap + 63) / 64);
-    k_reduce_panel<T><<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols,
-                                                  H.rcount, P.Ktot, panel, F.zpart, zs_a, zs_task);
+    const int na_cap = std::max(1, std::min(4, (P.kcap[l] + 15) / 16));
+    auto rp = na_cap == 1 ? k_reduce_panel<T, 1> : na_cap == 2 ? k_reduce_panel<T, 2>
+            : na_cap == 3 ? k_reduce_panel<T, 3> : k_reduce_panel<T, 4>;
+    rp<<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols, H.rcount, P.Ktot,
+                                   panel, F.zpart, zs_a, zs_task);
     timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
     launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
