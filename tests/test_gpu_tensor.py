@@ -5,7 +5,9 @@ Tolerance: relative 1e-9 (2-norm) for scalars, exact for grid indices, proposals
 accept flags -- the bar used for the 1-D sampler's draws.  The factors f_h contain
 W_h b, a product with the symmetric factor of K~_h (nugget 1e-6), which the factor
 parity tests hold to max(1e-9, 2 u kappa(leaf)) (leaf Cholesky forward error); each f_h
-is held to that same bar.  The
+is held to that same bar, and the scalars built on the product G = prod_h f_h carry the
+sum of the factors' bars (beta), magnified by 2 |beta G| / |y - beta G| for the residual
+sum of squares and tau.  The
 quadratic forms q = |W_h^-1 f_h|^2 carry twice the bar of a W^-1 product of K~_h,
 max(1e-9, 2 u kappa(leaf)) -- the leaf Cholesky forward-error bound of the factor
 parity tests -- and the Metropolis log ratio D = -1/2 (l' - l) - (q' - q)/2, a
@@ -97,9 +99,15 @@ def _compare(s, r, o, it, kb):
     assert s["k"] == r["k"], (it, s["k"], r["k"])
     assert s["last_proposal"] == r["proposal"], it
     assert s["last_accept"] == [int(a) for a in r["accept"]], it
+    # G = prod_h f_h carries the factors' bars (added); sse = |y - beta G|^2 magnifies an
+    # error in beta G by 2 |beta G| / |y - beta G|, and tau follows sse
+    tws = sum(_tw(o, h, kb[h]) for h in range(d))
+    bG = abs(r["beta"]) * float(np.linalg.norm(o.product()))
+    bars = {"beta": 2 * tws, "beta_mean": 2 * tws, "beta_sd": 2 * tws,
+            "sse": 2 * tws * bG / np.sqrt(r["sse"]), "tau": 2 * tws * bG / np.sqrt(r["sse"])}
     for key in ["tau", "beta", "sse", "beta_mean", "beta_sd"]:
         ref = r[key]
-        assert abs(s[key] - ref) <= 1e-9 * abs(ref), (it, key, s[key], ref)
+        assert abs(s[key] - ref) <= max(1e-9, bars[key]) * abs(ref), (it, key, s[key], ref)
     for h in range(d):
         # q = |W_h^-1 f_h|^2: twice the relative bar of W_h^-1 (plus its square)
         tq = _tw(o, h, r["k"][h])
