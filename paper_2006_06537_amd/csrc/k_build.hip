@@ -86,34 +86,80 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ t
 // ---------------------------------------------------------------------------------
 // small dense helpers on LDS matrices (column-major, leading dimension ldm)
 // ---------------------------------------------------------------------------------
-// in-place lower Cholesky of an m x m SPD matrix; returns false on a non-positive pivot
-__device__ bool lds_cholesky(double* A, int m, int ldm) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
+// Cholesky with diagonal pivoting of an m x m positive semidefinite Gram matrix G (full
+// symmetric storage): P G P' = L L', taking the largest remaining diagonal at each step and
+// stopping once it falls to the rounding level 64 m u max diag(G) (the stopping rule for
+// semidefinite matrices, Higham 1990).  Repeated inputs make G singular: a window with
+// more data points than interpolation nodes but fewer distinct values has rank < m.  On
+// return A holds F = P' L (row i: basis function i; column a: step a; columns >= rank are
+// zero), so that G = F F', and perm[a] is the basis function pivoted at step a.  tmp is an
+// m x m LDS scratch.  Returns the rank, or -1 on a NaN diagonal.
+__device__ int lds_pchol(double* A, int m, int ldm, int* perm, double* tmp) {
+  __shared__ int rk, piv, bad;
+  __shared__ double dfloor;
+  if (threadIdx.x == 0) {
+    double dmax = 0.0;
+    bad = 0;
+    for (int j = 0; j < m; ++j) {
+      const double d = A[j + j * ldm];
+      if (d != d) bad = 1;
+      dmax = fmax(dmax, d);
+      perm[j] = j;
+    }
+    dfloor = 64.0 * m * (DBL_EPSILON * 0.5) * dmax;
+    rk = m;
+  }
   __syncthreads();
+  if (bad) return -1;
   for (int j = 0; j < m; ++j) {
     if (threadIdx.x == 0) {
-      const double d = A[j + j * ldm];
-      if (!(d > 0.0)) bad = 1;
-      A[j + j * ldm] = d > 0.0 ? sqrt(d) : 1.0;
+      int k = j;
+      for (int i = j + 1; i < m; ++i)
+        if (A[i + i * ldm] > A[k + k * ldm]) k = i;
+      if (A[k + k * ldm] > dfloor) {
+        piv = k;
+        const int t = perm[j]; perm[j] = perm[k]; perm[k] = t;
+      } else {
+        piv = -1;
+        rk = j;
+      }
     }
     __syncthreads();
-    const double ljj = A[j + j * ldm];
+    const int k = piv;
+    if (k < 0) break;
+    if (k != j) {  // symmetric interchange of rows and columns j and k
+      for (int i = threadIdx.x; i < m; i += NTHREADS) {
+        const double t = A[j + i * ldm]; A[j + i * ldm] = A[k + i * ldm]; A[k + i * ldm] = t;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += NTHREADS) {
+        const double t = A[i + j * ldm]; A[i + j * ldm] = A[i + k * ldm]; A[i + k * ldm] = t;
+      }
+      __syncthreads();
+    }
+    const double ljj = sqrt(A[j + j * ldm]);
+    __syncthreads();
+    if (threadIdx.x == 0) A[j + j * ldm] = ljj;
     for (int r = j + 1 + threadIdx.x; r < m; r += NTHREADS) A[r + j * ldm] /= ljj;
     __syncthreads();
     const int w = m - j - 1;
     for (int idx = threadIdx.x; idx < w * w; idx += NTHREADS) {
       const int r = j + 1 + idx % w, cc = j + 1 + idx / w;
-      if (cc <= r) A[r + cc * ldm] -= A[r + j * ldm] * A[cc + j * ldm];
+      A[r + cc * ldm] -= A[r + j * ldm] * A[cc + j * ldm];
     }
     __syncthreads();
   }
+  const int r = rk;
+  // F[perm[a], b] = L[a, b] for b <= a, b < rank
   for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS) {
-    const int r = idx % m, cc = idx / m;
-    if (cc > r) A[r + cc * ldm] = 0.0;
+    const int a = idx % m, b = idx / m;
+    tmp[perm[a] + b * m] = (b <= a && b < r) ? A[a + b * ldm] : 0.0;
   }
   __syncthreads();
-  return bad == 0;
+  for (int idx = threadIdx.x; idx < m * m; idx += NTHREADS)
+    A[idx % m + (idx / m) * ldm] = tmp[idx];
+  __syncthreads();
+  return r;
 }
 
 // One-sided Jacobi on the columns of M (mr x qc, mr >= qc) with right vectors Q (qc x qc).
@@ -231,9 +277,10 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     }
   }
   __syncthreads();
-  const bool okI = lds_cholesky(GI, pI, ld);
-  const bool okJ = lds_cholesky(GJ, pJ, ld);
-  if (!okI || !okJ) {
+  __shared__ int permI[PMAX], permJ[PMAX];
+  const int rkI = lds_pchol(GI, pI, ld, permI, Tm);
+  const int rkJ = lds_pchol(GJ, pJ, ld, permJ, Tm);
+  if (rkI < 0 || rkJ < 0) {
     if (threadIdx.x == 0) { atomicOr(status, ST_NOTSPD); rank[h] = 0; }
     return;
   }
@@ -282,11 +329,11 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
       Cm[idx % pI + (idx / pI) * ld] = Tm[idx % pI + (idx / pI) * ld];
     __syncthreads();
   }
-  // X = L_I' C_T L_J   (G = L L', R = L')
+  // X = F_I' C_T F_J   (G = F F', F = P' L)
   for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
     const int r = idx % pI, t = idx / pI;
     double acc = 0.0;
-    for (int s = r; s < pI; ++s) acc += GI[s + r * ld] * Cm[s + t * ld];
+    for (int s = 0; s < pI; ++s) acc += GI[s + r * ld] * Cm[s + t * ld];
     Tm[r + t * ld] = acc;
   }
   __syncthreads();
@@ -295,7 +342,7 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
   for (int idx = threadIdx.x; idx < pI * pJ; idx += NTHREADS) {
     const int r = idx % pI, t = idx / pI;
     double acc = 0.0;
-    for (int s = t; s < pJ; ++s) acc += Tm[r + s * ld] * GJ[s + t * ld];
+    for (int s = 0; s < pJ; ++s) acc += Tm[r + s * ld] * GJ[s + t * ld];
     if (trans) Cm[t + r * ld] = acc; else Cm[r + t * ld] = acc;
   }
   __syncthreads();
@@ -324,7 +371,8 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
   }
   __syncthreads();
   if (threadIdx.x < qc) sv[(size_t)h * PMAX + threadIdx.x] = sig[order[threadIdx.x]];
-  // T_U = L_I^-T (U_X sqrt s), T_V = L_J^-T (V_X sqrt s)
+  // T_U = F_I^-T (U_X sqrt s), T_V = F_J^-T (V_X sqrt s); F' is upper triangular in the
+  // pivot order, and the unknowns of steps at or beyond the rank are zero
   const int k = kk;
   const int kc = kcap[q.level];
   double* TU = tbuf + q.toff_u;
@@ -335,18 +383,18 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     const int j = order[c];
     const double sj = sig[j], rs = sqrt(sj);
     const int p = side ? pJ : pI;
-    const double* L = side ? GJ : GI;
+    const int rkp = side ? rkJ : rkI;
+    const int* pv = side ? permJ : permI;
+    const double* F = side ? GJ : GI;
     double* out = side ? (TV + (size_t)c * pJ) : (TU + (size_t)c * pI);
-    // rhs entries: left vector if (side == 0) != trans ... see orientation table
     // no transpose: U_X = M[:,j]/s_j (length pI), V_X = Q[:,j] (length pJ)
     // transpose   : U_X = Q[:,j] (length pI),   V_X = M[:,j]/s_j (length pJ)
     const bool fromM = (side == 0) != trans;
-    // back substitution L' y = rhs, written directly into out
-    for (int r = p - 1; r >= 0; --r) {
-      const double rhs = fromM ? Cm[r + j * ld] / sj * rs : Vm[r + j * ld] * rs;
-      double acc = rhs;
-      for (int s = r + 1; s < p; ++s) acc -= L[s + r * ld] * out[s];
-      out[r] = acc / L[r + r * ld];
+    for (int a = p - 1; a >= 0; --a) {
+      if (a >= rkp) { out[pv[a]] = 0.0; continue; }
+      double acc = fromM ? Cm[a + j * ld] / sj * rs : Vm[a + j * ld] * rs;
+      for (int b = a + 1; b < rkp; ++b) acc -= F[pv[b] + a * ld] * out[pv[b]];
+      out[pv[a]] = acc / F[pv[a] + a * ld];
     }
   }
   (void)kc;

@@ -16,10 +16,10 @@ Tolerances
 """
 import numpy as np
 import pytest
-import scipy.linalg as sla
 
 from oracle import hodlr as oh, kernels, kalman, rng, sampler
 from workloads import small_1d, sinusoid_1d
+from bands import InvLeafFactor
 
 pytestmark = pytest.mark.gpu
 
@@ -35,31 +35,6 @@ def rel(a, b):
     a = np.asarray(a, float)
     b = np.asarray(b, float)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-class InvLeafFactor(oh.Factor):
-    """The oracle factor with an unblocked column-by-column leaf Cholesky and explicit
-    leaf inverses: an equally valid FP64 evaluation of the same W, used only to measure
-    the oracle's reproducibility band."""
-
-    @staticmethod
-    def _leaf_chol(A):
-        A = np.array(A, dtype=np.float64, copy=True)
-        m = A.shape[0]
-        for j in range(m):
-            if not A[j, j] > 0.0:
-                raise np.linalg.LinAlgError("not positive definite")
-            A[j, j] = np.sqrt(A[j, j])
-            A[j + 1:, j] /= A[j, j]
-            A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j + 1:, j])
-        return np.tril(A)
-
-    def _leaf_solve(self, start, Y, trans=False):
-        Y = np.array(Y, dtype=np.float64, copy=True)
-        for a, c, Lb in self._leaf_iter(start, Y.shape[0]):
-            Li = sla.solve_triangular(Lb, np.eye(Lb.shape[0]), lower=True)
-            Y[a:c] = (Li.T if trans else Li) @ Y[a:c]
-        return Y
 
 
 CASES = [

@@ -83,6 +83,23 @@ def test_maxnorm_bound_and_spectral_rank(n, leaf, ell, tol, kind):
         assert abs(b.k - r_exact) <= 1, (l, j, b.k, r_exact)
 
 
+def test_repeated_inputs_meet_the_bound():
+    """Repeated inputs (about 50 distinct values among 400 points) leave windows with
+    more points than interpolation nodes but fewer distinct values; the compressed
+    matrix still meets the max-norm bound, the leaves stay exact, and the factor of
+    K~_1 reproduces it."""
+    x = np.sort(np.round(_x(400, 9) * 50) / 50)
+    assert np.unique(x).size < 60
+    for kind, leaf in [(kernels.SE, 32), (kernels.EXP, 16)]:
+        H = hodlr.HODLR(x, kind, 0.05, 1e-6, leaf, 1e-10)
+        A = H.dense()
+        K = kernels.K1_dense(kind, 0.05, 1e-6, x)
+        assert np.abs(A - K).max() <= 1e-10
+        assert np.array_equal(np.diag(A), np.diag(K))
+        W = hodlr.Factor(H, 1.0, 0.0).dense_W()
+        assert np.linalg.norm(W @ W.T - A) / np.linalg.norm(A) < 1e-12
+
+
 def test_single_leaf_is_cholesky():
     x = _x(50, 3)
     H = hodlr.HODLR(x, kernels.SE, 0.2, 1e-6, 64, 1e-10)
