@@ -270,6 +270,40 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
                             double* r_out, double* mu_out, fg_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Function posterior at new inputs (Appendix, "Function posterior at new inputs").
+ * Given the chain's state after its last sweep -- f, sigma_f^2 and the length-scale's
+ * K~_1 = K_1 + eta I with its factor W_1 -- each new input x*_j has
+ *   f*_j | f ~ N(mu*_j, s2*_j),
+ *   mu*_j = k1(x*_j, X) K~_1^-1 f,
+ *   s2*_j = sigma_f^2 (1 + eta - k1(x*_j, X) K~_1^-1 k1(X, x*_j)),
+ * with the nugget read as part of the process (it enters k** as it enters K~_1's diagonal).
+ * The points are drawn from their marginals, independently of each other.  Both terms go
+ * through the factor: with z = W_1^-1 f and Z_j = W_1^-1 k1(X, x*_j),
+ * mu*_j = Z_j . z and s2*_j = sigma_f^2 (1 + eta - |Z_j|^2).
+ *
+ * gibbs_predict_inputs -- copies `nstar` new inputs (device, any order; 0 clears them)
+ *   into the chain.  Z depends on the length-scale only, so the chain keeps it for up to
+ *   `max_grid_points` grid points at once (least recently used evicted; each costs
+ *   8 n nstar bytes of device memory, owned by the chain and freed with it or by the next
+ *   call) -- the pre-solve per grid value the paper suggests.  The first buffer is
+ *   allocated here, the others on first use (a failed allocation there evicts instead).
+ *   Synchronises `stream` first.
+ *   Errors: FG_EINVAL (NULL, nstar < 0 or > 2^31 - 1, max_grid_points < 1), FG_ENOMEM.
+ * gibbs_predict -- one draw per new input: fstar (device, nstar) receives f*, and mu and
+ *   s2 (device, nstar; either may be NULL) the mean and variance.  The normals are the
+ *   Philox stream with tag 8 at iteration = the number of sweeps the chain has made.  Each
+ *   call costs one W_1^-1 f and two length-n reductions per new input, plus, when Z of the
+ *   current grid point is not cached, the kernel columns and nstar / 4 inverse
+ *   applications of W_1.  Enqueued on `stream`, no synchronisation.
+ *   Errors: FG_EINVAL (NULL fstar, no inputs set), FG_EDEVICE.
+ * gibbs_predict_stats -- grid points whose Z is cached, and Z computations so far.
+ * ------------------------------------------------------------------------- */
+fg_status gibbs_predict_inputs(fg_chain c, const double* xstar, int64_t nstar,
+                               int32_t max_grid_points, fg_stream stream);
+fg_status gibbs_predict(fg_chain c, double* fstar, double* mu, double* s2, fg_stream stream);
+fg_status gibbs_predict_stats(fg_chain c, int32_t* cached_grid_points, int64_t* builds);
+
+/* ---------------------------------------------------------------------------
  * Tensor-product surface chain (Section 4.2): y_i = beta prod_h f_h(x[h,i]) + e_i,
  * e_i ~ N(0, 1/tau), f_h unit-variance GPs (kernel `kind`, length-scale on a grid
  * per factor).  One sweep, in order:

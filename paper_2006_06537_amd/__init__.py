@@ -371,6 +371,35 @@ class Chain:
         check(lib().gibbs_chain_state(self._c, C.byref(snap), None, None, None, _stream()))
         return snap.as_dict()
 
+    def predict_inputs(self, xstar, max_grid_points=4):
+        """Set the new inputs of predict() (gibbs_predict_inputs); None clears them.  Z is
+        kept for up to max_grid_points length-scale grid points (8 n m bytes each)."""
+        if xstar is None:
+            check(lib().gibbs_predict_inputs(self._c, None, 0, 1, _stream()))
+            self.nstar = 0
+            return
+        m = int(xstar.shape[0])
+        check(lib().gibbs_predict_inputs(self._c, _dev(xstar, m), m, int(max_grid_points),
+                                         _stream()))
+        self.nstar = m
+
+    def predict_stats(self):
+        """(grid points with Z cached, Z computations so far)."""
+        k = C.c_int32()
+        b = C.c_int64()
+        check(lib().gibbs_predict_stats(self._c, C.byref(k), C.byref(b)))
+        return k.value, b.value
+
+    def predict(self):
+        """One draw of f at the new inputs (gibbs_predict): (f*, mu*, s2*) on the device."""
+        torch = _torch()
+        m = getattr(self, "nstar", 0)
+        fs = torch.empty(max(m, 1), dtype=torch.float64, device="cuda")
+        mu = torch.empty_like(fs)
+        s2 = torch.empty_like(fs)
+        check(lib().gibbs_predict(self._c, _dev(fs), _dev(mu), _dev(s2), _stream()))
+        return fs[:m], mu[:m], s2[:m]
+
     def __del__(self):
         c = getattr(self, "_c", None)
         try:

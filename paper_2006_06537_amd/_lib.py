@@ -23,7 +23,9 @@ EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", 
            "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
            "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
-           "gibbs_step_batch", "gibbs_chain_state", "tp_chain_create", "tp_step", "tp_chain_state",
+           "gibbs_step_batch", "gibbs_chain_state", "gibbs_predict_inputs", "gibbs_predict",
+           "gibbs_predict_stats",
+           "tp_chain_create", "tp_step", "tp_chain_state",
            "fg_footprint_bytes", "serve_create", "serve_submit", "serve_poll", "serve_drain",
            "serve_stats", "serve_destroy", "fg_timer_start", "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
            "factor_destroy", "gibbs_chain_destroy", "tp_chain_destroy"]
@@ -150,6 +152,9 @@ def lib():
         "gibbs_step": ([P, I32, P], I32),
         "gibbs_step_batch": ([C.POINTER(P), I32, I32, I32, I32, P], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),
+        "gibbs_predict_inputs": ([P, DP, I64, I32, P], I32),
+        "gibbs_predict_stats": ([P, C.POINTER(I32), C.POINTER(I64)], I32),
+        "gibbs_predict": ([P, DP, DP, DP, P], I32),
         "fg_footprint_bytes": ([C.POINTER(ChainCfg), P, I64, C.POINTER(U64)], I32),
         "serve_create": ([C.POINTER(ServeCfg), C.POINTER(P)], I32),
         "serve_submit": ([P, C.POINTER(Job), C.POINTER(U64)], I32),

@@ -41,6 +41,18 @@ struct fg_chain_s {
   bool pcg_failed = false;
   hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double* xstar = nullptr;                    // new inputs of the predictive draws
+  int nstar = 0;
+  struct ZEntry {
+    int k;                                    // grid index, -1 = empty
+    double* z;                                // n x nstar: W_1^-1 k1(X, X*) at that grid point
+    uint64_t used;                            // last use, for least-recently-used eviction
+  };
+  std::vector<ZEntry> zcache;                 // at most zcache_cap entries
+  int zcache_cap = 0;
+  uint64_t zclock = 0;
+  int64_t zbuilds = 0;                        // Z computations so far (cache misses)
+  double* pwork = nullptr;                    // W_1^-1 f (n) and the draw's normals (nstar)
   std::map<uint64_t, hipGraphExec_t> graphs;  // captured sweeps by (cur, k, proposal)
   std::vector<uint64_t> graph_order;          // insertion order, for eviction
 };
@@ -68,7 +80,9 @@ static void chain_free(fg_chain c) {
   fg::factor_free(c->WM);
   fg::factor_free(c->WM64);
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
-  double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork};
+  for (auto& e : c->zcache)
+    if (e.z) (void)hipFree(e.z);
+  double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork, c->xstar, c->pwork};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->st) (void)hipFree(c->st);
@@ -501,6 +515,110 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
   host_out->pcg_iters = c->pcg_iters;
   host_out->pcg_relres = c->pcg_relres;
   host_out->precision_used = (c->mixed && !c->fell_back) ? FG_MIXED : FG_FP64;
+  return FG_OK;
+}
+
+static void predict_release(fg_chain c) {
+  for (auto& e : c->zcache)
+    if (e.z) (void)hipFree(e.z);
+  c->zcache.clear();
+  for (double** b : {&c->xstar, &c->pwork}) {
+    if (*b) (void)hipFree(*b);
+    *b = nullptr;
+  }
+  c->nstar = 0;
+  c->zcache_cap = 0;
+}
+
+fg_status gibbs_predict_inputs(fg_chain c, const double* xstar, int64_t nstar,
+                               int32_t max_grid_points, fg_stream stream) {
+  if (!c || nstar < 0 || (nstar > 0 && (!xstar || max_grid_points < 1)))
+    return cfail(FG_EINVAL, "bad arguments");
+  if (nstar > (int64_t)INT32_MAX) return cfail(FG_EINVAL, "too many new inputs");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // work already queued on the stream may still read the old buffers
+  if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "stream failed");
+  predict_release(c);
+  if (nstar == 0) return FG_OK;
+  const size_t n = (size_t)c->n, m = (size_t)nstar;
+  double* z0 = nullptr;
+  if (hipMalloc(&c->xstar, sizeof(double) * m) != hipSuccess ||
+      hipMalloc(&c->pwork, sizeof(double) * (n + m)) != hipSuccess ||
+      hipMalloc(&z0, sizeof(double) * n * m) != hipSuccess) {
+    if (z0) (void)hipFree(z0);
+    predict_release(c);
+    (void)hipGetLastError();
+    return cfail(FG_ENOMEM, "device allocation for the new inputs failed");
+  }
+  c->zcache.push_back({-1, z0, 0});
+  c->zcache_cap = max_grid_points;
+  if (hipMemcpyAsync(c->xstar, xstar, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return cfail(FG_EDEVICE, "copy of the new inputs failed");
+  c->nstar = (int)nstar;
+  return FG_OK;
+}
+
+// The Z of the current grid point: a cached one, else an empty slot, a new slot while
+// fewer than zcache_cap exist (and the allocation succeeds), or the least recently used.
+static double* predict_z(fg_chain c, hipStream_t s) {
+  const int n = c->n, N = c->nstar;
+  ++c->zclock;
+  for (auto& e : c->zcache)
+    if (e.k == c->k) {
+      e.used = c->zclock;
+      return e.z;
+    }
+  fg_chain_s::ZEntry* slot = nullptr;
+  for (auto& e : c->zcache)
+    if (e.k < 0) { slot = &e; break; }
+  if (!slot && (int)c->zcache.size() < c->zcache_cap) {
+    double* z = nullptr;
+    if (hipMalloc(&z, sizeof(double) * (size_t)n * (size_t)N) == hipSuccess) {
+      c->zcache.push_back({-1, z, 0});
+      slot = &c->zcache.back();
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (!slot) {
+    slot = &c->zcache[0];
+    for (auto& e : c->zcache)
+      if (e.used < slot->used) slot = &e;
+  }
+  fg::FactorData& W1 = c->W[c->cur];
+  fg::launch_cross_cov(c->x, n, c->xstar, N, c->cfg.kind, c->grid[c->k], slot->z, n, s);
+  for (int j = 0; j < N; j += 4)
+    fg::launch_apply_w(W1, 2, slot->z + (size_t)j * n, std::min(4, N - j), n, W1.work, s);
+  slot->k = c->k;
+  slot->used = c->zclock;
+  ++c->zbuilds;
+  return slot->z;
+}
+
+fg_status gibbs_predict(fg_chain c, double* fstar, double* mu, double* s2, fg_stream stream) {
+  if (!c || !fstar) return cfail(FG_EINVAL, "NULL argument");
+  if (c->nstar == 0) return cfail(FG_EINVAL, "no new inputs set (gibbs_predict_inputs)");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = c->n, N = c->nstar;
+  fg::FactorData& W1 = c->W[c->cur];
+  const double* Z = predict_z(c, s);
+  double* zf = c->pwork;
+  double* xi = zf + n;
+  hipMemcpyAsync(zf, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  fg::launch_apply_w(W1, 2, zf, 1, n, W1.work, s);
+  fg::launch_normals(c->cfg.seed, 8, (uint64_t)c->iter, c->cfg.stream_id, N, xi, s);
+  fg::launch_predict_point(Z, n, n, zf, xi, &c->st->sigf2, c->cfg.nugget, N, fstar, mu, s2, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("predict launch: ") + hipGetErrorString(e));
+  return FG_OK;
+}
+
+fg_status gibbs_predict_stats(fg_chain c, int32_t* cached_grid_points, int64_t* builds) {
+  if (!c) return cfail(FG_EINVAL, "NULL chain");
+  int used = 0;
+  for (auto& e : c->zcache) used += e.k >= 0;
+  if (cached_grid_points) *cached_grid_points = used;
+  if (builds) *builds = c->zbuilds;
   return FG_OK;
 }
 

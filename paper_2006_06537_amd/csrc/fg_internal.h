@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -27,6 +28,14 @@ constexpr int KID_WHITEN = 4;
 constexpr int ST_NOTSPD = 1;
 constexpr int ST_NOTCONV = 2;
 constexpr int ST_TOL = 4;
+
+// k_1(a, b) without the nugget: squared exponential exp(-(a-b)^2 / (2 ell^2)) or
+// exponential exp(-|a-b| / ell) (Section 2.1 with rho = 1 / (2 ell^2)).
+__device__ __forceinline__ double k1_value(int kind, double ell, double a, double b) {
+  const double d = a - b;
+  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
+  return exp(-fabs(d) / ell);
+}
 
 // Panels are stored in 16-row tiles: rows of a tile are contiguous (128 bytes per
 // column), then the K columns of that tile, then the next tile.  A 16-row segment of
@@ -192,6 +201,12 @@ void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_ta
                  int nsides, int esz, double* zfin, int zf_side, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,
                   const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
+// function posterior at new inputs (k_predict.hip)
+void launch_cross_cov(const double* x, int n, const double* xstar, int nstar, int kind,
+                      double ell, double* Z, int64_t ld, hipStream_t s);
+void launch_predict_point(const double* Z, int64_t ld, int n, const double* zf, const double* xi,
+                          const double* sigf2_p, double eta, int nstar, double* fstar,
+                          double* mu, double* s2, hipStream_t s);
 
 size_t matvec_work_doubles(const HostPlan& P, int nrhs);
 size_t apply_work_doubles(const HostPlan& P, int nrhs);

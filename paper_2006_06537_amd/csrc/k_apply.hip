@@ -15,12 +15,6 @@ namespace fg {
 
 constexpr int NRHS_MAX = 4;
 
-__device__ __forceinline__ double kernel_v(int kind, double ell, double a, double b) {
-  const double d = a - b;
-  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
-  return exp(-fabs(d) / ell);
-}
-
 __device__ __forceinline__ double wave_red(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -269,7 +263,7 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
   const double xr = xs[r];
   double kacc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
   for (int s2 = 0; s2 < m; ++s2) {
-    const double kv = kernel_v(kind, ell, xr, xs[s2]);
+    const double kv = k1_value(kind, ell, xr, xs[s2]);
     for (int c = 0; c < nrhs; ++c) kacc[c] += kv * vs[c][s2];
   }
   for (int c = 0; c < nrhs; ++c) acc[c] += alpha * kacc[c];

@@ -17,12 +17,6 @@
 
 namespace fg {
 
-__device__ __forceinline__ double kernel1(int kind, double ell, double a, double b) {
-  const double d = a - b;
-  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
-  return exp(-fabs(d) / ell);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -291,7 +285,7 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     const int s = idx % pI, t = idx / pI;
     const double xs = q.exactI ? x[q.i0 + s] : cI + hI * cos((2 * s + 1) * M_PI / (2.0 * pI));
     const double yt = q.exactJ ? x[q.mid + t] : cJ + hJ * cos((2 * t + 1) * M_PI / (2.0 * pJ));
-    Cm[s + t * ld] = kernel1(kind, ell, xs, yt);
+    Cm[s + t * ld] = k1_value(kind, ell, xs, yt);
   }
   __syncthreads();
   // C_T = A_I C A_J'
@@ -502,7 +496,7 @@ __global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
       return;
     }
   }
-  out[t] = kernel1(kind, ell, x[i], x[j]) + (i == j ? nugget : 0.0);
+  out[t] = k1_value(kind, ell, x[i], x[j]) + (i == j ? nugget : 0.0);
 }
 
 // ---------------------------------------------------------------------------------

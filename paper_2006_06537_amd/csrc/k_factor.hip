@@ -17,12 +17,6 @@
 
 namespace fg {
 
-__device__ __forceinline__ double kern1(int kind, double ell, double a, double b) {
-  const double d = a - b;
-  if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
-  return exp(-fabs(d) / ell);
-}
-
 __device__ __forceinline__ double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -155,7 +149,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       const int c = LG * jj + tc;
       double v = (r == c) ? 1.0 : 0.0;
       if (r < m && c < m) {
-        v = alpha * kern1(kind, ell, xs[r], xs[c]);
+        v = alpha * k1_value(kind, ell, xs[r], xs[c]);
         if (r == c) v += alpha * nugget + beta + (diag ? diag[lo + r] : 0.0);
       }
       a[LT(i, jj)] = (T)v;  // entries are formed in FP64 and stored in T

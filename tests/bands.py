@@ -29,3 +29,19 @@ class InvLeafFactor(oh.Factor):
             Li = sla.solve_triangular(Lb, np.eye(Lb.shape[0]), lower=True)
             Y[a:c] = (Li.T if trans else Li) @ Y[a:c]
         return Y
+
+
+def perturbed_panels(H, rel=4.0 * 2.0 ** -53, seed=0):
+    """A copy of the oracle's HODLR whose off-diagonal factors U, V carry independent
+    relative perturbations of `rel` (a few units of rounding): the compressed matrix as a
+    different, equally valid FP64 compression would store it.  Leaves are shared."""
+    import copy
+    g = np.random.default_rng(seed)
+    H2 = copy.copy(H)
+    H2.blocks = {}
+    for key, b in H.blocks.items():
+        b2 = copy.copy(b)
+        b2.U = b.U * (1.0 + rel * g.standard_normal(b.U.shape))
+        b2.V = b.V * (1.0 + rel * g.standard_normal(b.V.shape))
+        H2.blocks[key] = b2
+    return H2

@@ -96,3 +96,65 @@ def test_logdet_k1(big):
     O1 = oh.Factor(H, 1.0, 0.0)
     ref = O1.logdet()
     assert abs(float(W1.logdet().cpu()[0]) - ref) <= 1e-9 * _logdet_mass(H, 1.0, 0.0, ref)
+
+
+def test_first_sweep_and_predictions_full_size(big):
+    """One sweep of the large workload as the benchmark runs it (n = 2^20, leaf 128), then
+    predictive draws at 8 new inputs, against the oracle's chain.  Bars: the grid move is
+    exact; f takes the W-operator bar b_W = max(1e-9, 2 u kappa(leaf)) (f = w + K~ r with
+    w containing W_1 b); tau follows the sum of squares |y - f|^2, whose relative error is
+    at most 2 b_W |f| / |y - f|; q = |W_1^-1 f|^2 takes 2.5 b_W, and sigma_f^2 follows q;
+    the log-likelihood takes the log-det mass bar of M~ plus 1e-9 |y'r|.  The predictions
+    take the bars of the small-size prediction test with b_W, plus four times the oracle's
+    own band (unblocked leaves; panels perturbed by 4 u)."""
+    from oracle import predict, rng, sampler
+    from bands import InvLeafFactor, perturbed_panels
+    fg, H, c = big["fg"], big["H"], big["c"]
+    x, y, dev = big["x"], big["y"], big["dev"]
+    g = fg.Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0=c["ell0"],
+                 tau0=c["tau0"], sigf2_0=c["sigf2_0"], nugget=c["nugget"], leaf=c["leaf"],
+                 tol=c["tol"], seed=c["seed"])
+    xs = np.array([0.0, 0.123456, 0.5, 0.5000001, 0.77, 0.999, 1.05, -0.2])
+    g.predict_inputs(torch.tensor(xs, device=dev))
+    g.step(1)
+    s = g.state(with_vectors=True)
+    fs, mu, s2 = (t.cpu().numpy() for t in g.predict())
+    o = sampler.Chain(x, y, kernels.SE, c["ell0"], c["nugget"], c["leaf"], c["tol"], c["tau0"],
+                      c["sigf2_0"], c["seed"])
+    kap = max(np.linalg.cond(o.H.leaf_block(lo, hi)) for lo, hi in o.H.tree.leaves())
+    bw = max(1e-9, 2.0 * 2.0 ** -53 * kap)
+    r = o.step()
+    assert s["status"] == 0
+    assert (s["k"], s["last_proposal"], s["last_accept"]) == (r["k"], r["proposal"], int(r["accept"]))
+    f = s["f"].cpu().numpy()
+    assert np.linalg.norm(f - o.f) <= bw * np.linalg.norm(o.f)
+    e = np.linalg.norm(y - o.f)
+    assert abs(s["tau"] - r["tau"]) <= (1e-9 + 2.0 * bw * np.linalg.norm(o.f) / e) * r["tau"]
+    assert abs(s["q"] - r["q"]) <= 2.5 * bw * r["q"]
+    assert abs(s["sigf2"] - r["sigf2"]) <= (1e-9 + 2.5 * bw) * r["sigf2"]
+    ldM = r["logdet_sigma"] + c["n"] * np.log(c["tau0"])
+    # the f-draw factors M~ at the starting length-scale, whose oracle HODLR is H
+    mass = _logdet_mass(H, c["tau0"] * c["sigf2_0"], 1.0, ldM)
+    assert abs(s["loglik"] - r["loglik"]) <= 0.5e-9 * mass + 0.5e-9 * abs(r["yr"])
+    # predictive draws at the state after the sweep
+    xi = rng.normals(xs.size, c["seed"], rng.TAG_PRED, o.it, 0)
+    ref = predict.predict(o.H, o.W1, o.f, o.sigf2, xs, xi)
+    Kx = kernels.k1(kernels.SE, o.H.ell, x, xs)
+    zn = np.linalg.norm(o.W1.apply_Winv(Kx), axis=0)
+    zf = np.linalg.norm(o.W1.apply_Winv(o.f))
+    # the oracle's own band for these outputs: an unblocked-leaf evaluation of W_1 and a
+    # compression whose panels differ by a few rounding units (near and past the data's
+    # edge K~_1^-1 k grows to ~1e2 and the quadratic form follows the compression closely)
+    band_mu, band_s2 = np.zeros(xs.size), np.zeros(xs.size)
+    for Hv, Wv in [(o.H, InvLeafFactor(o.H, 1.0, 0.0))] + [
+            (Hp, oh.Factor(Hp, 1.0, 0.0)) for Hp in [perturbed_panels(o.H, seed=s_) for s_ in (1, 2)]]:
+        v = predict.predict(Hv, Wv, o.f, o.sigf2, xs, xi)
+        band_mu = np.maximum(band_mu, np.abs(v[1] - ref[1]))
+        band_s2 = np.maximum(band_s2, np.abs(v[2] - ref[2]))
+    b_mu = 2.0 * bw * zn * zf + 4.0 * band_mu + 1e-15
+    b_s2 = 2.0 * bw * o.sigf2 * (1.0 + zn ** 2) + 4.0 * band_s2 + 1e-15
+    print("prediction errors / bars: mu", np.max(np.abs(mu - ref[1]) / b_mu),
+          "s2", np.max(np.abs(s2 - ref[2]) / b_s2))
+    assert np.all(np.abs(mu - ref[1]) <= b_mu), np.abs(mu - ref[1]) / b_mu
+    assert np.all(np.abs(s2 - ref[2]) <= b_s2), np.abs(s2 - ref[2]) / b_s2
+    assert np.all(np.abs(fs - ref[0]) <= b_mu + np.sqrt(b_s2) * np.abs(xi))
