@@ -17,6 +17,11 @@ Other workloads (--workload), each printing its own JSON line:
   tensor  the d = 4, n = 65,536 tensor-product surface chain; value = sweeps/s.
   copy    a plain 2 GiB FP64 copy kernel (one read, one write of 2 GiB per launch): the
           calibration run for the HBM byte counters (FETCH_SIZE, WRITE_SIZE).
+  predict the large 1-D chain with predictive draws at --nstar new inputs
+          (workloads.new_inputs) after every sweep (Appendix, function posterior at new
+          inputs); W_1^-1 k1(X, X*) kept for up to --zcache grid points.  value = Gibbs
+          iterations/s including the draws; the cached and rebuilt draw costs are
+          reported beside it, with the roofline of the per-point reduction kernel.
   serve   GP-regression jobs of mixed n (workloads.served_jobs) through the serving
           loop: first all at once (saturation throughput), then Poisson arrivals at
           0.7 x that rate; value = p50 latency (s), with p99 and the same arrival list
@@ -45,7 +50,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--workload", default="large_1d",
-                    choices=["large_1d", "batch", "tensor", "serve", "copy"])
+                    choices=["large_1d", "batch", "tensor", "serve", "copy", "predict"])
+    ap.add_argument("--nstar", type=int, default=1024, help="predict: new inputs per draw")
+    ap.add_argument("--zcache", type=int, default=8,
+                    help="predict: grid points whose W_1^-1 k1(X, X*) is kept")
     ap.add_argument("--jobs", type=int, default=64, help="serve workload: number of jobs")
     ap.add_argument("--job-iters", type=int, default=20, help="serve workload: sweeps per job")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturation")
@@ -220,6 +228,94 @@ def bench_tensor(args):
                        "tol 1e-10", "d": T["d"], "n": n}, **extra)
 
 
+def bench_predict(args):
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import LARGE_1D, large_1d, new_inputs
+    cfg = dict(LARGE_1D)
+    x, y = large_1d(cfg["n"], cfg["seed"])
+    n, m = cfg["n"], args.nstar
+    dev = torch.device("cuda:0")
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    chain = fg.Chain(xt, yt, ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"],
+                     nugget=cfg["nugget"], leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"])
+    chain.predict_inputs(torch.tensor(new_inputs(m), device=dev), max_grid_points=args.zcache)
+
+    def sweep_and_draw():
+        chain.step(1)
+        return chain.predict()
+
+    for _ in range(args.warmup):
+        sweep_and_draw()
+    torch.cuda.synchronize()
+    b0 = chain.predict_stats()[1]
+    print(f"bench: predict warm-up done, {b0} Z builds", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fs, mu, s2 = sweep_and_draw()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cached, builds = chain.predict_stats()
+    timed_builds = builds - b0
+    # one draw with Z cached, alone: events on the stream the kernels are launched on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    timer = fg.KernelTimer(fg.KID_PREDICT)
+    timer.start()
+    ev[0].record()
+    reps = 5
+    for _ in range(reps):
+        chain.predict()
+    ev[1].record()
+    torch.cuda.synchronize()
+    cached_ms = ev[0].elapsed_time(ev[1]) / reps
+    ktime_ms, launches, kbytes = timer.stop()
+    # one draw that builds Z (new inputs: nothing cached)
+    chain.predict_inputs(torch.tensor(new_inputs(m), device=dev), max_grid_points=args.zcache)
+    torch.cuda.synchronize()
+    ev[0].record()
+    chain.predict()
+    ev[1].record()
+    torch.cuda.synchronize()
+    build_ms = ev[0].elapsed_time(ev[1])
+    st = chain.state()
+    print(f"bench: predict {args.steps} sweeps+draws in {dt:.3f} s, {timed_builds} Z builds, "
+          f"cached draw {cached_ms:.2f} ms, building draw {build_ms:.1f} ms, status "
+          f"{st['status']}", file=sys.stderr, flush=True)
+    achieved = kbytes / (ktime_ms * 1e-3) / 1e9 if ktime_ms > 0 else None
+    roof = {"bound": "hbm", "kernel": "k_predict_partial", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "launches": launches, "avg_launch_us": 1e3 * ktime_ms / max(launches, 1),
+            "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
+    extra = {"predictive_draws_per_s": m * args.steps / dt,
+             "cached_draw_ms": cached_ms, "building_draw_ms": build_ms,
+             "z_builds_in_timed_region": timed_builds, "grid_points_cached": cached,
+             "zcache_bytes": 8 * n * m * cached}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import hodlr as oh, kernels, predict, rng
+        sub = 64  # new inputs in the CPU sample
+        H = oh.HODLR(x, kernels.SE, cfg["ell0"], cfg["nugget"], cfg["leaf"], cfg["tol"])
+        W1 = oh.Factor(H, 1.0, 0.0)
+        f = W1.apply_W(rng.normals(n, 1, 1, 0, 0))
+        t1 = time.perf_counter()
+        predict.predict(H, W1, f, 1.0, new_inputs(m)[:sub], rng.normals(sub, 1, rng.TAG_PRED, 0, 0))
+        dto = time.perf_counter() - t1
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        extra["cpu_baseline"] = {"value": sub / dto, "unit": "predictive draws/s (uncached)",
+                                 "cores": threads, "kind": "oracle",
+                                 "sample": f"{sub} new inputs at n={n}, oracle factor given, "
+                                           f"{dto:.1f} s"}
+    _line(f"Gibbs iters/s with predictive draws at {m} new inputs, n=2^20 (FP64)",
+          args.steps / dt, "Gibbs iters/s", args, dt, "f64",
+          {"workload": f"predict: large_1d chain (n=2^20, leaf 128, tol 1e-10, ell0 0.02) with "
+                       f"one draw of f at {m} new inputs U[-0.02,1.02] after every sweep; Z "
+                       f"kept for up to {args.zcache} grid points", "n": n, "nstar": m},
+          roofline=roof, **extra)
+
+
 def bench_serve(args):
     import threading
 
@@ -322,6 +418,8 @@ def main():
         return bench_serve(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "predict":
+        return bench_predict(args)
     import numpy as np
     import torch
 

@@ -288,7 +288,7 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
  *   call) -- the pre-solve per grid value the paper suggests.  The first buffer is
  *   allocated here, the others on first use (a failed allocation there evicts instead).
  *   Synchronises `stream` first.
- *   Errors: FG_EINVAL (NULL, nstar < 0 or > 2^31 - 1, max_grid_points < 1), FG_ENOMEM.
+ *   Errors: FG_EINVAL (NULL, nstar < 0 or > 65535 * 4, max_grid_points < 1), FG_ENOMEM.
  * gibbs_predict -- one draw per new input: fstar (device, nstar) receives f*, and mu and
  *   s2 (device, nstar; either may be NULL) the mean and variance.  The normals are the
  *   Philox stream with tag 8 at iteration = the number of sweeps the chain has made.  Each
@@ -425,7 +425,8 @@ void serve_destroy(fg_server s);
  * HIP events, on the launch stream, around every following launch of kernel `id`
  * (FG_KID_LEAF: leaf Cholesky and inverse; FG_KID_REDUCE: level Gram reduction;
  * FG_KID_UPDATE: level update of the coarser panels; FG_KID_WHITEN: whitening of every
- * panel row by the leaf inverses, on matrix cores).  fg_timer_stop
+ * panel row by the leaf inverses, on matrix cores; FG_KID_PREDICT: the per-point
+ * reductions of gibbs_predict).  fg_timer_stop
  * synchronises the device and returns the summed kernel time (ms), the launch count
  * and the algorithmic HBM bytes of those launches (each kernel's minimum traffic:
  * every operand read once and every result written once).  Not thread-safe.
@@ -434,6 +435,7 @@ void serve_destroy(fg_server s);
 #define FG_KID_REDUCE 2
 #define FG_KID_UPDATE 3
 #define FG_KID_WHITEN 4
+#define FG_KID_PREDICT 5
 fg_status fg_timer_start(int32_t kernel_id);
 fg_status fg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
 

@@ -15,11 +15,12 @@ from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, 
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
            "draw_f_hetero", "step_batch", "solve_refined", "Server", "footprint_bytes", "FP64", "MIXED", "KERNEL_SE",
-           "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE", "KID_WHITEN"]
+           "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE", "KID_WHITEN",
+           "KID_PREDICT"]
 
-KID_LEAF, KID_REDUCE, KID_UPDATE, KID_WHITEN = 1, 2, 3, 4
+KID_LEAF, KID_REDUCE, KID_UPDATE, KID_WHITEN, KID_PREDICT = 1, 2, 3, 4, 5
 KID_NAMES = {KID_LEAF: "k_leaf", KID_REDUCE: "k_reduce_panel", KID_UPDATE: "k_update_panel",
-             KID_WHITEN: "k_whiten"}
+             KID_WHITEN: "k_whiten", KID_PREDICT: "k_predict_partial"}
 
 
 class KernelTimer:

@@ -52,7 +52,7 @@ struct fg_chain_s {
   int zcache_cap = 0;
   uint64_t zclock = 0;
   int64_t zbuilds = 0;                        // Z computations so far (cache misses)
-  double* pwork = nullptr;                    // W_1^-1 f (n) and the draw's normals (nstar)
+  double* pwork = nullptr;                    // W_1^-1 f (n), the draw's normals (nstar), partials
   std::map<uint64_t, hipGraphExec_t> graphs;  // captured sweeps by (cur, k, proposal)
   std::vector<uint64_t> graph_order;          // insertion order, for eviction
 };
@@ -534,7 +534,7 @@ fg_status gibbs_predict_inputs(fg_chain c, const double* xstar, int64_t nstar,
                                int32_t max_grid_points, fg_stream stream) {
   if (!c || nstar < 0 || (nstar > 0 && (!xstar || max_grid_points < 1)))
     return cfail(FG_EINVAL, "bad arguments");
-  if (nstar > (int64_t)INT32_MAX) return cfail(FG_EINVAL, "too many new inputs");
+  if (nstar > (int64_t)fg::MAX_NSTAR) return cfail(FG_EINVAL, "too many new inputs");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // work already queued on the stream may still read the old buffers
   if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "stream failed");
@@ -543,7 +543,8 @@ fg_status gibbs_predict_inputs(fg_chain c, const double* xstar, int64_t nstar,
   const size_t n = (size_t)c->n, m = (size_t)nstar;
   double* z0 = nullptr;
   if (hipMalloc(&c->xstar, sizeof(double) * m) != hipSuccess ||
-      hipMalloc(&c->pwork, sizeof(double) * (n + m)) != hipSuccess ||
+      hipMalloc(&c->pwork, sizeof(double) * (n + m + fg::predict_part_doubles(c->n, (int)m))) !=
+          hipSuccess ||
       hipMalloc(&z0, sizeof(double) * n * m) != hipSuccess) {
     if (z0) (void)hipFree(z0);
     predict_release(c);
@@ -607,7 +608,8 @@ fg_status gibbs_predict(fg_chain c, double* fstar, double* mu, double* s2, fg_st
   hipMemcpyAsync(zf, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
   fg::launch_apply_w(W1, 2, zf, 1, n, W1.work, s);
   fg::launch_normals(c->cfg.seed, 8, (uint64_t)c->iter, c->cfg.stream_id, N, xi, s);
-  fg::launch_predict_point(Z, n, n, zf, xi, &c->st->sigf2, c->cfg.nugget, N, fstar, mu, s2, s);
+  fg::launch_predict_point(Z, n, n, zf, xi, &c->st->sigf2, c->cfg.nugget, N, xi + N, fstar, mu,
+                           s2, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("predict launch: ") + hipGetErrorString(e));
   return FG_OK;

@@ -23,6 +23,7 @@ constexpr int KID_LEAF = 1;
 constexpr int KID_REDUCE = 2;
 constexpr int KID_UPDATE = 3;
 constexpr int KID_WHITEN = 4;
+constexpr int KID_PREDICT = 5;
 
 // status bits written by kernels (device word, OR-ed)
 constexpr int ST_NOTSPD = 1;
@@ -204,9 +205,12 @@ void launch_axpby(int n, const double* x, const double* y, double* out,
 // function posterior at new inputs (k_predict.hip)
 void launch_cross_cov(const double* x, int n, const double* xstar, int nstar, int kind,
                       double ell, double* Z, int64_t ld, hipStream_t s);
+constexpr int PC_PREDICT = 4;         // new points per work-group of the predictive reduction
+constexpr int MAX_NSTAR = 65535 * PC_PREDICT;
+size_t predict_part_doubles(int n, int nstar);  // partial sums of the predictive reduction
 void launch_predict_point(const double* Z, int64_t ld, int n, const double* zf, const double* xi,
-                          const double* sigf2_p, double eta, int nstar, double* fstar,
-                          double* mu, double* s2, hipStream_t s);
+                          const double* sigf2_p, double eta, int nstar, double* part,
+                          double* fstar, double* mu, double* s2, hipStream_t s);
 
 size_t matvec_work_doubles(const HostPlan& P, int nrhs);
 size_t apply_work_doubles(const HostPlan& P, int nrhs);

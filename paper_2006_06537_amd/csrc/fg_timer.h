@@ -10,4 +10,6 @@ bool timer_active();  // a kernel is being timed (launches must stay eager)
 void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const int* kmax_dev,
                   int ntask);
 void timer_after(int kid, hipStream_t s);
+// for a kernel whose algorithmic bytes are known at launch
+void timer_before_bytes(int kid, hipStream_t s, double bytes);
 }  // namespace fg

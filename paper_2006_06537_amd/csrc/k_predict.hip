@@ -6,6 +6,7 @@
 // never formed.
 #include "fg_internal.h"
 #include "fg_rng.h"
+#include "fg_timer.h"
 
 namespace fg {
 
@@ -26,39 +27,70 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// one work-group per new point: the two length-n reductions in a fixed order
-__global__ void __launch_bounds__(NTHREADS) k_predict_point(
-    const double* __restrict__ Z, int64_t ld, int n, const double* __restrict__ zf,
-    const double* __restrict__ xi, const double* __restrict__ sigf2_p, double eta, int nstar,
-    double* __restrict__ fstar, double* __restrict__ mu, double* __restrict__ s2) {
-  const int j = blockIdx.x;
-  if (j >= nstar) return;
-  const double* col = Z + (size_t)j * (size_t)ld;
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < n; i += NTHREADS) {
-    const double z = col[i];
-    a += z * zf[i];
-    b += z * z;
+// Stage 1: work-group (chunk, group) takes PT_ROWS rows of PC new points, so each
+// slice of z_f is read once for PC columns of Z.  Partial sums go to
+// part[(chunk * nstar + j) * 2 + {0: Z_j . z_f, 1: |Z_j|^2}].
+constexpr int PT_ROWS = 16384;  // measured best with 4 points per work-group (5.9 TB/s at n = 2^20)
+
+template <int PC>
+__global__ void __launch_bounds__(NTHREADS) k_predict_partial(
+    const double* __restrict__ Z, int64_t ld, int n, const double* __restrict__ zf, int nstar,
+    double* __restrict__ part) {
+  const int chunk = blockIdx.x, j0 = blockIdx.y * PC;
+  const int r0 = chunk * PT_ROWS, r1 = min(r0 + PT_ROWS, n);
+  const int pc = min(PC, nstar - j0);
+  double a[PC], b[PC];
+#pragma unroll
+  for (int c = 0; c < PC; ++c) a[c] = b[c] = 0.0;
+  const double* col = Z + (size_t)j0 * (size_t)ld;
+  for (int i = r0 + threadIdx.x; i < r1; i += NTHREADS) {
+    const double z = zf[i];
+#pragma unroll
+    for (int c = 0; c < PC; ++c) {
+      if (c < pc) {
+        const double v = col[(size_t)c * (size_t)ld + i];
+        a[c] += v * z;
+        b[c] += v * v;
+      }
+    }
   }
-  a = wave_total(a);
-  b = wave_total(b);
-  __shared__ double ra[NTHREADS / 64], rb[NTHREADS / 64];
+  __shared__ double red[NTHREADS / 64][2 * PC];
+#pragma unroll
+  for (int c = 0; c < PC; ++c) {
+    a[c] = wave_total(a[c]);
+    b[c] = wave_total(b[c]);
+  }
   if ((threadIdx.x & 63) == 0) {
-    ra[threadIdx.x >> 6] = a;
-    rb[threadIdx.x >> 6] = b;
+#pragma unroll
+    for (int c = 0; c < PC; ++c) {
+      red[threadIdx.x >> 6][2 * c] = a[c];
+      red[threadIdx.x >> 6][2 * c + 1] = b[c];
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int w = 0; w < NTHREADS / 64; ++w) {
-      ta += ra[w];
-      tb += rb[w];
-    }
-    const double v = (*sigf2_p) * (1.0 + eta - tb);
-    fstar[j] = ta + sqrt(fmax(v, 0.0)) * xi[j];
-    if (mu) mu[j] = ta;
-    if (s2) s2[j] = v;
+  if (threadIdx.x < 2 * pc) {
+    double t = 0.0;
+    for (int w = 0; w < NTHREADS / 64; ++w) t += red[w][threadIdx.x];
+    part[((size_t)chunk * nstar + j0 + (threadIdx.x >> 1)) * 2 + (threadIdx.x & 1)] = t;
   }
+}
+
+// Stage 2: one thread per new point sums its chunk partials in chunk order.
+__global__ void __launch_bounds__(NTHREADS) k_predict_final(
+    const double* __restrict__ part, int nchunk, int nstar, const double* __restrict__ xi,
+    const double* __restrict__ sigf2_p, double eta, double* __restrict__ fstar,
+    double* __restrict__ mu, double* __restrict__ s2) {
+  const int j = blockIdx.x * NTHREADS + threadIdx.x;
+  if (j >= nstar) return;
+  double ta = 0.0, tb = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    ta += part[((size_t)c * nstar + j) * 2];
+    tb += part[((size_t)c * nstar + j) * 2 + 1];
+  }
+  const double v = (*sigf2_p) * (1.0 + eta - tb);
+  fstar[j] = ta + sqrt(fmax(v, 0.0)) * xi[j];
+  if (mu) mu[j] = ta;
+  if (s2) s2[j] = v;
 }
 
 void launch_cross_cov(const double* x, int n, const double* xstar, int nstar, int kind,
@@ -70,10 +102,21 @@ void launch_cross_cov(const double* x, int n, const double* xstar, int nstar, in
   }
 }
 
+size_t predict_part_doubles(int n, int nstar) {
+  return (size_t)((n + PT_ROWS - 1) / PT_ROWS) * (size_t)nstar * 2;
+}
+
 void launch_predict_point(const double* Z, int64_t ld, int n, const double* zf, const double* xi,
-                          const double* sigf2_p, double eta, int nstar, double* fstar,
-                          double* mu, double* s2, hipStream_t s) {
-  k_predict_point<<<nstar, NTHREADS, 0, s>>>(Z, ld, n, zf, xi, sigf2_p, eta, nstar, fstar, mu, s2);
+                          const double* sigf2_p, double eta, int nstar, double* part,
+                          double* fstar, double* mu, double* s2, hipStream_t s) {
+  const int nchunk = (n + PT_ROWS - 1) / PT_ROWS;
+  // algorithmic bytes: Z read once, z_f and the normals read, three outputs written
+  timer_before_bytes(KID_PREDICT, s, 8.0 * ((double)n * nstar + n + 4.0 * nstar));
+  const int ng = (nstar + PC_PREDICT - 1) / PC_PREDICT;  // <= 65535 (checked by the caller)
+  k_predict_partial<PC_PREDICT><<<dim3(nchunk, ng), NTHREADS, 0, s>>>(Z, ld, n, zf, nstar, part);
+  timer_after(KID_PREDICT, s);
+  k_predict_final<<<(nstar + NTHREADS - 1) / NTHREADS, NTHREADS, 0, s>>>(
+      part, nchunk, nstar, xi, sigf2_p, eta, fstar, mu, s2);
 }
 
 }  // namespace fg

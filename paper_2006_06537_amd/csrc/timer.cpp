@@ -13,6 +13,7 @@ namespace {
 struct Rec {
   int kid, level, n, L, nleaf, B, ntask, ring_off;
   double sum_leaf_tri;  // sum over leaves of m (m + 1) / 2
+  double fixed_bytes;   // > 0: the launch's bytes, known at launch
 };
 struct TimerState {
   bool on = false;
@@ -62,6 +63,21 @@ void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const in
   g_t.recs.push_back(r);
 }
 
+void timer_before_bytes(int kid, hipStream_t s, double bytes) {
+  if (!timer_wants(kid)) return;
+  Rec r{};
+  r.kid = kid;
+  r.ring_off = -1;
+  r.fixed_bytes = bytes;
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  hipEventRecord(a, s);
+  g_t.ev.push_back(a);
+  g_t.ev.push_back(b);
+  g_t.recs.push_back(r);
+}
+
 void timer_after(int kid, hipStream_t s) {
   if (!g_t.on || g_t.kid != kid || g_t.ev.empty()) return;
   if (g_t.ev.size() != 2 * g_t.recs.size()) return;
@@ -70,6 +86,7 @@ void timer_after(int kid, hipStream_t s) {
 
 // algorithmic bytes of one launch (see the kernel notes in each source file)
 static double launch_bytes(const Rec& r, const std::vector<int>& km) {
+  if (r.fixed_bytes > 0.0) return r.fixed_bytes;
   const double n = r.n;
   double K = 0;
   for (int l = 0; l < r.L; ++l) K += km[l];
@@ -99,7 +116,7 @@ extern "C" {
 
 fg_status fg_timer_start(int32_t kernel_id) {
   using namespace fg;
-  if (kernel_id < KID_LEAF || kernel_id > KID_WHITEN) return FG_EINVAL;
+  if (kernel_id < KID_LEAF || kernel_id > KID_PREDICT) return FG_EINVAL;
   for (auto e : g_t.ev) hipEventDestroy(e);
   g_t.ev.clear();
   g_t.recs.clear();

@@ -91,3 +91,9 @@ def served_jobs(count: int = 512, seed: int = 5):
         x, y = sinusoid_1d(n, seed=jseed, noise=noise)
         jobs.append(dict(x=x, y=y, ell0=ell0, noise=noise, seed=jseed, n=n))
     return jobs
+
+
+def new_inputs(count: int = 1024, seed: int = 7):
+    """New inputs for predictive draws: uniform on [-0.02, 1.02] (the data's range on
+    [0, 1] and a little past both ends), in no particular order."""
+    return np.random.default_rng(seed).uniform(-0.02, 1.02, count)
