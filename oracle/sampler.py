@@ -86,8 +86,15 @@ class Chain:
         return hodlr.HODLR(self.x, self.kind, self.grid[k], self.nugget, self.leaf, self.tol)
 
     def step(self):
-        n, y, t, s, sd = self.y.size, self.y, self.it, self.stream, self.seed
         rec = {}
+        self._f_and_tau(rec)
+        self._sigf_and_rho(rec)
+        self.it += 1
+        self.last = rec
+        return rec
+
+    def _f_and_tau(self, rec):
+        n, y, t, s, sd = self.y.size, self.y, self.it, self.stream, self.seed
         # f | -
         WM = hodlr.Factor(self.H, self.tau * self.sigf2, 1.0)
         a = rng.normals(n, sd, rng.TAG_A, t, s)
@@ -105,6 +112,10 @@ class Chain:
         rec["sse"] = float(e @ e)
         g, _ = rng.gamma(0.5 * (self.a1 + n), sd, rng.TAG_G_TAU, t, s)
         self.tau = g / (0.5 * (self.b1 + rec["sse"]))
+
+    def _sigf_and_rho(self, rec):
+        n, t, s, sd = self.y.size, self.it, self.stream, self.seed
+        f = self.f
         # sigma_f^-2 | -
         u1 = self.W1.apply_Winv(f)
         q = float(u1 @ u1)
@@ -128,6 +139,3 @@ class Chain:
                 self.k, self.H, self.W1, self.logdet1 = kp, Hp, Wp, ldp
                 rec["accept"] = True
         rec["tau"], rec["sigf2"], rec["k"] = self.tau, self.sigf2, self.k
-        self.it += 1
-        self.last = rec
-        return rec
