@@ -22,6 +22,10 @@ Other workloads (--workload), each printing its own JSON line:
           inputs); W_1^-1 k1(X, X*) kept for up to --zcache grid points.  value = Gibbs
           iterations/s including the draws; the cached and rebuilt draw costs are
           reported beside it, with the roofline of the per-point reduction kernel.
+  collapse gridded data with repeats (workloads.gridded_1d: 2^20 observations on 2^14
+          grid inputs, 64 each): the chain on the collapsed data (Appendix, non-unique
+          input points); value = Gibbs iterations/s, with the plain chain on the raw
+          2^20 observations timed beside it.
   serve   GP-regression jobs of mixed n (workloads.served_jobs) through the serving
           loop: first all at once (saturation throughput), then Poisson arrivals at
           0.7 x that rate; value = p50 latency (s), with p99 and the same arrival list
@@ -50,7 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--workload", default="large_1d",
-                    choices=["large_1d", "batch", "tensor", "serve", "copy", "predict"])
+                    choices=["large_1d", "batch", "tensor", "serve", "copy", "predict",
+                             "collapse"])
     ap.add_argument("--nstar", type=int, default=1024, help="predict: new inputs per draw")
     ap.add_argument("--zcache", type=int, default=8,
                     help="predict: grid points whose W_1^-1 k1(X, X*) is kept")
@@ -316,6 +321,75 @@ def bench_predict(args):
           roofline=roof, **extra)
 
 
+def bench_collapse(args):
+    import numpy as np
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import LARGE_1D, gridded_1d
+    cfg = dict(LARGE_1D)
+    x, y = gridded_1d()
+    dev = torch.device("cuda:0")
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    kw = dict(ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"], nugget=cfg["nugget"],
+              leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"])
+    t0 = time.perf_counter()
+    ch = fg.Chain(xt, yt, collapse=True, **kw)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    timer = fg.KernelTimer(args.kernel)
+    timer.start()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktime_ms, launches, kbytes = timer.stop()
+    st = ch.state()
+    print(f"bench: collapsed chain U={ch.n} of n={ch.n_obs}: {args.steps} sweeps in {dt:.3f} s, "
+          f"status {st['status']}, tau {st['tau']:.4g}", file=sys.stderr, flush=True)
+    # the plain chain on the raw observations (repeated inputs kept), sorted by input
+    order = np.argsort(x, kind="stable")
+    raw = fg.Chain(torch.tensor(x[order], device=dev), torch.tensor(y[order], device=dev), **kw)
+    raw_steps = max(1, min(args.steps, 5))
+    raw.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    raw.step(raw_steps)
+    torch.cuda.synchronize()
+    dt_raw = time.perf_counter() - t0
+    rst = raw.state()
+    print(f"bench: plain chain on n={x.size}: {raw_steps} sweeps in {dt_raw:.3f} s, status "
+          f"{rst['status']}, tau {rst['tau']:.4g}", file=sys.stderr, flush=True)
+    achieved = kbytes / (ktime_ms * 1e-3) / 1e9 if ktime_ms > 0 else None
+    roof = {"bound": "hbm", "kernel": timer.name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": None, "launches": launches,
+            "avg_launch_us": 1e3 * ktime_ms / max(launches, 1)}
+    extra = {"uncollapsed_iters_per_s": raw_steps / dt_raw, "uncollapsed_status": rst["status"],
+             "speedup": (args.steps / dt) / (raw_steps / dt_raw), "create_s": t_create}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import collapse, kernels
+        oc = collapse.CollapsedChain(x, y, kernels.SE, cfg["ell0"], cfg["nugget"], cfg["leaf"],
+                                     cfg["tol"], cfg["tau0"], cfg["sigf2_0"], cfg["seed"])
+        t1 = time.perf_counter()
+        oc.step()
+        dto = time.perf_counter() - t1
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        extra["cpu_baseline"] = {"value": 1.0 / dto, "unit": "Gibbs iters/s", "cores": threads,
+                                 "kind": "oracle",
+                                 "sample": f"one sweep of the collapsed chain (U={ch.n}), {dto:.2f} s"}
+    _line(f"Gibbs iters/s on collapsed gridded data, n={ch.n_obs} observations on U={ch.n} "
+          "inputs (FP64)", args.steps / dt, "Gibbs iters/s", args, dt, "f64",
+          {"workload": f"collapse: {ch.n_obs} observations on a grid of {ch.n} inputs (64 each), "
+                       "5-sinusoid signal + N(0,0.2^2), SE kernel ell0=0.02, leaf 128, tol 1e-10, "
+                       "nugget 1e-6", "n": ch.n_obs, "unique": ch.n},
+          roofline=roof, **extra)
+
+
 def bench_serve(args):
     import threading
 
@@ -420,6 +494,8 @@ def main():
         return bench_copy(args)
     if args.workload == "predict":
         return bench_predict(args)
+    if args.workload == "collapse":
+        return bench_collapse(args)
     import numpy as np
     import torch
 

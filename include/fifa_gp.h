@@ -270,6 +270,27 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
                             double* r_out, double* mu_out, fg_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Non-unique inputs (Appendix, "Non-unique input points").
+ * gibbs_chain_create_collapsed -- as gibbs_chain_create, for n observations (x, y on the
+ *   device, any order) whose inputs may repeat.  The U distinct inputs (ascending) with
+ *   counts |Q_i| and averages ybar_i are formed on the host, and the chain runs on them:
+ *   f | - is Algorithm 1.h with noise precisions |Q_i| tau (the mean of |Q_i| independent
+ *   observations of precision tau; the paper prints |Q_i|^2 tau), computed on g = f /
+ *   sigma_f with prior K~_1 and f = sigma_f g; tau | - ~ Ga((a1 + n)/2, (b1 + SSE)/2)
+ *   with the full-data SSE = sum_i |Q_i| (ybar_i - f_i)^2 + the within-group sum of
+ *   squares; sigma_f^-2 and the length-scale steps are those of the plain chain on the U
+ *   inputs.  The snapshot's loglik is that of the averages, ybar ~ N(0, sigma_f^2 K~_1 +
+ *   diag(1 / (tau |Q_i|))), and its sse the full-data SSE; f, r and mu have U entries.
+ *   FP64 only.  Errors: as gibbs_chain_create, FG_EINVAL for FG_MIXED or a NaN input.
+ * gibbs_chain_inputs -- the chain's input count U, the observation count n (U for a plain
+ *   chain), and, when the device pointers are not NULL, its U inputs and counts.
+ * ------------------------------------------------------------------------- */
+fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x, const double* y,
+                                       int64_t n, fg_stream stream, fg_chain* out);
+fg_status gibbs_chain_inputs(fg_chain c, int64_t* n_points, int64_t* n_obs, double* x_out,
+                             double* counts_out, fg_stream stream);
+
+/* ---------------------------------------------------------------------------
  * Function posterior at new inputs (Appendix, "Function posterior at new inputs").
  * Given the chain's state after its last sweep -- f, sigma_f^2 and the length-scale's
  * K~_1 = K_1 + eta I with its factor W_1 -- each new input x*_j has

@@ -345,14 +345,27 @@ class Chain:
 
     def __init__(self, x, y, ell0, tau0, sigf2_0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
                  seed=0, stream_id=0, kind=KERNEL_SE, priors=(1.0, 1.0, 1.0, 1.0),
-                 grid_size=100, grid_center=50, precision=FP64):
-        self.n = int(x.shape[0])
+                 grid_size=100, grid_center=50, precision=FP64, collapse=False):
+        """collapse=True: repeated inputs are merged (gibbs_chain_create_collapsed) and the
+        chain runs on the unique inputs (self.n of them; self.n_obs observations)."""
+        m = int(x.shape[0])
         cfg = ChainCfg(kind, ell0, nugget, leaf, tol, tau0, sigf2_0, priors[0], priors[1],
                        priors[2], priors[3], grid_size, grid_center, seed, stream_id, precision)
         c = C.c_void_p()
-        check(lib().gibbs_chain_create(C.byref(cfg), _dev(x, self.n), _dev(y, self.n), self.n,
-                                       _stream(), C.byref(c)))
+        create = lib().gibbs_chain_create_collapsed if collapse else lib().gibbs_chain_create
+        check(create(C.byref(cfg), _dev(x, m), _dev(y, m), m, _stream(), C.byref(c)))
         self._c = c
+        u, nobs = C.c_int64(), C.c_int64()
+        check(lib().gibbs_chain_inputs(c, C.byref(u), C.byref(nobs), None, None, _stream()))
+        self.n, self.n_obs = u.value, nobs.value
+
+    def inputs(self):
+        """(inputs, counts) of the chain on the device."""
+        torch = _torch()
+        xo = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        wo = torch.empty_like(xo)
+        check(lib().gibbs_chain_inputs(self._c, None, None, _dev(xo), _dev(wo), _stream()))
+        return xo, wo
 
     def step(self, iters=1):
         check(lib().gibbs_step(self._c, iters, _stream()))

@@ -14,6 +14,7 @@
 #include "fg_rng.h"
 #include "fg_pcg.h"
 #include "fg_timer.h"
+#include "fg_tensor.h"
 
 struct fg_chain_s {
   fg_chain_cfg cfg{};
@@ -41,6 +42,11 @@ struct fg_chain_s {
   bool pcg_failed = false;
   hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // non-unique inputs: the chain runs on the unique inputs with the averages as y
+  bool collapsed = false;
+  double* cw = nullptr;                       // |Q_i| (n), then precisions and their inverses
+  double within = 0.0;                        // within-group sum of squares
+  int64_t n_obs = 0;                          // observations before collapsing
   double* xstar = nullptr;                    // new inputs of the predictive draws
   int nstar = 0;
   struct ZEntry {
@@ -82,7 +88,8 @@ static void chain_free(fg_chain c) {
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
   for (auto& e : c->zcache)
     if (e.z) (void)hipFree(e.z);
-  double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork, c->xstar, c->pwork};
+  double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork, c->xstar, c->pwork,
+                    c->cw};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->st) (void)hipFree(c->st);
@@ -117,14 +124,56 @@ void prepare_sweep(fg_chain c, const Proposal& pr) {
   const int cur = c->cur, oth = 1 - cur;
   fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
   WM.H = &c->H[cur];
-  WM.alpha = 0.0;  // taken from the device scalar
-  WM.beta = 1.0;
+  if (c->collapsed) {  // K~_1 + D^-1, D^-1 passed as the diagonal
+    WM.alpha = 1.0;
+    WM.beta = 0.0;
+  } else {
+    WM.alpha = 0.0;  // taken from the device scalar
+    WM.beta = 1.0;
+  }
   if (pr.ongrid) {
     c->H[oth].pk = c->packs[pr.kp];
     c->W[oth].H = &c->H[oth];
     c->W[oth].alpha = 1.0;
     c->W[oth].beta = 0.0;
   }
+}
+
+// f | - and tau | - on collapsed data (Appendix, non-unique input points): Algorithm 1.h
+// on g = f / sigma_f, whose prior is K~_1 and whose data ybar / sigma_f have precisions
+// D = tau sigma_f^2 |Q_i|; then f = sigma_f g, and tau from the full-data residual.
+static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
+  const int n = c->n;
+  const fg_chain_cfg& cf = c->cfg;
+  const int cur = c->cur;
+  double* v0 = c->vecs;
+  double* v1 = v0 + n;
+  double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, ybar / sigma_f]
+  double* v3 = v2 + n;
+  double* dprec = c->cw + n;
+  double* dinv = dprec + n;
+  const uint64_t* itp = &c->st->iter;
+  fg::launch_collapsed_weights(n, c->cw, &c->st->alphaM, dprec, dinv, s);
+  fg::launch_factor(c->WM, nullptr, nullptr, dinv, s);
+  hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
+  fg::launch_scale_sqrt(n, dprec, v0, s);  // a ~ N(0, D)
+  fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
+  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
+  fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+  fg::launch_axpby(n, v2, v1, v2, nullptr, 1.0, nullptr, 1.0, s);  // Z = K~_1 a + W_1 b
+  fg::launch_div_scalar(n, c->y, &c->st->sigf, v3, s);
+  fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
+  fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
+  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v3, v0, 1, n, c->H[cur].work, s);
+  fg::launch_hetero_finish(n, v0, v2, dprec, c->f, nullptr, nullptr, s);  // g = R + Z* / D
+  fg::launch_axpby(n, c->f, nullptr, c->f, &c->st->sigf, 0.0, nullptr, 0.0, s);
+  fg::launch_axpby(n, v0, nullptr, c->mu, &c->st->sigf, 0.0, nullptr, 0.0, s);
+  fg::launch_div_scalar(n, v3, &c->st->sigf, c->r, s);  // Sigma^-1 ybar
+  fg::launch_dot(c->y, v3, n, 0, &c->st->yr, c->dotwork, s);
+  fg::launch_wsse(c->y, c->f, c->cw, n, &c->st->sse, c->dotwork + 1024, s);
+  fg::launch_tau_step_collapsed(c->st, n, c->n_obs, c->within, cf.a1, cf.b1, cf.seed,
+                                cf.stream_id, s);
 }
 
 void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
@@ -150,59 +199,63 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
                    c->aux);
   }
   hipEventRecord(c->ev_join, c->aux);
-  // f | -  (Algorithm 1)
-  fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
-  fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
-  hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-  fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
-  fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
-  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
-  fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
-  fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
-  fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
-  if (c->mixed && !c->fell_back) {
-    // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
-    // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
-    // residual test comes after as many iterations as the last draw needed.
-    std::string err;
-    const int min_it = std::max(1, c->pcg_iters);
-    const fg_status st = fg::pcg_solve(c->H[cur], 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
-                                       PCG_RTOL, PCG_MAXIT, c->pcg, s, &c->pcg_iters,
-                                       &c->pcg_relres, err, min_it);
-    if (st == FG_OK) {
-      hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-    } else {
-      // kappa(M~) u32 ~ 1: the FP32 factor is no preconditioner.  M~ is factored in FP64
-      // from now on (this draw included); the right-hand sides in v2, v3 are intact.
-      c->fell_back = true;
-      c->pcg_iters = 0;
-      c->pcg_relres = 0.0;
-      (void)hipStreamSynchronize(s);
-      std::string e2;
-      if (fg::factor_alloc(c->WM64, c->caps, e2) != FG_OK) {
-        c->pcg_failed = true;
-      } else {
-        c->WM64.H = &c->H[cur];
-        c->WM64.alpha = 0.0;
-        c->WM64.beta = 1.0;
-        fg::launch_factor(c->WM64, &c->st->alphaM, nullptr, nullptr, s);
-        hipMemcpyAsync(&c->st->logdetM, c->WM64.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-        fg::launch_apply_w(c->WM64, 2, v2, 2, n, c->WM64.work, s);
-        fg::launch_apply_w(c->WM64, 3, v2, 2, n, c->WM64.work, s);
-      }
-    }
+  if (c->collapsed) {
+    enqueue_f_tau_collapsed(c, s);
   } else {
-    fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
-    fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
+    // f | -  (Algorithm 1)
+    fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
+    fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
+    hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+    fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
+    fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
+    fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
+    fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
+    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
+    if (c->mixed && !c->fell_back) {
+      // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
+      // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
+      // residual test comes after as many iterations as the last draw needed.
+      std::string err;
+      const int min_it = std::max(1, c->pcg_iters);
+      const fg_status st = fg::pcg_solve(c->H[cur], 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
+                                         PCG_RTOL, PCG_MAXIT, c->pcg, s, &c->pcg_iters,
+                                         &c->pcg_relres, err, min_it);
+      if (st == FG_OK) {
+        hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      } else {
+        // kappa(M~) u32 ~ 1: the FP32 factor is no preconditioner.  M~ is factored in FP64
+        // from now on (this draw included); the right-hand sides in v2, v3 are intact.
+        c->fell_back = true;
+        c->pcg_iters = 0;
+        c->pcg_relres = 0.0;
+        (void)hipStreamSynchronize(s);
+        std::string e2;
+        if (fg::factor_alloc(c->WM64, c->caps, e2) != FG_OK) {
+          c->pcg_failed = true;
+        } else {
+          c->WM64.H = &c->H[cur];
+          c->WM64.alpha = 0.0;
+          c->WM64.beta = 1.0;
+          fg::launch_factor(c->WM64, &c->st->alphaM, nullptr, nullptr, s);
+          hipMemcpyAsync(&c->st->logdetM, c->WM64.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+          fg::launch_apply_w(c->WM64, 2, v2, 2, n, c->WM64.work, s);
+          fg::launch_apply_w(c->WM64, 3, v2, 2, n, c->WM64.work, s);
+        }
+      }
+    } else {
+      fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
+      fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
+    }
+    fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
+                      c->H[cur].work, s);
+    fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
+    hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
+    fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
+    // tau | -
+    fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, cf.stream_id, s);
   }
-  fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
-                    c->H[cur].work, s);
-  fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
-  hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-  fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
-  fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
-  // tau | -
-  fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, cf.stream_id, s);
   // sigma_f^-2 | -
   hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
   fg::launch_apply_w(c->W[cur], 2, v0, 1, n, c->W[cur].work, s);
@@ -420,6 +473,98 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
   }
   *out = c;
   return FG_OK;
+}
+
+fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x, const double* y,
+                                       int64_t n, fg_stream stream, fg_chain* out) {
+  if (!out) return cfail(FG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !x || !y) return cfail(FG_EINVAL, "NULL argument");
+  if (n < 1 || n >= (int64_t(1) << 31)) return cfail(FG_EINVAL, "n out of range");
+  if (cfg->precision != FG_FP64) return cfail(FG_EINVAL, "collapsed chains run in FP64");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<double> xh(n), yh(n);
+  if (hipMemcpyAsync(xh.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(yh.data(), y, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return cfail(FG_EDEVICE, "copy of x, y to the host failed");
+  // group equal inputs (stable order inside a group), then average
+  std::vector<int64_t> idx(n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(xh[i] == xh[i])) return cfail(FG_EINVAL, "x holds a NaN");
+    idx[i] = i;
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return xh[a] < xh[b]; });
+  std::vector<double> xu, ybar, w;
+  std::vector<int64_t> start;
+  for (int64_t k = 0; k < n; ++k) {
+    if (k == 0 || xh[idx[k]] != xh[idx[k - 1]]) {
+      xu.push_back(xh[idx[k]]);
+      ybar.push_back(0.0);
+      w.push_back(0.0);
+      start.push_back(k);
+    }
+    ybar.back() += yh[idx[k]];
+    w.back() += 1.0;
+  }
+  const int64_t u = (int64_t)xu.size();
+  for (int64_t i = 0; i < u; ++i) ybar[i] /= w[i];
+  double within = 0.0;
+  for (int64_t i = 0; i < u; ++i) {
+    const int64_t e = (i + 1 < u) ? start[i + 1] : n;
+    for (int64_t k = start[i]; k < e; ++k) {
+      const double d = yh[idx[k]] - ybar[i];
+      within += d * d;
+    }
+  }
+  double *dx = nullptr, *dy = nullptr;
+  if (hipMalloc(&dx, sizeof(double) * u) != hipSuccess || hipMalloc(&dy, sizeof(double) * u) != hipSuccess) {
+    if (dx) (void)hipFree(dx);
+    (void)hipGetLastError();
+    return cfail(FG_ENOMEM, "device allocation failed");
+  }
+  hipMemcpyAsync(dx, xu.data(), sizeof(double) * u, hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(dy, ybar.data(), sizeof(double) * u, hipMemcpyHostToDevice, s);
+  fg_chain c = nullptr;
+  fg_status st = gibbs_chain_create(cfg, dx, dy, u, stream, &c);  // synchronises s
+  (void)hipFree(dx);
+  (void)hipFree(dy);
+  if (st != FG_OK) return st;
+  if (hipMalloc(&c->cw, sizeof(double) * 3 * (size_t)u) != hipSuccess) {
+    chain_free(c);
+    (void)hipGetLastError();
+    return cfail(FG_ENOMEM, "device allocation failed");
+  }
+  hipMemcpyAsync(c->cw, w.data(), sizeof(double) * u, hipMemcpyHostToDevice, s);
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_EDEVICE, "copy of the counts failed");
+  }
+  c->collapsed = true;
+  c->within = within;
+  c->n_obs = n;
+  *out = c;
+  return FG_OK;
+}
+
+fg_status gibbs_chain_inputs(fg_chain c, int64_t* n_points, int64_t* n_obs, double* x_out,
+                             double* counts_out, fg_stream stream) {
+  if (!c) return cfail(FG_EINVAL, "NULL chain");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nb = sizeof(double) * (size_t)c->n;
+  if (n_points) *n_points = c->n;
+  if (n_obs) *n_obs = c->collapsed ? c->n_obs : c->n;
+  if (x_out) hipMemcpyAsync(x_out, c->x, nb, hipMemcpyDeviceToDevice, s);
+  if (counts_out) {
+    if (c->collapsed)
+      hipMemcpyAsync(counts_out, c->cw, nb, hipMemcpyDeviceToDevice, s);
+    else {  // every input once
+      const std::vector<double> ones((size_t)c->n, 1.0);
+      hipMemcpyAsync(counts_out, ones.data(), nb, hipMemcpyHostToDevice, s);
+      (void)hipStreamSynchronize(s);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? FG_OK : cfail(FG_EDEVICE, "copy failed");
 }
 
 fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {

@@ -202,6 +202,12 @@ void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_ta
                  int nsides, int esz, double* zfin, int zf_side, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,
                   const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
+// non-unique inputs: sum w (a - b)^2, out = x / *den, and the averages' precisions
+void launch_wsse(const double* a, const double* b, const double* w, int n, double* out,
+                 double* work, hipStream_t s);
+void launch_div_scalar(int n, const double* x, const double* den_dev, double* out, hipStream_t s);
+void launch_collapsed_weights(int n, const double* w, const double* alpha_dev, double* dprec,
+                              double* dinv, hipStream_t s);
 // function posterior at new inputs (k_predict.hip)
 void launch_cross_cov(const double* x, int n, const double* xstar, int nstar, int kind,
                       double ell, double* Z, int64_t ld, hipStream_t s);

@@ -75,6 +75,59 @@ __global__ void __launch_bounds__(NTHREADS) k_dot_stage2(const double* __restric
   }
 }
 
+// sum_i w_i (a_i - b_i)^2, stage 1 (stage 2 as for the plain dot)
+__global__ void __launch_bounds__(NTHREADS) k_wdot_stage1(const double* __restrict__ a,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ w, int n,
+                                                          double* __restrict__ part) {
+  __shared__ double red[NTHREADS / 64];
+  double s = 0.0;
+  for (int i = blockIdx.x * NTHREADS + threadIdx.x; i < n; i += DOT_BLOCKS * NTHREADS) {
+    const double d = a[i] - b[i];
+    s += w[i] * d * d;
+  }
+  s = wsum64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int v = 0; v < NTHREADS / 64; ++v) t += red[v];
+    part[blockIdx.x] = t;
+  }
+}
+
+void launch_wsse(const double* a, const double* b, const double* w, int n, double* out,
+                 double* work, hipStream_t s) {
+  k_wdot_stage1<<<DOT_BLOCKS, NTHREADS, 0, s>>>(a, b, w, n, work);
+  k_dot_stage2<<<1, NTHREADS, 0, s>>>(work, out);
+}
+
+// out = x / *den
+__global__ void k_div_scalar(int n, const double* __restrict__ x, const double* __restrict__ den,
+                             double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[i] / *den;
+}
+void launch_div_scalar(int n, const double* x, const double* den_dev, double* out, hipStream_t s) {
+  if (n > 0) k_div_scalar<<<(n + 255) / 256, 256, 0, s>>>(n, x, den_dev, out);
+}
+
+// precisions of the averages on the sigma_f scale, and their inverses:
+// dprec_i = (tau sigma_f^2) |Q_i|, dinv_i = 1 / dprec_i
+__global__ void k_collapsed_weights(int n, const double* __restrict__ w,
+                                    const double* __restrict__ alpha, double* __restrict__ dprec,
+                                    double* __restrict__ dinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = (*alpha) * w[i];
+  dprec[i] = d;
+  dinv[i] = 1.0 / d;
+}
+void launch_collapsed_weights(int n, const double* w, const double* alpha_dev, double* dprec,
+                              double* dinv, hipStream_t s) {
+  if (n > 0) k_collapsed_weights<<<(n + 255) / 256, 256, 0, s>>>(n, w, alpha_dev, dprec, dinv);
+}
+
 void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
                 hipStream_t s) {
   k_dot_stage1<<<DOT_BLOCKS, NTHREADS, 0, s>>>(a, b, n, mode, work);
@@ -138,6 +191,19 @@ __global__ void k_tau_step(DevState* st, int n, double a1, double b1, uint64_t s
   st->tau = g / (0.5 * (b1 + st->sse));
 }
 
+// collapsed data: the averages' log-likelihood (Sigma = sigma_f^2 (K~_1 + D^-1), st->yr
+// holding ybar' P^-1 (ybar / sigma_f)) and tau from the full-data residual
+__global__ void k_tau_step_collapsed(DevState* st, int u, int64_t n_obs, double within, double a1,
+                                     double b1, uint64_t seed, uint64_t strm) {
+  const uint64_t iter = st->iter;
+  st->yr = st->yr / st->sigf;
+  st->logdet_sigma = st->logdetM + u * log(st->sigf2);
+  st->loglik = -0.5 * u * log(2.0 * M_PI) - 0.5 * st->logdet_sigma - 0.5 * st->yr;
+  st->sse += within;
+  const double g = gamma_mt(0.5 * (a1 + (double)n_obs), seed, 3, iter, strm, &st->status);
+  st->tau = g / (0.5 * (b1 + st->sse));
+}
+
 __global__ void k_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed,
                             uint64_t strm) {
   const uint64_t iter = st->iter;
@@ -176,6 +242,10 @@ void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t
 void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, uint64_t strm,
                      hipStream_t s) {
   k_tau_step<<<1, 1, 0, s>>>(st, n, a1, b1, seed, strm);
+}
+void launch_tau_step_collapsed(DevState* st, int u, int64_t n_obs, double within, double a1,
+                               double b1, uint64_t seed, uint64_t strm, hipStream_t s) {
+  k_tau_step_collapsed<<<1, 1, 0, s>>>(st, u, n_obs, within, a1, b1, seed, strm);
 }
 void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t strm,
                       hipStream_t s) {

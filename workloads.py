@@ -97,3 +97,19 @@ def new_inputs(count: int = 1024, seed: int = 7):
     """New inputs for predictive draws: uniform on [-0.02, 1.02] (the data's range on
     [0, 1] and a little past both ends), in no particular order."""
     return np.random.default_rng(seed).uniform(-0.02, 1.02, count)
+
+
+def gridded_1d(n_unique: int = 1 << 14, reps: int = 64, seed: int = 11, noise: float = 0.2):
+    """Repeated measurements on a grid: n_unique evenly spaced inputs on (0, 1), each
+    observed `reps` times (n = n_unique * reps observations, in shuffled order), y = a
+    5-sinusoid signal as in sinusoid_1d plus N(0, noise^2)."""
+    g = np.random.default_rng(seed)
+    xu = (np.arange(n_unique) + 0.5) / n_unique
+    x = np.repeat(xu, reps)
+    freq = g.uniform(1.0, 20.0, 5)
+    amp = g.normal(0.0, 1.0, 5)
+    phase = g.uniform(0.0, 2.0 * math.pi, 5)
+    y = sum(amp[k] * np.sin(2.0 * math.pi * freq[k] * x + phase[k]) for k in range(5))
+    y = y + noise * g.normal(size=x.size)
+    p = g.permutation(x.size)
+    return x[p], y[p]
