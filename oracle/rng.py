@@ -33,6 +33,7 @@ MASK32 = np.uint64(0xFFFFFFFF)
 TAG_A, TAG_B, TAG_G_TAU, TAG_G_SIGF, TAG_PROP, TAG_ACC = 1, 2, 3, 4, 5, 6
 TAG_BETA = 7          # tensor-product model: normal draw of beta
 TAG_PRED = 8          # function draws at new inputs
+TAG_RHO = 9           # exact discrete length-scale conditional (inverse-CDF uniform)
 TAG_FACTOR_STRIDE = 16  # tensor-product model: factor h uses tag + 16*(h+1)
 
 
