@@ -26,6 +26,10 @@ Other workloads (--workload), each printing its own JSON line:
           grid inputs, 64 each): the chain on the collapsed data (Appendix, non-unique
           input points); value = Gibbs iterations/s, with the plain chain on the raw
           2^20 observations timed beside it.
+  exact   the length-scale drawn from its exact grid conditional (gibbs_chain_create_grid:
+          all 100 grid factorizations kept), n = 2^17 sinusoid inputs; value = Gibbs
+          iterations/s, with the Metropolis chain on the same data beside it and the
+          set-up time and device memory of the grid.
   serve   GP-regression jobs of mixed n (workloads.served_jobs) through the serving
           loop: first all at once (saturation throughput), then Poisson arrivals at
           0.7 x that rate; value = p50 latency (s), with p99 and the same arrival list
@@ -55,7 +59,7 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override n (testing only)")
     ap.add_argument("--workload", default="large_1d",
                     choices=["large_1d", "batch", "tensor", "serve", "copy", "predict",
-                             "collapse"])
+                             "collapse", "exact"])
     ap.add_argument("--nstar", type=int, default=1024, help="predict: new inputs per draw")
     ap.add_argument("--zcache", type=int, default=8,
                     help="predict: grid points whose W_1^-1 k1(X, X*) is kept")
@@ -390,6 +394,79 @@ def bench_collapse(args):
           roofline=roof, **extra)
 
 
+def bench_exact(args):
+    import torch
+
+    import paper_2006_06537_amd as fg
+    from workloads import LARGE_1D, sinusoid_1d
+    cfg = dict(LARGE_1D)
+    n = args.n or (1 << 17)
+    x, y = sinusoid_1d(n, seed=cfg["seed"])
+    dev = torch.device("cuda:0")
+    xt, yt = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    kw = dict(ell0=cfg["ell0"], tau0=cfg["tau0"], sigf2_0=cfg["sigf2_0"], nugget=cfg["nugget"],
+              leaf=cfg["leaf"], tol=cfg["tol"], seed=cfg["seed"])
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    t0 = time.perf_counter()
+    ch = fg.Chain(xt, yt, exact_rho=True, **kw)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    held = free0 - torch.cuda.mem_get_info()[0]
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ch.state()
+    print(f"bench: grid chain n={n}: set-up {t_create:.2f} s ({held / 1e9:.1f} GB), "
+          f"{args.steps} sweeps in {dt:.3f} s, k {st['k']}, moves {st['accepts']}, status "
+          f"{st['status']}", file=sys.stderr, flush=True)
+    # the same sweeps replayed from captured graphs (one graph per grid index)
+    fg.step_batch([ch], iters=args.warmup, nstreams=1, graphs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fg.step_batch([ch], iters=args.steps, nstreams=1, graphs=True)
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t0
+    print(f"bench: grid chain from captured graphs: {args.steps} sweeps in {dt_graph:.3f} s",
+          file=sys.stderr, flush=True)
+    mh = fg.Chain(xt, yt, **kw)
+    mh.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mh.step(args.steps)
+    torch.cuda.synchronize()
+    dt_mh = time.perf_counter() - t0
+    extra = {"metropolis_iters_per_s": args.steps / dt_mh, "graphs_iters_per_s": args.steps / dt_graph,
+             "setup_s": t_create,
+             "grid_bytes": held, "grid_points": 100, "moves": st["accepts"]}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import exact_rho, kernels
+        sub = 1 << 13  # the oracle's set-up (100 factorizations) at n = 2^17 runs for minutes
+        xs_, ys_ = sinusoid_1d(sub, seed=cfg["seed"])
+        oc = exact_rho.ExactGridChain(xs_, ys_, kernels.SE, cfg["ell0"], cfg["nugget"],
+                                      cfg["leaf"], cfg["tol"], cfg["tau0"], cfg["sigf2_0"],
+                                      cfg["seed"])
+        t1 = time.perf_counter()
+        oc.step()
+        dto = time.perf_counter() - t1
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        extra["cpu_baseline"] = {"value": 1.0 / dto, "unit": "Gibbs iters/s", "cores": threads,
+                                 "kind": "oracle",
+                                 "sample": f"one sweep of the oracle grid chain at n={sub} "
+                                           f"(set-up untimed), {dto:.2f} s"}
+    _line(f"Gibbs iters/s with the exact grid conditional of the length-scale, n={n} (FP64)",
+          args.steps / dt, "Gibbs iters/s", args, dt, "f64",
+          {"workload": f"exact: n={n} sorted U[0,1], 5-sinusoid y + N(0,0.05^2), SE kernel "
+                       "ell0=0.02, 100-point grid with every factorization kept, leaf 128, "
+                       "tol 1e-10, nugget 1e-6", "n": n},
+          roofline=None, **extra)
+
+
 def bench_serve(args):
     import threading
 
@@ -496,6 +573,8 @@ def main():
         return bench_predict(args)
     if args.workload == "collapse":
         return bench_collapse(args)
+    if args.workload == "exact":
+        return bench_exact(args)
     import numpy as np
     import torch
 

@@ -270,6 +270,23 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
                             double* r_out, double* mu_out, fg_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * gibbs_chain_create_grid -- as gibbs_chain_create, with the length-scale drawn from its
+ * exact discrete conditional (Section 4.1, the fourth conditional; uniform prior over the
+ * grid) in place of the Metropolis step: every grid point's K~_1, W_1 and log det K~_1 are
+ * built once at creation and kept on the device (grid_size factorizations: memory grows
+ * with grid_size, see chain_device_bytes), and each sweep computes q_h = |W_h^-1 f|^2 for
+ * every h on four library streams, then draws h with probability proportional to
+ * exp(-1/2 log det K~_1(s_h) - q_h / (2 sigma_f^2)) by inverse CDF with the Philox uniform
+ * of tag 9 (the first h whose cumulative weight exceeds u times the total).  In the
+ * snapshot, last_proposal is the drawn index, last_accept whether it differs from the
+ * previous one, mh_log_ratio the drawn index's log-probability and q its q_h.  FP64 only.
+ * Errors: as gibbs_chain_create; FG_ENOTSPD if a grid point's K~_1 is not positive
+ * definite; FG_ENOMEM when the grid does not fit.
+ * ------------------------------------------------------------------------- */
+fg_status gibbs_chain_create_grid(const fg_chain_cfg* cfg, const double* x, const double* y,
+                                  int64_t n, fg_stream stream, fg_chain* out);
+
+/* ---------------------------------------------------------------------------
  * Non-unique inputs (Appendix, "Non-unique input points").
  * gibbs_chain_create_collapsed -- as gibbs_chain_create, for n observations (x, y on the
  *   device, any order) whose inputs may repeat.  The U distinct inputs (ascending) with

@@ -345,14 +345,19 @@ class Chain:
 
     def __init__(self, x, y, ell0, tau0, sigf2_0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
                  seed=0, stream_id=0, kind=KERNEL_SE, priors=(1.0, 1.0, 1.0, 1.0),
-                 grid_size=100, grid_center=50, precision=FP64, collapse=False):
+                 grid_size=100, grid_center=50, precision=FP64, collapse=False, exact_rho=False):
         """collapse=True: repeated inputs are merged (gibbs_chain_create_collapsed) and the
-        chain runs on the unique inputs (self.n of them; self.n_obs observations)."""
+        chain runs on the unique inputs (self.n of them; self.n_obs observations).
+        exact_rho=True: the length-scale is drawn from its exact grid conditional
+        (gibbs_chain_create_grid)."""
+        if collapse and exact_rho:
+            raise ValueError("collapse and exact_rho are separate chain kinds")
         m = int(x.shape[0])
         cfg = ChainCfg(kind, ell0, nugget, leaf, tol, tau0, sigf2_0, priors[0], priors[1],
                        priors[2], priors[3], grid_size, grid_center, seed, stream_id, precision)
         c = C.c_void_p()
-        create = lib().gibbs_chain_create_collapsed if collapse else lib().gibbs_chain_create
+        create = (lib().gibbs_chain_create_collapsed if collapse else
+                  lib().gibbs_chain_create_grid if exact_rho else lib().gibbs_chain_create)
         check(create(C.byref(cfg), _dev(x, m), _dev(y, m), m, _stream(), C.byref(c)))
         self._c = c
         u, nobs = C.c_int64(), C.c_int64()

@@ -23,7 +23,8 @@ EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", 
            "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
            "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
-           "gibbs_step_batch", "gibbs_chain_state", "gibbs_chain_create_collapsed", "gibbs_chain_inputs",
+           "gibbs_step_batch", "gibbs_chain_state", "gibbs_chain_create_grid", "gibbs_chain_create_collapsed",
+           "gibbs_chain_inputs",
            "gibbs_predict_inputs", "gibbs_predict",
            "gibbs_predict_stats",
            "tp_chain_create", "tp_step", "tp_chain_state",
@@ -154,6 +155,7 @@ def lib():
         "gibbs_step_batch": ([C.POINTER(P), I32, I32, I32, I32, P], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),
         "gibbs_chain_create_collapsed": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
+        "gibbs_chain_create_grid": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
         "gibbs_chain_inputs": ([P, C.POINTER(I64), C.POINTER(I64), DP, DP, P], I32),
         "gibbs_predict_inputs": ([P, DP, I64, I32, P], I32),
         "gibbs_predict_stats": ([P, C.POINTER(I32), C.POINTER(I64)], I32),

@@ -42,6 +42,16 @@ struct fg_chain_s {
   bool pcg_failed = false;
   hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // exact discrete conditional of the length-scale: every grid point's K~_1 and W_1
+  bool exact = false;
+  std::vector<fg::HodlrData> Hg;
+  std::vector<fg::FactorData> Wg;
+  double* ldg = nullptr;                      // log det K~_1 per grid point
+  double* qg = nullptr;                       // |W_h^-1 f|^2 per grid point
+  double* qbuf = nullptr;                     // one work vector per q stream
+  double* qdot = nullptr;                     // dot partials per q stream
+  hipStream_t qs[4] = {};
+  hipEvent_t qev[5] = {};
   // non-unique inputs: the chain runs on the unique inputs with the averages as y
   bool collapsed = false;
   double* cw = nullptr;                       // |Q_i| (n), then precisions and their inverses
@@ -83,13 +93,19 @@ static void chain_free(fg_chain c) {
   if (c->aux) (void)hipStreamDestroy(c->aux);
   fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
+  for (auto& h : c->Hg) fg::hodlr_free(h);
+  for (auto& w : c->Wg) fg::factor_free(w);
+  for (auto q : c->qs)
+    if (q) (void)hipStreamDestroy(q);
+  for (auto e : c->qev)
+    if (e) (void)hipEventDestroy(e);
   fg::factor_free(c->WM);
   fg::factor_free(c->WM64);
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
   for (auto& e : c->zcache)
     if (e.z) (void)hipFree(e.z);
   double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork, c->xstar, c->pwork,
-                    c->cw};
+                    c->cw, c->ldg, c->qg, c->qbuf, c->qdot};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->st) (void)hipFree(c->st);
@@ -103,9 +119,15 @@ struct Proposal {
   int kp, ongrid;
 };
 
+// the current length-scale's K~_1 and W_1: a grid slot in exact mode, else the slot of the
+// two-slot (current, proposal) pair
+fg::HodlrData& Hcur(fg_chain c) { return c->exact ? c->Hg[c->k] : c->H[c->cur]; }
+fg::FactorData& Wcur(fg_chain c) { return c->exact ? c->Wg[c->k] : c->W[c->cur]; }
+
 // The grid proposal of the next sweep: its uniform is addressed by the iteration
 // count, which the host knows, so the proposal needs no device round trip.
 Proposal propose(fg_chain c) {
+  if (c->exact) return Proposal{c->k, 0};  // no proposal: the whole grid is weighed
   uint64_t w[4];
   fg::philox4x64_10(0, 5, (uint64_t)c->iter, c->cfg.stream_id, c->cfg.seed, 0, w);
   Proposal p;
@@ -123,7 +145,7 @@ Proposal propose(fg_chain c) {
 void prepare_sweep(fg_chain c, const Proposal& pr) {
   const int cur = c->cur, oth = 1 - cur;
   fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
-  WM.H = &c->H[cur];
+  WM.H = &Hcur(c);
   if (c->collapsed) {  // K~_1 + D^-1, D^-1 passed as the diagonal
     WM.alpha = 1.0;
     WM.beta = 0.0;
@@ -145,7 +167,8 @@ void prepare_sweep(fg_chain c, const Proposal& pr) {
 static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
   const int n = c->n;
   const fg_chain_cfg& cf = c->cfg;
-  const int cur = c->cur;
+  fg::HodlrData& H1 = Hcur(c);
+  fg::FactorData& W1 = Wcur(c);
   double* v0 = c->vecs;
   double* v1 = v0 + n;
   double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, ybar / sigma_f]
@@ -159,13 +182,13 @@ static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
   fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
   fg::launch_scale_sqrt(n, dprec, v0, s);  // a ~ N(0, D)
   fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
-  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
-  fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+  fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, s);
+  fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, s);
   fg::launch_axpby(n, v2, v1, v2, nullptr, 1.0, nullptr, 1.0, s);  // Z = K~_1 a + W_1 b
   fg::launch_div_scalar(n, c->y, &c->st->sigf, v3, s);
   fg::launch_apply_w(c->WM, 2, v2, 2, n, c->WM.work, s);
   fg::launch_apply_w(c->WM, 3, v2, 2, n, c->WM.work, s);
-  fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v3, v0, 1, n, c->H[cur].work, s);
+  fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v3, v0, 1, n, H1.work, s);
   fg::launch_hetero_finish(n, v0, v2, dprec, c->f, nullptr, nullptr, s);  // g = R + Z* / D
   fg::launch_axpby(n, c->f, nullptr, c->f, &c->st->sigf, 0.0, nullptr, 0.0, s);
   fg::launch_axpby(n, v0, nullptr, c->mu, &c->st->sigf, 0.0, nullptr, 0.0, s);
@@ -176,6 +199,26 @@ static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
                                 cf.stream_id, s);
 }
 
+// q_h = |W_h^-1 f|^2 for every grid point, spread over the chain's q streams, then one
+// draw from the discrete conditional (k_rho_exact).
+static void enqueue_rho_exact(fg_chain c, hipStream_t s) {
+  const int n = c->n, G = (int)c->Wg.size();
+  hipEventRecord(c->qev[0], s);
+  for (int q = 0; q < 4; ++q) hipStreamWaitEvent(c->qs[q], c->qev[0], 0);
+  for (int h = 0; h < G; ++h) {
+    const int q = h & 3;
+    double* v = c->qbuf + (size_t)q * n;
+    hipMemcpyAsync(v, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->qs[q]);
+    fg::launch_apply_w(c->Wg[h], 2, v, 1, n, c->Wg[h].work, c->qs[q]);
+    fg::launch_dot(v, v, n, 0, c->qg + h, c->qdot + (size_t)q * 2048, c->qs[q]);
+  }
+  for (int q = 0; q < 4; ++q) {
+    hipEventRecord(c->qev[1 + q], c->qs[q]);
+    hipStreamWaitEvent(s, c->qev[1 + q], 0);
+  }
+  fg::launch_rho_exact(c->st, c->ldg, c->qg, G, c->cfg.seed, c->cfg.stream_id, s);
+}
+
 void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   const int n = c->n;
   const fg_chain_cfg& cf = c->cfg;
@@ -184,7 +227,9 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   double* v2 = v1 + n;  // v2, v3: the two right-hand sides [Z, tau y]
   double* v3 = v2 + n;
   const uint64_t* itp = &c->st->iter;
-  const int cur = c->cur, oth = 1 - cur;
+  const int oth = 1 - c->cur;
+  fg::HodlrData& H1 = Hcur(c);
+  fg::FactorData& W1 = Wcur(c);
   fg::launch_sweep_begin(c->st, s);
   // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
   // the chain's second stream while this stream factors M~ and draws f.
@@ -208,8 +253,8 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
     fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
     fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
-    fg::launch_matvec(c->H[cur], 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, c->H[cur].work, s);
-    fg::launch_apply_w(c->W[cur], 0, v1, 1, n, c->W[cur].work, s);
+    fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, s);
+    fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, s);
     fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
     fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
     if (c->mixed && !c->fell_back) {
@@ -218,7 +263,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
       // residual test comes after as many iterations as the last draw needed.
       std::string err;
       const int min_it = std::max(1, c->pcg_iters);
-      const fg_status st = fg::pcg_solve(c->H[cur], 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
+      const fg_status st = fg::pcg_solve(H1, 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
                                          PCG_RTOL, PCG_MAXIT, c->pcg, s, &c->pcg_iters,
                                          &c->pcg_relres, err, min_it);
       if (st == FG_OK) {
@@ -234,7 +279,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
         if (fg::factor_alloc(c->WM64, c->caps, e2) != FG_OK) {
           c->pcg_failed = true;
         } else {
-          c->WM64.H = &c->H[cur];
+          c->WM64.H = &H1;
           c->WM64.alpha = 0.0;
           c->WM64.beta = 1.0;
           fg::launch_factor(c->WM64, &c->st->alphaM, nullptr, nullptr, s);
@@ -247,8 +292,8 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
       fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
       fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
     }
-    fg::launch_matvec(c->H[cur], 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
-                      c->H[cur].work, s);
+    fg::launch_matvec(H1, 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
+                      H1.work, s);
     fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
     hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
@@ -258,11 +303,16 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   }
   // sigma_f^-2 | -
   hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-  fg::launch_apply_w(c->W[cur], 2, v0, 1, n, c->W[cur].work, s);
+  fg::launch_apply_w(W1, 2, v0, 1, n, W1.work, s);
   fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
   fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
-  // length-scale | -  (Metropolis on the grid)
   hipStreamWaitEvent(s, c->ev_join, 0);
+  if (c->exact) {  // length-scale | -  (exact, over the whole grid)
+    enqueue_rho_exact(c, s);
+    hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+    return;
+  }
+  // length-scale | -  (Metropolis on the grid)
   if (pr.ongrid) {
     hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
@@ -275,7 +325,9 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
 
 // after the sweep's stream has been synchronised: the accepted proposal becomes current
 void finish_sweep(fg_chain c, const Proposal& pr) {
-  if (c->st_host->accept) {
+  if (c->exact) {
+    c->k = c->st_host->k;
+  } else if (c->st_host->accept) {
     c->cur = 1 - c->cur;
     c->k = pr.kp;
   }
@@ -547,6 +599,78 @@ fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x,
   return FG_OK;
 }
 
+fg_status gibbs_chain_create_grid(const fg_chain_cfg* cfg, const double* x, const double* y,
+                                  int64_t n, fg_stream stream, fg_chain* out) {
+  if (!out) return cfail(FG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (cfg && cfg->precision != FG_FP64) return cfail(FG_EINVAL, "grid chains run in FP64");
+  fg_chain c = nullptr;
+  fg_status st = gibbs_chain_create(cfg, x, y, n, stream, &c);
+  if (st != FG_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int G = cfg->grid_size;
+  std::string err;
+  c->Hg.resize(G);
+  c->Wg.resize(G);
+  for (int h = 0; h < G; ++h) {
+    if ((st = fg::hodlr_alloc(c->Hg[h], c->caps, err)) != FG_OK ||
+        (st = fg::factor_alloc(c->Wg[h], c->caps, err)) != FG_OK) {
+      chain_free(c);
+      return cfail(st, err + " (grid factorizations)");
+    }
+  }
+  const size_t nb = sizeof(double) * (size_t)c->n;
+  if (hipMalloc(&c->ldg, sizeof(double) * G) != hipSuccess ||
+      hipMalloc(&c->qg, sizeof(double) * G) != hipSuccess ||
+      hipMalloc(&c->qbuf, 4 * nb) != hipSuccess ||
+      hipMalloc(&c->qdot, sizeof(double) * 4 * 2048) != hipSuccess) {
+    chain_free(c);
+    (void)hipGetLastError();
+    return cfail(FG_ENOMEM, "grid chain allocation failed");
+  }
+  for (int q = 0; q < 4; ++q)
+    if (hipStreamCreateWithFlags(&c->qs[q], hipStreamNonBlocking) != hipSuccess) {
+      chain_free(c);
+      return cfail(FG_EDEVICE, "stream creation failed");
+    }
+  for (auto& e : c->qev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      chain_free(c);
+      return cfail(FG_EDEVICE, "event creation failed");
+    }
+  // every grid point's K~_1, W_1 and log-determinant, once
+  for (int h = 0; h < G; ++h) {
+    fg::HodlrData& H = c->Hg[h];
+    fg::FactorData& W = c->Wg[h];
+    hipMemcpyAsync(H.x, c->x, nb, hipMemcpyDeviceToDevice, s);
+    H.pk = c->packs[h];
+    fg::launch_build(H, s);
+    W.H = &H;
+    W.alpha = 1.0;
+    W.beta = 0.0;
+    fg::launch_factor(W, nullptr, nullptr, nullptr, s);
+    hipMemcpyAsync(c->ldg + h, W.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
+  int bad = 0;
+  for (int h = 0; h < G && hipStreamSynchronize(s) == hipSuccess; ++h) {
+    int hs = 0, ws = 0;
+    hipMemcpy(&hs, c->Hg[h].status, sizeof(int), hipMemcpyDeviceToHost);
+    hipMemcpy(&ws, c->Wg[h].status, sizeof(int), hipMemcpyDeviceToHost);
+    bad |= hs | ws;
+  }
+  if (hipGetLastError() != hipSuccess) {
+    chain_free(c);
+    return cfail(FG_EDEVICE, "grid factorizations failed on the device");
+  }
+  if (bad & fg::ST_NOTSPD) {
+    chain_free(c);
+    return cfail(FG_ENOTSPD, "a grid point's K~_1 is not positive definite");
+  }
+  c->exact = true;
+  *out = c;
+  return FG_OK;
+}
+
 fg_status gibbs_chain_inputs(fg_chain c, int64_t* n_points, int64_t* n_obs, double* x_out,
                              double* counts_out, fg_stream stream) {
   if (!c) return cfail(FG_EINVAL, "NULL chain");
@@ -635,8 +759,8 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
   if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "state copy failed");
   int fst = 0;
   int hs = 0, ws = 0, ms = 0;
-  hipMemcpy(&hs, c->H[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
-  hipMemcpy(&ws, c->W[c->cur].status, sizeof(int), hipMemcpyDeviceToHost);
+  hipMemcpy(&hs, Hcur(c).status, sizeof(int), hipMemcpyDeviceToHost);
+  hipMemcpy(&ws, Wcur(c).status, sizeof(int), hipMemcpyDeviceToHost);
   hipMemcpy(&ms, (c->fell_back ? c->WM64 : c->WM).status, sizeof(int), hipMemcpyDeviceToHost);
   fst = c->st_host->status | hs | ws | ms;
   const fg::DevState& d = *c->st_host;
@@ -731,7 +855,7 @@ static double* predict_z(fg_chain c, hipStream_t s) {
     for (auto& e : c->zcache)
       if (e.used < slot->used) slot = &e;
   }
-  fg::FactorData& W1 = c->W[c->cur];
+  fg::FactorData& W1 = Wcur(c);
   fg::launch_cross_cov(c->x, n, c->xstar, N, c->cfg.kind, c->grid[c->k], slot->z, n, s);
   for (int j = 0; j < N; j += 4)
     fg::launch_apply_w(W1, 2, slot->z + (size_t)j * n, std::min(4, N - j), n, W1.work, s);
@@ -746,7 +870,7 @@ fg_status gibbs_predict(fg_chain c, double* fstar, double* mu, double* s2, fg_st
   if (c->nstar == 0) return cfail(FG_EINVAL, "no new inputs set (gibbs_predict_inputs)");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int n = c->n, N = c->nstar;
-  fg::FactorData& W1 = c->W[c->cur];
+  fg::FactorData& W1 = Wcur(c);
   const double* Z = predict_z(c, s);
   double* zf = c->pwork;
   double* xi = zf + n;

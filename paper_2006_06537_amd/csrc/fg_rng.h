@@ -85,6 +85,8 @@ void launch_tau_step(DevState* st, int n, double a1, double b1, uint64_t seed, u
                      hipStream_t s);
 void launch_sigf_step(DevState* st, int n, double a2, double b2, uint64_t seed, uint64_t strm,
                       hipStream_t s);
+void launch_rho_exact(DevState* st, const double* ld, const double* q, int G, uint64_t seed,
+                      uint64_t strm, hipStream_t s);
 void launch_tau_step_collapsed(DevState* st, int u, int64_t n_obs, double within, double a1,
                                double b1, uint64_t seed, uint64_t strm, hipStream_t s);
 void launch_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, uint64_t strm,

@@ -235,6 +235,46 @@ __global__ void k_mh_step(DevState* st, int kprop, int ongrid, uint64_t seed, ui
   }
 }
 
+// The exact discrete conditional of the length-scale (Section 4.1, uniform prior over the
+// grid): log-weights lp_h = -1/2 log det K~_1(s_h) - q_h / (2 sigma_f^2), one uniform (tag 9)
+// through the inverse CDF: the first h whose cumulative weight exceeds u times the total.
+// Ends the sweep like the Metropolis step.
+__global__ void k_rho_exact(DevState* st, const double* __restrict__ ld,
+                            const double* __restrict__ q, int G, uint64_t seed, uint64_t strm) {
+  const uint64_t iter = st->iter;
+  st->iter = iter + 1;
+  const double s2 = st->sigf2;
+  double m = -INFINITY;
+  for (int h = 0; h < G; ++h) m = fmax(m, -0.5 * ld[h] - q[h] / (2.0 * s2));
+  double tot = 0.0;
+  for (int h = 0; h < G; ++h) tot += exp(-0.5 * ld[h] - q[h] / (2.0 * s2) - m);
+  uint64_t w[4];
+  philox4x64_10(0, 9, iter, strm, seed, 0, w);
+  const double t = to_unit(w[0]) * tot;
+  double c = 0.0;
+  int pick = G - 1;
+  for (int h = 0; h < G; ++h) {
+    c += exp(-0.5 * ld[h] - q[h] / (2.0 * s2) - m);
+    if (c > t) {
+      pick = h;
+      break;
+    }
+  }
+  const int old = st->k;
+  st->kprop = pick;
+  st->accept = pick != old;
+  st->accepts += st->accept;
+  st->k = pick;
+  st->logdet1 = ld[pick];
+  st->q = q[pick];
+  st->mh = -0.5 * ld[pick] - q[pick] / (2.0 * s2) - (m + log(tot));
+}
+
+void launch_rho_exact(DevState* st, const double* ld, const double* q, int G, uint64_t seed,
+                      uint64_t strm, hipStream_t s) {
+  k_rho_exact<<<1, 1, 0, s>>>(st, ld, q, G, seed, strm);
+}
+
 void launch_sweep_begin(DevState* st, hipStream_t s) { k_sweep_begin<<<1, 1, 0, s>>>(st); }
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s) {
   k_set_draw_scalars<<<1, 1, 0, s>>>(st, tau, sigf2);
