@@ -177,3 +177,90 @@ def test_clamp_keeps_sign_and_floor():
     g = np.array([0.0, 1e-200, -1e-200, -3.0, 2e-150])
     out = tensor.clamp_g(g)
     assert list(out) == [1e-150, 1e-150, -1e-150, -3.0, 2e-150]
+
+
+# --- additive tensor products (several components) -------------------------------
+
+def make_additive(d=2, n=150, C=2, leaf=32, seed=4):
+    x, y = tensor_surface(d, n, seed=seed)
+    c = tensor.TensorChain(x, y, kernels.SE, [0.1 + 0.05 * h for h in range(d)], 1e-6, leaf,
+                           1e-12, 30.0, 0.9, seed, ncomp=C)
+    r = np.random.default_rng(12)
+    c.F = 1.0 + 0.5 * r.standard_normal((C * d, n))
+    c.betas = [0.9, -0.4][:C]
+    return x, y, c
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_additive_factor_conditional_dense(m):
+    """Factor m = c d + h of a two-component model: the data are the partial residual
+    y - beta_c' G_c' written out observation by observation, with
+    g_i = beta_c prod_{k != h} f_{c,k}(x_i); mean and covariance against the dense
+    conditional."""
+    x, y, c = make_additive()
+    cc, h = divmod(m, c.d)
+    n = c.n
+    other = 1 - cc
+    r = np.array([y[i] - c.betas[other] * np.prod([c.F[other * c.d + k, i] for k in range(c.d)])
+                  for i in range(n)])
+    g = np.array([c.betas[cc] * np.prod([c.F[cc * c.d + k, i] for k in range(c.d) if k != h])
+                  for i in range(n)])
+    K = dense_k(x[h], c.grids[m][c.k[m]])
+    D = c.tau * g * g
+    mean = np.linalg.solve(np.eye(n) + K * D[None, :], K @ (c.tau * g * r))
+    z = np.zeros(n)
+    f0 = c.update_factor(m, z, z)[0]
+    assert np.linalg.norm(c.F[m] - mean) <= 1e-8 * np.linalg.norm(mean)
+    p = c.perm[h]
+    # the draw is affine in its normals (a, b): its covariance from the unit responses
+    Mb = np.stack([c.update_factor(m, z, np.eye(n)[j])[0] - f0 for j in range(n)], axis=1)
+    Ma = np.stack([c.update_factor(m, np.eye(n)[j], z)[0] - f0 for j in range(n)], axis=1)
+    cov = Ma @ Ma.T + Mb @ Mb.T
+    Ks = dense_k(x[h][p], c.grids[m][c.k[m]])
+    Ds = D[p]
+    ref = np.linalg.solve(np.eye(n) + Ks * Ds[None, :], Ks)
+    assert np.linalg.norm(cov - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_additive_with_a_silent_component_is_the_single_product():
+    """beta_1 = 0: component 0 sees y itself, so its factor draws and beta_0 equal those
+    of the one-component chain with the same state and seed."""
+    x, y, c2 = make_additive()
+    c2.betas = [0.9, 0.0]
+    c1 = tensor.TensorChain(x, y, kernels.SE, [0.1 + 0.05 * h for h in range(2)], 1e-6, 32,
+                            1e-12, 30.0, 0.9, 4)
+    c1.F = c2.F[:2].copy()
+    c1.betas = [0.9]
+    for m in range(2):
+        D2, y2 = c2.factor_inputs(m)
+        D1, y1 = c1.factor_inputs(m)
+        np.testing.assert_array_equal(D2, D1)
+        np.testing.assert_array_equal(y2, y1)
+
+
+def test_additive_tau_uses_the_full_residual():
+    x, y, c = make_additive()
+    rec = c.step()
+    fit = np.array([sum(c.betas[cc] * np.prod([c.F[cc * c.d + k, i] for k in range(c.d)])
+                        for cc in range(c.C)) for i in range(c.n)])
+    assert rec["sse"] == pytest.approx(float(np.sum((y - fit) ** 2)), rel=1e-12)
+    assert len(rec["betas"]) == 2 and rec["betas"][0] == c.beta
+
+
+def test_additive_beta_on_the_partial_residual_quadrature():
+    """beta_c | -: prior N(0, s^2) times prod_i N(r_i; beta G_c,i, 1/tau) with the partial
+    residual r_i = y_i - beta_c' G_c',i written out per observation, integrated
+    numerically."""
+    x, y, c = make_additive()
+    n = c.n
+    G = np.array([np.prod([c.F[c.d + k, i] for k in range(c.d)]) for i in range(n)])
+    r = np.array([y[i] - c.betas[0] * np.prod([c.F[k, i] for k in range(c.d)]) for i in range(n)])
+    mean, sd = c.beta_moments(1)
+    b = np.linspace(mean - 12 * sd, mean + 12 * sd, 20001)
+    logp = -0.5 * b ** 2 / tensor.S_BETA ** 2 - 0.5 * c.tau * np.sum(
+        (r[None, :] - b[:, None] * G[None, :]) ** 2, axis=1)
+    w = np.exp(logp - logp.max())
+    m_q = float(np.sum(w * b) / np.sum(w))
+    s_q = math.sqrt(float(np.sum(w * (b - m_q) ** 2) / np.sum(w)))
+    assert m_q == pytest.approx(mean, rel=1e-6, abs=1e-9)
+    assert s_q == pytest.approx(sd, rel=1e-5)
