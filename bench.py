@@ -61,6 +61,8 @@ def parse():
                     choices=["large_1d", "batch", "tensor", "serve", "copy", "predict",
                              "collapse", "exact"])
     ap.add_argument("--nstar", type=int, default=1024, help="predict: new inputs per draw")
+    ap.add_argument("--ncomp", type=int, default=1,
+                    help="tensor: additive tensor-product components (ncomp * d <= 8)")
     ap.add_argument("--zcache", type=int, default=8,
                     help="predict: grid points whose W_1^-1 k1(X, X*) is kept")
     ap.add_argument("--jobs", type=int, default=64, help="serve workload: number of jobs")
@@ -206,7 +208,7 @@ def bench_tensor(args):
     dev = torch.device("cuda:0")
     ch = fg.TensorChain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), T["ell0"],
                         tau0=T["tau0"], beta0=T["beta0"], nugget=T["nugget"], leaf=T["leaf"],
-                        tol=T["tol"], seed=T["seed"])
+                        tol=T["tol"], seed=T["seed"], ncomp=args.ncomp)
     ch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -222,7 +224,7 @@ def bench_tensor(args):
 
         from oracle import kernels, tensor
         oc = tensor.TensorChain(x, y, kernels.SE, T["ell0"], T["nugget"], T["leaf"], T["tol"],
-                                T["tau0"], T["beta0"], T["seed"])
+                                T["tau0"], T["beta0"], T["seed"], ncomp=args.ncomp)
         t1 = time.perf_counter()
         oc.step()
         dto = time.perf_counter() - t1
@@ -230,11 +232,14 @@ def bench_tensor(args):
         extra["cpu_baseline"] = {"value": 1.0 / dto, "unit": "tensor sweeps/s", "cores": threads,
                                  "kind": "oracle",
                                  "sample": f"one sweep of the same chain (set-up untimed), {dto:.1f} s"}
-    _line(f"tensor-product sweeps/s, d={T['d']} x n={n} (FP64)", args.steps / dt, "sweeps/s",
+    comp = "" if args.ncomp == 1 else f", {args.ncomp} additive components"
+    model = ("y = beta prod_h f_h(x_h) + noise" if args.ncomp == 1 else
+             "y = sum_c beta_c prod_h f_ch(x_h) + noise")
+    _line(f"tensor-product sweeps/s, d={T['d']} x n={n}{comp} (FP64)", args.steps / dt, "sweeps/s",
           args, dt, "f64",
-          {"workload": f"tensor: y = beta prod_h f_h(x_h) + noise, d={T['d']}, n={n}, x ~ U[0,1]^d, "
+          {"workload": f"tensor: {model}, d={T['d']}, n={n}, x ~ U[0,1]^d, "
                        "s(x)=sin(4x)sqrt(4x) per factor, Algorithm 1.h per factor, leaf 128, "
-                       "tol 1e-10", "d": T["d"], "n": n}, **extra)
+                       "tol 1e-10", "d": T["d"], "n": n, "ncomp": args.ncomp}, **extra)
 
 
 def bench_predict(args):

@@ -355,11 +355,18 @@ fg_status gibbs_predict_stats(fg_chain c, int32_t* cached_grid_points, int64_t* 
  * Start: f_h = 1, beta = beta0, tau = tau0, every grid index at grid_center.
  * Random numbers: factor h uses the 1-D tags plus 16 (h+1) (a, b, proposal,
  * acceptance); tau uses tag 3; beta the normal of tag 7.
+ *
+ * Additive tensor products (Sections 4.2 and 5.2), ncomp = C > 1 components:
+ * y_i = sum_c beta_c prod_h f_{c,h}(x[h,i]) + e_i.  Factor m = c d + h (C d <= 8).  For
+ * c = 0..C-1: component c's factors are drawn as above from the partial residual
+ * r_c = y - sum_{c' != c} beta_c' G_c' in place of y, then beta_c | - from r_c; then tau
+ * from the full residual; then every factor's length-scale.  beta_c's normal uses tag 7
+ * for c = 0 and 7 + 16 (9 + c) otherwise.  With C = 1 this is the sweep above.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t kind;          /* FG_KERNEL_SE / FG_KERNEL_EXP */
-  int32_t d;             /* number of factors, 1..8 */
-  double ell0[8];        /* grid centre length-scale per factor */
+  int32_t d;             /* number of input dimensions, 1..8 */
+  double ell0[8];        /* grid centre length-scale per factor m = c d + h */
   double nugget;         /* added to every K_h's diagonal */
   int32_t leaf;          /* maximum leaf size */
   double tol;            /* max-norm tolerance on each K_h */
@@ -370,6 +377,7 @@ typedef struct {
   int32_t grid_center;   /* starting index */
   uint64_t seed;
   uint64_t stream_id;
+  int32_t ncomp;         /* additive components C, 1..4 (0 is read as 1), C d <= 8 */
 } fg_tp_cfg;
 
 typedef struct {
@@ -386,6 +394,9 @@ typedef struct {
   double q[8];               /* f_h' K~_h^-1 f_h at the current length-scales */
   double mh_log_ratio[8];
   int32_t status;
+  int32_t ncomp;
+  double betas[4];           /* beta_c per component (betas[0] == beta) */
+  double beta_means[4], beta_sds[4];
 } fg_tp_snapshot;
 
 /* x: device d x n (row h = dimension h, observation order, any order of values);
@@ -395,7 +406,8 @@ fg_status tp_chain_create(const fg_tp_cfg* cfg, const double* x, const double* y
                           fg_stream stream, fg_tp_chain* out);
 /* Runs `iters` sweeps; synchronises once per sweep. */
 fg_status tp_step(fg_tp_chain c, int32_t iters, fg_stream stream);
-/* Host snapshot; F_out (device d x n, observation order, or NULL) receives f_h(x[h,i]). */
+/* Host snapshot; F_out (device (C d) x n, observation order, or NULL) receives
+ * f_m(x[m mod d, i]) for every factor m.  The per-factor arrays hold C d entries. */
 fg_status tp_chain_state(fg_tp_chain c, fg_tp_snapshot* host_out, double* F_out,
                          fg_stream stream);
 

@@ -217,19 +217,26 @@ def draw_f_hetero(K: Hodlr, WK: Factor, WP: Factor, D, y, seed, iteration, strea
 
 class TensorChain:
     """Tensor-product surface chain (tp_chain_create / tp_step / tp_chain_state).
-    x: (d, n) float64 device tensor in observation order; y: n."""
+    x: (d, n) float64 device tensor in observation order; y: n.  ncomp > 1: a sum of
+    that many tensor products; ell0 then holds d values (shared by the components) or
+    ncomp * d (factor m = c d + h)."""
 
     def __init__(self, x, y, ell0, tau0=100.0, beta0=1.0, nugget=1e-6, leaf=128, tol=1e-10,
                  seed=0, stream_id=0, kind=KERNEL_SE, a1=1.0, b1=1.0, s_beta=10.0,
-                 grid_size=100, grid_center=50):
+                 grid_size=100, grid_center=50, ncomp=1):
         torch = _torch()
         self.d, self.n = int(x.shape[0]), int(x.shape[1])
-        if len(ell0) != self.d:
-            raise ValueError("one ell0 per factor")
+        self.ncomp = int(ncomp)
+        self.nf = self.d * self.ncomp
+        ell0 = [float(v) for v in ell0]
+        if len(ell0) == self.d:
+            ell0 = ell0 * self.ncomp
+        if len(ell0) != self.nf or self.nf > 8:
+            raise ValueError("one ell0 per dimension or per factor, at most 8 factors")
         x = x.contiguous()
-        e = (C.c_double * 8)(*([float(v) for v in ell0] + [0.0] * (8 - self.d)))
+        e = (C.c_double * 8)(*(ell0 + [0.0] * (8 - self.nf)))
         cfg = TpCfg(kind, self.d, e, nugget, leaf, tol, tau0, beta0, a1, b1, s_beta, grid_size,
-                    grid_center, seed, stream_id)
+                    grid_center, seed, stream_id, self.ncomp)
         c = C.c_void_p()
         check(lib().tp_chain_create(C.byref(cfg), _dev(x.reshape(-1)), _dev(y, self.n), self.n,
                                     _stream(), C.byref(c)))
@@ -243,10 +250,10 @@ class TensorChain:
         snap = TpSnapshot()
         F = None
         if with_factors:
-            F = self._torch.empty((self.d, self.n), dtype=self._torch.float64, device="cuda")
+            F = self._torch.empty((self.nf, self.n), dtype=self._torch.float64, device="cuda")
         check(lib().tp_chain_state(self._c, C.byref(snap), _dev(F.reshape(-1)) if F is not None
                                    else None, _stream()))
-        out = snap.as_dict(self.d)
+        out = snap.as_dict(self.nf)
         if F is not None:
             out["F"] = F
         return out

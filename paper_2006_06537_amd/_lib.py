@@ -70,7 +70,8 @@ class TpCfg(C.Structure):
                 ("nugget", C.c_double), ("leaf", C.c_int32), ("tol", C.c_double),
                 ("tau0", C.c_double), ("beta0", C.c_double), ("a1", C.c_double),
                 ("b1", C.c_double), ("s_beta", C.c_double), ("grid_size", C.c_int32),
-                ("grid_center", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64)]
+                ("grid_center", C.c_int32), ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("ncomp", C.c_int32)]
 
 
 class TpSnapshot(C.Structure):
@@ -79,13 +80,18 @@ class TpSnapshot(C.Structure):
                 ("k", C.c_int32 * 8), ("last_proposal", C.c_int32 * 8),
                 ("last_accept", C.c_int32 * 8), ("accepts", C.c_int32 * 8),
                 ("ell", C.c_double * 8), ("logdet", C.c_double * 8), ("q", C.c_double * 8),
-                ("mh_log_ratio", C.c_double * 8), ("status", C.c_int32)]
+                ("mh_log_ratio", C.c_double * 8), ("status", C.c_int32), ("ncomp", C.c_int32),
+                ("betas", C.c_double * 4), ("beta_means", C.c_double * 4),
+                ("beta_sds", C.c_double * 4)]
 
     def as_dict(self, d):
         out = {}
         for f, _ in self._fields_:
             v = getattr(self, f)
-            out[f] = list(v)[:d] if hasattr(v, "__len__") else v
+            if f in ("betas", "beta_means", "beta_sds"):
+                out[f] = list(v)[:max(self.ncomp, 1)]
+            else:
+                out[f] = list(v)[:d] if hasattr(v, "__len__") else v
         return out
 
 

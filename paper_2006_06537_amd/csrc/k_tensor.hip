@@ -17,12 +17,13 @@ constexpr double G_FLOOR = 1e-150;
 // D, 1/D and y/g of factor h, in the sorted order of dimension h
 __global__ void k_tp_prepare(int n, int d, int h, const int* __restrict__ perm,
                              const double* __restrict__ F, const double* __restrict__ y,
-                             const TpState* __restrict__ st, double* __restrict__ D,
-                             double* __restrict__ Dinv, double* __restrict__ yt) {
+                             const TpState* __restrict__ st, const double* __restrict__ beta_p,
+                             double* __restrict__ D, double* __restrict__ Dinv,
+                             double* __restrict__ yt) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int i = perm[j];
-  double g = st->beta;
+  double g = *beta_p;
   for (int k = 0; k < d; ++k)
     if (k != h) g *= F[(size_t)k * n + i];
   if (fabs(g) < G_FLOOR) g = (g < 0.0) ? -G_FLOOR : G_FLOOR;
@@ -49,6 +50,27 @@ __global__ void k_hetero_finish(int n, const double* __restrict__ R, const doubl
   if (perm) Fh[perm[j]] = v;
 }
 
+// partial residual of component c and the fitted sum (observation order)
+__global__ void k_tp_partial(int n, int C, int c, const double* __restrict__ y,
+                             const double* __restrict__ G, const TpState* __restrict__ st,
+                             double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = y[i];
+  for (int cc = 0; cc < C; ++cc)
+    if (cc != c) v -= st->beta[cc] * G[(size_t)cc * n + i];
+  r[i] = v;
+}
+
+__global__ void k_tp_fit(int n, int C, const double* __restrict__ G,
+                         const TpState* __restrict__ st, double* __restrict__ fit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int cc = 0; cc < C; ++cc) v += st->beta[cc] * G[(size_t)cc * n + i];
+  fit[i] = v;
+}
+
 // G_i = prod_h f_h(x[h, i])  (observation order)
 __global__ void k_tp_product(int n, int d, const double* __restrict__ F, double* __restrict__ G) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,19 +80,19 @@ __global__ void k_tp_product(int n, int d, const double* __restrict__ F, double*
   G[i] = g;
 }
 
-// beta | - ~ N(tau G'y / prec, 1 / prec), prec = tau G'G + s_beta^-2; the normal is
-// z[0] of the normals stream of tag 7 (Box-Muller cosine branch of block 0)
-__global__ void k_tp_beta_step(TpState* st, double s_beta, uint64_t seed, uint64_t iter,
+// beta_c | - ~ N(tau G_c'r_c / prec, 1 / prec), prec = tau G_c'G_c + s_beta^-2; the normal
+// is z[0] of the normals stream of beta_c's tag (Box-Muller cosine branch of block 0)
+__global__ void k_tp_beta_step(TpState* st, int c, double s_beta, uint64_t seed, uint64_t iter,
                                uint64_t strm) {
   const double prec = st->tau * st->GG + 1.0 / (s_beta * s_beta);
   const double mean = st->tau * st->Gy / prec;
   const double sd = 1.0 / sqrt(prec);
   uint64_t w[4];
-  philox4x64_10(0, TP_TAG_BETA, iter, strm, seed, 0, w);
+  philox4x64_10(0, tp_beta_tag(c), iter, strm, seed, 0, w);
   const double z = sqrt(-2.0 * log(to_unit(w[0]))) * cos(2.0 * M_PI * to_unit(w[1]));
-  st->beta_mean = mean;
-  st->beta_sd = sd;
-  st->beta = mean + sd * z;
+  st->beta_mean[c] = mean;
+  st->beta_sd[c] = sd;
+  st->beta[c] = mean + sd * z;
 }
 
 __global__ void k_tp_tau_step(TpState* st, int n, double a1, double b1, uint64_t seed,
@@ -103,8 +125,16 @@ __global__ void k_tp_mh_step(TpState* st, int h, int kprop, int ongrid, uint64_t
 static inline unsigned nblk(int n) { return (unsigned)((n + 255) / 256); }
 
 void launch_tp_prepare(int n, int d, int h, const int* perm, const double* F, const double* y,
-                       const TpState* st, double* D, double* Dinv, double* yt, hipStream_t s) {
-  if (n > 0) k_tp_prepare<<<nblk(n), 256, 0, s>>>(n, d, h, perm, F, y, st, D, Dinv, yt);
+                       const TpState* st, const double* beta_p, double* D, double* Dinv,
+                       double* yt, hipStream_t s) {
+  if (n > 0) k_tp_prepare<<<nblk(n), 256, 0, s>>>(n, d, h, perm, F, y, st, beta_p, D, Dinv, yt);
+}
+void launch_tp_partial(int n, int C, int c, const double* y, const double* G, const TpState* st,
+                       double* r, hipStream_t s) {
+  if (n > 0) k_tp_partial<<<nblk(n), 256, 0, s>>>(n, C, c, y, G, st, r);
+}
+void launch_tp_fit(int n, int C, const double* G, const TpState* st, double* fit, hipStream_t s) {
+  if (n > 0) k_tp_fit<<<nblk(n), 256, 0, s>>>(n, C, G, st, fit);
 }
 void launch_scale_sqrt(int n, const double* D, double* v, hipStream_t s) {
   if (n > 0) k_scale_sqrt<<<nblk(n), 256, 0, s>>>(n, D, v);
@@ -116,9 +146,9 @@ void launch_hetero_finish(int n, const double* R, const double* Zs, const double
 void launch_tp_product(int n, int d, const double* F, double* G, hipStream_t s) {
   if (n > 0) k_tp_product<<<nblk(n), 256, 0, s>>>(n, d, F, G);
 }
-void launch_tp_beta_step(TpState* st, double s_beta, uint64_t seed, uint64_t iter, uint64_t strm,
-                         hipStream_t s) {
-  k_tp_beta_step<<<1, 1, 0, s>>>(st, s_beta, seed, iter, strm);
+void launch_tp_beta_step(TpState* st, int c, double s_beta, uint64_t seed, uint64_t iter,
+                         uint64_t strm, hipStream_t s) {
+  k_tp_beta_step<<<1, 1, 0, s>>>(st, c, s_beta, seed, iter, strm);
 }
 void launch_tp_tau_step(TpState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
                         uint64_t strm, hipStream_t s) {

@@ -82,7 +82,7 @@ def _tw(o, h, k):
     if not 0 <= k < len(o.grids[h]):
         return 1e-9
     ell = o.grids[h][k]
-    xs = o.xs[h]
+    xs = o.xs[h % o.d]  # factor h = c d + dimension
     kap = max(np.linalg.cond(kernels.K1_dense(kernels.SE, ell, 1e-6, xs[lo:hi]))
               for lo, hi in o.H[h].tree.leaves())
     return max(1e-9, 2.0 * 2.0 ** -53 * kap)
@@ -171,3 +171,46 @@ def test_tensor_chain_deterministic():
         runs.append(c.state(with_factors=True))
     assert torch.equal(runs[0]["F"], runs[1]["F"])
     assert runs[0]["tau"] == runs[1]["tau"] and runs[0]["beta"] == runs[1]["beta"]
+
+
+def test_additive_tensor_chain_matches_oracle():
+    """Two components over d = 2 (factor m = c d + h) on n = 2500 observations.  Every
+    component's scalars carry the bars above with the factors' bars summed over all
+    factors (component c's data are the partial residual, which holds the others);
+    sse and tau use |fit| / |y - fit| with fit = sum_c beta_c G_c."""
+    d, C, n = 2, 2, 2500
+    x, y = tensor_surface(d, n, seed=8)
+    dev = torch.device("cuda:0")
+    ell0 = (0.08, 0.15)
+    g = fg().TensorChain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0,
+                         tau0=50.0, beta0=0.7, nugget=1e-6, leaf=64, tol=1e-10, seed=8, ncomp=C)
+    o = tensor.TensorChain(x, y, kernels.SE, ell0, 1e-6, 64, 1e-10, 50.0, 0.7, 8, ncomp=C)
+    seen = [set() for _ in range(o.nf)]
+    for it in range(5):
+        g.step(1)
+        s = g.state(with_factors=(it == 4))
+        kb = list(o.k)
+        for m in range(o.nf):
+            seen[m].add(kb[m])
+        r = o.step()
+        assert s["status"] == 0 and s["ncomp"] == C
+        assert s["k"] == r["k"] and s["last_proposal"] == r["proposal"], it
+        assert s["last_accept"] == [int(a) for a in r["accept"]], it
+        tws = sum(_tw(o, m, kb[m]) for m in range(o.nf))
+        fit = float(np.linalg.norm(o.fitted()))
+        res = np.sqrt(r["sse"])
+        for cc in range(C):
+            for key, ref in [("betas", r["betas"][cc]), ("beta_means", r["beta_means"][cc]),
+                             ("beta_sds", r["beta_sds"][cc])]:
+                assert abs(s[key][cc] - ref) <= max(1e-9, 2 * tws) * abs(ref), (it, key, cc)
+        for key in ["sse", "tau"]:
+            bar = max(1e-9, 2 * tws * fit / res)
+            assert abs(s[key] - r[key]) <= bar * abs(r[key]), (it, key, s[key], r[key])
+        for m in range(o.nf):
+            tq = _tw(o, m, r["k"][m])
+            q_now = r["q_prop"][m] if r["accept"][m] else r["q"][m]
+            assert abs(s["q"][m] - q_now) <= 2.5 * tq * abs(q_now), (it, m)
+    F = s["F"].cpu().numpy()
+    for m in range(o.nf):
+        bar = max(_tw(o, m, k) for k in seen[m])
+        assert rel(F[m], o.F[m]) <= bar, (m, rel(F[m], o.F[m]), bar)
