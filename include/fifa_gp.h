@@ -52,11 +52,16 @@ typedef struct fg_factor_s* fg_factor;   /* W with W W' = alpha K~_1 + beta I + 
 typedef struct fg_chain_s* fg_chain;     /* one Gibbs chain and its cached factors */
 typedef struct fg_tp_chain_s* fg_tp_chain; /* one tensor-product chain (Section 4.2) */
 
+/* Kernels k_1 (Section 2.1; unit amplitude, d = |x - x'|): squared exponential
+ * exp(-d^2 / (2 ell^2)); exponential exp(-d / ell); Matern-3/2 (1 + u) exp(-u) with
+ * u = sqrt(3) d / ell; Matern-5/2 (1 + u + u^2/3) exp(-u) with u = sqrt(5) d / ell. */
 #define FG_KERNEL_SE 0
 #define FG_KERNEL_EXP 1
+#define FG_KERNEL_MATERN32 2
+#define FG_KERNEL_MATERN52 3
 
 typedef struct {
-  int32_t kind;          /* FG_KERNEL_SE or FG_KERNEL_EXP                 */
+  int32_t kind;          /* FG_KERNEL_SE, _EXP, _MATERN32 or _MATERN52    */
   double lengthscale;    /* ell > 0                                        */
   double nugget;         /* >= 0, added to the diagonal of K_1             */
 } fg_kernel;
@@ -205,7 +210,7 @@ fg_status gp_draw_f_hetero(fg_hodlr K, fg_factor WK, fg_factor WP, const double*
  * (proposal), 6 (acceptance) of (seed, iteration, stream_id).
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int32_t kind;          /* FG_KERNEL_SE / FG_KERNEL_EXP */
+  int32_t kind;          /* FG_KERNEL_SE / _EXP / _MATERN32 / _MATERN52 */
   double ell0;           /* grid centre length-scale */
   double nugget;         /* added to K_1's diagonal */
   int32_t leaf;          /* maximum leaf size */
@@ -364,7 +369,7 @@ fg_status gibbs_predict_stats(fg_chain c, int32_t* cached_grid_points, int64_t* 
  * for c = 0 and 7 + 16 (9 + c) otherwise.  With C = 1 this is the sweep above.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int32_t kind;          /* FG_KERNEL_SE / FG_KERNEL_EXP */
+  int32_t kind;          /* FG_KERNEL_SE / _EXP / _MATERN32 / _MATERN52 */
   int32_t d;             /* number of input dimensions, 1..8 */
   double ell0[8];        /* grid centre length-scale per factor m = c d + h */
   double nugget;         /* added to every K_h's diagonal */

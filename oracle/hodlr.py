@@ -88,16 +88,37 @@ def window_radius(kind, ell, tol):
     """Distance beyond which k_1 < tol/3."""
     if kind == kernels.SE:
         return ell * math.sqrt(2.0 * math.log(3.0 / tol))
-    return ell * math.log(3.0 / tol)
+    if kind == kernels.EXP:
+        return ell * math.log(3.0 / tol)
+    # Matern: P(u) exp(-u) = tol/3 with P increasing, solved by u = log(3 P(u) / tol) from
+    # below (the iterates increase to the root)
+    c = math.sqrt(3.0) if kind == kernels.MATERN32 else math.sqrt(5.0)
+    poly = (lambda u: 1.0 + u) if kind == kernels.MATERN32 else (lambda u: 1.0 + u + u * u / 3.0)
+    u = math.log(3.0 / tol)
+    for _ in range(200):
+        u_new = math.log(3.0 * poly(u) / tol)
+        if abs(u_new - u) <= 1e-14 * u_new:
+            u = u_new
+            break
+        u = u_new
+    return ell * u / c
 
 
 def interp_bound(kind, p, h, ell):
     """Bound on the max error of p-node first-kind Chebyshev interpolation in one
     variable over an interval of half-width h:  h^p / (2^(p-1) p!) * max|d^p k_1|.
     SE: |d^p exp(-t^2/(2 ell^2))| <= KAPPA_H ell^-p sqrt(p!)  (Hermite functions).
-    EXP on separated intervals: |d^p exp(-t/ell)| <= ell^-p."""
+    EXP on separated intervals: |d^p exp(-t/ell)| <= ell^-p.
+    Matern on separated intervals (t >= 0), with a = sqrt(3)/ell, resp. sqrt(5)/ell and
+    u = a t:  d^p/du^p [(1+u) e^-u] = (-1)^p e^-u (1 + u - p), bounded by max(p - 1, 1);
+    d^p/du^p [(1+u+u^2/3) e^-u] = (-1)^p e^-u (1 + u + u^2/3 - p (1 + 2u/3) + p(p-1)/3),
+    bounded by p^2/3 + p + 1; so |d^p k_1| <= a^p times those."""
     if h <= 0.0:
         return 0.0
+    if kind in (kernels.MATERN32, kernels.MATERN52):
+        a = (math.sqrt(3.0) if kind == kernels.MATERN32 else math.sqrt(5.0)) / ell
+        m = max(p - 1.0, 1.0) if kind == kernels.MATERN32 else p * p / 3.0 + p + 1.0
+        return math.exp(math.log(2.0 * m) + p * math.log(h * a / 2.0) - math.lgamma(p + 1.0))
     r = math.log(h / (2.0 * ell))
     if kind == kernels.SE:
         return math.exp(math.log(2.0 * KAPPA_H) + p * r - 0.5 * math.lgamma(p + 1.0))

@@ -9,6 +9,10 @@ Exponential (Matern-1/2), k_1(x,x') = exp(-|x-x'|/ell): Section 2.1 admits Mater
 kernels.  It is kept as a test kernel: on sorted inputs its off-diagonal blocks have
 rank one exactly, and an O(n) state-space recursion (kalman.py) gives its log
 determinant and solves exactly at any n.
+
+Matern-3/2 and Matern-5/2 (Section 2.1 names the Matern family), in the usual
+length-scale form with u = sqrt(3) |x-x'| / ell, resp. u = sqrt(5) |x-x'| / ell:
+    k_1 = (1 + u) exp(-u),   k_1 = (1 + u + u^2 / 3) exp(-u).
 """
 from __future__ import annotations
 
@@ -16,6 +20,8 @@ import numpy as np
 
 SE = 0
 EXP = 1
+MATERN32 = 2
+MATERN52 = 3
 
 
 def k1(kind: int, ell: float, a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -25,6 +31,12 @@ def k1(kind: int, ell: float, a: np.ndarray, b: np.ndarray) -> np.ndarray:
         return np.exp(-(d * d) / (2.0 * ell * ell))
     if kind == EXP:
         return np.exp(-np.abs(d) / ell)
+    if kind == MATERN32:
+        u = np.sqrt(3.0) * np.abs(d) / ell
+        return (1.0 + u) * np.exp(-u)
+    if kind == MATERN52:
+        u = np.sqrt(5.0) * np.abs(d) / ell
+        return (1.0 + u + u * u / 3.0) * np.exp(-u)
     raise ValueError(f"unknown kernel kind {kind}")
 
 

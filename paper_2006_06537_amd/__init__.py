@@ -10,12 +10,12 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, ChainCfg, ChainSnapshot, FgError, Job,
+from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, KERNEL_MATERN32, KERNEL_MATERN52, ChainCfg, ChainSnapshot, FgError, Job,
                    Kernel, Result, ServeCfg, ServeStats, TpCfg, TpSnapshot, check, lib)
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
            "draw_f_hetero", "step_batch", "solve_refined", "Server", "footprint_bytes", "FP64", "MIXED", "KERNEL_SE",
-           "KERNEL_EXP", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE", "KID_WHITEN",
+           "KERNEL_EXP", "KERNEL_MATERN32", "KERNEL_MATERN52", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE", "KID_WHITEN",
            "KID_PREDICT"]
 
 KID_LEAF, KID_REDUCE, KID_UPDATE, KID_WHITEN, KID_PREDICT = 1, 2, 3, 4, 5

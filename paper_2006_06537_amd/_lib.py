@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfifagp.so")
 
 FP64, MIXED = 0, 1
 FG_OK, FG_EINVAL, FG_ENOMEM, FG_ENOTSPD, FG_ETOL, FG_ENOTCONV, FG_EDEVICE = 0, -1, -2, -3, -4, -5, -6
-KERNEL_SE, KERNEL_EXP = 0, 1
+KERNEL_SE, KERNEL_EXP, KERNEL_MATERN32, KERNEL_MATERN52 = 0, 1, 2, 3
 STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", -4: "FG_ETOL",
                 -5: "FG_ENOTCONV", -6: "FG_EDEVICE"}
 

@@ -30,12 +30,18 @@ constexpr int ST_NOTSPD = 1;
 constexpr int ST_NOTCONV = 2;
 constexpr int ST_TOL = 4;
 
-// k_1(a, b) without the nugget: squared exponential exp(-(a-b)^2 / (2 ell^2)) or
-// exponential exp(-|a-b| / ell) (Section 2.1 with rho = 1 / (2 ell^2)).
+// k_1(a, b) without the nugget (Section 2.1; rho = 1 / (2 ell^2) for the squared
+// exponential): squared exponential, exponential, Matern-3/2, Matern-5/2.
 __device__ __forceinline__ double k1_value(int kind, double ell, double a, double b) {
   const double d = a - b;
   if (kind == FG_KERNEL_SE) return exp(-(d * d) / (2.0 * ell * ell));
-  return exp(-fabs(d) / ell);
+  if (kind == FG_KERNEL_EXP) return exp(-fabs(d) / ell);
+  if (kind == FG_KERNEL_MATERN32) {
+    const double u = 1.7320508075688772 * fabs(d) / ell;  // sqrt(3)
+    return (1.0 + u) * exp(-u);
+  }
+  const double u = 2.23606797749979 * fabs(d) / ell;      // sqrt(5), Matern-5/2
+  return (1.0 + u + u * u / 3.0) * exp(-u);
 }
 
 // Panels are stored in 16-row tiles: rows of a tile are contiguous (128 bytes per

@@ -23,8 +23,19 @@
 
 namespace fg {
 
+// Error of p-node Chebyshev interpolation over half-width h: h^p / (2^(p-1) p!) times a
+// bound on |d^p k_1| over the window.  Squared exponential: KAPPA_H ell^-p sqrt(p!)
+// (Hermite functions); exponential on separated intervals: ell^-p; Matern on separated
+// intervals (u = a t >= 0, a = sqrt(3)/ell or sqrt(5)/ell): the p-th u-derivative of
+// (1+u)e^-u is e^-u (1 + u - p) up to sign, at most max(p-1, 1); that of (1+u+u^2/3)e^-u
+// is e^-u (1 + u + u^2/3 - p(1 + 2u/3) + p(p-1)/3), at most p^2/3 + p + 1.
 static double interp_bound(int kind, int p, double h, double ell) {
   if (h <= 0.0) return 0.0;
+  if (kind == FG_KERNEL_MATERN32 || kind == FG_KERNEL_MATERN52) {
+    const double a = (kind == FG_KERNEL_MATERN32 ? std::sqrt(3.0) : std::sqrt(5.0)) / ell;
+    const double m = kind == FG_KERNEL_MATERN32 ? std::max(p - 1.0, 1.0) : p * p / 3.0 + p + 1.0;
+    return std::exp(std::log(2.0 * m) + p * std::log(h * a / 2.0) - std::lgamma(p + 1.0));
+  }
   const double r = std::log(h / (2.0 * ell));
   if (kind == FG_KERNEL_SE)
     return std::exp(std::log(2.0 * KAPPA_H) + p * r - 0.5 * std::lgamma(p + 1.0));
@@ -32,6 +43,23 @@ static double interp_bound(int kind, int p, double h, double ell) {
 }
 
 static double lebesgue_bound(int p) { return 2.0 / M_PI * std::log(p + 1.0) + 1.0; }
+
+// distance beyond which k_1 < tol/3; for Matern, P(u) e^-u = tol/3 with P increasing is
+// solved by the increasing iteration u <- log(3 P(u) / tol)
+static double window_radius(int kind, double ell, double tol) {
+  if (kind == FG_KERNEL_SE) return ell * std::sqrt(2.0 * std::log(3.0 / tol));
+  if (kind == FG_KERNEL_EXP) return ell * std::log(3.0 / tol);
+  const bool m32 = kind == FG_KERNEL_MATERN32;
+  double u = std::log(3.0 / tol);
+  for (int it = 0; it < 200; ++it) {
+    const double poly = m32 ? 1.0 + u : 1.0 + u + u * u / 3.0;
+    const double un = std::log(3.0 * poly / tol);
+    const bool done = std::fabs(un - u) <= 1e-14 * un;
+    u = un;
+    if (done) break;
+  }
+  return ell * u / (m32 ? std::sqrt(3.0) : std::sqrt(5.0));
+}
 
 static int choose_p(int kind, double h, double ell, double target, double factor) {
   for (int p = 1; p <= PMAX; ++p)
@@ -51,7 +79,7 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
     err = "tol and lengthscale must be > 0, nugget >= 0";
     return FG_EINVAL;
   }
-  if (kind != FG_KERNEL_SE && kind != FG_KERNEL_EXP) { err = "unknown kernel"; return FG_EINVAL; }
+  if (kind < FG_KERNEL_SE || kind > FG_KERNEL_MATERN52) { err = "unknown kernel"; return FG_EINVAL; }
   for (int i = 1; i < n; ++i)
     if (!(xh[i] >= xh[i - 1])) { err = "x must be sorted ascending"; return FG_EINVAL; }
   P = HostPlan();
@@ -72,8 +100,7 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
   P.leaf_lo.resize(P.nleaf + 1);
   for (int j = 0; j < P.nleaf; ++j) P.leaf_lo[j] = lo[P.nint + j];
   P.leaf_lo[P.nleaf] = n;
-  const double R = (kind == FG_KERNEL_SE) ? ell * std::sqrt(2.0 * std::log(3.0 / tol))
-                                          : ell * std::log(3.0 / tol);
+  const double R = window_radius(kind, ell, tol);
   P.nodes.resize(P.nint);
   P.kcap.assign(L, 0);
   P.coff.assign(L + 1, 0);

@@ -55,3 +55,26 @@ def test_chain_deterministic():
     for key in ["tau", "sigf2", "k", "loglik", "accepts"]:
         assert sa[key] == sb[key]
     assert torch.equal(sa["f"], sb["f"])
+
+
+@pytest.mark.parametrize("kind", [kernels.MATERN32, kernels.MATERN52, kernels.EXP])
+def test_chain_other_kernels_match_oracle(kind):
+    """The sweep with the exponential and Matern kernels (Section 2.1 names the Matern
+    family) against the oracle's chain, at the plain chain's 1e-9."""
+    c = SMALL_1D
+    x, y = small_1d(1200, 9)
+    dev = torch.device("cuda:0")
+    g = fg().Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0=0.05,
+                   tau0=c["tau0"], sigf2_0=c["sigf2_0"], nugget=c["nugget"], leaf=c["leaf"],
+                   tol=1e-10, seed=9, kind=kind)
+    o = sampler.Chain(x, y, kind, 0.05, c["nugget"], c["leaf"], 1e-10, c["tau0"], c["sigf2_0"], 9)
+    for it in range(6):
+        g.step(1)
+        s = g.state(with_vectors=(it == 5))
+        r = o.step()
+        assert s["status"] == 0
+        assert (s["k"], s["last_proposal"], s["last_accept"]) == (r["k"], r["proposal"], int(r["accept"]))
+        for key in ["tau", "sigf2", "loglik"]:
+            assert abs(s[key] - r[key]) <= 1e-9 * abs(r[key]), (it, key, s[key], r[key])
+    f = s["f"].cpu().numpy()
+    assert np.linalg.norm(f - o.f) <= 1e-9 * np.linalg.norm(o.f)

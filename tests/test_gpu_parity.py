@@ -46,6 +46,8 @@ CASES = [
     (1200, 64, 0.05, 1e-10, kernels.EXP, 4),  # exponential kernel: rank-one blocks
     (50, 64, 0.2, 1e-10, kernels.SE, 5),      # one leaf: W = Cholesky factor
     (900, 16, 1e-4, 1e-10, kernels.SE, 6),    # empty windows: rank-zero nodes
+    (1500, 64, 0.05, 1e-10, kernels.MATERN32, 7),
+    (2000, 64, 0.08, 1e-10, kernels.MATERN52, 8),
 ]
 IDS = [f"n{c[0]}-B{c[1]}-ell{c[2]}-k{c[4]}" for c in CASES]
 

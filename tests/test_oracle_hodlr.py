@@ -66,7 +66,8 @@ def test_si_cost_vs_dimension_ranks():
 @pytest.mark.parametrize("n,leaf,ell,tol,kind", [
     (1000, 64, 0.1, 1e-12, kernels.SE), (3001, 64, 0.03, 1e-10, kernels.SE),
     (2048, 128, 0.3, 1e-8, kernels.SE), (1500, 32, 0.01, 1e-10, kernels.SE),
-    (1200, 64, 0.05, 1e-10, kernels.EXP)])
+    (1200, 64, 0.05, 1e-10, kernels.EXP), (1500, 64, 0.05, 1e-10, kernels.MATERN32),
+    (2000, 64, 0.08, 1e-10, kernels.MATERN52), (1000, 32, 0.02, 1e-12, kernels.MATERN52)])
 def test_maxnorm_bound_and_spectral_rank(n, leaf, ell, tol, kind):
     """|K_1 - K~_1|_max <= tol by construction (Section 3.2); ranks equal those of the
     exact block's truncated SVD at tol/3 within one (the interpolant only perturbs the
@@ -190,3 +191,21 @@ def test_kl_decreases_with_tolerance():
         mu_q, S_q = dense.posterior_f(Kt, tau, y)
         kls.append(dense.kl_gauss(mu_p, S_p, mu_q, S_q))
     assert kls[0] > 10 * kls[1] > 100 * kls[2] > 0.0
+
+
+@pytest.mark.parametrize("kind", [kernels.MATERN32, kernels.MATERN52])
+def test_matern_window_radius_and_interpolation_bound(kind):
+    """The window radius is where k_1 falls to tol/3, and the p-node Chebyshev
+    interpolant of k_1(., y) over a window separated from y meets interp_bound."""
+    for ell, tol in [(0.1, 1e-10), (0.02, 1e-12)]:
+        R = hodlr.window_radius(kind, ell, tol)
+        assert kernels.k1(kind, ell, [0.0], [R])[0, 0] == pytest.approx(tol / 3.0, rel=1e-9)
+    ell = 0.05
+    for a, b, y in [(0.0, 0.1, 0.1), (0.3, 0.35, 0.5), (0.0, 0.02, 0.021)]:
+        for p in [3, 6, 10, 16]:
+            nodes, wts = hodlr.cheb_nodes(p, a, b)
+            xs = np.linspace(a, b, 801)
+            L = hodlr.lagrange_matrix(xs, nodes, wts)
+            err = np.abs(L @ kernels.k1(kind, ell, nodes, [y])[:, 0]
+                         - kernels.k1(kind, ell, xs, [y])[:, 0]).max()
+            assert err <= hodlr.interp_bound(kind, p, 0.5 * (b - a), ell) * (1 + 1e-9) + 1e-15
