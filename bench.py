@@ -78,8 +78,9 @@ def parse():
 
 
 def counter_traffic(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed counter summary, if the
-    library sources are still the ones it was taken on (else None)."""
+    """HBM bytes per launch of `kernel_name` (all its template instances, weighted by
+    their launch counts) from the committed counter summary, if the library sources are
+    still the ones it was taken on (else None)."""
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_large_1d.md")
@@ -95,10 +96,13 @@ def counter_traffic(kernel_name):
         h.update(open(f, "rb").read())
     if h.hexdigest()[:16] != doc.get("source_hash"):
         return None
-    for key in (f"fg::{kernel_name}<double>", f"fg::{kernel_name}"):
-        if key in doc["kernels"]:
-            return doc["kernels"][key]["traffic_bytes"]
-    return None
+    # every instance of the kernel (templated variants included), weighted by launches
+    rows = [v for k, v in doc["kernels"].items()
+            if k == f"fg::{kernel_name}" or k.startswith(f"fg::{kernel_name}<")]
+    launches = sum(v["launches"] for v in rows)
+    if not launches:
+        return None
+    return sum(v["traffic_bytes"] * v["launches"] for v in rows) / launches
 
 
 def bench_copy(args):
