@@ -204,6 +204,8 @@ void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, i
 // out = scale * sum (a-b)^2 or sum a*b etc (deterministic two-stage)
 void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
                 hipStream_t s);
+// Sums the task partials of every node side with more than one task; a side with one
+// task is left to its consumer, which reads that task's partial in place.
 void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
                  int nsides, int esz, double* zfin, int zf_side, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,

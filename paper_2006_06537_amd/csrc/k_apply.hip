@@ -140,11 +140,11 @@ __global__ void __launch_bounds__(64) k_node_coef(
   for (int idx = threadIdx.x; idx < 2 * kn; idx += blockDim.x) {
     const int side = idx / kn, e = idx % kn;
     double s = 0.0;
-    if (zsum) {  // presummed per node side (k_zsum)
+    const int t0 = node_task_off[2 * h + side] - tbase;
+    const int t1 = node_task_off[2 * h + side + 1] - tbase;
+    if (zsum && t1 - t0 > 1) {  // presummed per node side (k_zsum)
       s = zsum[(size_t)(2 * jn + side) * zs_task + e];
     } else {
-      const int t0 = node_task_off[2 * h + side] - tbase;
-      const int t1 = node_task_off[2 * h + side + 1] - tbase;
       for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + e];
     }
     if (side) T[e / nrhs][e % nrhs] = s; else S[e / nrhs][e % nrhs] = s;

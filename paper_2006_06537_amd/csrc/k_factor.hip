@@ -474,7 +474,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
 
 // ---------------------------------------------------------------------------------
 // deterministic sum of task partials per node side: zfin[side][e] = sum_t zpart[t][e]
-// (4 task lanes per entry, combined in a fixed order)
+// (4 task lanes per entry, combined in a fixed order).  Sides with a single task are
+// skipped: their consumers read zpart[t0] in place.
 // ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zpart, int zs_task,
                                                    int tbase, const int* __restrict__ node_task_off,
@@ -484,6 +485,7 @@ __global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zp
   if (sd >= nsides) return;
   const int h = hbase + (sd >> 1), side = sd & 1;
   const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
+  if (t1 - t0 <= 1) return;
   const int e = blockIdx.y * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   __shared__ double red[4][64];
   double s = 0.0;
@@ -505,92 +507,213 @@ void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_ta
 }
 
 // ---------------------------------------------------------------------------------
-// symmetric Jacobi eigen-decomposition of an m x m LDS matrix (A <- diag, E <- vectors)
+// symmetric Jacobi eigen-decomposition of an m x m LDS matrix (A <- diag, E <- vectors),
+// for a work-group of one wave (64 lanes); lda must be even and at least m
+//
+// Cyclic Jacobi in the round-robin parallel order: a step rotates the disjoint index
+// pairs (p_t, q_t), t < me/2, at once, and me - 1 steps make a sweep (me = m rounded up
+// to even; an odd m is padded with a zero row and column, whose rotations are the
+// identity).  Lane b owns the 2 x 2 block (pair t) x (pair u), b = t np + u, of A and of
+// E.  It computes the rotations of both pairs itself from a_pp, a_qq and a_pq, so a step
+// is one pass of reads, one of writes and one barrier.  A is double-buffered (A, T, A,
+// ...), E is rotated in place (its blocks are disjoint).  Blocks t < u of A also write
+// their transpose (blocks t > u write nothing), so A stays exactly symmetric; a
+// diagonal block takes the classical update a_pp - t a_pq, a_qq + t a_pq, a_pq = 0.
+// Converged once the off-diagonal part is at most 4 m eps of the Frobenius norm
+// (checked before each sweep, at most 30 sweeps); returns false otherwise.
 // ---------------------------------------------------------------------------------
-__device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
-  __shared__ int perm[PMAX + 1];
-  __shared__ double cs[PMAX / 2 + 1], sn[PMAX / 2 + 1];
-  __shared__ double red[4][2];
-  __shared__ int done;
-  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x)
-    E[idx % m + (idx / m) * lda] = (idx % m == idx / m) ? 1.0 : 0.0;
+struct JRot {
+  double c, s, t;
+};
+
+__device__ __forceinline__ JRot jacobi_rot(double app, double aqq, double apq) {
+  JRot r{1.0, 0.0, 0.0};
+  if (apq != 0.0) {
+    const double th = (aqq - app) / (2.0 * apq);
+    const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+    r.c = 1.0 / sqrt(tt * tt + 1.0);
+    r.s = tt * r.c;
+    r.t = tt;
+  }
+  return r;
+}
+
+// index at position j of the round-robin schedule after `off` steps (positions 1..me-1
+// rotate, position 0 stays)
+__device__ __forceinline__ int rr_index(int j, int off, int me) {
+  if (j == 0) return 0;
+  int v = j - 1 + off;
+  if (v >= me - 1) v -= me - 1;
+  return 1 + v;
+}
+
+__device__ bool lds_sym_eig(double* A, double* E, double* T, int m, int lda) {
+  const int lane = threadIdx.x & 63;
+  const int me = m + (m & 1);
+  for (int c = 0; c < me; ++c)
+    for (int r = lane; r < me; r += 64) {
+      E[r + c * lda] = (r == c) ? 1.0 : 0.0;
+      if (r == m || c == m) A[r + c * lda] = 0.0;  // padding (odd m)
+    }
   __syncthreads();
   if (m < 2) return true;
-  const int me = m + (m & 1), np = me / 2;
+  const int np = me >> 1, nb = np * np;
+  const int t0 = lane / np, u0 = lane - t0 * np;
+  double* cur = A;
+  double* nxt = T;
   bool conv = false;
+  int roff = 0;
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const double v = A[idx % m + (idx / m) * lda];
-      tot += v * v;
-      if (idx % m != idx / m) off += v * v;
-    }
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) {
+        const double v = cur[r + c * lda];
+        tot += v * v;
+        if (r != c) off += v * v;
+      }
     off = wsum(off);
     tot = wsum(tot);
-    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][0] = off; red[threadIdx.x >> 6][1] = tot; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double o = 0.0, s = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { o += red[w][0]; s += red[w][1]; }
-      // converged once the off-diagonal part is at the rounding level of the matrix
-      const double lim = 4.0 * m * DBL_EPSILON;
-      done = (o <= lim * lim * s) ? 1 : 0;
+    const double lim = 4.0 * m * DBL_EPSILON;
+    if (__builtin_amdgcn_readfirstlane((int)(off <= lim * lim * tot))) {
+      conv = true;
+      break;
     }
-    __syncthreads();
-    if (done) { conv = true; break; }
+#pragma unroll 1
     for (int step = 0; step < me - 1; ++step) {
-      if (threadIdx.x < me) {
-        const int j = threadIdx.x;
-        perm[j] = (j == 0) ? 0 : 1 + ((j - 1 + step) % (me - 1));
-      }
-      __syncthreads();
-      if (threadIdx.x < np) {
-        int p = perm[threadIdx.x], q = perm[me - 1 - threadIdx.x];
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        double c = 1.0, s = 0.0;
-        if (q < m) {
-          const double apq = A[p + q * lda];
-          if (apq != 0.0) {
-            const double th = (A[q + q * lda] - A[p + p * lda]) / (2.0 * apq);
-            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
-            s = tt * c;
+      int t = t0, u = u0;
+#pragma unroll 1
+      for (int b = lane; b < nb; b += 64) {
+        int pt = rr_index(t, roff, me), qt = rr_index(me - 1 - t, roff, me);
+        int pu = rr_index(u, roff, me), qu = rr_index(me - 1 - u, roff, me);
+        if (pt > qt) { const int x = pt; pt = qt; qt = x; }
+        if (pu > qu) { const int x = pu; pu = qu; qu = x; }
+        const int cpt = __umul24(pt, lda), cqt = __umul24(qt, lda);
+        const int cpu = __umul24(pu, lda), cqu = __umul24(qu, lda);
+        const JRot ru = jacobi_rot(cur[pu + cpu], cur[qu + cqu], cur[pu + cqu]);
+        const JRot rt = jacobi_rot(cur[pt + cpt], cur[qt + cqt], cur[pt + cqt]);
+        // E <- E J on columns (pu, qu), rows pt and qt
+        const double e00 = E[pt + cpu], e01 = E[pt + cqu];
+        const double e10 = E[qt + cpu], e11 = E[qt + cqu];
+        E[pt + cpu] = ru.c * e00 - ru.s * e01;
+        E[pt + cqu] = ru.s * e00 + ru.c * e01;
+        E[qt + cpu] = ru.c * e10 - ru.s * e11;
+        E[qt + cqu] = ru.s * e10 + ru.c * e11;
+        if (t <= u) {
+          const double b00 = cur[pt + cpu], b01 = cur[pt + cqu];
+          const double b10 = cur[qt + cpu], b11 = cur[qt + cqu];
+          double x00, x01, x10, x11;
+          if (t == u) {
+            x00 = b00 - ru.t * b01;
+            x11 = b11 + ru.t * b01;
+            x01 = 0.0;
+            x10 = 0.0;
+          } else {
+            // rows (pair t), then columns (pair u)
+            const double y00 = rt.c * b00 - rt.s * b10, y10 = rt.s * b00 + rt.c * b10;
+            const double y01 = rt.c * b01 - rt.s * b11, y11 = rt.s * b01 + rt.c * b11;
+            x00 = ru.c * y00 - ru.s * y01;
+            x01 = ru.s * y00 + ru.c * y01;
+            x10 = ru.c * y10 - ru.s * y11;
+            x11 = ru.s * y10 + ru.c * y11;
           }
+          nxt[pt + cpu] = x00;
+          nxt[pu + cpt] = x00;
+          nxt[pt + cqu] = x01;
+          nxt[qu + cpt] = x01;
+          nxt[qt + cpu] = x10;
+          nxt[pu + cqt] = x10;
+          nxt[qt + cqu] = x11;
+          nxt[qu + cqt] = x11;
         }
-        cs[threadIdx.x] = c;
-        sn[threadIdx.x] = s;
+        u += 64;
+        while (u >= np) { u -= np; ++t; }
       }
       __syncthreads();
-      // rows p, q  (A <- J' A)
-      for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
-        const int pr = idx / m, col = idx % m;
-        int p = perm[pr], q = perm[me - 1 - pr];
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        if (q >= m) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[p + col * lda], aq = A[q + col * lda];
-        A[p + col * lda] = c * ap - s * aq;
-        A[q + col * lda] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns p, q  (A <- A J, E <- E J)
-      for (int idx = threadIdx.x; idx < np * m; idx += blockDim.x) {
-        const int pr = idx / m, row = idx % m;
-        int p = perm[pr], q = perm[me - 1 - pr];
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
-        if (q >= m) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[row + p * lda], aq = A[row + q * lda];
-        A[row + p * lda] = c * ap - s * aq;
-        A[row + q * lda] = s * ap + c * aq;
-        const double ep = E[row + p * lda], eq = E[row + q * lda];
-        E[row + p * lda] = c * ep - s * eq;
-        E[row + q * lda] = s * ep + c * eq;
-      }
-      __syncthreads();
+      double* x = cur;
+      cur = nxt;
+      nxt = x;
+      if (++roff == me - 1) roff = 0;
     }
   }
+  if (cur != A) {
+    for (int c = 0; c < m; ++c)
+      for (int r = lane; r < m; r += 64) A[r + c * lda] = cur[r + c * lda];
+    __syncthreads();
+  }
   return conv;
+}
+
+// ---------------------------------------------------------------------------------
+// pivoted Cholesky of an m x m LDS Gram matrix G (symmetric positive semi-definite) by
+// one wave: Pi' G Pi = L L' with diagonal pivoting (largest remaining diagonal, first
+// index on ties), stopped at the first pivot at or below 64 m (u/2) max_i G_ii (Higham's
+// floor for semidefinite Cholesky).  Writes the square root S = L' Pi' (r x m, so that
+// S'S = G up to the dropped tail) into S (leading dimension lda) and returns the rank r,
+// or -1 if the diagonal of G holds a NaN.  G is overwritten.
+// ---------------------------------------------------------------------------------
+__device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
+  const int lane = threadIdx.x & 63;
+  const double d0 = lane < m ? G[lane + lane * lda] : 0.0;
+  if (__ballot(d0 != d0) != 0) return -1;
+  double dmax = d0;
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  const double dfloor = 64.0 * m * (DBL_EPSILON * 0.5) * dmax;
+  if (lane < m) perm[lane] = lane;
+  __syncthreads();
+  int r = m;
+  for (int j = 0; j < m; ++j) {
+    double v = (lane >= j && lane < m) ? G[lane + lane * lda] : -DBL_MAX;
+    int iv = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int i2 = __shfl_xor(iv, o, 64);
+      if (v2 > v || (v2 == v && i2 < iv)) {
+        v = v2;
+        iv = i2;
+      }
+    }
+    // every lane holds the same (v, iv): the butterfly's comparisons are symmetric
+    if (__builtin_amdgcn_readfirstlane((int)!(v > dfloor))) {
+      r = j;
+      break;
+    }
+    const int piv = __builtin_amdgcn_readfirstlane(iv);
+    if (piv != j) {  // symmetric interchange of rows and columns j and piv
+      if (lane < m) {
+        const double t = G[j + lane * lda];
+        G[j + lane * lda] = G[piv + lane * lda];
+        G[piv + lane * lda] = t;
+      }
+      __syncthreads();
+      if (lane < m) {
+        const double t = G[lane + j * lda];
+        G[lane + j * lda] = G[lane + piv * lda];
+        G[lane + piv * lda] = t;
+      }
+      if (lane == 0) {
+        const int t = perm[j];
+        perm[j] = perm[piv];
+        perm[piv] = t;
+      }
+      __syncthreads();
+    }
+    const double ljj = sqrt(G[j + j * lda]);
+    double lij = 0.0;
+    if (lane > j && lane < m) {
+      lij = G[lane + j * lda] / ljj;
+      G[lane + j * lda] = lij;
+    }
+    if (lane == j) G[j + j * lda] = ljj;
+    __syncthreads();
+    if (lane > j && lane < m)
+      for (int c = j + 1; c < m; ++c) G[lane + c * lda] -= lij * G[c + j * lda];
+    __syncthreads();
+  }
+  // S[b][perm[a]] = L[a][b] for b <= a, b < r
+  for (int a = lane; a < m; a += 64)
+    for (int b = 0; b < r; ++b) S[b + perm[a] * lda] = (b <= a) ? G[a + b * lda] : 0.0;
+  __syncthreads();
+  return r;
 }
 
 // ---------------------------------------------------------------------------------
@@ -600,7 +723,7 @@ __device__ bool lds_sym_eig(double* A, double* E, int m, int lda) {
 __global__ void __launch_bounds__(64) k_node_factor(
     int l, const int* __restrict__ rank, const int* __restrict__ kmax,
     const int* __restrict__ rcount, const int* __restrict__ node_task_off, int tbase,
-    const double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
+    double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
     int zf_side, double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
     double* __restrict__ node_ld, double* __restrict__ coef, int cs_node, int cs_a,
     int* __restrict__ status, int kc, double gap_floor) {
@@ -611,9 +734,12 @@ __global__ void __launch_bounds__(64) k_node_factor(
     if (threadIdx.x == 0) node_ld[h] = 0.0;
     return;
   }
-  // final Gram blocks Z_side[a][b] = Z[a * zs_a + b] (summed by k_zsum)
-  double* ZI = zfin + (size_t)j * 2 * zf_side;
-  double* ZJ = ZI + zf_side;
+  // final Gram blocks Z_side[a][b] = Z[a * zs_a + b]: summed by k_zsum, or the side's
+  // only task partial (ZJ is overwritten below, in either place)
+  const int tI = node_task_off[2 * h] - tbase, tJ = node_task_off[2 * h + 1] - tbase;
+  const int tE = node_task_off[2 * h + 2] - tbase;
+  double* ZI = (tJ - tI == 1) ? zpart + (size_t)tI * zs_task : zfin + (size_t)j * 2 * zf_side;
+  double* ZJ = (tE - tJ == 1) ? zpart + (size_t)tJ * zs_task : zfin + (size_t)(2 * j + 1) * zf_side;
   const int zW = zs_a;
   extern __shared__ double lds[];
   double* GU = lds;
@@ -621,39 +747,35 @@ __global__ void __launch_bounds__(64) k_node_factor(
   double* E = GV + kc * kc;
   double* Hm = E + kc * kc;
   double* X = Hm + kc * kc;
-  __shared__ double lam[PMAX], g1[PMAX], g2[PMAX];
+  __shared__ double g1[PMAX], g2[PMAX];
+  __shared__ int perm[PMAX];
   for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     GU[a + b * kc] = 0.5 * (ZI[(size_t)a * zW + b] + ZI[(size_t)b * zW + a]);
     GV[a + b * kc] = 0.5 * (ZJ[(size_t)a * zW + b] + ZJ[(size_t)b * zW + a]);
   }
   __syncthreads();
-  bool ok = lds_sym_eig(GU, E, k, kc);
-  if (threadIdx.x < k) lam[threadIdx.x] = sqrt(fmax(GU[threadIdx.x + threadIdx.x * kc], 0.0));
-  __syncthreads();
-  // S_U = diag(sqrt(lambda)) E'  -> X
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-    const int a = idx % k, b = idx / k;
-    X[a + b * kc] = lam[a] * E[b + a * kc];
-  }
-  __syncthreads();
-  // E <- S_U G_V ; Hm <- E S_U'
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-    const int a = idx % k, b = idx / k;
+  // S_U (r x k, S_U' S_U = G_U) by pivoted Cholesky; the node's outputs do not depend
+  // on which square root of G_U is used
+  const int rc = wave_pchol(GU, k, kc, X, perm);
+  const int r = rc < 0 ? 0 : rc;
+  // E <- S_U G_V (r x k) ; Hm <- E S_U' (r x r)
+  for (int idx = threadIdx.x; idx < r * k; idx += blockDim.x) {
+    const int a = idx % r, b = idx / r;
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += X[a + c * kc] * GV[c + b * kc];
     E[a + b * kc] = acc;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-    const int a = idx % k, b = idx / k;
+  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+    const int a = idx % r, b = idx / r;
     double acc = 0.0;
     for (int c = 0; c < k; ++c) acc += E[a + c * kc] * X[b + c * kc];
     Hm[a + b * kc] = acc;
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {  // symmetrise
-    const int a = idx % k, b = idx / k;
+  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {  // symmetrise
+    const int a = idx % r, b = idx / r;
     if (a < b) {
       const double v = 0.5 * (Hm[a + b * kc] + Hm[b + a * kc]);
       Hm[a + b * kc] = v;
@@ -661,11 +783,12 @@ __global__ void __launch_bounds__(64) k_node_factor(
     }
   }
   __syncthreads();
-  ok = lds_sym_eig(Hm, E, k, kc) && ok;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
+  const bool ok = lds_sym_eig(Hm, E, GU, r, kc);  // GU is free until B
+  {
+    // lane a: the coefficients of s_a^2 and its log(1 - s_a^2)
+    double lg = 0.0;
     bool spd = true;
-    for (int a = 0; a < k; ++a) {
+    for (int a = threadIdx.x; a < r; a += 64) {
       double s2 = fmax(Hm[a + a * kc], 0.0);
       if (gap_floor > 0.0) {
         // FP32 panels: 1 - s^2 below their resolution is noise; the floor keeps the
@@ -678,18 +801,22 @@ __global__ void __launch_bounds__(64) k_node_factor(
       const double d = sqrt(1.0 - s2);
       g1[a] = -1.0 / (1.0 + d);
       g2[a] = 1.0 / (d * (1.0 + d));
-      s += log1p(-s2);
+      lg += log1p(-s2);
     }
-    node_ld[h] = s;
-    if (!spd) atomicOr(status, ST_NOTSPD);
-    if (!ok) atomicOr(status, ST_NOTCONV);
+    lg = wsum(lg);
+    const bool notspd = __ballot(!spd) != 0 || rc < 0;
+    if (threadIdx.x == 0) {
+      node_ld[h] = lg;
+      if (notspd) atomicOr(status, ST_NOTSPD);
+      if (!ok) atomicOr(status, ST_NOTCONV);
+    }
   }
   __syncthreads();
-  // B = S_U' P  -> GU
-  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+  // B = S_U' P (k x r) -> GU
+  for (int idx = threadIdx.x; idx < k * r; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double acc = 0.0;
-    for (int c = 0; c < k; ++c) acc += X[c + a * kc] * E[c + b * kc];
+    for (int c = 0; c < r; ++c) acc += X[c + a * kc] * E[c + b * kc];
     GU[a + b * kc] = acc;
   }
   __syncthreads();
@@ -698,7 +825,7 @@ __global__ void __launch_bounds__(64) k_node_factor(
   for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int a = idx % k, b = idx / k;
     double f1 = 0.0, f2 = 0.0;
-    for (int c = 0; c < k; ++c) {
+    for (int c = 0; c < r; ++c) {
       const double pr = GU[a + c * kc] * GU[b + c * kc];
       f1 += pr * g1[c];
       f2 += pr * g2[c];
@@ -861,9 +988,10 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
                                    panel, F.zpart, zs_a, zs_task);
     timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
-    launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
-                zs_task, s);
-    const int kc = std::max(P.kcap[l], 1);
+    if (P.max_tps[l] > 1)
+      launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
+                  zs_task, s);
+    const int kc = std::max(P.kcap[l], 1) + (std::max(P.kcap[l], 1) & 1);  // even pitch
     const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
     k_node_factor<<<1 << l, 64, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
