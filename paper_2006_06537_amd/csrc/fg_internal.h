@@ -92,6 +92,7 @@ struct HostPlan {
   std::vector<int> node_task_off;        // per node side: first level task (2*nint+1)
   int max_ltasks = 0;
   std::vector<int> max_tps;              // per level: most tasks on one node side
+  std::vector<int> max_trows;            // per level: most rows in one level task
   int nmt = 0, ngt = 0, nlt = 0;         // task counts (kept after the vectors are freed)
 };
 

@@ -93,7 +93,14 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__
 }
 
 // level reduce with a vector right operand: z[t][a][c] = sum_rows P[i, coff + a] v[i, c]
-template <typename T>
+//
+// The panel stores 16-row groups with each column's 16 rows contiguous, so the level's
+// columns of one group are contiguous too.  A wave reads 4 adjacent columns x 16 rows
+// (512 contiguous bytes) per load: lane = 16 * (column slot) + (row in group), and the
+// group's 16 entries of each v column (read straight from memory).  Waves stride over the
+// task's groups; rows outside the task (partial first and last groups) are masked.  Lane partials are summed over the 16 row lanes, then over the 4 waves in
+// a fixed order.  NR >= nrhs bounds the vector columns held in registers.
+template <typename T, int NR>
 __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
     const int* __restrict__ coff, const int* __restrict__ kmax, const T* __restrict__ P,
@@ -104,22 +111,63 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
   const Task tk = tasks[tbase + t];
   const int l = nodes[tk.h].level;
   const int c0 = coff[l], kl = kmax[l];
-  const int rw = tk.r1 - tk.r0;
-  __shared__ double vs[NRHS_MAX][RCH];
-  for (int idx = threadIdx.x; idx < rw * nrhs; idx += NTHREADS)
-    vs[idx / rw][idx % rw] = v[(size_t)(idx / rw) * ldv + tk.r0 + idx % rw];
-  __syncthreads();
+  const int gr0 = tk.r0 & ~15;                 // first row of the first group
+  const int ng = (tk.r1 - gr0 + 15) >> 4;      // groups touched
+  __shared__ double red[NTHREADS / 64][16][NR];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int a = wv; a < kl; a += NTHREADS / 64) {
-    double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = lane; i < rw; i += 64) {
-      const double pv = (double)P[pix(tk.r0 + i, c0 + a, K)];
-      for (int c = 0; c < nrhs; ++c) acc[c] += pv * vs[c][i];
+  const int rl = lane & 15, cslot = lane >> 4;
+  for (int q0 = 0; q0 < kl; q0 += 16) {
+    double acc[4][NR];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[j][c] = 0.0;
+    // 4 groups per pass (g, g + NW, g + 2 NW, g + 3 NW): all their loads are issued
+    // before any product
+    constexpr int NW = NTHREADS / 64;
+    for (int g0 = wv; g0 < ng; g0 += 4 * NW) {
+      double p[4][4], vv[4][NR];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int g = g0 + bb * NW;
+        const int r = gr0 + g * 16 + rl;
+        const bool ok = g < ng && r >= tk.r0 && r < tk.r1;
+        const T* pg = P + ((size_t)((gr0 >> 4) + g) * K + c0 + q0) * 16 + lane;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          p[bb][j] = (ok && q0 + 4 * j + cslot < kl) ? (double)pg[64 * j] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          vv[bb][c] = (ok && c < nrhs) ? v[(size_t)c * ldv + r] : 0.0;
+      }
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < nrhs)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j][c] += p[bb][j] * vv[bb][c];
     }
-    for (int c = 0; c < nrhs; ++c) {
-      const double s = wave_red(acc[c]);
-      if (lane == 0) zpart[(size_t)t * zs_task + a * nrhs + c] = s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nrhs)
+          for (int o = 1; o < 16; o <<= 1) acc[j][c] += __shfl_xor(acc[j][c], o, 64);
+    if (rl == 0)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < nrhs) red[wv][4 * j + cslot][c] = acc[j][c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * nrhs; e += NTHREADS) {
+      const int aa = e / nrhs, c = e - aa * nrhs, a = q0 + aa;
+      if (a < kl)
+        zpart[(size_t)t * zs_task + a * nrhs + c] =
+            (red[0][aa][c] + red[1][aa][c]) + (red[2][aa][c] + red[3][aa][c]);
     }
+    __syncthreads();
   }
 }
 
@@ -208,6 +256,8 @@ __global__ void __launch_bounds__(64) k_node_coef(
 }
 
 // v[rows of side] += P[rows, coff + a] coef_side[a][c]
+// One row per thread (work-group y of a task takes rows r0 + 256 y + thread, stepping by
+// 256 gridDim.y); the row's panel columns are loaded 8 at a time before they are used.
 template <typename T>
 __global__ void __launch_bounds__(NTHREADS) k_update_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
@@ -226,13 +276,30 @@ __global__ void __launch_bounds__(NTHREADS) k_update_vec(
   for (int e = threadIdx.x; e < k * nrhs; e += NTHREADS) cs[e] = cf[e];
   __syncthreads();
   const int cb = coff[l];
-  for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
+  for (int r = tk.r0 + blockIdx.y * NTHREADS + threadIdx.x; r < tk.r1;
+       r += NTHREADS * gridDim.y) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < k; ++a) {
-      const double pv = (double)P[pix(r, cb + a, K)];
-      for (int c = 0; c < nrhs; ++c) acc[c] += pv * cs[a * nrhs + c];
+    const T* pr = P + ((size_t)(r >> 4) * K + cb) * 16 + (r & 15);
+    int a = 0;
+    for (; a + 8 <= k; a += 8) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = (double)pr[(size_t)(a + u) * 16];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < NRHS_MAX; ++c)
+          if (c < nrhs) acc[c] += p[u] * cs[(a + u) * nrhs + c];
     }
-    for (int c = 0; c < nrhs; ++c) v[(size_t)c * ldv + r] += acc[c];
+    for (; a < k; ++a) {
+      const double pv = (double)pr[(size_t)a * 16];
+#pragma unroll
+      for (int c = 0; c < NRHS_MAX; ++c)
+        if (c < nrhs) acc[c] += pv * cs[a * nrhs + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NRHS_MAX; ++c)
+      if (c < nrhs) v[(size_t)c * ldv + r] += acc[c];
   }
 }
 
@@ -312,8 +379,9 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
   double* coef = work + (size_t)std::max(P.max_ltasks, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   const int hbase = (1 << l) - 1;
-  k_reduce_vec<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, panel,
-                                          P.Ktot, v, nrhs, ld, zpart, zs_task);
+  auto rv = nrhs <= 1 ? k_reduce_vec<T, 1> : nrhs <= 2 ? k_reduce_vec<T, 2> : k_reduce_vec<T, 4>;
+  rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, panel, P.Ktot, v, nrhs,
+                             ld, zpart, zs_task);
   double* zs = nullptr;
   if (P.max_tps[l] > 1) {
     zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
@@ -323,8 +391,10 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
                                     zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr, coef,
                                     cs_node, zs);
   const int skip_left = (op == 0 || op == 2) ? 1 : 0;
-  k_update_vec<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
-                                          panel, P.Ktot, v, nrhs, ld, coef, cs_node, skip_left);
+  const dim3 grid_u(nt, (std::min(P.max_trows[l], RCH) + NTHREADS - 1) / NTHREADS);
+  k_update_vec<T><<<grid_u, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
+                                              panel, P.Ktot, v, nrhs, ld, coef, cs_node,
+                                              skip_left);
 }
 
 template <typename T>
@@ -371,8 +441,10 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
   double* coef = work + (size_t)std::max(nt, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   if (P.L > 0) {
-    k_reduce_vec<double><<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel,
-                                         P.Ktot, v, nrhs, ld, zpart, zs_task);
+    auto rv = nrhs <= 1 ? k_reduce_vec<double, 1>
+            : nrhs <= 2 ? k_reduce_vec<double, 2> : k_reduce_vec<double, 4>;
+    rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel, P.Ktot, v,
+                               nrhs, ld, zpart, zs_task);
     double* zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
     launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task, s);
     k_node_coef<<<P.nint, 64, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart, zs_task,

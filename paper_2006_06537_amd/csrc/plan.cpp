@@ -180,6 +180,9 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
   P.node_task_off[2 * P.nint] = int(P.ltasks.size());
   P.ltask_off[L] = int(P.ltasks.size());
   P.max_tps.assign(std::max(L, 1), 1);
+  P.max_trows.assign(std::max(L, 1), 1);
+  for (const Task& tk : P.ltasks)
+    P.max_trows[P.nodes[tk.h].level] = std::max(P.max_trows[P.nodes[tk.h].level], tk.r1 - tk.r0);
   for (int l = 0; l < L; ++l)
     P.max_ltasks = std::max(P.max_ltasks, P.ltask_off[l + 1] - P.ltask_off[l]);
   for (int h = 0; h < P.nint; ++h)
