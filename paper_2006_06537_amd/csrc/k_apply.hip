@@ -20,35 +20,154 @@ __device__ __forceinline__ double wave_red(double v) {
   return v;
 }
 
-// leaf block operator, in place on v: op 0 L, 1 L', 2 L^-1, 3 L^-T.  L is the leaf's lower
-// triangle; Dinv holds the inverses of its 16 x 16 diagonal blocks (in the diagonal
-// blocks of the slot).  L^-1 and L^-T are blocked substitutions:
-//   forward:  v_i <- D_i^-1 (v_i - sum_{j<i} L_ij v_j),   i = 0, 1, ...
-//   backward: v_i <- D_i^-T (v_i - sum_{j>i} L_ji' v_j),  i = nb-1, ..., 0
-// (factor data of precision T; vectors and arithmetic in FP64)
+// leaf block operators L v (op 0) and L^-1 v (op 2), in place on v.  L is the leaf's
+// lower triangle (column-major, leading dimension Bc); Dinv holds the inverses of its
+// 16 x 16 diagonal blocks (in the diagonal blocks of the slot).  One work-group of BMAX
+// threads per leaf; thread r owns row r of the leaf's vector block (nrhs columns in
+// registers), so a wave's load of one column of L covers 64 consecutive rows.
+//   L v:    row r sums L[r][s] v_s over s <= r, 16 columns per batch of loads.
+//   L^-1 v: right-looking blocked substitution over the 16-row diagonal blocks:
+//           v_j = D_j^-1 t_j, then every row below takes t_r -= L_rj v_j, j = 0, 1, ...;
+//           a row's 16 coefficients of a step are loaded at the start of the step.
+// (Factor data of precision T; vectors and arithmetic in FP64.)
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
-                                                         const T* __restrict__ Lm,
-                                                         const T* __restrict__ Dinv, int Bc,
-                                                         int op, double* __restrict__ v,
-                                                         int nrhs, int ld) {
+__global__ void __launch_bounds__(BMAX) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
+                                                     const T* __restrict__ Lm,
+                                                     const T* __restrict__ Dinv, int Bc,
+                                                     int op, double* __restrict__ v,
+                                                     int nrhs, int ld) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
-  __shared__ double vs[NRHS_MAX][BMAX];
+  const int r = threadIdx.x;
+  const bool live = r < m;
+  const T* Mb = Lm + (size_t)b * Bc * Bc;
+  double x[NRHS_MAX];
+#pragma unroll
+  for (int c = 0; c < NRHS_MAX; ++c)
+    x[c] = (live && c < nrhs) ? v[(size_t)c * ld + lo + r] : 0.0;
+  if (op == 0) {
+    __shared__ double vs[NRHS_MAX][BMAX];  // rows >= m hold zeros
+#pragma unroll
+    for (int c = 0; c < NRHS_MAX; ++c) vs[c][r] = x[c];
+    __syncthreads();
+    if (!live) return;
+    double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 <= r; s0 += 16) {
+      double p[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        p[u] = (s0 + u <= r) ? (double)Mb[r + (size_t)(s0 + u) * Bc] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+#pragma unroll
+        for (int c = 0; c < NRHS_MAX; ++c)
+          if (c < nrhs) acc[c] += p[u] * vs[c][(s0 + u) & (BMAX - 1)];
+    }
+#pragma unroll
+    for (int c = 0; c < NRHS_MAX; ++c)
+      if (c < nrhs) v[(size_t)c * ld + lo + r] = acc[c];
+    return;
+  }
+  __shared__ double ts[NRHS_MAX][16], vj[NRHS_MAX][16];
+  // zeros where a ragged block has no rows (they meet zero coefficients)
+  if (r < NRHS_MAX * 16) {
+    ts[r >> 4][r & 15] = 0.0;
+    vj[r >> 4][r & 15] = 0.0;
+  }
+  __syncthreads();
+  const T* Db = Dinv + (size_t)b * Bc * Bc;
+  const int nb = (m + 15) >> 4;
+  const int jr = r >> 4, rr = r & 15;
+  for (int j = 0; j < nb; ++j) {
+    const int r0 = j * 16, mj = min(16, m - r0);
+    const bool inb = live && jr == j;
+    const bool upd = live && jr > j;
+    // a row of D_j^-1 on block j's rows, L[r][r0 + u] on the rows below, zeros elsewhere
+    double q[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      double w = 0.0;
+      if (u < mj) {
+        if (inb) {
+          if (u <= rr) w = (double)Db[r + (size_t)(r0 + u) * Bc];
+        } else if (upd) {
+          w = (double)Mb[r + (size_t)(r0 + u) * Bc];
+        }
+      }
+      q[u] = w;
+    }
+    if (inb)
+#pragma unroll
+      for (int c = 0; c < NRHS_MAX; ++c)
+        if (c < nrhs) ts[c][rr] = x[c];
+    __syncthreads();
+    if (inb) {
+#pragma unroll
+      for (int c = 0; c < NRHS_MAX; ++c) {
+        if (c < nrhs) {
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) acc += q[u] * ts[c][u];
+          x[c] = acc;
+          vj[c][rr] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (upd) {
+#pragma unroll
+      for (int c = 0; c < NRHS_MAX; ++c) {
+        if (c < nrhs) {
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) acc += q[u] * vj[c][u];
+          x[c] -= acc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NRHS_MAX; ++c)
+    if (live && c < nrhs) v[(size_t)c * ld + lo + r] = x[c];
+}
+
+// transposed leaf block operators L' v (op 1) and L^-T v (op 3), in place on v.  Their
+// reads run along L's columns, so threads take consecutive entries of one column:
+//   L' v:   one thread per (row r, vector column) sums L[s][r] v_s over s >= r, 16 rows
+//           of column r per batch of loads.
+//   L^-T v: left-looking blocked substitution,
+//           v_i <- D_i^-T (v_i - sum_{j>i} L_ji' v_j),  i = nb-1, ..., 0,
+//           four threads per (row of block i, vector column) reading consecutive rows of
+//           L's column, their partial sums combined by shuffles.
+// (Factor data of precision T; vectors and arithmetic in FP64.)
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t(const int* __restrict__ leaf_lo,
+                                                           int nleaf, const T* __restrict__ Lm,
+                                                           const T* __restrict__ Dinv, int Bc,
+                                                           int op, double* __restrict__ v,
+                                                           int nrhs, int ld) {
+  const int b = blockIdx.x;
+  if (b >= nleaf) return;
+  const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  __shared__ double vs[NRHS_MAX][BMAX];  // rows >= m hold zeros
   __shared__ double ts[NRHS_MAX][16];
-  for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
-    vs[idx / m][idx % m] = v[(size_t)(idx / m) * ld + lo + idx % m];
+  for (int idx = threadIdx.x; idx < BMAX * nrhs; idx += NTHREADS) {
+    const int c = idx / BMAX, r = idx % BMAX;
+    vs[c][r] = r < m ? v[(size_t)c * ld + lo + r] : 0.0;
+  }
   __syncthreads();
   const T* Mb = Lm + (size_t)b * Bc * Bc;
-  if (op < 2) {
+  if (op == 1) {
     for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS) {
       const int r = idx % m, c = idx / m;
       double acc = 0.0;
-      if (op == 0) {
-        for (int s = 0; s <= r; ++s) acc += (double)Mb[r + s * Bc] * vs[c][s];
-      } else {
-        for (int s = r; s < m; ++s) acc += (double)Mb[s + r * Bc] * vs[c][s];
+      for (int s0 = r; s0 < m; s0 += 16) {  // 16 entries of column r per batch of loads
+        double p[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) p[u] = (s0 + u < m) ? (double)Mb[s0 + u + (size_t)r * Bc] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += p[u] * vs[c][(s0 + u) & (BMAX - 1)];
       }
       v[(size_t)c * ld + lo + r] = acc;
     }
@@ -56,34 +175,23 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__
   }
   const T* Db = Dinv + (size_t)b * Bc * Bc;
   const int nb = (m + 15) >> 4;
-  // 4 threads per (row of the block, column): partial sums combined by shuffles
-  const int q = threadIdx.x & 3, e = threadIdx.x >> 2;  // e: 0..63 = row r (16) x column c (4)
+  const int q = threadIdx.x & 3, e = threadIdx.x >> 2;  // e: 0..63 = row (16) x column (4)
   const int rr = e & 15, c = e >> 4;
-  for (int step = 0; step < nb; ++step) {
-    const int i = (op == 2) ? step : nb - 1 - step;
+  for (int i = nb - 1; i >= 0; --i) {
     const int r = i * 16 + rr;
     double t = 0.0;
-    if (c < nrhs && r < m) {
-      if (op == 2) {
-        for (int s = q; s < i * 16; s += 4) t += (double)Mb[r + (size_t)s * Bc] * vs[c][s];
-      } else {
-        for (int s = (i + 1) * 16 + q; s < m; s += 4) t += (double)Mb[s + (size_t)r * Bc] * vs[c][s];
-      }
-    }
+    if (c < nrhs && r < m)
+      for (int s = (i + 1) * 16 + q; s < m; s += 4) t += (double)Mb[s + (size_t)r * Bc] * vs[c][s];
     t += __shfl_xor(t, 1, 64);
     t += __shfl_xor(t, 2, 64);
     if (q == 0 && c < nrhs) ts[c][rr] = (r < m) ? vs[c][r] - t : 0.0;
     __syncthreads();
-    // v_i = D_i^-1 t (forward) or D_i^-T t (backward); D_i^-1 is lower triangular
+    // v_i = D_i^-T t, with D_i^-1 lower triangular
     if (q == 0 && c < nrhs && r < m) {
       double u = 0.0;
-      const int r0 = i * 16;
-      const int mi = min(16, m - r0);
-      if (op == 2) {
-        for (int s2 = 0; s2 <= rr; ++s2) u += (double)Db[(r0 + rr) + (size_t)(r0 + s2) * Bc] * ts[c][s2];
-      } else {
-        for (int s2 = rr; s2 < mi; ++s2) u += (double)Db[(r0 + s2) + (size_t)(r0 + rr) * Bc] * ts[c][s2];
-      }
+      const int r0 = i * 16, mi = min(16, m - r0);
+      for (int s2 = rr; s2 < mi; ++s2)
+        u += (double)Db[(r0 + s2) + (size_t)(r0 + rr) * Bc] * ts[c][s2];
       vs[c][r] = u;
     }
     __syncthreads();
@@ -98,8 +206,9 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply(const int* __restrict__
 // columns of one group are contiguous too.  A wave reads 4 adjacent columns x 16 rows
 // (512 contiguous bytes) per load: lane = 16 * (column slot) + (row in group), and the
 // group's 16 entries of each v column (read straight from memory).  Waves stride over the
-// task's groups; rows outside the task (partial first and last groups) are masked.  Lane partials are summed over the 16 row lanes, then over the 4 waves in
-// a fixed order.  NR >= nrhs bounds the vector columns held in registers.
+// task's groups; rows outside the task (partial first and last groups) are masked.  Lane
+// partials are summed over the 16 row lanes, then over the 4 waves in a fixed order.
+// NR >= nrhs bounds the vector columns held in registers.
 template <typename T, int NR>
 __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
     const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
@@ -404,8 +513,12 @@ static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const T* p
   const int* leaf_lo = F.H->pk->D.leaf_lo;
   // W = L_D W_(L-1) ... W_(0)
   auto leaf = [&](int lop) {
-    k_leaf_apply<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop, v,
-                                                 nrhs, ld);
+    if (lop == 0 || lop == 2)
+      k_leaf_apply<T><<<P.nleaf, BMAX, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop, v,
+                                               nrhs, ld);
+    else
+      k_leaf_apply_t<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop,
+                                                     v, nrhs, ld);
   };
   if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
     for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 0, l, v, nrhs, ld, work, s);
