@@ -41,7 +41,8 @@ struct fg_chain_s {
   double pcg_relres = 0.0;
   bool pcg_failed = false;
   hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t zs = nullptr;                   // Z and tau y, beside the factorization of M~
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_z = nullptr, ev_f = nullptr;
   // exact discrete conditional of the length-scale: every grid point's K~_1 and W_1
   bool exact = false;
   std::vector<fg::HodlrData> Hg;
@@ -90,7 +91,10 @@ static void chain_free(fg_chain c) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_z) (void)hipEventDestroy(c->ev_z);
+  if (c->ev_f) (void)hipEventDestroy(c->ev_f);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->zs) (void)hipStreamDestroy(c->zs);
   fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   for (auto& h : c->Hg) fg::hodlr_free(h);
@@ -243,20 +247,24 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
                    c->aux);
   }
-  hipEventRecord(c->ev_join, c->aux);
   if (c->collapsed) {
     enqueue_f_tau_collapsed(c, s);
   } else {
-    // f | -  (Algorithm 1)
+    // f | -  (Algorithm 1).  Z = sqrt(tau) sigma_f^2 K~_1 a + sigma_f W_1 b and tau y use
+    // the previous sweep's scalars only: the chain's third stream forms them while this
+    // stream factors M~.
+    hipStreamWaitEvent(c->zs, c->ev_fork, 0);
+    fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, c->zs, itp);
+    fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, c->zs, itp);
+    fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, c->zs);
+    fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, c->zs);
+    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, c->zs);
+    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, c->zs);
+    hipEventRecord(c->ev_z, c->zs);
     fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
     fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
     hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-    fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
-    fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
-    fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, s);
-    fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, s);
-    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, s);
-    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, s);
+    hipStreamWaitEvent(s, c->ev_z, 0);
     if (c->mixed && !c->fell_back) {
       // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
       // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
@@ -301,6 +309,16 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     // tau | -
     fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, cf.stream_id, s);
   }
+  // f is final: the proposal's quadratic form |W_1'^-1 f|^2 runs on the second stream,
+  // beside this stream's |W_1^-1 f|^2 (v1 is free from here on)
+  if (!c->exact && pr.ongrid) {
+    hipEventRecord(c->ev_f, s);
+    hipStreamWaitEvent(c->aux, c->ev_f, 0);
+    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->aux);
+    fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, c->aux);
+    fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork + 2048, c->aux);
+  }
+  hipEventRecord(c->ev_join, c->aux);
   // sigma_f^-2 | -
   hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
   fg::launch_apply_w(W1, 2, v0, 1, n, W1.work, s);
@@ -313,11 +331,6 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     return;
   }
   // length-scale | -  (Metropolis on the grid)
-  if (pr.ongrid) {
-    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-    fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
-    fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
-  }
   fg::launch_mh_step(c->st, pr.kp, pr.ongrid, cf.seed, cf.stream_id,
                      pr.ongrid ? c->H[oth].status : nullptr, pr.ongrid ? c->W[oth].status : nullptr, s);
   hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
@@ -487,15 +500,18 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
       hipMalloc(reinterpret_cast<void**>(&c->r), nb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->mu), nb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->vecs), 4 * nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 2048) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 3072) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(fg::DevState)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::DevState)) != hipSuccess) {
     chain_free(c);
     return cfail(FG_ENOMEM, "chain allocation failed");
   }
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_z, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming) != hipSuccess) {
     chain_free(c);
     return cfail(FG_EDEVICE, "stream or event creation failed");
   }
