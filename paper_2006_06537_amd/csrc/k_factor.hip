@@ -39,82 +39,80 @@ constexpr int LG = 16;        // thread grid side
 constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
 constexpr int LPD = 17;       // LDS pitch of 16-wide rows
 
-// broadcast of lane `l`'s value to the whole wave (a register read, no LDS round trip)
-__device__ __forceinline__ double bcast(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ float bcast(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+// LDS ordering between the lanes of one wave (no work-group barrier: only the factoring
+// wave runs diag_factor16)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD).  Lane r (and its
-// copies r + 16, r + 32, r + 48) owns row r; pivots and finished rows travel by register
-// broadcast.  Writes L into Lk and L^-1 into Lik (LDS, pitch LPD, zero upper triangles);
-// returns the sum of the log pivots (every lane) and flags a non-positive pivot.
+// One wave: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD), worked in LDS
+// so that the caller's registers (the leaf's blocks) stay free of it: lane l owns the
+// elements (l & 15, (l >> 4) + 4 q), q = 0..3, of the block.  Writes L into Lk and L^-1
+// into Lik (pitch LPD, zero upper triangles); returns the sum of the log pivots (every
+// lane) and flags a non-positive pivot (which then counts as 1).
 template <typename T>
 __device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
   const int lane = threadIdx.x & 63;
-  const int r = lane & 15;
-  T row[16], x[16], inv[16];
+  const int r = lane & 15, c0 = lane >> 4;
 #pragma unroll
-  for (int c = 0; c < 16; ++c) row[c] = Dk[r * LPD + c];
-  // right-looking Cholesky on rows: column j scaled by 1/sqrt(pivot), then the rows
-  // below take the rank-one update with row j's finished column entries
-#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + 4 * q;
+    Lk[r * LPD + c] = (c <= r) ? Dk[r * LPD + c] : T(0);
+    Lik[r * LPD + c] = (c == r) ? T(1) : T(0);
+  }
+  wave_lds_sync();
+  // right-looking Cholesky: column j scaled by 1/sqrt(pivot), then the trailing lower
+  // triangle takes the rank-one update with column j
   for (int j = 0; j < 16; ++j) {
-    const T piv = bcast(row[j], j);
+    const T piv = Lk[j * LPD + j];
     const bool ok = piv > T(0);
     bad |= !ok;
     const T sq = ok ? sqrt(piv) : T(1);
-    inv[j] = T(1) / sq;
-    const T lrj = (r > j) ? row[j] * inv[j] : ((r == j) ? sq : T(0));
-    row[j] = lrj;
+    const T invj = T(1) / sq;
+    wave_lds_sync();
 #pragma unroll
-    for (int c = j + 1; c < 16; ++c) {
-      const T lcj = bcast(row[j], c);
-      if (c <= r) row[c] -= lrj * lcj;
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 4 * q;
+      if (c == j && r > j) Lk[r * LPD + j] *= invj;
+      if (c == j && r == j) Lk[j * LPD + j] = sq;
     }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 4 * q;
+      if (c > j && c <= r) Lk[r * LPD + c] -= Lk[r * LPD + j] * Lk[c * LPD + j];
+    }
+    wave_lds_sync();
   }
-  // L^-1 by rows: x = e_r, then for k = 0..15 row k is finished by lane k and
-  // broadcast to the rows below it
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = (c == r) ? T(1) : T(0);
-#pragma unroll
+  // L^-1 by rows: row k is finished (scaled by 1/L[k][k]) at step k, then the rows below
+  // take its multiple
   for (int k = 0; k < 16; ++k) {
-    if (r == k) {
+    const T dinv = T(1) / Lk[k * LPD + k];
 #pragma unroll
-      for (int c = 0; c <= k; ++c) x[c] *= inv[k];
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 4 * q;
+      if (r == k && c <= k) Lik[k * LPD + c] *= dinv;
     }
-    const T lrk = row[k];
+    wave_lds_sync();
 #pragma unroll
-    for (int c = 0; c <= k; ++c) {
-      const T xk = bcast(x[c], k);
-      if (r > k) x[c] -= lrk * xk;
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 4 * q;
+      if (r > k && c <= k) Lik[r * LPD + c] -= Lk[r * LPD + k] * Lik[k * LPD + c];
     }
+    wave_lds_sync();
   }
   // log pivots: lane r takes 2 log L[r][r], summed over the 16 rows
-  T dr = T(1);
-#pragma unroll
-  for (int c = 0; c < 16; ++c)
-    if (c == r) dr = row[c];
+  const T dr = Lk[r * LPD + r];
   double ls = (dr > T(0)) ? 2.0 * log((double)dr) : 0.0;
   for (int o = 8; o > 0; o >>= 1) ls += __shfl_xor(ls, o, 16);
-  if (lane < 16) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      Lk[r * LPD + c] = (c <= r) ? row[c] : T(0);
-      Lik[r * LPD + c] = (c <= r) ? x[c] : T(0);
-    }
-  }
   return ls;
 }
 
 #define LT(i, j) ((i) * ((i) + 1) / 2 + (j))
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
+__global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
     const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
     double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
     const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
@@ -127,13 +125,15 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
   const double alpha = alpha_p ? *alpha_p : alpha_v;
   const double beta = beta_p ? *beta_p : beta_v;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  // LDS: Likk 8 blocks | Lk | Dk | Lp (2 x 128 rows) | Pp 128 rows
+  // LDS: Likk (the current diagonal block's inverse) | Lk | Dk | Lp 128 rows | Pp 128 rows
+  // (42 KB in FP64: three work-groups per CU)
   __shared__ double xs[BMAX];
-  __shared__ T Likk[LE * 16 * LPD];
+  __shared__ T Likk[16 * LPD];
   __shared__ T Lk[16 * LPD];
   __shared__ T Dk[16 * LPD];
-  __shared__ T Lp[2 * BMAX * LPD];
+  __shared__ T Lp[BMAX * LPD];
   __shared__ T Pp[BMAX * LPD];
+  T* Lig = leafLinv + (size_t)b * Bc * Bc;
   __shared__ int bad;
   __shared__ double ldsum;
   if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
@@ -171,12 +171,18 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
     __syncthreads();
     if ((threadIdx.x >> 6) == (kb & 3)) {  // the factoring wave rotates over the SIMDs
       bool wb = false;
-      const double ls = diag_factor16(Dk, Lk, Likk + kb * (16 * LPD), wb);
+      const double ls = diag_factor16(Dk, Lk, Likk, wb);
       if ((threadIdx.x & 63) == 0) ldsum += ls;
       if (wb) bad = 1;
     }
     __syncthreads();
-    const T* Li = Likk + kb * (16 * LPD);
+    // the inverse of the diagonal block goes to the diagonal block of the leaf's L^-1 slot
+    {
+      const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
+      if (kb * 16 + r < m && c <= r)
+        Lig[(kb * 16 + r) + (size_t)(kb * 16 + c) * Bc] = Likk[r * LPD + c];
+    }
+    const T* Li = Likk;
     T* L1 = Lp;
 #pragma unroll
     for (int i = 0; i < LE; ++i) {
@@ -193,7 +199,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       }
     }
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 1
     for (int t = 0; t < 16; ++t) {
       T lr[LE], lc[LE];
 #pragma unroll
@@ -229,15 +235,9 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_leaf(
       if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[LT(i, jj)];  // lower triangle only
     }
   }
-  // the inverses of the 16 x 16 diagonal blocks (from the diagonal factorizations) go to
-  // the diagonal blocks of the leaf's L^-1 slot; L^-1 itself is never formed (its
-  // products are blocked substitutions: k_whiten, k_leaf_apply)
-  T* Lig = leafLinv + (size_t)b * Bc * Bc;
-  for (int kb = 0; kb < nb; ++kb) {
-    const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
-    if (kb * 16 + r < m && c <= r)
-      Lig[(kb * 16 + r) + (size_t)(kb * 16 + c) * Bc] = Likk[kb * (16 * LPD) + r * LPD + c];
-  }
+  // (the inverses of the 16 x 16 diagonal blocks were written at each block step; L^-1
+  // itself is never formed: its products are blocked substitutions, k_whiten and
+  // k_leaf_apply)
 }
 
 #undef LT
