@@ -47,6 +47,16 @@ __device__ __forceinline__ double k1_value(int kind, double ell, double a, doubl
 // Panels are stored in 16-row tiles: rows of a tile are contiguous (128 bytes per
 // column), then the K columns of that tile, then the next tile.  A 16-row segment of
 // one column is a single cache line and the columns of a tile are adjacent.
+// index at position j (0 <= j < me, me even) of the round-robin pairing schedule of the
+// parallel Jacobi methods after `off` < me - 1 steps: position 0 stays, positions 1..me-1
+// rotate; the pairs of a step are positions (t, me - 1 - t)
+__device__ __forceinline__ int rr_index(int j, int off, int me) {
+  if (j == 0) return 0;
+  int v = j - 1 + off;
+  if (v >= me - 1) v -= me - 1;
+  return 1 + v;
+}
+
 __host__ __device__ __forceinline__ size_t pix(int r, int c, int K) {
   return ((size_t)(r >> 4) * (size_t)K + (size_t)c) * 16 + (size_t)(r & 15);
 }

@@ -91,31 +91,44 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ t
 __device__ int lds_pchol(double* A, int m, int ldm, int* perm, double* tmp) {
   __shared__ int rk, piv, bad;
   __shared__ double dfloor;
-  if (threadIdx.x == 0) {
-    double dmax = 0.0;
-    bad = 0;
-    for (int j = 0; j < m; ++j) {
-      const double d = A[j + j * ldm];
-      if (d != d) bad = 1;
-      dmax = fmax(dmax, d);
-      perm[j] = j;
+  // wave 0 reduces over the diagonal (m <= PMAX < 64: one entry per lane)
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const double d = lane < m ? A[lane + lane * ldm] : 0.0;
+    double dmax = d;
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    const bool nan = __ballot(lane < m && d != d) != 0;
+    if (lane < m) perm[lane] = lane;
+    if (lane == 0) {
+      bad = nan ? 1 : 0;
+      dfloor = 64.0 * m * (DBL_EPSILON * 0.5) * dmax;
+      rk = m;
     }
-    dfloor = 64.0 * m * (DBL_EPSILON * 0.5) * dmax;
-    rk = m;
   }
   __syncthreads();
   if (bad) return -1;
   for (int j = 0; j < m; ++j) {
-    if (threadIdx.x == 0) {
-      int k = j;
-      for (int i = j + 1; i < m; ++i)
-        if (A[i + i * ldm] > A[k + k * ldm]) k = i;
-      if (A[k + k * ldm] > dfloor) {
-        piv = k;
-        const int t = perm[j]; perm[j] = perm[k]; perm[k] = t;
-      } else {
-        piv = -1;
-        rk = j;
+    if (threadIdx.x < 64) {
+      // largest remaining diagonal entry, first index on ties
+      const int lane = threadIdx.x;
+      double v = (lane >= j && lane < m) ? A[lane + lane * ldm] : -DBL_MAX;
+      int iv = lane;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(v, o, 64);
+        const int i2 = __shfl_xor(iv, o, 64);
+        if (v2 > v || (v2 == v && i2 < iv)) {
+          v = v2;
+          iv = i2;
+        }
+      }
+      if (lane == 0) {
+        if (v > dfloor) {
+          piv = iv;
+          const int t = perm[j]; perm[j] = perm[iv]; perm[iv] = t;
+        } else {
+          piv = -1;
+          rk = j;
+        }
       }
     }
     __syncthreads();
@@ -157,35 +170,64 @@ __device__ int lds_pchol(double* A, int m, int ldm, int* perm, double* tmp) {
 }
 
 // One-sided Jacobi on the columns of M (mr x qc, mr >= qc) with right vectors Q (qc x qc).
-// Returns false if 40 sweeps did not converge.
-__device__ bool lds_jacobi_svd(double* M, int mr, int qc, int ldm, double* Q, int ldq) {
-  __shared__ int rotated;
-  __shared__ int perm[PMAX + 1];
+// A pair is rotated unless its columns are orthogonal to working precision, or both of
+// them are below nu = min(1e-13 max|col|, thr_lo / 8), thr_lo = max(tol/3, 8 (u/2) max|col|)
+// (max over the columns at the start of the sweep).  Such columns stay under the
+// truncation threshold max(tol/3, 8 (u/2) s_max) >= thr_lo, so every column that is kept
+// is still orthogonalised against all others, and a discarded singular value is off by at
+// most nu.  Returns false if 40 sweeps did not converge.
+__device__ bool lds_jacobi_svd(double* M, int mr, int qc, int ldm, double* Q, int ldq,
+                               double tol) {
+  __shared__ double nu2s;
+  // per sweep parity; the next sweep's flag (the one read at the end of the previous
+  // sweep) is reset after this sweep's first barrier, when every thread has read it
+  __shared__ int rotated[2];
   for (int idx = threadIdx.x; idx < qc * qc; idx += NTHREADS)
     Q[idx % qc + (idx / qc) * ldq] = (idx % qc == idx / qc) ? 1.0 : 0.0;
   const int qe = qc + (qc & 1);  // even number of players
   const int npair = qe / 2;
   const int g = threadIdx.x >> 3, gl = threadIdx.x & 7;  // 8 lanes per pair
+  if (threadIdx.x == 0) rotated[0] = 0;
   __syncthreads();
   if (qc < 2) return true;
   bool conv = false;
   for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int step = 0; step < qe - 1; ++step) {
-      if (threadIdx.x < qe) {
-        const int j = threadIdx.x;
-        perm[j] = (j == 0) ? 0 : 1 + ((j - 1 + step) % (qe - 1));
+    if (threadIdx.x < 64) {  // the largest column norm (qc <= PMAX < 64 columns)
+      double n2 = 0.0;
+      if (threadIdx.x < qc)
+        for (int r = 0; r < mr; ++r) n2 += M[r + threadIdx.x * ldm] * M[r + threadIdx.x * ldm];
+      for (int o = 32; o > 0; o >>= 1) n2 = fmax(n2, __shfl_xor(n2, o, 64));
+      if (threadIdx.x == 0) {
+        const double mx = sqrt(n2);
+        const double thr_lo = fmax(tol / 3.0, 8.0 * (DBL_EPSILON * 0.5) * mx);
+        const double nu = fmin(1e-13 * mx, thr_lo / 8.0);
+        nu2s = nu * nu;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    const double nu2 = nu2s;
+    for (int step = 0; step < qe - 1; ++step) {
       if (g < npair) {
-        int i = perm[g], k = perm[qe - 1 - g];
+        // pair g of this step of the round-robin order
+        int i = rr_index(g, step, qe), k = rr_index(qe - 1 - g, step, qe);
         if (i > k) { const int tmp = i; i = k; k = tmp; }
+        // this lane's rows (gl, gl + 8, ...) of columns i and k of M and Q, loaded at once
+        constexpr int RPL = (PMAX + 7) / 8;
+        double mu[RPL], mv[RPL], qu[RPL], qv[RPL];
+        const bool live = k < qc;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = gl + 8 * t;
+          mu[t] = (live && r < mr) ? M[r + i * ldm] : 0.0;
+          mv[t] = (live && r < mr) ? M[r + k * ldm] : 0.0;
+          qu[t] = (live && r < qc) ? Q[r + i * ldq] : 0.0;
+          qv[t] = (live && r < qc) ? Q[r + k * ldq] : 0.0;
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (k < qc) {
-          for (int r = gl; r < mr; r += 8) {
-            const double u = M[r + i * ldm], v = M[r + k * ldm];
-            al += u * u; be += v * v; ga += u * v;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          if (gl + 8 * t < mr) {
+            al += mu[t] * mu[t]; be += mv[t] * mv[t]; ga += mu[t] * mv[t];
           }
         }
         for (int o = 4; o > 0; o >>= 1) {
@@ -193,27 +235,30 @@ __device__ bool lds_jacobi_svd(double* M, int mr, int qc, int ldm, double* Q, in
           be += __shfl_xor(be, o, 8);
           ga += __shfl_xor(ga, o, 8);
         }
-        if (k < qc && fabs(ga) > 2.0 * DBL_EPSILON * sqrt(al * be) && ga != 0.0) {
+        if (live && (al >= nu2 || be >= nu2) && fabs(ga) > 2.0 * DBL_EPSILON * sqrt(al * be) &&
+            ga != 0.0) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int r = gl; r < mr; r += 8) {
-            const double u = M[r + i * ldm], v = M[r + k * ldm];
-            M[r + i * ldm] = cs * u - sn * v;
-            M[r + k * ldm] = sn * u + cs * v;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = gl + 8 * t;
+            if (r < mr) {
+              M[r + i * ldm] = cs * mu[t] - sn * mv[t];
+              M[r + k * ldm] = sn * mu[t] + cs * mv[t];
+            }
+            if (r < qc) {
+              Q[r + i * ldq] = cs * qu[t] - sn * qv[t];
+              Q[r + k * ldq] = sn * qu[t] + cs * qv[t];
+            }
           }
-          for (int r = gl; r < qc; r += 8) {
-            const double u = Q[r + i * ldq], v = Q[r + k * ldq];
-            Q[r + i * ldq] = cs * u - sn * v;
-            Q[r + k * ldq] = sn * u + cs * v;
-          }
-          if (gl == 0) rotated = 1;
+          if (gl == 0) rotated[sweep & 1] = 1;
         }
       }
       __syncthreads();
+      if (step == 0 && threadIdx.x == 0) rotated[(sweep + 1) & 1] = 0;
     }
-    conv = (rotated == 0);
-    __syncthreads();
+    conv = (rotated[sweep & 1] == 0);
   }
   return conv;
 }
@@ -340,7 +385,7 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     if (trans) Cm[t + r * ld] = acc; else Cm[r + t * ld] = acc;
   }
   __syncthreads();
-  const bool conv = lds_jacobi_svd(Cm, mr, qc, ld, Vm, ld);
+  const bool conv = lds_jacobi_svd(Cm, mr, qc, ld, Vm, ld, tol);
   if (!conv && threadIdx.x == 0) atomicOr(status, ST_NOTCONV);
   // singular values, descending order, rank
   if (threadIdx.x < qc) {
@@ -349,14 +394,16 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     sig[threadIdx.x] = sqrt(s);
   }
   __syncthreads();
+  // descending order of the singular values (ties by index): thread j finds its place
+  if (threadIdx.x < qc) {
+    const int j = threadIdx.x;
+    const double sj = sig[j];
+    int pos = 0;
+    for (int b = 0; b < qc; ++b) pos += (sig[b] > sj || (sig[b] == sj && b < j)) ? 1 : 0;
+    order[pos] = j;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    for (int j = 0; j < qc; ++j) order[j] = j;
-    for (int a = 0; a < qc; ++a) {  // selection sort, stable for ties
-      int best = a;
-      for (int b = a + 1; b < qc; ++b)
-        if (sig[order[b]] > sig[order[best]]) best = b;
-      const int tmp = order[a]; order[a] = order[best]; order[best] = tmp;
-    }
     const double thr = fmax(tol / 3.0, 8.0 * (DBL_EPSILON * 0.5) * sig[order[0]]);
     int k = 0;
     while (k < qc && sig[order[k]] > thr) ++k;
@@ -371,8 +418,13 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
   const int kc = kcap[q.level];
   double* TU = tbuf + q.toff_u;
   double* TV = tbuf + q.toff_v;
-  // column c of U_X sqrt(s) and V_X sqrt(s) for sorted index c
-  for (int idx = threadIdx.x; idx < 2 * k; idx += NTHREADS) {
+  // column c of U_X sqrt(s) and V_X sqrt(s) for sorted index c: 8 lanes per column, lane gl
+  // holding the unknowns of pivot positions gl, gl + 8, ... in registers
+  constexpr int RPL = (PMAX + 7) / 8;
+  const int gq = threadIdx.x >> 3, gl = threadIdx.x & 7;
+  for (int idx0 = 0; idx0 < 2 * k; idx0 += NTHREADS / 8) {
+    const int idx = idx0 + gq;
+    if (idx >= 2 * k) break;  // uniform over the 8 lanes of a column
     const int c = idx % k, side = idx / k;
     const int j = order[c];
     const double sj = sig[j], rs = sqrt(sj);
@@ -384,11 +436,28 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     // no transpose: U_X = M[:,j]/s_j (length pI), V_X = Q[:,j] (length pJ)
     // transpose   : U_X = Q[:,j] (length pI),   V_X = M[:,j]/s_j (length pJ)
     const bool fromM = (side == 0) != trans;
-    for (int a = p - 1; a >= 0; --a) {
-      if (a >= rkp) { out[pv[a]] = 0.0; continue; }
-      double acc = fromM ? Cm[a + j * ld] / sj * rs : Vm[a + j * ld] * rs;
-      for (int b = a + 1; b < rkp; ++b) acc -= F[pv[b] + a * ld] * out[pv[b]];
-      out[pv[a]] = acc / F[pv[a] + a * ld];
+    double sol[RPL];
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) sol[t] = 0.0;
+    for (int a = rkp - 1; a >= 0; --a) {
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int b = gl + 8 * t;
+        if (b > a && b < rkp) part += F[pv[b] + a * ld] * sol[t];
+      }
+      for (int o = 4; o > 0; o >>= 1) part += __shfl_xor(part, o, 8);
+      const double rhs = fromM ? Cm[a + j * ld] / sj * rs : Vm[a + j * ld] * rs;
+      const double val = (rhs - part) / F[pv[a] + a * ld];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (gl + 8 * t == a) sol[t] = val;
+    }
+    // unknowns at or beyond the rank stay zero
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int b = gl + 8 * t;
+      if (b < p) out[pv[b]] = sol[t];
     }
   }
   (void)kc;

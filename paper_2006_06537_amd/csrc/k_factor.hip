@@ -538,15 +538,6 @@ __device__ __forceinline__ JRot jacobi_rot(double app, double aqq, double apq) {
   return r;
 }
 
-// index at position j of the round-robin schedule after `off` steps (positions 1..me-1
-// rotate, position 0 stays)
-__device__ __forceinline__ int rr_index(int j, int off, int me) {
-  if (j == 0) return 0;
-  int v = j - 1 + off;
-  if (v >= me - 1) v -= me - 1;
-  return 1 + v;
-}
-
 __device__ bool lds_sym_eig(double* A, double* E, double* T, int m, int lda) {
   const int lane = threadIdx.x & 63;
   const int me = m + (m & 1);
