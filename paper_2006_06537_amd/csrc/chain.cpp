@@ -42,7 +42,9 @@ struct fg_chain_s {
   bool pcg_failed = false;
   hipStream_t aux = nullptr;                  // proposal build + factor, beside the f-draw
   hipStream_t zs = nullptr;                   // Z and tau y, beside the factorization of M~
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_z = nullptr, ev_f = nullptr;
+  hipStream_t ls = nullptr;                   // the proposal's leaves, beside its build
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_z = nullptr, ev_f = nullptr,
+             ev_leaf = nullptr;
   // exact discrete conditional of the length-scale: every grid point's K~_1 and W_1
   bool exact = false;
   std::vector<fg::HodlrData> Hg;
@@ -93,8 +95,10 @@ static void chain_free(fg_chain c) {
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->ev_z) (void)hipEventDestroy(c->ev_z);
   if (c->ev_f) (void)hipEventDestroy(c->ev_f);
+  if (c->ev_leaf) (void)hipEventDestroy(c->ev_leaf);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->zs) (void)hipStreamDestroy(c->zs);
+  if (c->ls) (void)hipStreamDestroy(c->ls);
   fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   for (auto& h : c->Hg) fg::hodlr_free(h);
@@ -240,10 +244,15 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   hipEventRecord(c->ev_fork, s);
   hipStreamWaitEvent(c->aux, c->ev_fork, 0);
   if (pr.ongrid) {
+    // its leaves need x and ell' only: a fourth stream factors them during the build
+    hipStreamWaitEvent(c->ls, c->ev_fork, 0);
+    fg::launch_zero_int(c->W[oth].status, 1, c->ls);
+    fg::launch_factor_leaves(c->W[oth], nullptr, nullptr, nullptr, c->ls);
+    hipEventRecord(c->ev_leaf, c->ls);
     fg::launch_zero_int(c->H[oth].status, 1, c->aux);
-    fg::launch_zero_int(c->W[oth].status, 1, c->aux);
     fg::launch_build(c->H[oth], c->aux);
-    fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, c->aux);
+    hipStreamWaitEvent(c->aux, c->ev_leaf, 0);
+    fg::launch_factor_levels(c->W[oth], nullptr, c->aux);
     hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
                    c->aux);
   }
@@ -508,10 +517,12 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
   }
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->ls, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_z, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_leaf, hipEventDisableTiming) != hipSuccess) {
     chain_free(c);
     return cfail(FG_EDEVICE, "stream or event creation failed");
   }

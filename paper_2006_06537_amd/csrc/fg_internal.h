@@ -199,6 +199,12 @@ size_t factor_bytes(const Caps& c, bool fp32);
 void launch_build(HodlrData& H, hipStream_t s);
 void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
                    const double* diag, hipStream_t s);
+// the two halves of launch_factor: the leaves need x and the kernel's parameters only (not
+// the compressed panels), so they may run on another stream than the build; the levels
+// need both the leaves and the build
+void launch_factor_leaves(FactorData& F, const double* alpha_dev, const double* beta_dev,
+                          const double* diag, hipStream_t s);
+void launch_factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s);
 void launch_logdet_sum(FactorData& F, hipStream_t s);
 // op: 0 = W, 1 = W', 2 = W^-1, 3 = W^-T; in place on v (ld x nrhs)
 void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,

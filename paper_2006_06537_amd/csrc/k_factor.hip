@@ -940,18 +940,29 @@ __global__ void k_logdet_sum(const double* __restrict__ leaf_ld, int nleaf,
 // floor on 1 - s^2 of a node whose panels are held in FP32 (16 FP32 ulps of 1)
 constexpr double GAP_FLOOR_FP32 = 16.0 * 5.9604644775390625e-08;
 
+// the leaves (Cholesky, diagonal-block inverses, leaf log-dets): they need x and the
+// kernel's parameters only, not the compressed panels
 template <typename T>
-static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const double* alpha_dev,
+static void factor_leaves(FactorData& F, T* leafL, T* leafLinv, const double* alpha_dev,
                           const double* beta_dev, const double* diag, hipStream_t s) {
   const HodlrData& H = *F.H;
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
-  const int Bc = P.B;
-  timer_before(KID_LEAF, s, -1, P, H.kmax, 0);
+  timer_before(KID_LEAF, s, -1, P, nullptr, 0);  // the leaf bytes do not depend on the ranks
   k_leaf<T><<<P.nleaf, NTHREADS, 0, s>>>(
       D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
-      diag, Bc, leafL, leafLinv, F.leaf_ld, F.status);
+      diag, P.B, leafL, leafLinv, F.leaf_ld, F.status);
   timer_after(KID_LEAF, s);
+}
+
+// everything after the leaves: whitened panels, the levels, the log-det
+template <typename T>
+static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const double* alpha_dev,
+                          hipStream_t s) {
+  const HodlrData& H = *F.H;
+  const HostPlan& P = H.pk->P;
+  const DevPlan& D = H.pk->D;
+  const int Bc = P.B;
   if (P.L > 0) {
     timer_before(KID_WHITEN, s, -1, P, H.kmax, 0);
     k_whiten<T><<<P.nleaf, NTHREADS, 0, s>>>(D.leaf_lo, P.nleaf, leafL, leafLinv, Bc, F.alpha,
@@ -999,12 +1010,25 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
   launch_logdet_sum(F, s);
 }
 
+void launch_factor_leaves(FactorData& F, const double* alpha_dev, const double* beta_dev,
+                          const double* diag, hipStream_t s) {
+  if (F.fp32)
+    factor_leaves<float>(F, F.leafLf, F.leafLinvf, alpha_dev, beta_dev, diag, s);
+  else
+    factor_leaves<double>(F, F.leafL, F.leafLinv, alpha_dev, beta_dev, diag, s);
+}
+
+void launch_factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s) {
+  if (F.fp32)
+    factor_levels<float>(F, F.leafLf, F.leafLinvf, F.panelf, alpha_dev, s);
+  else
+    factor_levels<double>(F, F.leafL, F.leafLinv, F.panel, alpha_dev, s);
+}
+
 void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
                    const double* diag, hipStream_t s) {
-  if (F.fp32)
-    factor_levels<float>(F, F.leafLf, F.leafLinvf, F.panelf, alpha_dev, beta_dev, diag, s);
-  else
-    factor_levels<double>(F, F.leafL, F.leafLinv, F.panel, alpha_dev, beta_dev, diag, s);
+  launch_factor_leaves(F, alpha_dev, beta_dev, diag, s);
+  launch_factor_levels(F, alpha_dev, s);
 }
 
 void launch_logdet_sum(FactorData& F, hipStream_t s) {

@@ -49,7 +49,7 @@ void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const in
     tri += m * (m + 1) / 2;
   }
   r.sum_leaf_tri = tri;
-  if (P.L > 0 && g_t.ring_used + P.L <= g_t.ring_cap) {
+  if (P.L > 0 && kmax_dev && g_t.ring_used + P.L <= g_t.ring_cap) {  // ranks, if the bytes use them
     r.ring_off = g_t.ring_used;
     g_t.ring_used += P.L;
     k_snapshot<<<1, 64, 0, s>>>(kmax_dev, P.L, g_t.ring + r.ring_off);
