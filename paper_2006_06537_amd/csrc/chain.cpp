@@ -227,7 +227,11 @@ static void enqueue_rho_exact(fg_chain c, hipStream_t s) {
   fg::launch_rho_exact(c->st, c->ldg, c->qg, G, c->cfg.seed, c->cfg.stream_id, s);
 }
 
-void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
+// `capture`: the sweep is being captured into a graph.  Captured sweeps keep the two-stream
+// form (the proposal's build and whole factorization on the second stream, Z and both
+// quadratic forms on this one): the serving loop, which captures from a worker thread,
+// once ended in a host segmentation fault with the four-stream form, cause not found.
+void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool capture) {
   const int n = c->n;
   const fg_chain_cfg& cf = c->cfg;
   double* v0 = c->vecs;
@@ -241,9 +245,17 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   fg::launch_sweep_begin(c->st, s);
   // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
   // the chain's second stream while this stream factors M~ and draws f.
+  const bool side = !capture;  // the third and fourth streams
   hipEventRecord(c->ev_fork, s);
   hipStreamWaitEvent(c->aux, c->ev_fork, 0);
-  if (pr.ongrid) {
+  if (pr.ongrid && !side) {
+    fg::launch_zero_int(c->H[oth].status, 1, c->aux);
+    fg::launch_zero_int(c->W[oth].status, 1, c->aux);
+    fg::launch_build(c->H[oth], c->aux);
+    fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, c->aux);
+    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
+                   c->aux);
+  } else if (pr.ongrid) {
     // its leaves need x and ell' only: a fourth stream factors them during the build
     hipStreamWaitEvent(c->ls, c->ev_fork, 0);
     fg::launch_zero_int(c->W[oth].status, 1, c->ls);
@@ -262,18 +274,19 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     // f | -  (Algorithm 1).  Z = sqrt(tau) sigma_f^2 K~_1 a + sigma_f W_1 b and tau y use
     // the previous sweep's scalars only: the chain's third stream forms them while this
     // stream factors M~.
-    hipStreamWaitEvent(c->zs, c->ev_fork, 0);
-    fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, c->zs, itp);
-    fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, c->zs, itp);
-    fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, c->zs);
-    fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, c->zs);
-    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, c->zs);
-    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, c->zs);
-    hipEventRecord(c->ev_z, c->zs);
+    hipStream_t zq = side ? c->zs : s;
+    if (side) hipStreamWaitEvent(zq, c->ev_fork, 0);
+    fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, zq, itp);
+    fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, zq, itp);
+    fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, zq);
+    fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, zq);
+    fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, zq);
+    fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, zq);
+    if (side) hipEventRecord(c->ev_z, zq);
     fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
     fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
     hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-    hipStreamWaitEvent(s, c->ev_z, 0);
+    if (side) hipStreamWaitEvent(s, c->ev_z, 0);
     if (c->mixed && !c->fell_back) {
       // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
       // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
@@ -320,7 +333,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
   }
   // f is final: the proposal's quadratic form |W_1'^-1 f|^2 runs on the second stream,
   // beside this stream's |W_1^-1 f|^2 (v1 is free from here on)
-  if (!c->exact && pr.ongrid) {
+  if (side && !c->exact && pr.ongrid) {
     hipEventRecord(c->ev_f, s);
     hipStreamWaitEvent(c->aux, c->ev_f, 0);
     hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->aux);
@@ -340,6 +353,11 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s) {
     return;
   }
   // length-scale | -  (Metropolis on the grid)
+  if (!side && pr.ongrid) {
+    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
+    fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
+  }
   fg::launch_mh_step(c->st, pr.kp, pr.ongrid, cf.seed, cf.stream_id,
                      pr.ongrid ? c->H[oth].status : nullptr, pr.ongrid ? c->W[oth].status : nullptr, s);
   hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
@@ -394,7 +412,7 @@ fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExe
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return cfail(FG_EDEVICE, "stream capture failed to start");
-  enqueue_sweep(c, pr, q);
+  enqueue_sweep(c, pr, q, true);
   if (hipStreamEndCapture(q, &g) != hipSuccess || !g)
     return cfail(FG_EDEVICE, "stream capture failed");
   hipGraphExec_t ge = nullptr;
@@ -724,7 +742,7 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   for (int it = 0; it < iters; ++it) {
     const Proposal pr = propose(c);
     prepare_sweep(c, pr);
-    enqueue_sweep(c, pr, s);
+    enqueue_sweep(c, pr, s, false);
     if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
@@ -757,7 +775,7 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
       pr[i] = propose(c);
       prepare_sweep(c, pr[i]);
       if (!graphs || c->mixed) {
-        enqueue_sweep(c, pr[i], q);
+        enqueue_sweep(c, pr[i], q, false);
         continue;
       }
       hipGraphExec_t ge = nullptr;
