@@ -227,11 +227,14 @@ static void enqueue_rho_exact(fg_chain c, hipStream_t s) {
   fg::launch_rho_exact(c->st, c->ldg, c->qg, G, c->cfg.seed, c->cfg.stream_id, s);
 }
 
-// `capture`: the sweep is being captured into a graph.  Captured sweeps keep the two-stream
-// form (the proposal's build and whole factorization on the second stream, Z and both
-// quadratic forms on this one): the serving loop, which captures from a worker thread,
-// once ended in a host segmentation fault with the four-stream form, cause not found.
-void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool capture) {
+// `side`: Z and tau y on the chain's third stream, the proposal's leaves on its fourth and
+// the proposal's quadratic form on the second, which helps a chain that has the GPU to
+// itself.  Without it (batches of chains, which fill the GPU by themselves, and captured
+// sweeps) the sweep keeps the two-stream form: the proposal's build and whole
+// factorization on the second stream, Z and both quadratic forms on this one.  (The
+// serving loop, which captures from a worker thread, once ended in a host segmentation
+// fault with the four-stream form; the cause was not found.)  The arithmetic is the same.
+void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   const int n = c->n;
   const fg_chain_cfg& cf = c->cfg;
   double* v0 = c->vecs;
@@ -245,7 +248,6 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool capture) 
   fg::launch_sweep_begin(c->st, s);
   // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
   // the chain's second stream while this stream factors M~ and draws f.
-  const bool side = !capture;  // the third and fourth streams
   hipEventRecord(c->ev_fork, s);
   hipStreamWaitEvent(c->aux, c->ev_fork, 0);
   if (pr.ongrid && !side) {
@@ -412,7 +414,7 @@ fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExe
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return cfail(FG_EDEVICE, "stream capture failed to start");
-  enqueue_sweep(c, pr, q, true);
+  enqueue_sweep(c, pr, q, false);
   if (hipStreamEndCapture(q, &g) != hipSuccess || !g)
     return cfail(FG_EDEVICE, "stream capture failed");
   hipGraphExec_t ge = nullptr;
@@ -742,7 +744,7 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   for (int it = 0; it < iters; ++it) {
     const Proposal pr = propose(c);
     prepare_sweep(c, pr);
-    enqueue_sweep(c, pr, s, false);
+    enqueue_sweep(c, pr, s, true);
     if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
