@@ -265,17 +265,29 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     hipEventRecord(c->ev_leaf, c->ls);
     fg::launch_zero_int(c->H[oth].status, 1, c->aux);
     fg::launch_build(c->H[oth], c->aux);
+  }
+  // the rest of the proposal's factorization, once its build and leaves are done; it is
+  // enqueued after this stream's factorization of M~ and Z (one host thread enqueues every
+  // stream, and those are needed first), but before them on collapsed data
+  bool proposal_levels = side && pr.ongrid;
+  auto enqueue_proposal_levels = [&]() {
+    if (!proposal_levels) return;
+    proposal_levels = false;
     hipStreamWaitEvent(c->aux, c->ev_leaf, 0);
     fg::launch_factor_levels(c->W[oth], nullptr, c->aux);
     hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
                    c->aux);
-  }
+  };
   if (c->collapsed) {
+    enqueue_proposal_levels();
     enqueue_f_tau_collapsed(c, s);
   } else {
     // f | -  (Algorithm 1).  Z = sqrt(tau) sigma_f^2 K~_1 a + sigma_f W_1 b and tau y use
     // the previous sweep's scalars only: the chain's third stream forms them while this
     // stream factors M~.
+    fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
+    fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
+    hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
     hipStream_t zq = side ? c->zs : s;
     if (side) hipStreamWaitEvent(zq, c->ev_fork, 0);
     fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, zq, itp);
@@ -284,11 +296,11 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     fg::launch_apply_w(W1, 0, v1, 1, n, W1.work, zq);
     fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, zq);
     fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, zq);
-    if (side) hipEventRecord(c->ev_z, zq);
-    fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
-    fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
-    hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-    if (side) hipStreamWaitEvent(s, c->ev_z, 0);
+    if (side) {
+      hipEventRecord(c->ev_z, zq);
+      enqueue_proposal_levels();
+      hipStreamWaitEvent(s, c->ev_z, 0);
+    }
     if (c->mixed && !c->fell_back) {
       // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
       // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
