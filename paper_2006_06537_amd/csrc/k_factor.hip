@@ -37,7 +37,17 @@ __device__ __forceinline__ double wsum(double v) {
 // ---------------------------------------------------------------------------------
 constexpr int LG = 16;        // thread grid side
 constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
-constexpr int LPD = 17;       // LDS pitch of 16-wide rows
+constexpr int LPD = 18;       // LDS pitch of 16-wide rows: even, so that entries (t, t + 1)
+                              // of a row are one aligned pair, and 16 rows fall in distinct banks
+
+// entries t, t + 1 (t even) of an LDS row, in one read
+template <typename T> struct PairOf;
+template <> struct PairOf<double> { typedef double2 type; };
+template <> struct PairOf<float> { typedef float2 type; };
+template <typename T>
+__device__ __forceinline__ typename PairOf<T>::type lds_pair(const T* p) {
+  return *reinterpret_cast<const typename PairOf<T>::type*>(p);
+}
 
 // LDS ordering between the lanes of one wave (no work-group barrier: only the factoring
 // wave runs diag_factor16)
@@ -128,11 +138,11 @@ __global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
   // LDS: Likk (the current diagonal block's inverse) | Lk | Dk | Lp 128 rows | Pp 128 rows
   // (42 KB in FP64: three work-groups per CU)
   __shared__ double xs[BMAX];
-  __shared__ T Likk[16 * LPD];
-  __shared__ T Lk[16 * LPD];
-  __shared__ T Dk[16 * LPD];
-  __shared__ T Lp[BMAX * LPD];
-  __shared__ T Pp[BMAX * LPD];
+  __shared__ __align__(16) T Likk[16 * LPD];
+  __shared__ __align__(16) T Lk[16 * LPD];
+  __shared__ __align__(16) T Dk[16 * LPD];
+  __shared__ __align__(16) T Lp[BMAX * LPD];
+  __shared__ __align__(16) T Pp[BMAX * LPD];
   T* Lig = leafLinv + (size_t)b * Bc * Bc;
   __shared__ int bad;
   __shared__ double ldsum;
@@ -191,7 +201,12 @@ __global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
         // L[i][kb] = A[i][kb] L_kk^-T : row (16 i + tr) of the panel times column tc of Li'
         T s = T(0);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s += Pp[(LG * i + tr) * LPD + t] * Li[tc * LPD + t];
+        for (int t = 0; t < 16; t += 2) {
+          const auto pv = lds_pair(Pp + (LG * i + tr) * LPD + t);
+          const auto lv = lds_pair(Li + tc * LPD + t);
+          s += pv.x * lv.x;
+          s += pv.y * lv.y;
+        }
 #pragma unroll
         for (int jj = 0; jj < i; ++jj)
           if (jj == kb) a[LT(i, jj)] = s;
@@ -200,19 +215,27 @@ __global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
     }
     __syncthreads();
 #pragma unroll 1
-    for (int t = 0; t < 16; ++t) {
-      T lr[LE], lc[LE];
+    for (int t = 0; t < 16; t += 2) {  // columns t and t + 1 of the panel, one read each
+      T lc0[LE], lc1[LE];
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
-        lr[i] = (i > kb && i < nb) ? L1[(LG * i + tr) * LPD + t] : T(0);
-        lc[i] = (i > kb && i < nb) ? L1[(LG * i + tc) * LPD + t] : T(0);
+        lc0[i] = lc1[i] = T(0);
+        if (i > kb && i < nb) {
+          const auto pc = lds_pair(L1 + (LG * i + tc) * LPD + t);
+          lc0[i] = pc.x;
+          lc1[i] = pc.y;
+        }
       }
 #pragma unroll
       for (int i = 0; i < LE; ++i) {
         if (i > kb && i < nb) {
+          const auto pr = lds_pair(L1 + (LG * i + tr) * LPD + t);
 #pragma unroll
           for (int jj = 0; jj <= i; ++jj)
-            if (jj > kb) a[LT(i, jj)] -= lr[i] * lc[jj];
+            if (jj > kb) {
+              a[LT(i, jj)] -= pr.x * lc0[jj];
+              a[LT(i, jj)] -= pr.y * lc1[jj];
+            }
         }
       }
     }
