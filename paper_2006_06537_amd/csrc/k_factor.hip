@@ -658,6 +658,118 @@ __device__ bool lds_sym_eig(double* A, double* E, double* T, int m, int lda) {
 }
 
 // ---------------------------------------------------------------------------------
+// the same eigen-decomposition for a work-group of 256 threads (lda even, >= m + 1 when m
+// is odd).  Same round-robin order, rotations and convergence test as lds_sym_eig; a step
+// is two phases: the owner thread of each pair computes its rotation once and publishes,
+// per index i, its partner i*, the row coefficients (alpha_i, beta_i) (row i of J'A is
+// alpha_i row_i + beta_i row_i*) and the signed t of the classical diagonal update; then
+// thread e updates entry e of A (into T, double-buffered) as
+//   (a1 a_ij + b1 a_i*j*) + (a2 a_ij* + b2 a_i*j),  products of coefficient pairs first,
+// which is the same expression for (i, j) and (j, i), so A stays exactly symmetric; and
+// thread (r, u) rotates row r of E's column pair u in place.
+// ---------------------------------------------------------------------------------
+__device__ bool lds_sym_eig256(double* A, double* E, double* T, int m, int lda) {
+  __shared__ int partner[PMAX + 2], pp[PMAX / 2 + 1], pq[PMAX / 2 + 1];
+  __shared__ double alp[PMAX + 2], bet[PMAX + 2], tsg[PMAX + 2];
+  __shared__ double red[4][2];
+  const int tid = threadIdx.x;
+  const int me = m + (m & 1);
+  for (int e = tid; e < me * me; e += blockDim.x) {
+    const int r = e % me, c = e / me;
+    E[r + c * lda] = (r == c) ? 1.0 : 0.0;
+    if (r == m || c == m) A[r + c * lda] = 0.0;  // padding (odd m)
+  }
+  __syncthreads();
+  if (m < 2) return true;
+  const int np = me >> 1;
+  double* cur = A;
+  double* nxt = T;
+  bool conv = false;
+  int roff = 0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int r = e % m, c = e / m;
+      const double v = cur[r + c * lda];
+      tot += v * v;
+      if (r != c) off += v * v;
+    }
+    off = wsum(off);
+    tot = wsum(tot);
+    if ((tid & 63) == 0) {
+      red[tid >> 6][0] = off;
+      red[tid >> 6][1] = tot;
+    }
+    __syncthreads();
+    const double o = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    const double t2 = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    const double lim = 4.0 * m * DBL_EPSILON;
+    if (o <= lim * lim * t2) {  // the same sums in every thread
+      conv = true;
+      break;
+    }
+#pragma unroll 1
+    for (int step = 0; step < me - 1; ++step) {
+      if (tid < np) {  // owner of pair tid
+        int p = rr_index(tid, roff, me), q = rr_index(me - 1 - tid, roff, me);
+        if (p > q) { const int x = p; p = q; q = x; }
+        const JRot ro = jacobi_rot(cur[p + p * lda], cur[q + q * lda], cur[p + q * lda]);
+        partner[p] = q;
+        partner[q] = p;
+        alp[p] = ro.c;
+        alp[q] = ro.c;
+        bet[p] = -ro.s;
+        bet[q] = ro.s;
+        tsg[p] = -ro.t;
+        tsg[q] = ro.t;
+        pp[tid] = p;
+        pq[tid] = q;
+      }
+      __syncthreads();
+      for (int e = tid; e < me * me; e += blockDim.x) {
+        const int i = e % me, j = e / me;
+        const int is = partner[i], js = partner[j];
+        double x;
+        if (i == j) {
+          x = cur[i + i * lda] + tsg[i] * cur[i + is * lda];
+        } else if (is == j) {
+          x = 0.0;
+        } else {
+          const double ai = alp[i], bi = bet[i], aj = alp[j], bj = bet[j];
+          const double w1 = __dmul_rn(__dmul_rn(ai, aj), cur[i + j * lda]);
+          const double w4 = __dmul_rn(__dmul_rn(bi, bj), cur[is + js * lda]);
+          const double w2 = __dmul_rn(__dmul_rn(ai, bj), cur[i + js * lda]);
+          const double w3 = __dmul_rn(__dmul_rn(bi, aj), cur[is + j * lda]);
+          x = __dadd_rn(__dadd_rn(w1, w4), __dadd_rn(w2, w3));
+        }
+        nxt[i + j * lda] = x;
+      }
+      for (int e = tid; e < me * np; e += blockDim.x) {
+        const int r = e % me, u = e / me;
+        const int p = pp[u], q = pq[u];
+        const double c = alp[p], sn = -bet[p];
+        const double ep = E[r + p * lda], eq = E[r + q * lda];
+        E[r + p * lda] = c * ep - sn * eq;
+        E[r + q * lda] = sn * ep + c * eq;
+      }
+      __syncthreads();
+      double* x = cur;
+      cur = nxt;
+      nxt = x;
+      if (++roff == me - 1) roff = 0;
+    }
+  }
+  if (cur != A) {
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int r = e % m, c = e / m;
+      A[r + c * lda] = cur[r + c * lda];
+    }
+    __syncthreads();
+  }
+  return conv;
+}
+
+// ---------------------------------------------------------------------------------
 // pivoted Cholesky of an m x m LDS Gram matrix G (symmetric positive semi-definite) by
 // one wave: Pi' G Pi = L L' with diagonal pivoting (largest remaining diagonal, first
 // index on ties), stopped at the first pivot at or below 64 m (u/2) max_i G_ii (Higham's
@@ -667,12 +779,15 @@ __device__ bool lds_sym_eig(double* A, double* E, double* T, int m, int lda) {
 // ---------------------------------------------------------------------------------
 __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
   const int lane = threadIdx.x & 63;
+  // in a work-group of several waves every wave takes the same decisions from the same
+  // reads, and wave 0 alone writes
+  const bool w0 = threadIdx.x < 64;
   const double d0 = lane < m ? G[lane + lane * lda] : 0.0;
   if (__ballot(d0 != d0) != 0) return -1;
   double dmax = d0;
   for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
   const double dfloor = 64.0 * m * (DBL_EPSILON * 0.5) * dmax;
-  if (lane < m) perm[lane] = lane;
+  if (w0 && lane < m) perm[lane] = lane;
   __syncthreads();
   int r = m;
   for (int j = 0; j < m; ++j) {
@@ -693,18 +808,18 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
     }
     const int piv = __builtin_amdgcn_readfirstlane(iv);
     if (piv != j) {  // symmetric interchange of rows and columns j and piv
-      if (lane < m) {
+      if (w0 && lane < m) {
         const double t = G[j + lane * lda];
         G[j + lane * lda] = G[piv + lane * lda];
         G[piv + lane * lda] = t;
       }
       __syncthreads();
-      if (lane < m) {
+      if (w0 && lane < m) {
         const double t = G[lane + j * lda];
         G[lane + j * lda] = G[lane + piv * lda];
         G[lane + piv * lda] = t;
       }
-      if (lane == 0) {
+      if (threadIdx.x == 0) {
         const int t = perm[j];
         perm[j] = perm[piv];
         perm[piv] = t;
@@ -713,19 +828,20 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
     }
     const double ljj = sqrt(G[j + j * lda]);
     double lij = 0.0;
-    if (lane > j && lane < m) {
+    if (w0 && lane > j && lane < m) {
       lij = G[lane + j * lda] / ljj;
       G[lane + j * lda] = lij;
     }
-    if (lane == j) G[j + j * lda] = ljj;
+    if (w0 && lane == j) G[j + j * lda] = ljj;
     __syncthreads();
-    if (lane > j && lane < m)
+    if (w0 && lane > j && lane < m)
       for (int c = j + 1; c < m; ++c) G[lane + c * lda] -= lij * G[c + j * lda];
     __syncthreads();
   }
   // S[b][perm[a]] = L[a][b] for b <= a, b < r
-  for (int a = lane; a < m; a += 64)
-    for (int b = 0; b < r; ++b) S[b + perm[a] * lda] = (b <= a) ? G[a + b * lda] : 0.0;
+  if (w0)
+    for (int a = lane; a < m; a += 64)
+      for (int b = 0; b < r; ++b) S[b + perm[a] * lda] = (b <= a) ? G[a + b * lda] : 0.0;
   __syncthreads();
   return r;
 }
@@ -734,7 +850,7 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
 // node factor of one level (factorization): Gram blocks -> (G_V, F1, F2), log-det
 // and the update coefficients of the coarser panels
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_node_factor(
+__global__ void __launch_bounds__(256) k_node_factor(
     int l, const int* __restrict__ rank, const int* __restrict__ kmax,
     const int* __restrict__ rcount, const int* __restrict__ node_task_off, int tbase,
     double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
@@ -797,7 +913,9 @@ __global__ void __launch_bounds__(64) k_node_factor(
     }
   }
   __syncthreads();
-  const bool ok = lds_sym_eig(Hm, E, GU, r, kc);  // GU is free until B
+  // GU is free until B; levels of larger rank run 4 waves per node
+  const bool ok = blockDim.x >= 256 ? lds_sym_eig256(Hm, E, GU, r, kc)
+                                    : lds_sym_eig(Hm, E, GU, r, kc);
   {
     // lane a: the coefficients of s_a^2 and its log(1 - s_a^2)
     double lg = 0.0;
@@ -1018,7 +1136,7 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
                   zs_task, s);
     const int kc = std::max(P.kcap[l], 1) + (std::max(P.kcap[l], 1) & 1);  // even pitch
     const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
-    k_node_factor<<<1 << l, 64, lds_node, s>>>(
+    k_node_factor<<<1 << l, kc > 8 ? 256 : 64, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
         kc, sizeof(T) == 4 ? GAP_FLOOR_FP32 : 0.0);
