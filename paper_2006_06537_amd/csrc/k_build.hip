@@ -263,6 +263,150 @@ __device__ bool lds_jacobi_svd(double* M, int mr, int qc, int ldm, double* Q, in
   return conv;
 }
 
+// One-sided Jacobi SVD preconditioned by a column-pivoted QR (Drmac and Veselic): with
+// M P = Q_h R (Householder, largest remaining column first) the Jacobi method runs on the
+// rows of R, R' W = G, which are graded and converge in a few sweeps where the columns
+// of M took twenty.  On return, as from lds_jacobi_svd, M holds U S (= Q_h W S, columns
+// orthogonal with norms s = |G_j|) and Q holds V with M = M_in V: V = P G S^-1 (a column
+// with s = 0 is set to zero; it is never used).  T is a scratch of qc x qc (leading
+// dimension ld).  Returns false if the Jacobi sweeps did not converge.
+__device__ bool lds_svd_qr(double* M, int mr, int qc, int ld, double* Q, double* T, double tol) {
+  __shared__ double tau[PMAX], nrm[PMAX], sg[PMAX];
+  __shared__ int perm[PMAX], piv_s;
+  const int tid = threadIdx.x;
+  const int g = tid >> 3, gl = tid & 7;  // 8 lanes per column
+  for (int j = tid; j < qc; j += NTHREADS) {
+    double s = 0.0;
+    for (int r = 0; r < mr; ++r) s += M[r + j * ld] * M[r + j * ld];
+    nrm[j] = s;
+    perm[j] = j;
+  }
+  __syncthreads();
+  for (int k = 0; k < qc; ++k) {
+    if (tid < 64) {  // pivot: the largest remaining column (first index on ties)
+      double v = (tid >= k && tid < qc) ? nrm[tid] : -1.0;
+      int iv = tid;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(v, o, 64);
+        const int i2 = __shfl_xor(iv, o, 64);
+        if (v2 > v || (v2 == v && i2 < iv)) {
+          v = v2;
+          iv = i2;
+        }
+      }
+      if (tid == 0) piv_s = iv;
+    }
+    __syncthreads();
+    const int piv = piv_s;
+    if (piv != k) {
+      for (int r = tid; r < mr; r += NTHREADS) {
+        const double x = M[r + k * ld];
+        M[r + k * ld] = M[r + piv * ld];
+        M[r + piv * ld] = x;
+      }
+      if (tid == 0) {
+        const double x = nrm[k]; nrm[k] = nrm[piv]; nrm[piv] = x;
+        const int i = perm[k]; perm[k] = perm[piv]; perm[piv] = i;
+      }
+      __syncthreads();
+    }
+    if (tid < 64) {  // Householder vector of column k, rows k.. (v_k = 1 implicit)
+      const int r = k + tid;
+      const double x = r < mr ? M[r + k * ld] : 0.0;
+      double s2 = x * x;
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+      const double x0 = __shfl(x, 0, 64);
+      const double al = sqrt(s2);
+      double beta = 0.0, t = 0.0, scale = 0.0;
+      if (al > 0.0) {
+        beta = x0 >= 0.0 ? -al : al;
+        t = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+      if (r < mr) M[r + k * ld] = (tid == 0) ? beta : x * scale;
+      if (tid == 0) tau[k] = t;
+    }
+    __syncthreads();
+    // H_k on the columns right of k, and their norms over the rows below k
+    const double tk = tau[k];
+    for (int j0 = k + 1; j0 < qc; j0 += NTHREADS / 8) {
+      const int j = j0 + g;
+      if (j >= qc) break;  // uniform over the 8 lanes of a column
+      double w = 0.0;
+      for (int r = k + gl; r < mr; r += 8) w += (r == k ? 1.0 : M[r + k * ld]) * M[r + j * ld];
+      for (int o = 4; o > 0; o >>= 1) w += __shfl_xor(w, o, 8);
+      double n2 = 0.0;
+      for (int r = k + gl; r < mr; r += 8) {
+        const double y = M[r + j * ld] - tk * w * (r == k ? 1.0 : M[r + k * ld]);
+        M[r + j * ld] = y;
+        if (r > k) n2 += y * y;
+      }
+      for (int o = 4; o > 0; o >>= 1) n2 += __shfl_xor(n2, o, 8);
+      if (gl == 0) nrm[j] = n2;
+    }
+    __syncthreads();
+  }
+  // R' (lower triangular) into T
+  for (int e = tid; e < qc * qc; e += NTHREADS) {
+    const int a = e % qc, b = e / qc;
+    T[a + b * ld] = (b <= a) ? M[b + a * ld] : 0.0;
+  }
+  __syncthreads();
+  // explicit Q_h (mr x qc) in place, last reflector first
+  for (int k = qc - 1; k >= 0; --k) {
+    const double tk = tau[k];
+    for (int j0 = k + 1; j0 < qc; j0 += NTHREADS / 8) {
+      const int j = j0 + g;
+      if (j >= qc) break;
+      double w = 0.0;
+      for (int r = k + gl; r < mr; r += 8) w += (r == k ? 1.0 : M[r + k * ld]) * M[r + j * ld];
+      for (int o = 4; o > 0; o >>= 1) w += __shfl_xor(w, o, 8);
+      for (int r = k + gl; r < mr; r += 8)
+        M[r + j * ld] -= tk * w * (r == k ? 1.0 : M[r + k * ld]);
+    }
+    __syncthreads();
+    for (int r = tid; r < mr; r += NTHREADS)
+      M[r + k * ld] = r < k ? 0.0 : (r == k ? 1.0 - tk : -tk * M[r + k * ld]);
+    __syncthreads();
+  }
+  // one-sided Jacobi on the rows of R, W accumulated in Q
+  const bool conv = lds_jacobi_svd(T, qc, qc, ld, Q, ld, tol);
+  for (int j = tid; j < qc; j += NTHREADS) {
+    double s = 0.0;
+    for (int a = 0; a < qc; ++a) s += T[a + j * ld] * T[a + j * ld];
+    sg[j] = sqrt(s);
+  }
+  __syncthreads();
+  // M <- Q_h W S (each thread's entries in registers until every read is done)
+  constexpr int EPT = (PMAX * PMAX + NTHREADS - 1) / NTHREADS;
+  double acc[EPT];
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) {
+    const int e = tid + t * NTHREADS;
+    acc[t] = 0.0;
+    if (e < mr * qc) {
+      const int r = e % mr, j = e / mr;
+      double s = 0.0;
+      for (int a = 0; a < qc; ++a) s += M[r + a * ld] * Q[a + j * ld];
+      acc[t] = s * sg[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < EPT; ++t) {
+    const int e = tid + t * NTHREADS;
+    if (e < mr * qc) M[e % mr + (e / mr) * ld] = acc[t];
+  }
+  // Q <- P G S^-1
+  __syncthreads();
+  for (int e = tid; e < qc * qc; e += NTHREADS) {
+    const int a = e % qc, j = e / qc;
+    Q[perm[a] + j * ld] = sg[j] > 0.0 ? T[a + j * ld] / sg[j] : 0.0;
+  }
+  __syncthreads();
+  return conv;
+}
+
 // ---------------------------------------------------------------------------------
 // compression: one work-group per internal node
 // ---------------------------------------------------------------------------------
@@ -385,7 +529,7 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     if (trans) Cm[t + r * ld] = acc; else Cm[r + t * ld] = acc;
   }
   __syncthreads();
-  const bool conv = lds_jacobi_svd(Cm, mr, qc, ld, Vm, ld, tol);
+  const bool conv = lds_svd_qr(Cm, mr, qc, ld, Vm, Tm, tol);
   if (!conv && threadIdx.x == 0) atomicOr(status, ST_NOTCONV);
   // singular values, descending order, rank
   if (threadIdx.x < qc) {
