@@ -15,7 +15,8 @@ constexpr int PMAX = 60;          // interpolation nodes per side (and rank cap)
 constexpr int BMAX = 128;         // maximum leaf size
 constexpr int NTHREADS = 256;     // work-group size of every kernel
 constexpr int RCH = 1024;         // rows per level-task (reduce / update)
-constexpr int MCH = 4096;         // rows per moment / panel-generation task
+constexpr int MCH = 4096;         // rows per panel-generation task
+constexpr int MCHM = 1024;        // rows per moment task (one wave)
 constexpr double KAPPA_H = 1.086435;  // Cramer: |H_n(x)| e^{-x^2/2} <= KAPPA_H 2^{n/2} sqrt(n!)
 
 // kernels selectable for live timing (same values as FG_KID_* in fifa_gp.h)

@@ -17,63 +17,83 @@
 
 namespace fg {
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+// ---------------------------------------------------------------------------------
+// moments: partial sums of T_m(t_i), m < 2p-1, over the rows of one task; one wave per
+// task, so that the many short tasks of the deep levels take no block barriers.  Each
+// lane keeps the three-term recurrence of its MRPT rows in registers across the chunks
+// of MB moments, so every T_m(t_i) is formed once; rows past the end of the task start
+// at zero and stay zero.  The wave reduces its MB sums by recursive halving: at the step
+// with lane offset o, the lanes with bit o set keep the upper half of their values and
+// the others the lower half, each adding its partner's copy of the half it keeps.
+// ---------------------------------------------------------------------------------
+constexpr int MRPT = MCHM / 64;  // rows per lane
+constexpr int MB = 16;           // moments per chunk
+static_assert(MRPT * 64 == MCHM, "a moment task must fit the lanes of one wave");
 
-// ---------------------------------------------------------------------------------
-// moments: partial sums of T_m(t_i), m < 2p-1, over the rows of one task
-// ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ tasks, int ntask,
                                                       const NodePlan* __restrict__ nodes,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ mpart, int stride) {
-  const int t = blockIdx.x;
-  if (t >= ntask) return;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (NTHREADS / 64) + (threadIdx.x >> 6);
+  if (t >= ntask) return;  // whole waves: no barrier below
   const Task tk = tasks[t];
   const NodePlan q = nodes[tk.h];
   const int p = tk.side ? q.pJ : q.pI;
   const double a = tk.side ? q.aJ : q.aI, b = tk.side ? q.bJ : q.bI;
   const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
   const int nm = 2 * p - 1;
-  __shared__ double red[NTHREADS / 64][32];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int mb = 0; mb < nm; mb += 32) {
-    double acc[32];
+  double t2[MRPT], tc[MRPT], tn[MRPT];  // 2 t, T_m(t), T_{m+1}(t)
 #pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
-    for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
-      const double tt = hw > 0.0 ? (x[r] - c) / hw : 0.0;
-      double tm2 = 1.0, tm1 = tt;  // T_0, T_1
-      // advance to T_mb
-      for (int m = 0; m < mb; ++m) {
-        const double tn = 2.0 * tt * tm1 - tm2;
-        tm2 = tm1;
-        tm1 = tn;
+  for (int k = 0; k < MRPT; ++k) {
+    const int r = tk.r0 + lane + k * 64;
+    const bool in = r < tk.r1;
+    const double tt = (in && hw > 0.0) ? (x[r] - c) / hw : 0.0;
+    t2[k] = 2.0 * tt;
+    tc[k] = in ? 1.0 : 0.0;
+    tn[k] = tt;
+  }
+  // rows per lane that the task reaches (wave-uniform): short tasks skip the rest
+  const int kn = (tk.r1 - tk.r0 + 63) / 64;
+  // the element of the chunk that this lane holds after the four halving steps
+  const int e = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+                ((lane >> 2) & 1);
+  double* out = mpart + (size_t)t * stride;
+  for (int mb = 0; mb < nm; mb += MB) {
+    double v[MB];
+#pragma unroll
+    for (int j = 0; j < MB; ++j) v[j] = 0.0;
+#pragma unroll
+    for (int g = 0; g < MRPT; g += 4) {
+      if (g < kn) {
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+#pragma unroll
+          for (int k = g; k < g + 4; ++k) {
+            v[j] += tc[k];
+            const double nx = t2[k] * tn[k] - tc[k];
+            tc[k] = tn[k];
+            tn[k] = nx;
+          }
+        }
       }
-      // now tm2 = T_mb, tm1 = T_{mb+1}
+    }
 #pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        acc[j] += tm2;
-        const double tn = 2.0 * tt * tm1 - tm2;
-        tm2 = tm1;
-        tm1 = tn;
+    for (int st = 0; st < 4; ++st) {
+      const int o = 32 >> st;
+      const int half = MB >> (st + 1);
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const double send = up ? v[i] : v[i + half];
+        const double keep = up ? v[i + half] : v[i];
+        v[i] = keep + __shfl_xor(send, o, 64);
       }
     }
-#pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = wave_sum(acc[j]);
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < 32; ++j) red[wv][j] = acc[j];
-    }
-    __syncthreads();
-    if (threadIdx.x < 32 && mb + threadIdx.x < nm) {
-      double s = 0.0;
-      for (int w = 0; w < NTHREADS / 64; ++w) s += red[w][threadIdx.x];
-      mpart[(size_t)t * stride + mb + threadIdx.x] = s;
-    }
-    __syncthreads();
+    double sum = v[0];
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 1, 64);
+    if ((lane & 3) == 0 && mb + e < nm) out[mb + e] = sum;
   }
 }
 
@@ -721,7 +741,8 @@ void launch_build(HodlrData& H, hipStream_t s) {
   if (P.L == 0) return;
   const int nm = P.nmt;
   if (nm > 0)
-    k_moments<<<nm, NTHREADS, 0, s>>>(D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
+    k_moments<<<(nm + NTHREADS / 64 - 1) / (NTHREADS / 64), NTHREADS, 0, s>>>(
+        D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
   const int pm = std::max(P.pmax, 1);
   const size_t lds = sizeof(double) * 5 * pm * pm;
   static bool lds_set = false;  // raised once to the largest size any plan can ask for

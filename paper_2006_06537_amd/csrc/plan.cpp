@@ -154,9 +154,9 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
   for (int h = 0; h < P.nint; ++h) {
     const NodePlan& q = P.nodes[h];
     P.mtask_off[2 * h] = int(P.mtasks.size());
-    if (q.pI > 0 && !q.exactI) chunk(P.mtasks, h, 0, q.i0, q.mid, MCH);
+    if (q.pI > 0 && !q.exactI) chunk(P.mtasks, h, 0, q.i0, q.mid, MCHM);
     P.mtask_off[2 * h + 1] = int(P.mtasks.size());
-    if (q.pJ > 0 && !q.exactJ) chunk(P.mtasks, h, 1, q.mid, q.j1, MCH);
+    if (q.pJ > 0 && !q.exactJ) chunk(P.mtasks, h, 1, q.mid, q.j1, MCHM);
   }
   P.mtask_off[2 * P.nint] = int(P.mtasks.size());
   P.mpart_stride = 2 * PMAX;
