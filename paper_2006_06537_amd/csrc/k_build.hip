@@ -673,8 +673,19 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
   const double a = tk.side ? q.aJ : q.aI, b = tk.side ? q.bJ : q.bI;
   const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
   const double* T = tbuf + (tk.side ? q.toff_v : q.toff_u);
-  __shared__ double Ts[PMAX * PMAX];
-  for (int idx = threadIdx.x; idx < p * k; idx += NTHREADS) Ts[idx] = T[idx];
+  // exact windows: T as stored (column cc at cc * p); interpolated windows: T transposed,
+  // row m at m * kp, zero-padded to kp columns so that a chunk of PCB columns needs no guard
+  constexpr int PCB = 8;
+  __shared__ __align__(16) double Ts[PMAX * ((PMAX + PCB - 1) / PCB * PCB)];
+  const int kp = (k + PCB - 1) / PCB * PCB;
+  if (exact) {
+    for (int idx = threadIdx.x; idx < p * k; idx += NTHREADS) Ts[idx] = T[idx];
+  } else {
+    for (int idx = threadIdx.x; idx < p * kp; idx += NTHREADS) {
+      const int m = idx / kp, cc = idx - m * kp;
+      Ts[idx] = cc < k ? T[cc * p + m] : 0.0;
+    }
+  }
   __syncthreads();
   const int cb = coff[l];
   for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
@@ -687,17 +698,29 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
       const int e = r - w0;
       for (int cc = 0; cc < k; ++cc) panel[pix(r, cb + cc, K)] = Ts[cc * p + e];
     } else {
+      // the recurrence T_m(t) runs once per chunk of PCB columns; each column sums its
+      // terms in the order m = 0, 1, ..., p-1
       const double tt = hw > 0.0 ? (x[r] - c) / hw : 0.0;
-      for (int cc = 0; cc < k; ++cc) {
-        double tm2 = 1.0, tm1 = tt, acc = Ts[cc * p];
-        if (p > 1) acc += tt * Ts[cc * p + 1];
+      for (int c0 = 0; c0 < k; c0 += PCB) {
+        double acc[PCB];
+#pragma unroll
+        for (int j = 0; j < PCB; ++j) acc[j] = Ts[c0 + j];
+        if (p > 1) {
+#pragma unroll
+          for (int j = 0; j < PCB; ++j) acc[j] += tt * Ts[kp + c0 + j];
+        }
+        double tm2 = 1.0, tm1 = tt;
         for (int m = 2; m < p; ++m) {
           const double tn = 2.0 * tt * tm1 - tm2;
-          acc += tn * Ts[cc * p + m];
+          const double* row = Ts + m * kp + c0;
+#pragma unroll
+          for (int j = 0; j < PCB; ++j) acc[j] += tn * row[j];
           tm2 = tm1;
           tm1 = tn;
         }
-        panel[pix(r, cb + cc, K)] = acc;
+#pragma unroll
+        for (int j = 0; j < PCB; ++j)
+          if (c0 + j < k) panel[pix(r, cb + c0 + j, K)] = acc[j];
       }
     }
     for (int cc = k; cc < kl; ++cc) panel[pix(r, cb + cc, K)] = 0.0;
