@@ -630,26 +630,41 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
 // ---------------------------------------------------------------------------------
 // per-level maximum rank and the right-column lists used by the factorization
 // ---------------------------------------------------------------------------------
-__global__ void k_rank_levels(const int* __restrict__ rank, int L, const int* __restrict__ coff,
-                              int Ktot, int* __restrict__ kmax, int* __restrict__ rcols,
-                              int* __restrict__ rcount) {
+constexpr int RL_THREADS = 1024;
+__global__ void __launch_bounds__(RL_THREADS) k_rank_levels(
+    const int* __restrict__ rank, int L, const int* __restrict__ coff, int Ktot,
+    int* __restrict__ kmax, int* __restrict__ rcols, int* __restrict__ rcount) {
   if (blockIdx.x != 0) return;
   __shared__ int km[32];
-  if (threadIdx.x < L) {
-    const int l = threadIdx.x;
-    int m = 0;
-    for (int h = (1 << l) - 1; h < (2 << l) - 1; ++h) m = max(m, rank[h]);
-    km[l] = m;
-    kmax[l] = m;
-  }
+  if (threadIdx.x < 32) km[threadIdx.x] = 0;
+  __syncthreads();
+  // heap node h sits on level floor(log2(h + 1)); the tree is complete, 2^L - 1 nodes
+  const int nint = (1 << L) - 1;
+  for (int h = threadIdx.x; h < nint; h += RL_THREADS) atomicMax(&km[31 - __clz(h + 1)], rank[h]);
   __syncthreads();
   if (threadIdx.x < L) {
     const int l = threadIdx.x;
-    int c = 0;
-    for (int a = 0; a < km[l]; ++a) rcols[l * Ktot + c++] = coff[l] + a;
-    for (int lp = 0; lp < l; ++lp)
-      for (int a = 0; a < km[lp]; ++a) rcols[l * Ktot + c++] = coff[lp] + a;
+    kmax[l] = km[l];
+    int c = km[l];
+    for (int lp = 0; lp < l; ++lp) c += km[lp];
     rcount[l] = c;
+  }
+  // right-column list of level l: its own km[l] columns, then those of levels 0 .. l-1
+  for (int idx = threadIdx.x; idx < L * Ktot; idx += RL_THREADS) {
+    const int l = idx / Ktot;
+    int rem = idx - l * Ktot;
+    if (rem < km[l]) {
+      rcols[idx] = coff[l] + rem;
+      continue;
+    }
+    rem -= km[l];
+    for (int lp = 0; lp < l; ++lp) {
+      if (rem < km[lp]) {
+        rcols[idx] = coff[lp] + rem;
+        break;
+      }
+      rem -= km[lp];
+    }
   }
 }
 
@@ -778,7 +793,7 @@ void launch_build(HodlrData& H, hipStream_t s) {
   k_compress<<<P.nint, NTHREADS, lds, s>>>(D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart,
                                            P.mpart_stride, D.mtask_off, D.kcap, H.tbuf, H.sv,
                                            H.rank, H.status, pm);
-  k_rank_levels<<<1, 64, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
+  k_rank_levels<<<1, RL_THREADS, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
   const int ng = P.ngt;
   k_panel_gen<<<ng, NTHREADS, 0, s>>>(D.gtasks, ng, D.nodes, H.x, H.tbuf, H.rank, H.kmax,
                                       D.coff, H.panel, P.Ktot);
