@@ -449,9 +449,20 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
     if (k == 0) continue;
     const int side = (b >> (L - l - 1)) & 1;
     const double* cf = coef + (size_t)h * cs_node + side * PMAX * NRHS_MAX;
-    const int cb = coff[l];
-    for (int a = 0; a < k; ++a) {
-      const double pv = P[pix(i, cb + a, K)];
+    // column cb + a of row i lies a * 16 words after column cb; eight loads are issued
+    // before their products so that a wave keeps several in flight
+    const double* Pc = P + pix(i, coff[l], K);
+    int a = 0;
+    for (; a + 8 <= k; a += 8) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = Pc[(size_t)(a + u) * 16];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        for (int c = 0; c < nrhs; ++c) acc[c] += pv[u] * cf[(a + u) * nrhs + c];
+    }
+    for (; a < k; ++a) {
+      const double pv = Pc[(size_t)a * 16];
       for (int c = 0; c < nrhs; ++c) acc[c] += pv * cf[a * nrhs + c];
     }
   }
