@@ -223,9 +223,10 @@ void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, i
 void launch_dot(const double* a, const double* b, int n, int mode, double* out, double* work,
                 hipStream_t s);
 // Sums the task partials of every node side with more than one task; a side with one
-// task is left to its consumer, which reads that task's partial in place.
+// task is left to its consumer, which reads that task's partial in place.  max_tasks
+// bounds the tasks of any one side (the plan's per-level maximum).
 void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
-                 int nsides, int esz, double* zfin, int zf_side, hipStream_t s);
+                 int nsides, int esz, double* zfin, int zf_side, int max_tasks, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,
                   const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
 // non-unique inputs: sum w (a - b)^2, out = x / *den, and the averages' precisions

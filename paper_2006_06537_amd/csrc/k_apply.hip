@@ -505,7 +505,8 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
   double* zs = nullptr;
   if (P.max_tps[l] > 1) {
     zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
-    launch_zsum(zpart, zs_task, tb, D.node_task_off, hbase, 2 << l, zs_task, zs, zs_task, s);
+    launch_zsum(zpart, zs_task, tb, D.node_task_off, hbase, 2 << l, zs_task, zs, zs_task,
+                P.max_tps[l], s);
   }
   k_node_coef<<<1 << l, 64, 0, s>>>(op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart,
                                     zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr, coef,
@@ -570,7 +571,8 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
     rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel, P.Ktot, v,
                                nrhs, ld, zpart, zs_task);
     double* zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
-    launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task, s);
+    launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task,
+                *std::max_element(P.max_tps.begin(), P.max_tps.end()), s);
     k_node_coef<<<P.nint, 64, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart, zs_task,
                                       nrhs, nullptr, nullptr, alpha, alpha_dev, coef, cs_node, zs);
   }

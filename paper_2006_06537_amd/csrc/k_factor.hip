@@ -511,9 +511,20 @@ __global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zp
   if (t1 - t0 <= 1) return;
   const int e = blockIdx.y * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   __shared__ double red[4][64];
+  // group g sums tasks t0 + g, t0 + g + 4, ... in that order; eight loads are issued
+  // before their additions, so a long side does not wait on one load at a time
   double s = 0.0;
-  if (e < esz)
-    for (int t = t0 + g; t < t1; t += 4) s += zpart[(size_t)t * zs_task + e];
+  if (e < esz) {
+    int t = t0 + g;
+    for (; t + 28 < t1; t += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = zpart[(size_t)(t + 4 * u) * zs_task + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; t < t1; t += 4) s += zpart[(size_t)t * zs_task + e];
+  }
   red[g][threadIdx.x & 63] = s;
   __syncthreads();
   if (g == 0 && e < esz)
@@ -521,9 +532,37 @@ __global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zp
         (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
+// sides of at most four tasks: one element per thread, summed as (z0 + z1) + (z2 + z3),
+// the value k_zsum's four groups give, so that both kernels agree to the bit
+__global__ void __launch_bounds__(NTHREADS) k_zsum_few(const double* __restrict__ zpart,
+                                                       int zs_task, int tbase,
+                                                       const int* __restrict__ node_task_off,
+                                                       int hbase, int nsides, int esz,
+                                                       double* __restrict__ zfin, int zf_side) {
+  const int sd = blockIdx.x;
+  if (sd >= nsides) return;
+  const int h = hbase + (sd >> 1), side = sd & 1;
+  const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
+  const int nt = t1 - t0;
+  const int e = blockIdx.y * NTHREADS + threadIdx.x;
+  if (nt <= 1 || e >= esz) return;
+  const double* z = zpart + (size_t)t0 * zs_task + e;
+  const double a = z[0] + z[zs_task];
+  double b = 0.0;
+  if (nt > 2) b = z[2 * (size_t)zs_task];
+  if (nt > 3) b += z[3 * (size_t)zs_task];
+  zfin[(size_t)sd * zf_side + e] = a + b;
+}
+
 void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
-                 int nsides, int esz, double* zfin, int zf_side, hipStream_t s) {
+                 int nsides, int esz, double* zfin, int zf_side, int max_tasks, hipStream_t s) {
   if (nsides <= 0 || esz <= 0) return;
+  if (max_tasks <= 4) {
+    const dim3 grid(nsides, (esz + NTHREADS - 1) / NTHREADS);
+    k_zsum_few<<<grid, NTHREADS, 0, s>>>(zpart, zs_task, tbase, node_task_off, hbase, nsides, esz,
+                                         zfin, zf_side);
+    return;
+  }
   const dim3 grid(nsides, (esz + 63) / 64);
   k_zsum<<<grid, NTHREADS, 0, s>>>(zpart, zs_task, tbase, node_task_off, hbase, nsides, esz, zfin,
                                    zf_side);
@@ -1133,7 +1172,7 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
     if (P.max_tps[l] > 1)
       launch_zsum(F.zpart, zs_task, tb, D.node_task_off, (1 << l) - 1, 2 << l, zs_task, F.zfin,
-                  zs_task, s);
+                  zs_task, P.max_tps[l], s);
     const int kc = std::max(P.kcap[l], 1) + (std::max(P.kcap[l], 1) & 1);  // even pitch
     const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
     k_node_factor<<<1 << l, kc > 8 ? 256 : 64, lds_node, s>>>(
