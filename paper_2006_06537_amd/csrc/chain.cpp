@@ -346,20 +346,22 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     fg::launch_tau_step(c->st, n, cf.a1, cf.b1, cf.seed, cf.stream_id, s);
   }
   // f is final: the proposal's quadratic form |W_1'^-1 f|^2 runs on the second stream,
-  // beside this stream's |W_1^-1 f|^2 (v1 is free from here on)
-  if (side && !c->exact && pr.ongrid) {
-    hipEventRecord(c->ev_f, s);
+  // beside this stream's |W_1^-1 f|^2 (v1 is free from here on).  This stream's part is
+  // enqueued first: it is the longer one, and one host thread enqueues both.
+  const bool qprop_side = side && !c->exact && pr.ongrid;
+  if (qprop_side) hipEventRecord(c->ev_f, s);
+  // sigma_f^-2 | -
+  hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  fg::launch_apply_w(W1, 2, v0, 1, n, W1.work, s);
+  fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
+  fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
+  if (qprop_side) {
     hipStreamWaitEvent(c->aux, c->ev_f, 0);
     hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->aux);
     fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, c->aux);
     fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork + 2048, c->aux);
   }
   hipEventRecord(c->ev_join, c->aux);
-  // sigma_f^-2 | -
-  hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-  fg::launch_apply_w(W1, 2, v0, 1, n, W1.work, s);
-  fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
-  fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
   hipStreamWaitEvent(s, c->ev_join, 0);
   if (c->exact) {  // length-scale | -  (exact, over the whole grid)
     enqueue_rho_exact(c, s);
