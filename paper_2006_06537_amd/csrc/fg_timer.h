@@ -12,4 +12,7 @@ void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const in
 void timer_after(int kid, hipStream_t s);
 // for a kernel whose algorithmic bytes are known at launch
 void timer_before_bytes(int kid, hipStream_t s, double bytes);
+// the ranks behind kmax_dev are about to change (a build) or the buffer is being freed:
+// the next timed launch that reads them takes a new snapshot
+void timer_forget(const int* kmax_dev);
 }  // namespace fg

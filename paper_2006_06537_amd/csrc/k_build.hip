@@ -14,6 +14,7 @@
 #include <cfloat>
 
 #include "fg_internal.h"
+#include "fg_timer.h"
 
 namespace fg {
 
@@ -776,6 +777,7 @@ __global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
 void launch_build(HodlrData& H, hipStream_t s) {
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
+  timer_forget(H.kmax);  // the ranks change below
   if (P.L == 0) return;
   const int nm = P.nmt;
   if (nm > 0)

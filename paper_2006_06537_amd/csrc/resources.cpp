@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "fg_internal.h"
+#include "fg_timer.h"
 
 namespace fg {
 
@@ -162,6 +163,7 @@ fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err) {
 }
 
 void hodlr_free(HodlrData& H) {
+  timer_forget(H.kmax);
   dfree(H.x); dfree(H.tbuf); dfree(H.mpart); dfree(H.sv); dfree(H.rank); dfree(H.kmax);
   dfree(H.rcols); dfree(H.rcount); dfree(H.panel); dfree(H.status); dfree(H.work);
 }

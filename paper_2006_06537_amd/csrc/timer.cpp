@@ -1,7 +1,9 @@
 // Live per-kernel timing: HIP events recorded around every launch of one selected
 // kernel on the stream it is launched on, plus a device snapshot of the per-level
-// ranks at launch time so that the algorithmic bytes of each launch can be computed
-// after the fact without a host round trip.
+// ranks so that the algorithmic bytes of each launch can be computed after the fact
+// without a host round trip.  The ranks change only when their matrix is built, so one
+// snapshot serves every timed launch until the next build of that matrix.
+#include <unordered_map>
 #include <vector>
 
 #include "fg_internal.h"
@@ -22,6 +24,7 @@ struct TimerState {
   std::vector<Rec> recs;
   int* ring = nullptr;          // device: kmax snapshots
   int ring_cap = 0, ring_used = 0;
+  std::unordered_map<const int*, int> snap;  // rank buffer -> its current snapshot
 };
 TimerState g_t;
 constexpr int RING_CAP = 1 << 16;
@@ -49,10 +52,16 @@ void timer_before(int kid, hipStream_t s, int level, const HostPlan& P, const in
     tri += m * (m + 1) / 2;
   }
   r.sum_leaf_tri = tri;
-  if (P.L > 0 && kmax_dev && g_t.ring_used + P.L <= g_t.ring_cap) {  // ranks, if the bytes use them
-    r.ring_off = g_t.ring_used;
-    g_t.ring_used += P.L;
-    k_snapshot<<<1, 64, 0, s>>>(kmax_dev, P.L, g_t.ring + r.ring_off);
+  if (P.L > 0 && kmax_dev) {  // ranks, if the bytes use them
+    const auto it = g_t.snap.find(kmax_dev);
+    if (it != g_t.snap.end()) {
+      r.ring_off = it->second;
+    } else if (g_t.ring_used + P.L <= g_t.ring_cap) {
+      r.ring_off = g_t.ring_used;
+      g_t.ring_used += P.L;
+      k_snapshot<<<1, 64, 0, s>>>(kmax_dev, P.L, g_t.ring + r.ring_off);
+      g_t.snap[kmax_dev] = r.ring_off;
+    }
   }
   hipEvent_t a, b;
   hipEventCreate(&a);
@@ -77,6 +86,8 @@ void timer_before_bytes(int kid, hipStream_t s, double bytes) {
   g_t.ev.push_back(b);
   g_t.recs.push_back(r);
 }
+
+void timer_forget(const int* kmax_dev) { g_t.snap.erase(kmax_dev); }
 
 void timer_after(int kid, hipStream_t s) {
   if (!g_t.on || g_t.kid != kid || g_t.ev.empty()) return;
@@ -124,6 +135,7 @@ fg_status fg_timer_start(int32_t kernel_id) {
     return FG_ENOMEM;
   g_t.ring_cap = RING_CAP;
   g_t.ring_used = 0;
+  g_t.snap.clear();
   g_t.kid = kernel_id;
   g_t.on = true;
   return FG_OK;
