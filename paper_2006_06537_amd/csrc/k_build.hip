@@ -1,6 +1,6 @@
 // HODLR construction kernels (gfx950): interpolation moments, per-node compression
-// (Cholesky-QR of the Chebyshev basis + one-sided Jacobi SVD of the p x p core),
-// rank bookkeeping and panel generation.
+// (Cholesky-QR of the Chebyshev basis, then a one-sided Jacobi SVD of the p x p core
+// preconditioned by a column-pivoted QR), rank bookkeeping and panel generation.
 //
 // Off-diagonal block of node (I, J) on its windows: the first-kind Chebyshev
 // interpolant in both variables, written in the Chebyshev polynomial basis:
