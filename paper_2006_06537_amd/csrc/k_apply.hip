@@ -281,7 +281,13 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
 }
 
 // per-node coefficients.  op: 0 W, 1 W', 2 W^-1, 3 W^-T, 4 matvec (alpha scaling)
-__global__ void __launch_bounds__(64) k_node_coef(
+//
+// The two sides' sums S, T of the task partials come from zsum for sides it presummed,
+// else from the partials themselves: with E = 2 k nrhs elements, G = blockDim / E groups
+// per element sum tasks t0 + g, t0 + g + G, ... (eight loads in flight), and the G group
+// sums are added in group order.  A level whose sides hold many tasks runs 1 024 threads.
+constexpr int NC_MAX_THREADS = 1024;
+__global__ void __launch_bounds__(NC_MAX_THREADS) k_node_coef(
     int op, int hbase, int nnode, const int* __restrict__ rank,
     const int* __restrict__ node_task_off, int tbase, const double* __restrict__ zpart,
     int zs_task, int nrhs, const double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
@@ -293,17 +299,35 @@ __global__ void __launch_bounds__(64) k_node_coef(
   const int k = rank[h];
   if (k == 0) return;
   __shared__ double S[PMAX][NRHS_MAX], T[PMAX][NRHS_MAX], X[PMAX][NRHS_MAX];
-  const int kn = k * nrhs;
-  for (int idx = threadIdx.x; idx < 2 * kn; idx += blockDim.x) {
-    const int side = idx / kn, e = idx % kn;
+  const int kn = k * nrhs, E = 2 * kn;
+  const int G = E >= (int)blockDim.x ? 1 : (int)blockDim.x / E;
+  __shared__ double red[NC_MAX_THREADS];  // E * G <= max(E, blockDim) <= 1 024
+  for (int idx = threadIdx.x; idx < E * G; idx += blockDim.x) {
+    const int ei = idx % E, g = idx / E;
+    const int side = ei / kn, e = ei % kn;
     double s = 0.0;
     const int t0 = node_task_off[2 * h + side] - tbase;
     const int t1 = node_task_off[2 * h + side + 1] - tbase;
     if (zsum && t1 - t0 > 1) {  // presummed per node side (k_zsum)
-      s = zsum[(size_t)(2 * jn + side) * zs_task + e];
+      if (g == 0) s = zsum[(size_t)(2 * jn + side) * zs_task + e];
     } else {
-      for (int t = t0; t < t1; ++t) s += zpart[(size_t)t * zs_task + e];
+      int t = t0 + g;
+      for (; t + 7 * G < t1; t += 8 * G) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = zpart[(size_t)(t + u * G) * zs_task + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; t < t1; t += G) s += zpart[(size_t)t * zs_task + e];
     }
+    red[idx] = s;
+  }
+  __syncthreads();
+  for (int ei = threadIdx.x; ei < E; ei += blockDim.x) {
+    double s = red[ei];
+    for (int g = 1; g < G; ++g) s += red[g * E + ei];
+    const int side = ei / kn, e = ei % kn;
     if (side) T[e / nrhs][e % nrhs] = s; else S[e / nrhs][e % nrhs] = s;
   }
   __syncthreads();
@@ -502,15 +526,10 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
   auto rv = nrhs <= 1 ? k_reduce_vec<T, 1> : nrhs <= 2 ? k_reduce_vec<T, 2> : k_reduce_vec<T, 4>;
   rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, panel, P.Ktot, v, nrhs,
                              ld, zpart, zs_task);
-  double* zs = nullptr;
-  if (P.max_tps[l] > 1) {
-    zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
-    launch_zsum(zpart, zs_task, tb, D.node_task_off, hbase, 2 << l, zs_task, zs, zs_task,
-                P.max_tps[l], s);
-  }
-  k_node_coef<<<1 << l, 64, 0, s>>>(op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart,
-                                    zs_task, nrhs, F.nodemat, D.nodemat_off, 0.0, nullptr, coef,
-                                    cs_node, zs);
+  // the node coefficients sum the sides' task partials themselves (no separate pass)
+  k_node_coef<<<1 << l, P.max_tps[l] > 1 ? NC_MAX_THREADS : 64, 0, s>>>(
+      op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart, zs_task, nrhs, F.nodemat,
+      D.nodemat_off, 0.0, nullptr, coef, cs_node, nullptr);
   const int skip_left = (op == 0 || op == 2) ? 1 : 0;
   const dim3 grid_u(nt, (std::min(P.max_trows[l], RCH) + NTHREADS - 1) / NTHREADS);
   k_update_vec<T><<<grid_u, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
