@@ -91,6 +91,7 @@ struct HostPlan {
   std::vector<int> leaf_lo;              // nleaf + 1
   std::vector<NodePlan> nodes;           // nint
   std::vector<int> kcap, coff;           // per level
+  std::vector<int> lpmax;                // per level: largest interpolation order of a side
   int Ktot = 0, kcapmax = 0, pmax = 0;
   int tbuf_size = 0;                     // doubles for all T_U / T_V
   int mom_size = 0;                      // doubles for final moments

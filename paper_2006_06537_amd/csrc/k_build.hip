@@ -435,9 +435,11 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
     const NodePlan* __restrict__ nodes, int nint, const double* __restrict__ x, int kind,
     double ell, double tol, const double* __restrict__ mpart, int mstride,
     const int* __restrict__ mtask_off, const int* __restrict__ kcap, double* __restrict__ tbuf,
-    double* __restrict__ sv, int* __restrict__ rank, int* __restrict__ status, int pm) {
-  const int h = blockIdx.x;
-  if (h >= nint) return;
+    double* __restrict__ sv, int* __restrict__ rank, int* __restrict__ status, int pm, int h0,
+    int h1) {
+  // nodes h0 .. h1-1, each with interpolation orders of at most pm
+  const int h = h0 + blockIdx.x;
+  if (h >= h1 || h >= nint) return;
   const NodePlan q = nodes[h];
   const int pI = q.pI, pJ = q.pJ;
   if (threadIdx.x < PMAX) sv[(size_t)h * PMAX + threadIdx.x] = 0.0;
@@ -783,8 +785,19 @@ void launch_build(HodlrData& H, hipStream_t s) {
   if (nm > 0)
     k_moments<<<(nm + NTHREADS / 64 - 1) / (NTHREADS / 64), NTHREADS, 0, s>>>(
         D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
+  // A work-group holds five p x p matrices in LDS, p the largest order of its launch.  The
+  // top levels set the largest order; when every level from ls down needs at most half
+  // that LDS, those levels (nearly all the nodes) run in a second launch sized for their
+  // own order, so that they do not hold LDS and CU slots at the size of the few top nodes.
   const int pm = std::max(P.pmax, 1);
-  const size_t lds = sizeof(double) * 5 * pm * pm;
+  int ls = 0, pm_lo = pm;
+  for (int l = P.L - 1, suf = 0; l >= 1; --l) {
+    suf = std::max(suf, P.lpmax[l]);
+    if (2 * suf * suf > pm * pm) break;
+    ls = l;
+    pm_lo = std::max(suf, 1);
+  }
+  const int h_split = ls > 0 ? (1 << ls) - 1 : P.nint;
   static bool lds_set = false;  // raised once to the largest size any plan can ask for
   if (!lds_set) {
     (void)hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -792,9 +805,13 @@ void launch_build(HodlrData& H, hipStream_t s) {
     lds_set = true;
   }
 
-  k_compress<<<P.nint, NTHREADS, lds, s>>>(D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart,
-                                           P.mpart_stride, D.mtask_off, D.kcap, H.tbuf, H.sv,
-                                           H.rank, H.status, pm);
+  k_compress<<<h_split, NTHREADS, sizeof(double) * 5 * pm * pm, s>>>(
+      D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart, P.mpart_stride, D.mtask_off, D.kcap,
+      H.tbuf, H.sv, H.rank, H.status, pm, 0, h_split);
+  if (h_split < P.nint)
+    k_compress<<<P.nint - h_split, NTHREADS, sizeof(double) * 5 * pm_lo * pm_lo, s>>>(
+        D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart, P.mpart_stride, D.mtask_off,
+        D.kcap, H.tbuf, H.sv, H.rank, H.status, pm_lo, h_split, P.nint);
   k_rank_levels<<<1, RL_THREADS, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
   const int ng = P.ngt;
   k_panel_gen<<<ng, NTHREADS, 0, s>>>(D.gtasks, ng, D.nodes, H.x, H.tbuf, H.rank, H.kmax,

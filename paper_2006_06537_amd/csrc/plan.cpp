@@ -103,6 +103,7 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
   const double R = window_radius(kind, ell, tol);
   P.nodes.resize(P.nint);
   P.kcap.assign(L, 0);
+  P.lpmax.assign(std::max(L, 1), 0);
   P.coff.assign(L + 1, 0);
   for (int h = 0; h < P.nint; ++h) {
     NodePlan& q = P.nodes[h];
@@ -130,6 +131,7 @@ fg_status make_plan(const double* xh, int n, int kind, double ell, double nugget
     q.aJ = xh[q.mid]; q.bJ = xh[q.j1 - 1];
     P.kcap[l] = std::max(P.kcap[l], std::min(q.pI, q.pJ));
     P.pmax = std::max(P.pmax, std::max(q.pI, q.pJ));
+    P.lpmax[l] = std::max(P.lpmax[l], std::max(q.pI, q.pJ));
   }
   for (int l = 0; l < L; ++l) {
     P.kcap[l] = std::max(P.kcap[l], 1);
