@@ -787,8 +787,11 @@ void launch_build(HodlrData& H, hipStream_t s) {
         D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
   // A work-group holds five p x p matrices in LDS, p the largest order of its launch.  The
   // top levels set the largest order; when every level from ls down needs at most half
-  // that LDS, those levels (nearly all the nodes) run in a second launch sized for their
-  // own order, so that they do not hold LDS and CU slots at the size of the few top nodes.
+  // that LDS and those levels hold far more nodes than the GPU keeps resident at the top
+  // size (about 512 work-groups), they run in a second launch sized for their own order,
+  // so that they do not hold LDS and CU slots at the size of the few top nodes.  With
+  // fewer nodes the second launch would only add the top nodes' latency in series.
+  constexpr int SPLIT_MIN_NODES = 2048;
   const int pm = std::max(P.pmax, 1);
   int ls = 0, pm_lo = pm;
   for (int l = P.L - 1, suf = 0; l >= 1; --l) {
@@ -797,6 +800,7 @@ void launch_build(HodlrData& H, hipStream_t s) {
     ls = l;
     pm_lo = std::max(suf, 1);
   }
+  if (ls > 0 && P.nint - ((1 << ls) - 1) < SPLIT_MIN_NODES) ls = 0;
   const int h_split = ls > 0 ? (1 << ls) - 1 : P.nint;
   static bool lds_set = false;  // raised once to the largest size any plan can ask for
   if (!lds_set) {
