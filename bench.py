@@ -65,15 +65,18 @@ def parse():
                     help="tensor: additive tensor-product components (ncomp * d <= 8)")
     ap.add_argument("--zcache", type=int, default=8,
                     help="predict: grid points whose W_1^-1 k1(X, X*) is kept")
-    ap.add_argument("--jobs", type=int, default=64, help="serve workload: number of jobs")
-    ap.add_argument("--job-iters", type=int, default=20, help="serve workload: sweeps per job")
+    ap.add_argument("--jobs", type=int, default=512, help="serve workload: number of jobs")
+    ap.add_argument("--job-iters", type=int, default=100, help="serve workload: sweeps per job")
+    ap.add_argument("--slots", type=int, default=32, help="serve workload: jobs running at once")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturation")
     ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: M~ factored in FP32, its solves refined by PCG to 1e-10")
-    ap.add_argument("--kernel", type=int, default=2,
-                    help="kernel timed for the roofline: 1 leaf Cholesky, 2 level reduce (the "
-                         "largest total time), 3 level update, 4 leaf whitening")
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="kernel of the roofline line: 1 leaf Cholesky, 2 level reduce, 3 level "
+                         "update, 4 leaf whitening; 0 (default) = whichever of the four HBM-bound "
+                         "factorization kernels (2, 3, 4) takes the most time in the timed region. "
+                         "All four are timed in the same region and reported under 'kernels'")
     return ap.parse_args()
 
 
@@ -121,19 +124,24 @@ def bench_copy(args):
                       "bytes_written_per_launch": 8 * n}), flush=True)
 
 
-def cpu_baseline(x, y, cfg):
+def cpu_baseline(x, y, cfg, threads=None):
     """The oracle as it stands, on the host cores: one full Gibbs sweep of the same
-    workload (chain set-up untimed)."""
-    from threadpoolctl import threadpool_info
+    workload (chain set-up untimed), with the BLAS/LAPACK pools at `threads` threads
+    (None: their default, all host cores)."""
+    import contextlib
+
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import kernels, sampler
-    ch = sampler.Chain(x, y, kernels.SE, cfg["ell0"], cfg["nugget"], cfg["leaf"], cfg["tol"],
-                       cfg["tau0"], cfg["sigf2_0"], cfg["seed"])
-    t0 = time.perf_counter()
-    ch.step()
-    dt = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": 1.0 / dt, "unit": "Gibbs iters/s", "cores": threads, "kind": "oracle",
+    ctx = threadpool_limits(threads) if threads else contextlib.nullcontext()
+    with ctx:
+        ch = sampler.Chain(x, y, kernels.SE, cfg["ell0"], cfg["nugget"], cfg["leaf"], cfg["tol"],
+                           cfg["tau0"], cfg["sigf2_0"], cfg["seed"])
+        t0 = time.perf_counter()
+        ch.step()
+        dt = time.perf_counter() - t0
+        used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": 1.0 / dt, "unit": "Gibbs iters/s", "cores": used, "kind": "oracle",
             "sample": f"one Gibbs sweep of the same n={x.size} chain (set-up untimed), "
                       f"{dt:.1f} s"}
 
@@ -486,11 +494,11 @@ def bench_serve(args):
     from workloads import served_jobs
     jobs = served_jobs(args.jobs, seed=5)
     prec = fg.MIXED if args.precision == "mixed" else fg.FP64
-    budget = 96 << 30
-    common = dict(tau0=400.0, leaf=128, tol=1e-10, precision=prec, want_f=False)
+    budget = 160 << 30
+    common = dict(leaf=128, tol=1e-10, precision=prec, want_f=False)
 
     def run(arrivals):
-        srv = fg.Server(budget, max_active=48, nstreams=4, graphs=False)
+        srv = fg.Server(budget, max_active=args.slots)
         t0 = time.perf_counter()
 
         def feeder():
@@ -499,7 +507,7 @@ def bench_serve(args):
                 if dt > 0:
                     time.sleep(dt)
                 srv.submit(job["x"], job["y"], job["ell0"], args.job_iters, seed=job["seed"],
-                           stream_id=j, **common)
+                           stream_id=j, tau0=job["tau0"], **common)
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
@@ -531,7 +539,7 @@ def bench_serve(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         c = fg.Chain(torch.tensor(job["x"], device=dev), torch.tensor(job["y"], device=dev),
-                     ell0=job["ell0"], tau0=400.0, leaf=128, tol=1e-10, seed=job["seed"],
+                     ell0=job["ell0"], tau0=job["tau0"], leaf=128, tol=1e-10, seed=job["seed"],
                      stream_id=j)
         c.step(args.job_iters)
         torch.cuda.synchronize()
@@ -553,8 +561,10 @@ def bench_serve(args):
            "config": {"workload": f"serve: {len(jobs)} jobs, n log-uniform [1e3, 2e5] (mean "
                                   f"{np.mean(ns):.0f}), 5-sinusoid y, noise U[0.02,0.2], ell0 "
                                   f"LogU[0.01,0.3], {args.job_iters} sweeps each, Poisson "
-                                  f"arrivals at {args.load} x saturation; budget 96 GiB, "
-                                  "48 slots", "jobs": len(jobs), "sweeps_per_job": args.job_iters},
+                                  f"arrivals at {args.load} x saturation; budget "
+                                  f"{budget >> 30} GiB, {args.slots} slots, tau0 = 1/noise^2",
+                      "jobs": len(jobs), "sweeps_per_job": args.job_iters,
+                      "slots": args.slots},
            "p99": q(lat, 99), "throughput_jobs_per_s": len(jobs) / span,
            "saturation_jobs_per_s": sat, "arrival_rate": lam,
            "peak_bytes": st["peak_bytes"], "failed_jobs": bad,
@@ -606,14 +616,21 @@ def main():
     chain.step(args.warmup)
     torch.cuda.synchronize()
     print(f"bench: {args.warmup} warm-up sweeps done", file=sys.stderr, flush=True)
-    timer = fg.KernelTimer(args.kernel)
+    kids = [fg.KID_LEAF, fg.KID_REDUCE, fg.KID_UPDATE, fg.KID_WHITEN]
+    timer = fg.KernelTimer(kids[0], also=kids[1:])
     timer.start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     chain.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ktime_ms, launches, kbytes = timer.stop()
+    timer.stop()
+    per = {k: fg.KernelTimer.result(k) for k in kids}
+    kid = args.kernel
+    if kid == 0:  # the HBM-bound kernel with the largest total time
+        kid = max([fg.KID_REDUCE, fg.KID_UPDATE, fg.KID_WHITEN], key=lambda k: per[k][0])
+    ktime_ms, launches, kbytes = per[kid]
+    timer = fg.KernelTimer(kid)
     st = chain.state()
     print(f"bench: {args.steps} timed sweeps in {dt:.3f} s; status {st['status']}, "
           f"accepts {st['accepts']}, ell {st['ell']:.4g}, tau {st['tau']:.4g}",
@@ -629,6 +646,14 @@ def main():
         iso_ms, iso_n, iso_b = timer.stop()
         iso_us = 1e3 * iso_ms / max(iso_n, 1)
         del F1, K1
+    kernels = {}
+    for k, (ms_k, n_k, b_k) in per.items():
+        if n_k and ms_k > 0:
+            kernels[fg.KID_NAMES[k]] = {
+                "total_ms": ms_k, "share_of_timed_region": ms_k / (1e3 * dt), "launches": n_k,
+                "avg_launch_us": 1e3 * ms_k / n_k, "algorithmic_bytes_per_launch": b_k / n_k,
+                "achieved_GBs": b_k / (ms_k * 1e-3) / 1e9,
+                "frac": b_k / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS}
     roof = None
     if launches > 0 and ktime_ms > 0:
         achieved = kbytes / (ktime_ms * 1e-3) / 1e9
@@ -654,7 +679,8 @@ def main():
             "tau_rel": abs(a["tau"] - b["tau"]) / abs(b["tau"]),
             "sigf2_rel": abs(a["sigf2"] - b["sigf2"]) / abs(b["sigf2"]), "f_rel": fe,
             "loglik_abs": abs(a["loglik"] - b["loglik"]), "pcg_iters": a["pcg_iters"],
-            "pcg_relres": a["pcg_relres"]}
+            "pcg_relres": a["pcg_relres"], "precision_used": "mixed" if
+            a["precision_used"] == fg.MIXED else "fp64 (fell back)"}
         print(f"bench: mixed vs FP64 path {extra['vs_fp64_path']}", file=sys.stderr, flush=True)
     out = {
         "metric": "Gibbs iters/s at n=2^20 (mixed)" if mixed else "Gibbs iters/s at n=2^20 (FP64)",
@@ -669,19 +695,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": ("large_1d: single chain, M~ factored in FP32 (leaf Cholesky, "
-                                "FP32 MFMA panel Grams) with PCG to 1e-10 on the FP64 HODLR, "
-                                "W_1 FP64;" if mixed else "large_1d: single FP64 chain,") + " "
+        "config": {"workload": ("large_1d: single chain, M~ with its leaf Cholesky factors "
+                                "in FP32 (levels, node factors and log-det FP64), both solves "
+                                "refined by PCG to 1e-10 on the FP64 HODLR, W_1 FP64;"
+                                if mixed else "large_1d: single FP64 chain,") + " "
                                "n=2^20 sorted U[0,1], 5-sinusoid y "
                                "+ N(0,0.05^2), SE kernel ell0=0.02 (100-point grid), leaf 128, "
                                "tol 1e-10, nugget 1e-6",
                    "n": cfg["n"], "leaf": cfg["leaf"], "tol": cfg["tol"], "ell0": cfg["ell0"]},
         "roofline": roof,
+        "kernels": kernels,
     }
     out.update(extra)
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        print("bench: timing the CPU oracle (all host threads)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(x, y, cfg)
+        print(f"bench: oracle {out['cpu_baseline']['sample']}; now on one thread", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline_1core"] = cpu_baseline(x, y, cfg, threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -145,7 +145,10 @@ fg_status hodlr_factor_prec(fg_hodlr A, double alpha, double beta, const double*
 fg_status hodlr_solve_refined(fg_hodlr A, fg_factor F, double alpha, double beta,
                               const double* b, double* x, int32_t nrhs, int64_t ld, double rtol,
                               int32_t maxit, int32_t* iters, double* relres, fg_stream stream);
-/* x = (W W')^-1 b = W^-T W^-1 b for nrhs columns.  b and x may be the same. */
+/* x = (W W')^-1 b = W^-T W^-1 b for nrhs columns: the solves of Algorithm 1 (M~ w = Z,
+ * M~ r = tau y) with the factor of the SI factorization, one sweep up the tree (W^-1)
+ * and one down (W^-T).  b and x may be the same.  Errors: FG_EINVAL (NULL, nrhs < 1,
+ * ld < n); device failures of the factor are in its status word. */
 fg_status hodlr_solve(fg_factor F, const double* b, double* x, int32_t nrhs, int64_t ld,
                       fg_stream stream);
 
@@ -154,8 +157,17 @@ fg_status hodlr_solve(fg_factor F, const double* b, double* x, int32_t nrhs, int
  * and Sylvester's theorem).  logdet_dev: device, one double. */
 fg_status hodlr_logdet(fg_factor F, double* logdet_dev, fg_stream stream);
 
+/* The same log-determinant in its two parts (SI "Determinant computation speedup": the
+ * block-diagonal factor and the identity-plus-low-rank level factors contribute
+ * separately): parts_dev[0] = 2 sum log diag(L_leaf), parts_dev[1] = sum_nodes sum_i
+ * log(1 - sigma_i^2).  parts_dev: device, two doubles.  A diagnostic for parity checks:
+ * at large n the two parts nearly cancel, and each can be compared on its own. */
+fg_status hodlr_logdet_parts(fg_factor F, double* parts_dev, fg_stream stream);
+
 /* y = op(W) v with op = W (transpose=0, inverse=0), W' (1,0), W^-1 (0,1),
- * W^-T (1,1); nrhs columns.  v and y may be the same. */
+ * W^-T (1,1); nrhs columns.  v and y may be the same.  The factors of W are those of the
+ * SI factorization (W = L_D W_(L-1) ... W_(0)); Algorithm 1 uses W b to form Z and
+ * W^-1 f in the length-scale conditional.  Errors: FG_EINVAL (NULL, nrhs < 1, ld < n). */
 fg_status hodlr_apply_w(fg_factor F, int32_t transpose, int32_t inverse, const double* v,
                         double* y, int32_t nrhs, int64_t ld, fg_stream stream);
 
@@ -423,21 +435,28 @@ fg_status fg_footprint_bytes(const fg_chain_cfg* cfg, const double* x_host, int6
                              uint64_t* bytes);
 
 /* ---------------------------------------------------------------------------
- * Serving (a request loop for GP-regression jobs).  A job is one Gibbs chain on
- * (x, y) run for `iters` sweeps.  A worker thread admits submitted jobs in arrival
- * order while the footprint estimate (fg_footprint_bytes) fits within mem_budget minus
- * the bytes held by running jobs (a job is always admitted into an empty server) and
- * fewer than max_active run; it then advances every running job by one sweep
- * (gibbs_step_batch on its own stream) and retires the jobs that are done, releasing
- * their memory before the next admission.  Each job's result is the result of the
- * same chain run alone.  Times are seconds since serve_create (steady clock).
+ * Serving (a request loop for GP-regression jobs, with continuous batching).  A job is
+ * one Gibbs chain (Section 4.1's sweep) on (x, y) run for `iters` sweeps.
+ *   - serve_create allocates the whole device budget once (an arena of mem_budget bytes)
+ *     and max_active slots, each with its own streams.
+ *   - Planner threads make a submitted job's host plans and its exact device footprint
+ *     (fg_footprint_bytes plus the rounding of each allocation).
+ *   - A worker thread admits planned jobs in arrival order (head of line) while a slot is
+ *     free and a block of the job's footprint can be carved from the arena; the job's
+ *     chain lives in that block.  The worker makes no runtime allocation.
+ *   - Every running job advances on its own stream: when its last sweep has finished the
+ *     worker enqueues the next one, or retires the job (result, block returned) and
+ *     admits the next at once.  The sweeps of all running jobs overlap on the device.
+ *   - A job that can never fit (footprint above mem_budget) fails with FG_ENOMEM; a
+ *     mixed-precision job whose FP32 leaf factor stops being a preconditioner and whose
+ *     block has no room for an FP64 factor ends with FG_ENOTCONV.
+ * Each job's result is the result of the same chain run alone (gibbs_step).  Times are
+ * seconds since serve_create (steady clock).
  * ------------------------------------------------------------------------- */
 typedef struct fg_server_s* fg_server;
 typedef struct {
-  uint64_t mem_budget;   /* device bytes for running jobs (> 0) */
-  int32_t max_active;    /* most jobs in one batched sweep (>= 1) */
-  int32_t nstreams;      /* library streams of the batched sweep (1..4) */
-  int32_t use_graphs;    /* capture and replay sweep graphs (gibbs_step_batch) */
+  uint64_t mem_budget;   /* device bytes for running jobs (> 0), allocated at creation */
+  int32_t max_active;    /* most jobs running at once (1..256) */
 } fg_serve_cfg;
 typedef struct {
   const double* x;       /* host, n sorted inputs (copied at submission) */
@@ -484,7 +503,7 @@ void serve_destroy(fg_server s);
  * reductions of gibbs_predict).  fg_timer_stop
  * synchronises the device and returns the summed kernel time (ms), the launch count
  * and the algorithmic HBM bytes of those launches (each kernel's minimum traffic:
- * every operand read once and every result written once).  Not thread-safe.
+ * every operand read once and every result written once).
  * ------------------------------------------------------------------------- */
 #define FG_KID_LEAF 1
 #define FG_KID_REDUCE 2
@@ -493,6 +512,12 @@ void serve_destroy(fg_server s);
 #define FG_KID_PREDICT 5
 fg_status fg_timer_start(int32_t kernel_id);
 fg_status fg_timer_stop(double* total_ms, int64_t* launches, double* bytes);
+/* fg_timer_start for several kernels at once: bit k of `mask` times kernel id k
+ * (FG_KID_*).  fg_timer_stop then returns the sums over all of them, and
+ * fg_timer_result(k, ...) the figures of kernel k alone from that stop.  The timer
+ * state is guarded by a mutex; launches from any host thread are recorded. */
+fg_status fg_timer_start_mask(uint32_t mask);
+fg_status fg_timer_result(int32_t kernel_id, double* total_ms, int64_t* launches, double* bytes);
 
 /* Status word of a handle (synchronises the stream first). */
 fg_status hodlr_status(fg_hodlr A, fg_stream stream);

@@ -24,18 +24,31 @@ KID_NAMES = {KID_LEAF: "k_leaf", KID_REDUCE: "k_reduce_panel", KID_UPDATE: "k_up
 
 
 class KernelTimer:
-    """HIP-event timing of one library kernel over a region (fg_timer_start/stop)."""
+    """HIP-event timing of one library kernel over a region (fg_timer_start/stop).
+    With `also` (more kernel ids) every listed kernel is timed in the same region
+    (fg_timer_start_mask); stop() returns the first kernel's figures and result(kid)
+    any listed kernel's."""
 
-    def __init__(self, kernel_id):
+    def __init__(self, kernel_id, also=()):
         self.kid = kernel_id
         self.name = KID_NAMES[kernel_id]
+        self.kids = [kernel_id] + [k for k in also if k != kernel_id]
 
     def start(self):
-        check(lib().fg_timer_start(self.kid))
+        if len(self.kids) == 1:
+            check(lib().fg_timer_start(self.kid))
+        else:
+            check(lib().fg_timer_start_mask(sum(1 << k for k in self.kids)))
 
     def stop(self):
         ms, cnt, by = C.c_double(), C.c_int64(), C.c_double()
         check(lib().fg_timer_stop(C.byref(ms), C.byref(cnt), C.byref(by)))
+        return self.result(self.kid)
+
+    @staticmethod
+    def result(kid):
+        ms, cnt, by = C.c_double(), C.c_int64(), C.c_double()
+        check(lib().fg_timer_result(kid, C.byref(ms), C.byref(cnt), C.byref(by)))
         return ms.value, cnt.value, by.value
 
 
@@ -146,6 +159,13 @@ class Factor:
         torch = _torch()
         out = torch.empty(1, dtype=torch.float64, device="cuda")
         check(lib().hodlr_logdet(self._f, _dev(out), _stream()))
+        return out
+
+    def logdet_parts(self):
+        """(leaf part, node part) of the log-determinant, as a 2-element device tensor."""
+        torch = _torch()
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        check(lib().hodlr_logdet_parts(self._f, _dev(out), _stream()))
         return out
 
     def solve(self, b):
@@ -291,8 +311,8 @@ class Server:
     """Serving loop (serve_create / serve_submit / serve_poll / serve_drain).  Jobs are
     host numpy arrays; the server copies them at submission."""
 
-    def __init__(self, mem_budget, max_active=64, nstreams=4, graphs=True):
-        cfg = ServeCfg(int(mem_budget), max_active, nstreams, int(graphs))
+    def __init__(self, mem_budget, max_active=32):
+        cfg = ServeCfg(int(mem_budget), max_active)
         s = C.c_void_p()
         check(lib().serve_create(C.byref(cfg), C.byref(s)))
         self._s = s

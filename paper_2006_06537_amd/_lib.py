@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", 
 # names declared in include/fifa_gp.h, in declaration order
 EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", "hodlr_entries",
            "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
-           "hodlr_solve", "hodlr_logdet", "hodlr_apply_w",
+           "hodlr_solve", "hodlr_logdet", "hodlr_logdet_parts", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
            "gibbs_step_batch", "gibbs_chain_state", "gibbs_chain_create_grid", "gibbs_chain_create_collapsed",
            "gibbs_chain_inputs",
@@ -29,7 +29,7 @@ EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", 
            "gibbs_predict_stats",
            "tp_chain_create", "tp_step", "tp_chain_state",
            "fg_footprint_bytes", "serve_create", "serve_submit", "serve_poll", "serve_drain",
-           "serve_stats", "serve_destroy", "fg_timer_start", "fg_timer_stop", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
+           "serve_stats", "serve_destroy", "fg_timer_start", "fg_timer_stop", "fg_timer_start_mask", "fg_timer_result", "hodlr_status", "factor_status", "fg_last_error", "hodlr_destroy",
            "factor_destroy", "gibbs_chain_destroy", "tp_chain_destroy"]
 
 
@@ -96,8 +96,7 @@ class TpSnapshot(C.Structure):
 
 
 class ServeCfg(C.Structure):
-    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int32), ("nstreams", C.c_int32),
-                ("use_graphs", C.c_int32)]
+    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int32)]
 
 
 class Job(C.Structure):
@@ -148,6 +147,7 @@ def lib():
                                  C.POINTER(D), P], I32),
         "hodlr_solve": ([P, DP, DP, I32, I64, P], I32),
         "hodlr_logdet": ([P, DP, P], I32),
+        "hodlr_logdet_parts": ([P, DP, P], I32),
         "hodlr_apply_w": ([P, I32, I32, DP, DP, I32, I64, P], I32),
         "fg_normals": ([U64, U64, U64, U64, I64, DP, P], I32),
         "gp_draw_f": ([P, P, P, D, D, DP, U64, U64, U64, DP, DP, DP, P], I32),
@@ -175,6 +175,8 @@ def lib():
         "serve_destroy": ([P], None),
         "fg_timer_start": ([I32], I32),
         "fg_timer_stop": ([C.POINTER(D), C.POINTER(I64), C.POINTER(D)], I32),
+        "fg_timer_start_mask": ([C.c_uint32], I32),
+        "fg_timer_result": ([I32, C.POINTER(D), C.POINTER(I64), C.POINTER(D)], I32),
         "hodlr_status": ([P, P], I32),
         "factor_status": ([P, P], I32),
         "fg_last_error": ([], C.c_char_p),

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfifagp.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "resources.cpp", "abi.cpp", "chain.cpp", "chain_tp.cpp",
+SOURCES = ["alloc.cpp", "plan.cpp", "resources.cpp", "abi.cpp", "chain.cpp", "chain_tp.cpp",
            "timer.cpp", "k_build.hip", "k_factor.hip", "k_apply.hip", "k_rng.hip",
            "k_tensor.hip", "k_predict.hip", "pcg.cpp",
            "serve.cpp"]

@@ -230,6 +230,12 @@ fg_status hodlr_logdet(fg_factor F, double* logdet_dev, fg_stream stream) {
   return FG_OK;
 }
 
+fg_status hodlr_logdet_parts(fg_factor F, double* parts_dev, fg_stream stream) {
+  if (!F || !parts_dev) return fail(FG_EINVAL, "NULL argument");
+  fg::launch_logdet_parts(F->d, parts_dev, reinterpret_cast<hipStream_t>(stream));
+  return check_launch("hodlr_logdet_parts");
+}
+
 fg_status hodlr_apply_w(fg_factor F, int32_t transpose, int32_t inverse, const double* v, double* y,
                         int32_t nrhs, int64_t ld, fg_stream stream) {
   if (!F || !v || !y) return fail(FG_EINVAL, "NULL argument");

@@ -7,17 +7,25 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
+#include "fg_chain.h"
 #include "fg_internal.h"
 #include "fg_rng.h"
 #include "fg_pcg.h"
 #include "fg_timer.h"
 #include "fg_tensor.h"
 
+// a sweep's grid proposal: the proposed index and whether it lies on the grid
+struct SweepProposal {
+  int kp = 0, ongrid = 0;
+};
+
 struct fg_chain_s {
   fg_chain_cfg cfg{};
+  SweepProposal pending;                      // the proposal of the sweep in flight
   int n = 0;
   std::vector<double> grid;
   std::vector<fg::PlanPack*> packs;
@@ -32,11 +40,13 @@ struct fg_chain_s {
   double* vecs = nullptr;     // 4 n workspace
   double* dotwork = nullptr;  // reduction partials
   fg::DevState* st = nullptr;
+  fg::DevState* st_prev = nullptr;  // the state at the start of the last sweep
   fg::DevState* st_host = nullptr;  // pinned
-  bool mixed = false;                         // FP32 factor of M~ + PCG refinement
+  bool mixed = false;                         // FP32 leaf factor of M~ + PCG refinement
   bool fell_back = false;                     // M~ moved to FP64 after an FP32 failure
   fg::FactorData WM64;                        // FP64 factor of M~ used after the fallback
   fg::PcgWork pcg;
+  int pcg_nit = 6;                            // PCG iterations enqueued per f-draw
   int pcg_iters = 0;
   double pcg_relres = 0.0;
   bool pcg_failed = false;
@@ -45,6 +55,7 @@ struct fg_chain_s {
   hipStream_t ls = nullptr;                   // the proposal's leaves, beside its build
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_z = nullptr, ev_f = nullptr,
              ev_leaf = nullptr;
+  bool own_streams = true;                    // false: lent by the caller (serving slots)
   // exact discrete conditional of the length-scale: every grid point's K~_1 and W_1
   bool exact = false;
   std::vector<fg::HodlrData> Hg;
@@ -78,7 +89,7 @@ struct fg_chain_s {
 
 constexpr size_t GRAPH_CACHE = 48;  // captured sweeps kept per chain
 constexpr double PCG_RTOL = 1e-10;  // relative residual of the mixed-precision solves
-constexpr int PCG_MAXIT = 30;
+constexpr int PCG_MAXIT = 32;       // iteration budget beyond which M~ moves to FP64
 
 using fg::set_error;
 
@@ -87,18 +98,23 @@ static fg_status cfail(fg_status st, const std::string& m) {
   return st;
 }
 
-static void chain_free(fg_chain c) {
+// sync: wait for the whole device first (a public destroy: the caller may still have work
+// queued that reads the chain); without it the caller guarantees that nothing queued
+// touches the chain any more (the serving loop, after the chain's last event)
+static void chain_free(fg_chain c, bool sync = true) {
   if (!c) return;
-  (void)hipDeviceSynchronize();
+  if (sync) (void)hipDeviceSynchronize();
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-  if (c->ev_z) (void)hipEventDestroy(c->ev_z);
-  if (c->ev_f) (void)hipEventDestroy(c->ev_f);
-  if (c->ev_leaf) (void)hipEventDestroy(c->ev_leaf);
-  if (c->aux) (void)hipStreamDestroy(c->aux);
-  if (c->zs) (void)hipStreamDestroy(c->zs);
-  if (c->ls) (void)hipStreamDestroy(c->ls);
+  if (c->own_streams) {
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_z) (void)hipEventDestroy(c->ev_z);
+    if (c->ev_f) (void)hipEventDestroy(c->ev_f);
+    if (c->ev_leaf) (void)hipEventDestroy(c->ev_leaf);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->zs) (void)hipStreamDestroy(c->zs);
+    if (c->ls) (void)hipStreamDestroy(c->ls);
+  }
   fg::pcg_free(c->pcg);
   for (int i = 0; i < 2; ++i) { fg::hodlr_free(c->H[i]); fg::factor_free(c->W[i]); }
   for (auto& h : c->Hg) fg::hodlr_free(h);
@@ -111,21 +127,20 @@ static void chain_free(fg_chain c) {
   fg::factor_free(c->WM64);
   for (auto* p : c->packs) fg::plan_pack_destroy(p);
   for (auto& e : c->zcache)
-    if (e.z) (void)hipFree(e.z);
+    if (e.z) fg::dev_free(e.z);
   double* bufs[] = {c->x, c->y, c->f, c->r, c->mu, c->vecs, c->dotwork, c->xstar, c->pwork,
                     c->cw, c->ldg, c->qg, c->qbuf, c->qdot};
   for (double* b : bufs)
-    if (b) (void)hipFree(b);
-  if (c->st) (void)hipFree(c->st);
-  if (c->st_host) (void)hipHostFree(c->st_host);
+    if (b) fg::dev_free(b);
+  if (c->st) fg::dev_free(c->st);
+  if (c->st_prev) fg::dev_free(c->st_prev);
+  if (c->st_host) fg::host_free(c->st_host);
   delete c;
 }
 
 namespace {
 
-struct Proposal {
-  int kp, ongrid;
-};
+using Proposal = SweepProposal;
 
 // the current length-scale's K~_1 and W_1: a grid slot in exact mode, else the slot of the
 // two-slot (current, proposal) pair
@@ -245,7 +260,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   const int oth = 1 - c->cur;
   fg::HodlrData& H1 = Hcur(c);
   fg::FactorData& W1 = Wcur(c);
-  fg::launch_sweep_begin(c->st, s);
+  fg::launch_sweep_begin(c->st, c->st_prev, s);
   // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
   // the chain's second stream while this stream factors M~ and draws f.
   hipEventRecord(c->ev_fork, s);
@@ -302,36 +317,15 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
       hipStreamWaitEvent(s, c->ev_z, 0);
     }
     if (c->mixed && !c->fell_back) {
-      // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~ with the FP32 factor; the
-      // solution goes to v0, v1 (free at this point) and back into v2, v3.  The first
-      // residual test comes after as many iterations as the last draw needed.
-      std::string err;
-      const int min_it = std::max(1, c->pcg_iters);
-      const fg_status st = fg::pcg_solve(H1, 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n,
-                                         PCG_RTOL, PCG_MAXIT, c->pcg, s, &c->pcg_iters,
-                                         &c->pcg_relres, err, min_it);
-      if (st == FG_OK) {
-        hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-      } else {
-        // kappa(M~) u32 ~ 1: the FP32 factor is no preconditioner.  M~ is factored in FP64
-        // from now on (this draw included); the right-hand sides in v2, v3 are intact.
-        c->fell_back = true;
-        c->pcg_iters = 0;
-        c->pcg_relres = 0.0;
-        (void)hipStreamSynchronize(s);
-        std::string e2;
-        if (fg::factor_alloc(c->WM64, c->caps, e2) != FG_OK) {
-          c->pcg_failed = true;
-        } else {
-          c->WM64.H = &H1;
-          c->WM64.alpha = 0.0;
-          c->WM64.beta = 1.0;
-          fg::launch_factor(c->WM64, &c->st->alphaM, nullptr, nullptr, s);
-          hipMemcpyAsync(&c->st->logdetM, c->WM64.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-          fg::launch_apply_w(c->WM64, 2, v2, 2, n, c->WM64.work, s);
-          fg::launch_apply_w(c->WM64, 3, v2, 2, n, c->WM64.work, s);
-        }
-      }
+      // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~, preconditioned with the
+      // factor whose leaves are FP32: pcg_nit iterations with the convergence test on the
+      // device (the host checks the record after the sweep and runs the sweep again with
+      // a larger budget if it did not converge).  The solution goes to v0, v1 (free at
+      // this point) and back into v2, v3.
+      fg::pcg_enqueue(H1, 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n, PCG_RTOL, 0,
+                      c->pcg_nit, c->pcg, s, true);
+      fg::launch_pcg_record(c->pcg.sc, c->st, s);
+      hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     } else {
       fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
       fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
@@ -379,6 +373,40 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
 }
 
+// After the sweep's stream has been synchronised, before finish_sweep: whether the
+// mixed-precision f-draw's PCG converged within its budget.  If it did, the budget of the
+// next sweep becomes the iterations it needed plus one.  If not, the state is restored
+// (enqueued on s) and the caller runs the same sweep again: with twice the budget, or,
+// once the budget is at its cap or a residual was not finite, with M~ factored in FP64
+// from then on (the FP32 leaf factor is then no preconditioner).  A sweep run again from
+// the same state gives what it would have given with the larger budget at once.
+bool sweep_retry(fg_chain c, hipStream_t s) {
+  if (!c->mixed || c->fell_back || c->exact || c->collapsed) return false;
+  const fg::DevState& d = *c->st_host;
+  if (d.pcg_done == 1) {
+    c->pcg_iters = d.pcg_iters;
+    c->pcg_relres = d.pcg_relres;
+    c->pcg_nit = std::min(std::max(d.pcg_iters + 1, 2), PCG_MAXIT);
+    return false;
+  }
+  if (d.pcg_done == 0 && c->pcg_nit < PCG_MAXIT) {
+    c->pcg_nit = std::min(2 * c->pcg_nit, PCG_MAXIT);
+  } else {
+    std::string err;
+    if (fg::factor_alloc(c->WM64, c->caps, err) != FG_OK) {
+      c->pcg_failed = true;  // reported as FG_ENOTCONV; the chain keeps the FP32 factor
+      c->pcg_iters = d.pcg_iters;
+      c->pcg_relres = d.pcg_relres;
+      return false;
+    }
+    c->fell_back = true;
+    c->pcg_iters = 0;
+    c->pcg_relres = 0.0;
+  }
+  hipMemcpyAsync(c->st, c->st_prev, sizeof(fg::DevState), hipMemcpyDeviceToDevice, s);
+  return true;
+}
+
 // after the sweep's stream has been synchronised: the accepted proposal becomes current
 void finish_sweep(fg_chain c, const Proposal& pr) {
   if (c->exact) {
@@ -390,21 +418,25 @@ void finish_sweep(fg_chain c, const Proposal& pr) {
   c->iter += 1;
 }
 
-// A few default-priority streams shared by batched calls.
+// A few default-priority streams shared by batched calls.  They are created once, and
+// a batched call holds them (g_batch.mu) for its whole duration: two host threads that
+// step batches at the same time take turns instead of interleaving on shared streams.
 constexpr int BATCH_STREAMS = 4;
 struct BatchStreams {
+  std::mutex mu;
   bool init = false;
   hipStream_t s[BATCH_STREAMS] = {};
   hipEvent_t ev_in = nullptr;
 };
 BatchStreams g_batch;
 
+// with g_batch.mu held
 fg_status batch_streams_init() {
   if (g_batch.init) return FG_OK;
   for (int q = 0; q < BATCH_STREAMS; ++q)
-    if (hipStreamCreateWithFlags(&g_batch.s[q], hipStreamNonBlocking) != hipSuccess)
+    if (!g_batch.s[q] && hipStreamCreateWithFlags(&g_batch.s[q], hipStreamNonBlocking) != hipSuccess)
       return cfail(FG_EDEVICE, "stream creation failed");
-  if (hipEventCreateWithFlags(&g_batch.ev_in, hipEventDisableTiming) != hipSuccess)
+  if (!g_batch.ev_in && hipEventCreateWithFlags(&g_batch.ev_in, hipEventDisableTiming) != hipSuccess)
     return cfail(FG_EDEVICE, "event creation failed");
   g_batch.init = true;
   return FG_OK;
@@ -412,8 +444,11 @@ fg_status batch_streams_init() {
 
 // The captured sweep for (cur, k, proposal), instantiated on first use.
 fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExec_t& out) {
-  const uint64_t key = ((uint64_t)c->cur << 40) | ((uint64_t)(uint32_t)c->k << 20) |
-                       (uint64_t)(uint32_t)(pr.kp + 1);
+  // (slot, FP64 fallback, PCG budget, grid index, proposal): everything the enqueued
+  // sequence depends on
+  const uint64_t key = ((uint64_t)c->cur << 56) | ((uint64_t)c->fell_back << 55) |
+                       ((uint64_t)(c->mixed ? c->pcg_nit : 0) << 44) |
+                       ((uint64_t)(uint32_t)c->k << 22) | (uint64_t)(uint32_t)(pr.kp + 1);
   auto it = c->graphs.find(key);
   if (it != c->graphs.end()) {
     out = it->second;
@@ -453,6 +488,158 @@ size_t chain_bytes_from(const fg::Caps& caps, size_t plan_bytes, int n, bool mix
 }  // namespace
 
 namespace fg {
+
+ChainPlans::~ChainPlans() {
+  for (auto* p : packs) plan_pack_destroy(p);
+}
+
+fg_status chain_plan(const fg_chain_cfg& cfg, const double* xh, int n, ChainPlans& out,
+                     std::string& err) {
+  if (n < 1) { err = "n out of range"; return FG_EINVAL; }
+  if (cfg.grid_size < 1 || cfg.grid_center < 0 || cfg.grid_center >= cfg.grid_size) {
+    err = "bad grid";
+    return FG_EINVAL;
+  }
+  if (!(cfg.tau0 > 0) || !(cfg.sigf2_0 > 0) || !(cfg.ell0 > 0)) {
+    err = "tau0, sigf2_0 and ell0 must be > 0";
+    return FG_EINVAL;
+  }
+  if (cfg.precision != FG_FP64 && cfg.precision != FG_MIXED) {
+    err = "bad precision";
+    return FG_EINVAL;
+  }
+  for (auto* p : out.packs) plan_pack_destroy(p);
+  out.packs.clear();
+  out.caps = Caps();
+  out.plan_bytes = 0;
+  for (int g = 0; g < cfg.grid_size; ++g) {
+    fg_status st;
+    const double ell = cfg.ell0 * std::pow(10.0, (g - cfg.grid_center) / 50.0);
+    PlanPack* pk = plan_pack_make(xh, n, cfg.kind, ell, cfg.nugget, cfg.leaf, cfg.tol, st, err);
+    if (!pk) return st;
+    out.packs.push_back(pk);
+    out.caps.add(*pk);
+    out.plan_bytes += plan_device_bytes(*pk);
+  }
+  out.bytes = chain_bytes_from(out.caps, out.plan_bytes, n, cfg.precision == FG_MIXED);
+  return FG_OK;
+}
+
+fg_status chain_create_planned(const fg_chain_cfg& cfg, ChainPlans& plans, const double* x,
+                               const double* y, bool host_inputs, int n, hipStream_t s,
+                               const ChainStreams* borrowed, bool sync, fg_chain* out,
+                               std::string& err) {
+  *out = nullptr;
+  fg_chain c = new fg_chain_s();
+  c->cfg = cfg;
+  c->n = n;
+  c->grid.resize(cfg.grid_size);
+  for (int g = 0; g < cfg.grid_size; ++g)
+    c->grid[g] = cfg.ell0 * std::pow(10.0, (g - cfg.grid_center) / 50.0);
+  c->packs.swap(plans.packs);
+  c->caps = plans.caps;
+  fg_status st;
+  auto fail = [&](fg_status code, const std::string& m) {
+    err = m;
+    (void)hipStreamSynchronize(s);  // uploads already enqueued may still read or write
+    chain_free(c, sync);
+    return code;
+  };
+  for (auto* pk : c->packs)
+    if ((st = plan_pack_upload(pk, s, false, err)) != FG_OK) return fail(st, err);
+  const bool async = !sync;
+  for (int i = 0; i < 2; ++i) {
+    if ((st = hodlr_alloc(c->H[i], c->caps, err, s, async)) != FG_OK ||
+        (st = factor_alloc(c->W[i], c->caps, err, false, s, async)) != FG_OK)
+      return fail(st, err);
+  }
+  c->mixed = cfg.precision == FG_MIXED;
+  if ((st = factor_alloc(c->WM, c->caps, err, c->mixed, s, async)) != FG_OK) return fail(st, err);
+  if (c->mixed && (st = pcg_alloc(c->pcg, n, err)) != FG_OK) return fail(st, err);
+  const size_t nb = sizeof(double) * (size_t)n;
+  if (dev_alloc(reinterpret_cast<void**>(&c->x), nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->f), nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->r), nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->mu), nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->vecs), 4 * nb) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 3072) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->st), sizeof(DevState)) != hipSuccess ||
+      dev_alloc(reinterpret_cast<void**>(&c->st_prev), sizeof(DevState)) != hipSuccess ||
+      host_alloc(reinterpret_cast<void**>(&c->st_host), sizeof(DevState)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FG_ENOMEM, "chain allocation failed");
+  }
+  if (borrowed) {
+    c->own_streams = false;
+    c->aux = borrowed->aux;
+    c->zs = borrowed->zs;
+    c->ls = borrowed->ls;
+    c->ev_fork = borrowed->ev[0];
+    c->ev_join = borrowed->ev[1];
+    c->ev_z = borrowed->ev[2];
+    c->ev_f = borrowed->ev[3];
+    c->ev_leaf = borrowed->ev[4];
+  } else if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+             hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking) != hipSuccess ||
+             hipStreamCreateWithFlags(&c->ls, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_z, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&c->ev_leaf, hipEventDisableTiming) != hipSuccess) {
+    return fail(FG_EDEVICE, "stream or event creation failed");
+  }
+  const hipMemcpyKind kind = host_inputs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  hipMemcpyAsync(c->x, x, nb, kind, s);
+  hipMemcpyAsync(c->y, y, nb, kind, s);
+  hipMemsetAsync(c->f, 0, nb, s);
+  for (int i = 0; i < 2; ++i) hipMemcpyAsync(c->H[i].x, c->x, nb, hipMemcpyDeviceToDevice, s);
+  // initial state and the factor of K~_1 at the starting length-scale
+  DevState init{};
+  init.tau = cfg.tau0;
+  init.sigf2 = cfg.sigf2_0;
+  init.k = cfg.grid_center;
+  *c->st_host = init;
+  hipMemcpyAsync(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice, s);
+  c->k = cfg.grid_center;
+  c->cur = 0;
+  c->H[0].pk = c->packs[c->k];
+  launch_build(c->H[0], s);
+  c->W[0].H = &c->H[0];
+  c->W[0].alpha = 1.0;
+  c->W[0].beta = 0.0;
+  launch_factor(c->W[0], nullptr, nullptr, nullptr, s);
+  hipMemcpyAsync(&c->st->logdet1, c->W[0].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (sync && hipStreamSynchronize(s) != hipSuccess) return fail(FG_EDEVICE, "chain set-up failed on the device");
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FG_EDEVICE, std::string("chain set-up: ") + hipGetErrorString(e));
+  *out = c;
+  return FG_OK;
+}
+
+void chain_destroy_idle(fg_chain c) { chain_free(c, false); }
+
+void chain_begin_sweep(fg_chain c, hipStream_t s, bool again) {
+  if (!again) c->pending = propose(c);
+  prepare_sweep(c, c->pending);
+  enqueue_sweep(c, c->pending, s, false);
+}
+
+bool chain_end_sweep(fg_chain c, hipStream_t s) {
+  if (sweep_retry(c, s)) return true;
+  finish_sweep(c, c->pending);
+  return false;
+}
+
+const double* chain_f(fg_chain c) { return c->f; }
+
+// ten plan arrays per grid point; eleven per compressed matrix and eleven per factor,
+// with three of each; the chain's ten vectors and state words; the PCG workspace
+size_t chain_alloc_count(const fg_chain_cfg& cfg) {
+  return 10 * (size_t)std::max(cfg.grid_size, 1) + 2 * 11 + 4 * 12 + 10 + 8;
+}
+
 size_t chain_device_bytes(fg_chain c) {
   size_t pb = 0;
   for (auto* p : c->packs) pb += plan_device_bytes(*p);
@@ -472,20 +659,11 @@ fg_status fg_footprint_bytes(const fg_chain_cfg* cfg, const double* x_host, int6
   if (cfg->grid_size < 1 || cfg->grid_center < 0 || cfg->grid_center >= cfg->grid_size)
     return cfail(FG_EINVAL, "bad grid");
   // the capacity the chain takes is the largest over every plan of its grid
-  fg::Caps caps;
-  size_t plan_sum = 0;
-  for (int g = 0; g < cfg->grid_size; ++g) {
-    fg::PlanPack pk;
-    std::string err;
-    const double ell = cfg->ell0 * std::pow(10.0, (g - cfg->grid_center) / 50.0);
-    const fg_status st = fg::make_plan(x_host, int(n), cfg->kind, ell, cfg->nugget, cfg->leaf,
-                                       cfg->tol, pk.P, err);
-    if (st != FG_OK) return cfail(st, err);
-    fg::plan_pack_sizes(&pk);
-    caps.add(pk);
-    plan_sum += fg::plan_device_bytes(pk);
-  }
-  *bytes = chain_bytes_from(caps, plan_sum, int(n), cfg->precision == FG_MIXED);
+  fg::ChainPlans plans;
+  std::string err;
+  const fg_status st = fg::chain_plan(*cfg, x_host, int(n), plans, err);
+  if (st != FG_OK) return cfail(st, err);
+  *bytes = plans.bytes;
   return FG_OK;
 }
 
@@ -496,96 +674,24 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
   *out = nullptr;
   if (!cfg || !x || !y) return cfail(FG_EINVAL, "NULL argument");
   if (n < 1 || n >= (int64_t(1) << 31)) return cfail(FG_EINVAL, "n out of range");
+  // the configuration is checked before any device call
   if (cfg->grid_size < 1 || cfg->grid_center < 0 || cfg->grid_center >= cfg->grid_size)
     return cfail(FG_EINVAL, "bad grid");
   if (!(cfg->tau0 > 0) || !(cfg->sigf2_0 > 0) || !(cfg->ell0 > 0))
     return cfail(FG_EINVAL, "tau0, sigf2_0 and ell0 must be > 0");
+  if (cfg->precision != FG_FP64 && cfg->precision != FG_MIXED)
+    return cfail(FG_EINVAL, "bad precision");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  fg_chain c = new fg_chain_s();
-  c->cfg = *cfg;
-  c->n = int(n);
   std::vector<double> xh(n);
   if (hipMemcpyAsync(xh.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
-    chain_free(c);
+      hipStreamSynchronize(s) != hipSuccess)
     return cfail(FG_EDEVICE, "copy of x to the host failed");
-  }
-  c->grid.resize(cfg->grid_size);
-  for (int g = 0; g < cfg->grid_size; ++g)
-    c->grid[g] = cfg->ell0 * std::pow(10.0, (g - cfg->grid_center) / 50.0);
-  fg_status st;
   std::string err;
-  for (int g = 0; g < cfg->grid_size; ++g) {
-    fg::PlanPack* pk = fg::plan_pack_create(xh.data(), int(n), cfg->kind, c->grid[g], cfg->nugget,
-                                            cfg->leaf, cfg->tol, s, st, err);
-    if (!pk) { chain_free(c); return cfail(st, err); }
-    c->packs.push_back(pk);
-    c->caps.add(*pk);
-  }
-  for (int i = 0; i < 2; ++i) {
-    if ((st = fg::hodlr_alloc(c->H[i], c->caps, err)) != FG_OK ||
-        (st = fg::factor_alloc(c->W[i], c->caps, err)) != FG_OK) {
-      chain_free(c);
-      return cfail(st, err);
-    }
-  }
-  if (cfg->precision != FG_FP64 && cfg->precision != FG_MIXED) {
-    chain_free(c);
-    return cfail(FG_EINVAL, "bad precision");
-  }
-  c->mixed = cfg->precision == FG_MIXED;
-  if ((st = fg::factor_alloc(c->WM, c->caps, err, c->mixed)) != FG_OK) { chain_free(c); return cfail(st, err); }
-  if (c->mixed && (st = fg::pcg_alloc(c->pcg, int(n), err)) != FG_OK) { chain_free(c); return cfail(st, err); }
-  const size_t nb = sizeof(double) * (size_t)n;
-  if (hipMalloc(reinterpret_cast<void**>(&c->x), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->f), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->r), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->mu), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->vecs), 4 * nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 3072) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(fg::DevState)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::DevState)) != hipSuccess) {
-    chain_free(c);
-    return cfail(FG_ENOMEM, "chain allocation failed");
-  }
-  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->zs, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->ls, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_z, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_f, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_leaf, hipEventDisableTiming) != hipSuccess) {
-    chain_free(c);
-    return cfail(FG_EDEVICE, "stream or event creation failed");
-  }
-  hipMemcpyAsync(c->x, x, nb, hipMemcpyDeviceToDevice, s);
-  hipMemcpyAsync(c->y, y, nb, hipMemcpyDeviceToDevice, s);
-  hipMemsetAsync(c->f, 0, nb, s);
-  for (int i = 0; i < 2; ++i) hipMemcpyAsync(c->H[i].x, x, nb, hipMemcpyDeviceToDevice, s);
-  // initial state and the factor of K~_1 at the starting length-scale
-  fg::DevState init{};
-  init.tau = cfg->tau0;
-  init.sigf2 = cfg->sigf2_0;
-  init.k = cfg->grid_center;
-  *c->st_host = init;
-  hipMemcpyAsync(c->st, c->st_host, sizeof(fg::DevState), hipMemcpyHostToDevice, s);
-  c->k = cfg->grid_center;
-  c->cur = 0;
-  c->H[0].pk = c->packs[c->k];
-  fg::launch_build(c->H[0], s);
-  c->W[0].H = &c->H[0];
-  c->W[0].alpha = 1.0;
-  c->W[0].beta = 0.0;
-  fg::launch_factor(c->W[0], nullptr, nullptr, nullptr, s);
-  hipMemcpyAsync(&c->st->logdet1, c->W[0].logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
-  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) {
-    chain_free(c);
-    return cfail(FG_EDEVICE, "chain set-up failed on the device");
-  }
-  *out = c;
-  return FG_OK;
+  fg::ChainPlans plans;
+  fg_status st = fg::chain_plan(*cfg, xh.data(), int(n), plans, err);
+  if (st != FG_OK) return cfail(st, err);
+  st = fg::chain_create_planned(*cfg, plans, x, y, false, int(n), s, nullptr, true, out, err);
+  return st == FG_OK ? FG_OK : cfail(st, err);
 }
 
 fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x, const double* y,
@@ -631,8 +737,8 @@ fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x,
     }
   }
   double *dx = nullptr, *dy = nullptr;
-  if (hipMalloc(&dx, sizeof(double) * u) != hipSuccess || hipMalloc(&dy, sizeof(double) * u) != hipSuccess) {
-    if (dx) (void)hipFree(dx);
+  if (fg::dev_alloc(reinterpret_cast<void**>(&dx), sizeof(double) * u) != hipSuccess || fg::dev_alloc(reinterpret_cast<void**>(&dy), sizeof(double) * u) != hipSuccess) {
+    if (dx) fg::dev_free(dx);
     (void)hipGetLastError();
     return cfail(FG_ENOMEM, "device allocation failed");
   }
@@ -640,10 +746,10 @@ fg_status gibbs_chain_create_collapsed(const fg_chain_cfg* cfg, const double* x,
   hipMemcpyAsync(dy, ybar.data(), sizeof(double) * u, hipMemcpyHostToDevice, s);
   fg_chain c = nullptr;
   fg_status st = gibbs_chain_create(cfg, dx, dy, u, stream, &c);  // synchronises s
-  (void)hipFree(dx);
-  (void)hipFree(dy);
+  fg::dev_free(dx);
+  fg::dev_free(dy);
   if (st != FG_OK) return st;
-  if (hipMalloc(&c->cw, sizeof(double) * 3 * (size_t)u) != hipSuccess) {
+  if (fg::dev_alloc(reinterpret_cast<void**>(&c->cw), sizeof(double) * 3 * (size_t)u) != hipSuccess) {
     chain_free(c);
     (void)hipGetLastError();
     return cfail(FG_ENOMEM, "device allocation failed");
@@ -681,10 +787,10 @@ fg_status gibbs_chain_create_grid(const fg_chain_cfg* cfg, const double* x, cons
     }
   }
   const size_t nb = sizeof(double) * (size_t)c->n;
-  if (hipMalloc(&c->ldg, sizeof(double) * G) != hipSuccess ||
-      hipMalloc(&c->qg, sizeof(double) * G) != hipSuccess ||
-      hipMalloc(&c->qbuf, 4 * nb) != hipSuccess ||
-      hipMalloc(&c->qdot, sizeof(double) * 4 * 2048) != hipSuccess) {
+  if (fg::dev_alloc(reinterpret_cast<void**>(&c->ldg), sizeof(double) * G) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->qg), sizeof(double) * G) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->qbuf), 4 * nb) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->qdot), sizeof(double) * 4 * 2048) != hipSuccess) {
     chain_free(c);
     (void)hipGetLastError();
     return cfail(FG_ENOMEM, "grid chain allocation failed");
@@ -757,11 +863,14 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   for (int it = 0; it < iters; ++it) {
     const Proposal pr = propose(c);
-    prepare_sweep(c, pr);
-    enqueue_sweep(c, pr, s, true);
-    if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
+    for (;;) {
+      prepare_sweep(c, pr);
+      enqueue_sweep(c, pr, s, true);
+      if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
+      if (!sweep_retry(c, s)) break;
+    }
     finish_sweep(c, pr);
   }
   return FG_OK;
@@ -777,6 +886,7 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
       if (chains[j] == chains[i]) return cfail(FG_EINVAL, "a chain appears twice");
   }
   hipStream_t caller = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> batch_lock(g_batch.mu);
   fg_status st = batch_streams_init();
   if (st != FG_OK) return st;
   const bool graphs = use_graphs && !fg::timer_active();
@@ -784,25 +894,37 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
   if (hipEventRecord(g_batch.ev_in, caller) != hipSuccess) return cfail(FG_EDEVICE, "event record failed");
   for (int q = 0; q < nstreams; ++q) hipStreamWaitEvent(g_batch.s[q], g_batch.ev_in, 0);
   std::vector<Proposal> pr(nchains);
+  std::vector<int> todo(nchains), again;
   for (int it = 0; it < iters; ++it) {
     for (int i = 0; i < nchains; ++i) {
-      fg_chain c = chains[i];
-      hipStream_t q = g_batch.s[i % nstreams];
-      pr[i] = propose(c);
-      prepare_sweep(c, pr[i]);
-      if (!graphs || c->mixed) {
-        enqueue_sweep(c, pr[i], q, false);
-        continue;
-      }
-      hipGraphExec_t ge = nullptr;
-      if ((st = sweep_graph(c, pr[i], q, ge)) != FG_OK) return st;
-      if (hipGraphLaunch(ge, q) != hipSuccess) return cfail(FG_EDEVICE, "graph launch failed");
+      todo[i] = i;
+      pr[i] = propose(chains[i]);
     }
-    for (int q = 0; q < nstreams; ++q)
-      if (hipStreamSynchronize(g_batch.s[q]) != hipSuccess)
-        return cfail(FG_EDEVICE, "batched sweep failed on the device");
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("batched sweep: ") + hipGetErrorString(e));
+    // every chain's sweep, then again for the chains whose PCG budget was too small
+    std::vector<int> run = todo;
+    while (!run.empty()) {
+      for (int i : run) {
+        fg_chain c = chains[i];
+        hipStream_t q = g_batch.s[i % nstreams];
+        prepare_sweep(c, pr[i]);
+        if (!graphs) {
+          enqueue_sweep(c, pr[i], q, false);
+          continue;
+        }
+        hipGraphExec_t ge = nullptr;
+        if ((st = sweep_graph(c, pr[i], q, ge)) != FG_OK) return st;
+        if (hipGraphLaunch(ge, q) != hipSuccess) return cfail(FG_EDEVICE, "graph launch failed");
+      }
+      for (int q = 0; q < nstreams; ++q)
+        if (hipStreamSynchronize(g_batch.s[q]) != hipSuccess)
+          return cfail(FG_EDEVICE, "batched sweep failed on the device");
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("batched sweep: ") + hipGetErrorString(e));
+      again.clear();
+      for (int i : run)
+        if (sweep_retry(chains[i], g_batch.s[i % nstreams])) again.push_back(i);
+      run.swap(again);
+    }
     for (int i = 0; i < nchains; ++i) finish_sweep(chains[i], pr[i]);
   }
   return FG_OK;
@@ -850,10 +972,10 @@ fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_o
 
 static void predict_release(fg_chain c) {
   for (auto& e : c->zcache)
-    if (e.z) (void)hipFree(e.z);
+    if (e.z) fg::dev_free(e.z);
   c->zcache.clear();
   for (double** b : {&c->xstar, &c->pwork}) {
-    if (*b) (void)hipFree(*b);
+    if (*b) fg::dev_free(*b);
     *b = nullptr;
   }
   c->nstar = 0;
@@ -872,11 +994,11 @@ fg_status gibbs_predict_inputs(fg_chain c, const double* xstar, int64_t nstar,
   if (nstar == 0) return FG_OK;
   const size_t n = (size_t)c->n, m = (size_t)nstar;
   double* z0 = nullptr;
-  if (hipMalloc(&c->xstar, sizeof(double) * m) != hipSuccess ||
-      hipMalloc(&c->pwork, sizeof(double) * (n + m + fg::predict_part_doubles(c->n, (int)m))) !=
+  if (fg::dev_alloc(reinterpret_cast<void**>(&c->xstar), sizeof(double) * m) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->pwork), sizeof(double) * (n + m + fg::predict_part_doubles(c->n, (int)m))) !=
           hipSuccess ||
-      hipMalloc(&z0, sizeof(double) * n * m) != hipSuccess) {
-    if (z0) (void)hipFree(z0);
+      fg::dev_alloc(reinterpret_cast<void**>(&z0), sizeof(double) * n * m) != hipSuccess) {
+    if (z0) fg::dev_free(z0);
     predict_release(c);
     (void)hipGetLastError();
     return cfail(FG_ENOMEM, "device allocation for the new inputs failed");
@@ -904,7 +1026,7 @@ static double* predict_z(fg_chain c, hipStream_t s) {
     if (e.k < 0) { slot = &e; break; }
   if (!slot && (int)c->zcache.size() < c->zcache_cap) {
     double* z = nullptr;
-    if (hipMalloc(&z, sizeof(double) * (size_t)n * (size_t)N) == hipSuccess) {
+    if (fg::dev_alloc(reinterpret_cast<void**>(&z), sizeof(double) * (size_t)n * (size_t)N) == hipSuccess) {
       c->zcache.push_back({-1, z, 0});
       slot = &c->zcache.back();
     } else {

@@ -60,8 +60,8 @@ static void tp_free(fg_tp_chain c) {
     for (auto* p : v) fg::plan_pack_destroy(p);
   void* bufs[] = {c->perm, c->F, c->fs, c->y, c->vecs, c->dotwork, c->st, c->Gc, c->R};
   for (void* b : bufs)
-    if (b) (void)hipFree(b);
-  if (c->st_host) (void)hipHostFree(c->st_host);
+    if (b) fg::dev_free(b);
+  if (c->st_host) fg::host_free(c->st_host);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -137,16 +137,16 @@ fg_status tp_chain_create(const fg_tp_cfg* cfg, const double* x, const double* y
       }
   if ((st = fg::factor_alloc(c->WP, c->caps, err)) != FG_OK) { tp_free(c); return tfail(st, err); }
   const size_t nb = sizeof(double) * (size_t)nn;
-  if (hipMalloc(reinterpret_cast<void**>(&c->perm), sizeof(int) * (size_t)d * nn) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->F), nb * nf) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->fs), nb * nf) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->Gc), nb * ncomp) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->R), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->vecs), nb * 8) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 2048) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(fg::TpState)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::TpState)) != hipSuccess) {
+  if (fg::dev_alloc(reinterpret_cast<void**>(&c->perm), sizeof(int) * (size_t)d * nn) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->F), nb * nf) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->fs), nb * nf) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->Gc), nb * ncomp) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->R), nb) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->y), nb) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->vecs), nb * 8) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->dotwork), sizeof(double) * 2048) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->st), sizeof(fg::TpState)) != hipSuccess ||
+      fg::host_alloc(reinterpret_cast<void**>(&c->st_host), sizeof(fg::TpState)) != hipSuccess) {
     tp_free(c);
     return tfail(FG_ENOMEM, "tensor chain allocation failed");
   }

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -135,11 +137,18 @@ struct PlanPack {
   size_t zpart_size = 0, zfin_size = 0, coef_size = 0;  // factorization scratch (doubles)
   size_t mpart_size = 0;
   size_t mv_work = 0, ap_work = 0;
+  std::vector<int> kc_host, co_host;  // upload sources of D.kcap and D.coff
 };
 
 // Plans the tree for x (host copy), uploads it; nullptr on error (status, err set).
 PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
                            double tol, hipStream_t s, fg_status& st, std::string& err);
+// the two halves: the host plan alone (thread-safe, no device call), then its upload on s;
+// with sync = false nothing waits and the host task vectors are kept (the uploads may
+// still read them) until the pack is destroyed
+PlanPack* plan_pack_make(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                         double tol, fg_status& st, std::string& err);
+fg_status plan_pack_upload(PlanPack* pk, hipStream_t s, bool sync, std::string& err);
 void plan_pack_destroy(PlanPack* pk);
 void plan_pack_sizes(PlanPack* pk);  // buffer sizes of pk->P (host only)
 
@@ -163,10 +172,9 @@ struct HodlrData {
 struct FactorData {
   const HodlrData* H = nullptr;
   double alpha = 1, beta = 0;
-  bool fp32 = false;           // leaf factors and whitened panels held in FP32
-  float* leafLf = nullptr;     // FP32 copies of leafL / leafLinv / panel (fp32 only)
+  bool fp32 = false;           // leaf factor computed and held in FP32 (levels stay FP64)
+  float* leafLf = nullptr;     // FP32 leafL / leafLinv (fp32 only; the FP64 ones are unused)
   float* leafLinvf = nullptr;
-  float* panelf = nullptr;
   double* leafL = nullptr;     // nleaf x B x B
   double* leafLinv = nullptr;  // nleaf x B x B: inverses of L's 16 x 16 diagonal blocks
   double* leaf_ld = nullptr;   // nleaf
@@ -188,9 +196,13 @@ struct Caps {
   size_t mv_work = 1, ap_work = 1;
   void add(const PlanPack& pk);
 };
-fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err);
+// device buffers (dev_alloc); the status words and counters they start from are cleared
+// by hipMemset, or by hipMemsetAsync on s when async is set
+fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err, hipStream_t s = nullptr,
+                      bool async = false);
 void hodlr_free(HodlrData& H);
-fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32 = false);
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32 = false,
+                       hipStream_t s = nullptr, bool async = false);
 void factor_free(FactorData& F);
 // device bytes held by a plan upload, a compressed matrix and a factor of capacity c
 size_t plan_device_bytes(const PlanPack& pk);
@@ -208,6 +220,8 @@ void launch_factor_leaves(FactorData& F, const double* alpha_dev, const double* 
                           const double* diag, hipStream_t s);
 void launch_factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s);
 void launch_logdet_sum(FactorData& F, hipStream_t s);
+// out (device, 2): the leaf part and the node part of the log-det
+void launch_logdet_parts(const FactorData& F, double* out, hipStream_t s);
 // op: 0 = W, 1 = W', 2 = W^-1, 3 = W^-T; in place on v (ld x nrhs)
 void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
                     hipStream_t s);
@@ -251,5 +265,51 @@ size_t apply_work_doubles(const HostPlan& P, int nrhs);
 
 // error helper
 void set_error(const std::string& msg);
+
+// -------- memory (alloc.cpp) --------
+// A region of device (or pinned host) memory allocated once and sub-allocated best-fit
+// in 256-byte units.  Thread-safe.
+class Arena {
+ public:
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena();
+  fg_status init(size_t bytes, bool pinned_host, std::string& err);
+  // an arena over memory that belongs to someone else (a block of another arena); the
+  // base address must be 256-byte aligned
+  fg_status init_view(void* base, size_t bytes);
+  void release();
+  void* alloc(size_t bytes);  // nullptr when no free block is large enough
+  void free(void* p);
+  size_t capacity() const { return cap_; }
+  size_t largest_free() const;
+  size_t in_use() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0;
+  bool pinned_ = false;
+  bool view_ = false;
+  mutable std::mutex mu_;
+  std::map<size_t, size_t> free_;  // offset -> size
+  std::map<size_t, size_t> used_;
+  size_t in_use_ = 0;
+};
+// While an ArenaScope lives, dev_alloc / host_alloc on this thread take their memory from
+// the given arenas (a null arena: the runtime allocator).
+class ArenaScope {
+ public:
+  ArenaScope(Arena* dev, Arena* host);
+  ~ArenaScope();
+
+ private:
+  Arena* prev_dev_;
+  Arena* prev_host_;
+};
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);   // arena memory goes back to its arena, from any thread
+hipError_t host_alloc(void** p, size_t bytes);  // pinned host memory
+void host_free(void* p);
 
 }  // namespace fg

@@ -75,9 +75,16 @@ struct DevState {
   double logdet_sigma, loglik, mh;
   uint64_t iter;              // sweeps completed (the Philox iteration word)
   int k, kprop, accept, accepts, status, pad;
+  double pcg_relres;          // mixed precision: the f-draw's PCG record (0 in FP64)
+  int pcg_iters, pcg_done;
 };
 
-void launch_sweep_begin(DevState* st, hipStream_t s);
+// Starts a sweep (the draw's scalars from tau and sigma_f^2); when `prev` is not null it
+// first keeps a copy of the state there, from which the sweep can be run again.
+void launch_sweep_begin(DevState* st, DevState* prev, hipStream_t s);
+struct PcgScalars;
+// copies a PCG solve's convergence record into the state
+void launch_pcg_record(const PcgScalars* sc, DevState* st, hipStream_t s);
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s);
 // the steps below take the iteration word from st->iter; the Metropolis step ends the
 // sweep and advances it

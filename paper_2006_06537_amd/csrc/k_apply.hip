@@ -538,7 +538,7 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
 }
 
 template <typename T>
-static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const T* panel, int op,
+static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const double* panel, int op,
                     double* v, int nrhs, int ld, double* work, hipStream_t s) {
   const HostPlan& P = F.H->pk->P;
   const int* leaf_lo = F.H->pk->D.leaf_lo;
@@ -552,24 +552,24 @@ static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const T* p
                                                      v, nrhs, ld);
   };
   if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
-    for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 0, l, v, nrhs, ld, work, s);
+    for (int l = 0; l < P.L; ++l) sweep_level<double>(F, panel, 0, l, v, nrhs, ld, work, s);
     leaf(0);
   } else if (op == 1) {   // W' v = W_(0)' ... W_(L-1)' L_D' v
     leaf(1);
-    for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 1, l, v, nrhs, ld, work, s);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level<double>(F, panel, 1, l, v, nrhs, ld, work, s);
   } else if (op == 2) {   // W^-1 v = W_(0)^-1 ... W_(L-1)^-1 L_D^-1 v
     leaf(2);
-    for (int l = P.L - 1; l >= 0; --l) sweep_level<T>(F, panel, 2, l, v, nrhs, ld, work, s);
+    for (int l = P.L - 1; l >= 0; --l) sweep_level<double>(F, panel, 2, l, v, nrhs, ld, work, s);
   } else {                // W^-T v = L_D^-T W_(L-1)^-T ... W_(0)^-T v
-    for (int l = 0; l < P.L; ++l) sweep_level<T>(F, panel, 3, l, v, nrhs, ld, work, s);
+    for (int l = 0; l < P.L; ++l) sweep_level<double>(F, panel, 3, l, v, nrhs, ld, work, s);
     leaf(3);
   }
 }
 
 void launch_apply_w(FactorData& F, int op, double* v, int nrhs, int ld, double* work,
                     hipStream_t s) {
-  if (F.fp32)
-    apply_w<float>(F, F.leafLf, F.leafLinvf, F.panelf, op, v, nrhs, ld, work, s);
+  if (F.fp32)  // FP32 leaf factor, FP64 levels
+    apply_w<float>(F, F.leafLf, F.leafLinvf, F.panel, op, v, nrhs, ld, work, s);
   else
     apply_w<double>(F, F.leafL, F.leafLinv, F.panel, op, v, nrhs, ld, work, s);
 }

@@ -802,12 +802,14 @@ void launch_build(HodlrData& H, hipStream_t s) {
   }
   if (ls > 0 && P.nint - ((1 << ls) - 1) < SPLIT_MIN_NODES) ls = 0;
   const int h_split = ls > 0 ? (1 << ls) - 1 : P.nint;
-  static bool lds_set = false;  // raised once to the largest size any plan can ask for
-  if (!lds_set) {
+  // raised once to the largest size any plan can ask for (a function-local static is
+  // initialised exactly once, whichever host thread builds first)
+  static const bool lds_set = [] {
     (void)hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(sizeof(double) * 5 * PMAX * PMAX));
-    lds_set = true;
-  }
+    return true;
+  }();
+  (void)lds_set;
 
   k_compress<<<h_split, NTHREADS, sizeof(double) * 5 * pm * pm, s>>>(
       D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart, P.mpart_stride, D.mtask_off, D.kcap,

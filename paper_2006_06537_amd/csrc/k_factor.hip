@@ -393,7 +393,8 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
 // ---------------------------------------------------------------------------------
 // leaf whitening on matrix cores: dst = sqrt(alpha) L^-1 src for every active panel
 // column of every level, rows of one leaf per work-group, by blocked forward
-// substitution in 16-row blocks:  Y_j = D_j^-1 Y_j;  Y_i -= L_ij Y_j (i > j).
+// substitution in 16-row blocks:  Y_j = D_j^-1 Y_j;  Y_i -= L_ij Y_j (i > j).  L may be
+// stored in FP32 (TL = float, the mixed-precision factor); the substitution is FP64.
 //
 // The 28 strictly lower 16 x 16 blocks of L (negated) and the 8 diagonal-block inverses
 // D_j^-1 are staged in LDS once (pitch 17).  Each wave owns 16 panel columns at a time
@@ -405,10 +406,10 @@ constexpr int WB = BMAX / 16;          // 16-row blocks per leaf (8)
 constexpr int WTRI = WB * (WB + 1) / 2;  // lower blocks (36)
 constexpr int WPD = 17;                // LDS pitch of a staged block
 
-template <typename T>
+template <typename T, typename TL>
 __global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
-    const int* __restrict__ leaf_lo, int nleaf, const T* __restrict__ leafL,
-    const T* __restrict__ leafLinv, int Bc, double alpha_v, const double* __restrict__ alpha_p,
+    const int* __restrict__ leaf_lo, int nleaf, const TL* __restrict__ leafL,
+    const TL* __restrict__ leafLinv, int Bc, double alpha_v, const double* __restrict__ alpha_p,
     const double* __restrict__ src, T* __restrict__ dst, int K, const int* __restrict__ coff,
     const int* __restrict__ kmax, int L) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -417,10 +418,11 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const int nb = (m + 15) >> 4;
   __shared__ T Ls[WTRI * 16 * WPD];
-  const T* Lg = leafL + (size_t)b * Bc * Bc;
-  const T* Dg = leafLinv + (size_t)b * Bc * Bc;
+  const TL* Lg = leafL + (size_t)b * Bc * Bc;
+  const TL* Dg = leafLinv + (size_t)b * Bc * Bc;
   // stage: element (r, c) of block t = (bi, bj) at Ls[t*16*WPD + r*WPD + c]; r runs
-  // fastest so that reads of the column-major factors are contiguous
+  // fastest so that reads of the column-major factors are contiguous.  A factor held in
+  // FP32 is widened exactly: the products below are those of that factor, in FP64.
   for (int idx = threadIdx.x; idx < WTRI * 256; idx += NTHREADS) {
     const int t = idx >> 8, e = idx & 255, r = e & 15, c = e >> 4;
     int bi = 0;
@@ -429,9 +431,9 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
     const int gr = bi * 16 + r, gcol = bj * 16 + c;
     T v = T(0);
     if (bi == bj) {
-      if (gr < m && c <= r) v = Dg[gr + (size_t)gcol * Bc];
+      if (gr < m && c <= r) v = (T)Dg[gr + (size_t)gcol * Bc];
     } else if (bi < nb && gr < m) {
-      v = -Lg[gr + (size_t)gcol * Bc];
+      v = -(T)Lg[gr + (size_t)gcol * Bc];
     }
     Ls[t * 16 * WPD + r * WPD + c] = v;
   }
@@ -895,7 +897,7 @@ __global__ void __launch_bounds__(256) k_node_factor(
     double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
     int zf_side, double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
     double* __restrict__ node_ld, double* __restrict__ coef, int cs_node, int cs_a,
-    int* __restrict__ status, int kc, double gap_floor) {
+    int* __restrict__ status, int kc) {
   const int j = blockIdx.x;
   const int h = (1 << l) - 1 + j;
   const int k = rank[h], kl = kmax[l], W = rcount[l], Wc = W - kl;
@@ -961,11 +963,7 @@ __global__ void __launch_bounds__(256) k_node_factor(
     bool spd = true;
     for (int a = threadIdx.x; a < r; a += 64) {
       double s2 = fmax(Hm[a + a * kc], 0.0);
-      if (gap_floor > 0.0) {
-        // FP32 panels: 1 - s^2 below their resolution is noise; the floor keeps the
-        // (preconditioner) factor SPD
-        s2 = fmin(s2, 1.0 - gap_floor);
-      } else if (!(s2 < 1.0)) {
+      if (!(s2 < 1.0)) {
         spd = false;
         s2 = 1.0 - DBL_EPSILON;
       }
@@ -1117,9 +1115,6 @@ __global__ void k_logdet_sum(const double* __restrict__ leaf_ld, int nleaf,
 // ---------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------
-// floor on 1 - s^2 of a node whose panels are held in FP32 (16 FP32 ulps of 1)
-constexpr double GAP_FLOOR_FP32 = 16.0 * 5.9604644775390625e-08;
-
 // the leaves (Cholesky, diagonal-block inverses, leaf log-dets): they need x and the
 // kernel's parameters only, not the compressed panels
 template <typename T>
@@ -1135,28 +1130,38 @@ static void factor_leaves(FactorData& F, T* leafL, T* leafLinv, const double* al
   timer_after(KID_LEAF, s);
 }
 
-// everything after the leaves: whitened panels, the levels, the log-det
-template <typename T>
-static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const double* alpha_dev,
-                          hipStream_t s) {
+// everything after the leaves: whitened panels, the levels, the log-det.  The panels,
+// Gram blocks, node factors and updates are FP64 whatever the precision of the leaf
+// factor: the node gaps 1 - s^2 of a well-conditioned-at-the-leaves matrix can sit far
+// below FP32 resolution at the top levels (about 1 / (alpha n ell) for the squared
+// exponential), and only the leaf factor can be rounded without changing them by more
+// than a relative u32 kappa(leaf).
+static void factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s) {
   const HodlrData& H = *F.H;
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
   const int Bc = P.B;
+  double* panel = F.panel;
   if (P.L > 0) {
     timer_before(KID_WHITEN, s, -1, P, H.kmax, 0);
-    k_whiten<T><<<P.nleaf, NTHREADS, 0, s>>>(D.leaf_lo, P.nleaf, leafL, leafLinv, Bc, F.alpha,
-                                             alpha_dev, H.panel, panel, P.Ktot, D.coff, H.kmax,
-                                             P.L);
+    if (F.fp32)
+      k_whiten<double, float><<<P.nleaf, NTHREADS, 0, s>>>(
+          D.leaf_lo, P.nleaf, F.leafLf, F.leafLinvf, Bc, F.alpha, alpha_dev, H.panel, panel,
+          P.Ktot, D.coff, H.kmax, P.L);
+    else
+      k_whiten<double, double><<<P.nleaf, NTHREADS, 0, s>>>(
+          D.leaf_lo, P.nleaf, F.leafL, F.leafLinv, Bc, F.alpha, alpha_dev, H.panel, panel,
+          P.Ktot, D.coff, H.kmax, P.L);
     timer_after(KID_WHITEN, s);
   }
-  static bool lds_set = false;  // raised once to the largest size any plan can ask for
-  if (!lds_set) {
+  // raised once to the largest size any plan can ask for (thread-safe one-time init)
+  static const bool lds_set = [] {
     (void)hipFuncSetAttribute((const void*)k_node_factor,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(sizeof(double) * 5 * PMAX * PMAX));
-    lds_set = true;
-  }
+    return true;
+  }();
+  (void)lds_set;
   for (int l = P.L - 1; l >= 0; --l) {
     const int tb = P.ltask_off[l], nt = P.ltask_off[l + 1] - tb;
     const int Wcap = P.coff[l + 1];  // columns of levels <= l (capacity)
@@ -1164,8 +1169,8 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
     timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
     const dim3 grid_r(nt, (Wcap + 63) / 64);
     const int na_cap = std::max(1, std::min(4, (P.kcap[l] + 15) / 16));
-    auto rp = na_cap == 1 ? k_reduce_panel<T, 1> : na_cap == 2 ? k_reduce_panel<T, 2>
-            : na_cap == 3 ? k_reduce_panel<T, 3> : k_reduce_panel<T, 4>;
+    auto rp = na_cap == 1 ? k_reduce_panel<double, 1> : na_cap == 2 ? k_reduce_panel<double, 2>
+            : na_cap == 3 ? k_reduce_panel<double, 3> : k_reduce_panel<double, 4>;
     rp<<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols, H.rcount, P.Ktot,
                                    panel, F.zpart, zs_a, zs_task);
     timer_after(KID_REDUCE, s);
@@ -1178,10 +1183,10 @@ static void factor_levels(FactorData& F, T* leafL, T* leafLinv, T* panel, const 
     k_node_factor<<<1 << l, kc > 8 ? 256 : 64, lds_node, s>>>(
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
-        kc, sizeof(T) == 4 ? GAP_FLOOR_FP32 : 0.0);
+        kc);
     if (l > 0) {
       timer_before(KID_UPDATE, s, l, P, H.kmax, nt);
-      k_update_panel<T><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
+      k_update_panel<double><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
                                                 H.rcols, H.rcount, P.Ktot, panel, H.ld, F.coef,
                                                 cs_node, cs_a);
       timer_after(KID_UPDATE, s);
@@ -1199,16 +1204,46 @@ void launch_factor_leaves(FactorData& F, const double* alpha_dev, const double* 
 }
 
 void launch_factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s) {
-  if (F.fp32)
-    factor_levels<float>(F, F.leafLf, F.leafLinvf, F.panelf, alpha_dev, s);
-  else
-    factor_levels<double>(F, F.leafL, F.leafLinv, F.panel, alpha_dev, s);
+  factor_levels(F, alpha_dev, s);
 }
 
 void launch_factor(FactorData& F, const double* alpha_dev, const double* beta_dev,
                    const double* diag, hipStream_t s) {
   launch_factor_leaves(F, alpha_dev, beta_dev, diag, s);
   launch_factor_levels(F, alpha_dev, s);
+}
+
+// the two parts of the log-det separately: out[0] = sum of the leaf terms
+// (2 sum log diag L_D), out[1] = sum of the node terms (sum log(1 - s^2)), each in the
+// fixed order of k_logdet_sum
+__global__ void k_logdet_parts(const double* __restrict__ leaf_ld, int nleaf,
+                               const double* __restrict__ node_ld, int nint,
+                               double* __restrict__ out) {
+  __shared__ double red[2][NTHREADS / 64];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nleaf; i += NTHREADS) a += leaf_ld[i];
+  for (int i = threadIdx.x; i < nint; i += NTHREADS) b += node_ld[i];
+  a = wsum(a);
+  b = wsum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < NTHREADS / 64; ++w) {
+      ta += red[0][w];
+      tb += red[1][w];
+    }
+    out[0] = ta;
+    out[1] = tb;
+  }
+}
+
+void launch_logdet_parts(const FactorData& F, double* out, hipStream_t s) {
+  const HostPlan& P = F.H->pk->P;
+  k_logdet_parts<<<1, NTHREADS, 0, s>>>(F.leaf_ld, P.nleaf, F.node_ld, P.nint, out);
 }
 
 void launch_logdet_sum(FactorData& F, hipStream_t s) {

@@ -164,7 +164,8 @@ void launch_normals(uint64_t seed, uint64_t tag, uint64_t iter, uint64_t strm, i
 // scalar steps of the sweep (one thread)
 // ---------------------------------------------------------------------------------
 // derived scalars at the start of a sweep
-__global__ void k_sweep_begin(DevState* st) {
+__global__ void k_sweep_begin(DevState* st, DevState* prev) {
+  if (prev) *prev = *st;
   st->alphaM = st->tau * st->sigf2;
   st->c_ka = sqrt(st->tau) * st->sigf2;
   st->sigf = sqrt(st->sigf2);
@@ -275,7 +276,9 @@ void launch_rho_exact(DevState* st, const double* ld, const double* q, int G, ui
   k_rho_exact<<<1, 1, 0, s>>>(st, ld, q, G, seed, strm);
 }
 
-void launch_sweep_begin(DevState* st, hipStream_t s) { k_sweep_begin<<<1, 1, 0, s>>>(st); }
+void launch_sweep_begin(DevState* st, DevState* prev, hipStream_t s) {
+  k_sweep_begin<<<1, 1, 0, s>>>(st, prev);
+}
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s) {
   k_set_draw_scalars<<<1, 1, 0, s>>>(st, tau, sigf2);
 }
@@ -312,8 +315,13 @@ void launch_zero_int(int* p, int n, hipStream_t s) {
 namespace fg {
 
 __global__ void k_pcg_init(int n, int nrhs, const double* __restrict__ b, int ld,
-                           double* __restrict__ x, double* __restrict__ r) {
+                           double* __restrict__ x, double* __restrict__ r, PcgScalars* sc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc->done = 0;
+    sc->iters = 0;
+    sc->relres = INFINITY;
+  }
   if (i >= n) return;
   for (int c = 0; c < nrhs; ++c) {
     r[(size_t)c * n + i] = b[(size_t)c * ld + i];
@@ -331,7 +339,7 @@ __global__ void k_pcg_xr(int n, int nrhs, double* __restrict__ x, int ld, double
                          const double* __restrict__ p, const double* __restrict__ q,
                          const PcgScalars* __restrict__ sc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || sc->done) return;
   for (int c = 0; c < nrhs; ++c) {
     const double a = sc->pq[c] != 0.0 ? sc->rz[c] / sc->pq[c] : 0.0;
     x[(size_t)c * ld + i] += a * p[(size_t)c * n + i];
@@ -344,7 +352,7 @@ __global__ void k_pcg_xr(int n, int nrhs, double* __restrict__ x, int ld, double
 __global__ void k_pcg_p(int n, int nrhs, double* __restrict__ p, const double* __restrict__ z,
                         const PcgScalars* __restrict__ sc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || sc->done) return;
   for (int c = 0; c < nrhs; ++c) {
     const double bt = sc->rz[c] != 0.0 ? sc->rz_new[c] / sc->rz[c] : 0.0;
     p[(size_t)c * n + i] = z[(size_t)c * n + i] + bt * p[(size_t)c * n + i];
@@ -353,13 +361,47 @@ __global__ void k_pcg_p(int n, int nrhs, double* __restrict__ p, const double* _
 
 __global__ void k_pcg_rz(int nrhs, PcgScalars* sc) {
   const int c = threadIdx.x;
-  if (c < nrhs) sc->rz[c] = sc->rz_new[c];
+  if (c < nrhs && !sc->done) sc->rz[c] = sc->rz_new[c];
+}
+
+// the convergence test of iteration `it` (rr and bb hold |r|^2 and |b|^2 per column)
+__global__ void k_pcg_check(int nrhs, double rtol, int it, PcgScalars* sc) {
+  if (threadIdx.x != 0 || sc->done) return;
+  double worst = 0.0;
+  bool finite = true;
+  for (int c = 0; c < nrhs; ++c) {
+    const double bn = sc->bb[c], rn = sc->rr[c];
+    if (!isfinite(bn) || !isfinite(rn)) finite = false;
+    const double rel = bn > 0.0 ? sqrt(rn / bn) : 0.0;
+    if (!(rel <= worst)) worst = rel;
+  }
+  sc->iters = it;
+  if (!finite) {
+    sc->relres = NAN;
+    sc->done = -1;
+    return;
+  }
+  sc->relres = worst;
+  if (worst <= rtol) sc->done = 1;
 }
 
 static inline unsigned pblk(int n) { return (unsigned)((n + 255) / 256); }
 
-void launch_pcg_init(int n, int nrhs, const double* b, int ld, double* x, double* r, hipStream_t s) {
-  if (n > 0) k_pcg_init<<<pblk(n), 256, 0, s>>>(n, nrhs, b, ld, x, r);
+void launch_pcg_init(int n, int nrhs, const double* b, int ld, double* x, double* r,
+                     PcgScalars* sc, hipStream_t s) {
+  k_pcg_init<<<std::max(pblk(n), 1u), 256, 0, s>>>(n, nrhs, b, ld, x, r, sc);
+}
+void launch_pcg_check(int nrhs, double rtol, int it, PcgScalars* sc, hipStream_t s) {
+  k_pcg_check<<<1, 64, 0, s>>>(nrhs, rtol, it, sc);
+}
+
+__global__ void k_pcg_record(const PcgScalars* sc, DevState* st) {
+  st->pcg_relres = sc->relres;
+  st->pcg_iters = sc->iters;
+  st->pcg_done = sc->done;
+}
+void launch_pcg_record(const PcgScalars* sc, DevState* st, hipStream_t s) {
+  k_pcg_record<<<1, 1, 0, s>>>(sc, st);
 }
 void launch_pcg_copy(int n, int nrhs, const double* a, double* out, hipStream_t s) {
   if (n > 0) k_pcg_copy<<<pblk(n), 256, 0, s>>>(n, nrhs, a, out);

@@ -11,7 +11,7 @@ template <class T>
 static fg_status dalloc(T** p, size_t count, std::string& err) {
   *p = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+  if (dev_alloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
     (void)hipGetLastError();
     err = "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed";
     return FG_ENOMEM;
@@ -21,7 +21,7 @@ static fg_status dalloc(T** p, size_t count, std::string& err) {
 
 template <class T>
 static void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) dev_free(p);
   p = nullptr;
 }
 
@@ -62,16 +62,22 @@ void plan_pack_sizes(PlanPack* pk) {
   pk->ap_work = apply_work_doubles(P, 4);
 }
 
-PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
-                           double tol, hipStream_t s, fg_status& st, std::string& err) {
+PlanPack* plan_pack_make(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                         double tol, fg_status& st, std::string& err) {
   PlanPack* pk = new PlanPack();
   st = make_plan(xh, n, kind, ell, nugget, leaf, tol, pk->P, err);
   if (st != FG_OK) { delete pk; return nullptr; }
   plan_pack_sizes(pk);
+  return pk;
+}
+
+fg_status plan_pack_upload(PlanPack* pk, hipStream_t s, bool sync, std::string& err) {
+  fg_status st;
   HostPlan& P = pk->P;
   DevPlan& D = pk->D;
-  std::vector<int> kc(P.kcap), co(P.coff);
-  if (kc.empty()) kc.push_back(0);
+  pk->kc_host = P.kcap;
+  pk->co_host = P.coff;
+  if (pk->kc_host.empty()) pk->kc_host.push_back(0);
   if ((st = upload(&D.nodes, P.nodes, s, err)) != FG_OK ||
       (st = upload(&D.leaf_lo, P.leaf_lo, s, err)) != FG_OK ||
       (st = upload(&D.mtasks, P.mtasks, s, err)) != FG_OK ||
@@ -79,21 +85,30 @@ PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double
       (st = upload(&D.gtasks, P.gtasks, s, err)) != FG_OK ||
       (st = upload(&D.ltasks, P.ltasks, s, err)) != FG_OK ||
       (st = upload(&D.node_task_off, P.node_task_off, s, err)) != FG_OK ||
-      (st = upload(&D.coff, co, s, err)) != FG_OK || (st = upload(&D.kcap, kc, s, err)) != FG_OK ||
-      (st = upload(&D.nodemat_off, pk->nodemat_off, s, err)) != FG_OK) {
-    plan_pack_destroy(pk);
-    return nullptr;
-  }
+      (st = upload(&D.coff, pk->co_host, s, err)) != FG_OK ||
+      (st = upload(&D.kcap, pk->kc_host, s, err)) != FG_OK ||
+      (st = upload(&D.nodemat_off, pk->nodemat_off, s, err)) != FG_OK)
+    return st;
+  if (!sync) return FG_OK;  // the host vectors stay until the pack is destroyed
   // the uploads read host vectors: finish them before the vectors are released
   if (hipStreamSynchronize(s) != hipSuccess) {
     err = "stream synchronisation failed";
-    st = FG_EDEVICE;
-    plan_pack_destroy(pk);
-    return nullptr;
+    return FG_EDEVICE;
   }
   std::vector<Task>().swap(P.mtasks);
   std::vector<Task>().swap(P.gtasks);
   std::vector<Task>().swap(P.ltasks);
+  return FG_OK;
+}
+
+PlanPack* plan_pack_create(const double* xh, int n, int kind, double ell, double nugget, int leaf,
+                           double tol, hipStream_t s, fg_status& st, std::string& err) {
+  PlanPack* pk = plan_pack_make(xh, n, kind, ell, nugget, leaf, tol, st, err);
+  if (!pk) return nullptr;
+  if ((st = plan_pack_upload(pk, s, true, err)) != FG_OK) {
+    plan_pack_destroy(pk);
+    return nullptr;
+  }
   return pk;
 }
 
@@ -136,12 +151,19 @@ size_t hodlr_bytes(const Caps& c) {
 
 size_t factor_bytes(const Caps& c, bool fp32) {
   const size_t ld = round_ld(c.n), ni = std::max(c.nint, 1);
-  const size_t big = 2 * (size_t)c.nleaf * c.B * c.B + ld * c.Ktot;
-  return (fp32 ? 4 : 8) * big +
+  const size_t leaves = 2 * (size_t)c.nleaf * c.B * c.B;  // L and its diagonal-block inverses
+  return (fp32 ? 4 : 8) * leaves + 8 * ld * c.Ktot +
          8 * ((size_t)c.nleaf + c.nodemat + ni + c.zpart + c.zfin + c.coef + 1 + c.ap_work) + 4;
 }
 
-fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err) {
+static void zero_bytes(void* p, size_t bytes, hipStream_t s, bool async) {
+  if (async)
+    (void)hipMemsetAsync(p, 0, bytes, s);
+  else
+    (void)hipMemset(p, 0, bytes);
+}
+
+fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err, hipStream_t s, bool async) {
   fg_status st;
   H.ld = round_ld(c.n);
   const int Lm = std::max(c.L, 1);
@@ -157,8 +179,8 @@ fg_status hodlr_alloc(HodlrData& H, const Caps& c, std::string& err) {
     hodlr_free(H);
     return st;
   }
-  (void)hipMemset(H.status, 0, sizeof(int));
-  (void)hipMemset(H.kmax, 0, sizeof(int) * Lm);
+  zero_bytes(H.status, sizeof(int), s, async);
+  zero_bytes(H.kmax, sizeof(int) * Lm, s, async);
   return FG_OK;
 }
 
@@ -168,18 +190,17 @@ void hodlr_free(HodlrData& H) {
   dfree(H.rcols); dfree(H.rcount); dfree(H.panel); dfree(H.status); dfree(H.work);
 }
 
-fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32) {
+fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32, hipStream_t s,
+                       bool async) {
   fg_status st = FG_OK;
   const size_t ld = round_ld(c.n);
   const size_t bb = (size_t)c.nleaf * c.B * c.B;
   F.fp32 = fp32;
   const bool ok64 = fp32 || ((st = dalloc(&F.leafL, bb, err)) == FG_OK &&
-                             (st = dalloc(&F.leafLinv, bb, err)) == FG_OK &&
-                             (st = dalloc(&F.panel, ld * c.Ktot, err)) == FG_OK);
+                             (st = dalloc(&F.leafLinv, bb, err)) == FG_OK);
   const bool ok32 = !fp32 || ((st = dalloc(&F.leafLf, bb, err)) == FG_OK &&
-                              (st = dalloc(&F.leafLinvf, bb, err)) == FG_OK &&
-                              (st = dalloc(&F.panelf, ld * c.Ktot, err)) == FG_OK);
-  if (!ok64 || !ok32) {
+                              (st = dalloc(&F.leafLinvf, bb, err)) == FG_OK);
+  if (!ok64 || !ok32 || (st = dalloc(&F.panel, ld * c.Ktot, err)) != FG_OK) {
     factor_free(F);
     return st;
   }
@@ -193,14 +214,14 @@ fg_status factor_alloc(FactorData& F, const Caps& c, std::string& err, bool fp32
     factor_free(F);
     return st;
   }
-  (void)hipMemset(F.status, 0, sizeof(int));
-  (void)hipMemset(F.node_ld, 0, sizeof(double) * std::max(c.nint, 1));
+  zero_bytes(F.status, sizeof(int), s, async);
+  zero_bytes(F.node_ld, sizeof(double) * std::max(c.nint, 1), s, async);
   return FG_OK;
 }
 
 void factor_free(FactorData& F) {
   dfree(F.leafL); dfree(F.leafLinv); dfree(F.leaf_ld); dfree(F.panel); dfree(F.nodemat);
-  dfree(F.leafLf); dfree(F.leafLinvf); dfree(F.panelf);
+  dfree(F.leafLf); dfree(F.leafLinvf);
   dfree(F.node_ld); dfree(F.zpart); dfree(F.zfin); dfree(F.coef); dfree(F.logdet);
   dfree(F.status); dfree(F.work);
 }

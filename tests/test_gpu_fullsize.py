@@ -1,7 +1,15 @@
 """Parity at the full large 1-D workload (n = 2^20, leaf 128, tol 1e-10, ell 0.02):
-sampled entries of K~_1, log-determinants of K~_1 and of M~ = tau K~_1 + I, the solve
-r = M~^-1 tau y and the posterior mean mu~ = K~_1 r / tau, against the oracle run at
-the same size."""
+ranks and sampled entries of K~_1, the two parts of the log-determinants of K~_1 and of
+M~ = tau K~_1 + I, the solve r = M~^-1 tau y and the posterior mean mu~ = K~_1 r / tau,
+and the first Gibbs sweep, against the oracle run at the same size.
+
+Bars: integers exact (a rank may differ only where the oracle's singular value sits
+within 1e-9 of the truncation threshold); the leaf part 2 sum log diag L_D and the node
+part sum log(1 - s^2) of each log-determinant at 1e-9 relative, each on its own (at this
+size they are +9.0e4 and -8.9e4 around a total of 1.5e3 for M~, so the total is only as
+well conditioned as the parts); solves, products and everything built on M~ at 1e-9;
+outputs that pass through the factor of K~_1 itself (f contains W_1 b; q = |W_1^-1 f|^2)
+at four times the oracle's own reproducibility band measured here, never below 1e-9."""
 import numpy as np
 import pytest
 
@@ -47,7 +55,13 @@ def test_ranks_and_sampled_entries(big):
     got = K1.ranks()
     ref = [H.blocks[(l, j)].k for l in range(H.tree.L) for j in range(1 << l)]
     bad = [h for h in range(len(ref)) if got[h] != ref[h]]
-    assert len(bad) <= max(1, len(ref) // 1000), bad[:10]
+    # a mismatch is only acceptable at a near-tie of the rank rule
+    for h in bad:
+        l = int(np.log2(h + 1))
+        b = H.blocks[(l, h - (1 << l) + 1)]
+        margin = np.min(np.abs(b.sv / b.thr - 1.0))
+        assert margin < 1e-9, (h, got[h], ref[h], margin)
+    print(f"rank mismatches (all at near-ties): {len(bad)} of {len(ref)}")
     rs = np.random.default_rng(0)
     n = H.n
     ii = rs.integers(0, n, 4000)
@@ -58,6 +72,24 @@ def test_ranks_and_sampled_entries(big):
     g = g.cpu().numpy()
     ref = np.array([_entry(H, int(a), int(b)) for a, b in zip(ii, jj)])
     assert np.abs(g - ref).max() <= 1e-9
+
+
+def _oracle_parts(OF):
+    """(leaf part, node part) of the oracle factor's log-determinant."""
+    leaf = sum(2.0 * float(np.sum(np.log(np.diag(Lb)))) for Lb in OF.leafL)
+    node = sum(float(np.sum(np.log((1.0 - nf.sig) * (1.0 + nf.sig)))) for nf in OF.nodes.values())
+    return leaf, node
+
+
+def _check_parts(W, OF, what, node_bar=1e-9):
+    g = W.logdet_parts().cpu().numpy()
+    leaf, node = _oracle_parts(OF)
+    e_leaf, e_node = abs(g[0] - leaf) / abs(leaf), abs(g[1] - node) / abs(node)
+    print(f"{what}: leaf part {leaf:.6e} rel err {e_leaf:.2e}; node part {node:.6e} rel err "
+          f"{e_node:.2e} (bar {node_bar:.2e})")
+    assert e_leaf <= 1e-9 and e_node <= node_bar
+    # the reported total is the sum of the two parts
+    assert abs(float(W.logdet().cpu()[0]) - (g[0] + g[1])) <= 1e-12 * (abs(g[0]) + abs(g[1]))
 
 
 def _logdet_mass(H, alpha, beta, total):
@@ -78,9 +110,7 @@ def test_logdet_solve_mean(big):
     WM = fg.Factor(K1, tau, 1.0)
     OM = oh.Factor(H, tau, 1.0)
     assert WM.status() == 0
-    ld = float(WM.logdet().cpu()[0])
-    ref = OM.logdet()
-    assert abs(ld - ref) <= 1e-9 * _logdet_mass(H, tau, 1.0, ref)
+    _check_parts(WM, OM, "log|M~|")
     yt = torch.tensor(big["y"], device=big["dev"])
     r = WM.solve(tau * yt).cpu().numpy()
     ro = OM.solve(tau * big["y"])
@@ -91,22 +121,47 @@ def test_logdet_solve_mean(big):
 
 
 def test_logdet_k1(big):
+    """log|K~_1| (alpha 1, beta 0, nugget 1e-6).  The leaf part at 1e-9.  The top node
+    factors of K~_1 sit at 1 - s^2 ~ 1e-7, where a rounding-level change of s^2 moves
+    log(1 - s^2) by |d s^2| / (1 - s^2).  The node part is held to the larger of
+      * four times the oracle's own reproducibility band (the largest distance between
+        the oracle and the same factor (a) with unblocked leaf Choleskys and explicit leaf
+        inverses, (b) on compressed panels perturbed by 4 u, as another FP64 compression
+        would store them), never below 1e-9 -- the bar of every operator of this factor;
+      * the first-order error of the Gram route the HIP path takes for the node factors
+        (s^2 are eigenvalues of products of Gram matrices summed over the m rows of the
+        node): |d s_i^2| <= 2 s_i^2 sqrt(m) u, the usual rounding estimate of an m-term
+        FP64 sum, so |d node part| <= sum_nodes sum_i 2 s_i^2 sqrt(m) u / (1 - s_i^2)."""
+    from bands import InvLeafFactor, perturbed_panels
     fg, H, K1 = big["fg"], big["H"], big["K1"]
     W1 = fg.Factor(K1, 1.0, 0.0)
     O1 = oh.Factor(H, 1.0, 0.0)
-    ref = O1.logdet()
-    assert abs(float(W1.logdet().cpu()[0]) - ref) <= 1e-9 * _logdet_mass(H, 1.0, 0.0, ref)
+    node = _oracle_parts(O1)[1]
+    alts = [InvLeafFactor(H, 1.0, 0.0)] + [oh.Factor(perturbed_panels(H, seed=s_), 1.0, 0.0)
+                                           for s_ in (1, 2)]
+    band = max(abs(_oracle_parts(v)[1] - node) / abs(node) for v in alts)
+    u = 2.0 ** -53
+    gram = 0.0
+    for (l, j), nf in O1.nodes.items():
+        lo, mid, hi = H.tree.node(l, j)
+        s2 = nf.sig ** 2
+        gram += float(np.sum(2.0 * s2 / (1.0 - s2))) * np.sqrt(hi - lo) * u
+    gram /= abs(node)
+    print(f"node part of log|K~_1|: oracle band {band:.2e}, Gram-route bound {gram:.2e}")
+    _check_parts(W1, O1, "log|K~_1|", node_bar=max(1e-9, 4.0 * band, gram))
 
 
 def test_first_sweep_and_predictions_full_size(big):
     """One sweep of the large workload as the benchmark runs it (n = 2^20, leaf 128), then
     predictive draws at 8 new inputs, against the oracle's chain.  Bars: the grid move is
-    exact; f takes the W-operator bar b_W = max(1e-9, 2 u kappa(leaf)) (f = w + K~ r with
-    w containing W_1 b); tau follows the sum of squares |y - f|^2, whose relative error is
-    at most 2 b_W |f| / |y - f|; q = |W_1^-1 f|^2 takes 2.5 b_W, and sigma_f^2 follows q;
-    the log-likelihood takes the log-det mass bar of M~ plus 1e-9 |y'r|.  The predictions
-    take the bars of the small-size prediction test with b_W, plus four times the oracle's
-    own band (unblocked leaves; panels perturbed by 4 u)."""
+    exact; f, which contains W_1 b, takes b_f = max(1e-9, 4 x the oracle's own band for f)
+    -- the band being the distance between the oracle's f and the same draw with both
+    factors evaluated with unblocked leaf Choleskys and explicit leaf inverses; q =
+    |W_1^-1 f|^2 takes b_q, built the same way; tau follows the sum of squares |y - f|^2,
+    whose relative error is at most 2 b_f |f| / |y - f|; sigma_f^2 follows q; the
+    log-likelihood takes the parts bar of log|M~| plus 1e-9 |y'r|.  The predictions take
+    the bars of the small-size prediction test with the W_1^-1 band, plus four times the
+    oracle's own band of each output (unblocked leaves; panels perturbed by 4 u)."""
     from oracle import predict, rng, sampler
     from bands import InvLeafFactor, perturbed_panels
     fg, H, c = big["fg"], big["H"], big["c"]
@@ -121,19 +176,34 @@ def test_first_sweep_and_predictions_full_size(big):
     fs, mu, s2 = (t.cpu().numpy() for t in g.predict())
     o = sampler.Chain(x, y, kernels.SE, c["ell0"], c["nugget"], c["leaf"], c["tol"], c["tau0"],
                       c["sigf2_0"], c["seed"])
-    kap = max(np.linalg.cond(o.H.leaf_block(lo, hi)) for lo, hi in o.H.tree.leaves())
-    bw = max(1e-9, 2.0 * 2.0 ** -53 * kap)
+    H0, tau0, s20 = o.H, o.tau, o.sigf2
     r = o.step()
+    # the oracle's own band: the same draw with the second FP64 evaluation of both factors
+    n = x.size
+    a_ = rng.normals(n, c["seed"], rng.TAG_A, 0, 0)
+    b_ = rng.normals(n, c["seed"], rng.TAG_B, 0, 0)
+    W1v = InvLeafFactor(H0, 1.0, 0.0)
+    fv, _, _ = sampler.draw_f(H0, W1v, InvLeafFactor(H0, tau0 * s20, 1.0), s20, tau0, y, a_, b_)
+    band_f = np.linalg.norm(fv - o.f) / np.linalg.norm(o.f)
+    uf = W1v.apply_Winv(o.f)  # q is taken with the factor of the draw's length-scale
+    band_q = abs(float(uf @ uf) - r["q"]) / r["q"]
+    bf = max(1e-9, 4.0 * band_f)
+    bq = max(1e-9, 4.0 * band_q)
     assert s["status"] == 0
     assert (s["k"], s["last_proposal"], s["last_accept"]) == (r["k"], r["proposal"], int(r["accept"]))
     f = s["f"].cpu().numpy()
-    assert np.linalg.norm(f - o.f) <= bw * np.linalg.norm(o.f)
+    ef = np.linalg.norm(f - o.f) / np.linalg.norm(o.f)
+    print(f"f rel err {ef:.2e} (oracle band {band_f:.2e}, bar {bf:.2e}); q rel err "
+          f"{abs(s['q'] - r['q']) / r['q']:.2e} (band {band_q:.2e}, bar {bq:.2e})")
+    assert ef <= bf
     e = np.linalg.norm(y - o.f)
-    assert abs(s["tau"] - r["tau"]) <= (1e-9 + 2.0 * bw * np.linalg.norm(o.f) / e) * r["tau"]
-    assert abs(s["q"] - r["q"]) <= 2.5 * bw * r["q"]
-    assert abs(s["sigf2"] - r["sigf2"]) <= (1e-9 + 2.5 * bw) * r["sigf2"]
+    assert abs(s["tau"] - r["tau"]) <= (1e-9 + 2.0 * bf * np.linalg.norm(o.f) / e) * r["tau"]
+    assert abs(s["q"] - r["q"]) <= bq * r["q"]
+    assert abs(s["sigf2"] - r["sigf2"]) <= (1e-9 + bq) * r["sigf2"]
     ldM = r["logdet_sigma"] + c["n"] * np.log(c["tau0"])
-    # the f-draw factors M~ at the starting length-scale, whose oracle HODLR is H
+    # the f-draw factors M~ at the starting length-scale, whose oracle HODLR is H: its
+    # log-det parts are each held to 1e-9 (test_logdet_solve_mean), which bounds the
+    # total by 1e-9 (|leaf part| + |node part|)
     mass = _logdet_mass(H, c["tau0"] * c["sigf2_0"], 1.0, ldM)
     assert abs(s["loglik"] - r["loglik"]) <= 0.5e-9 * mass + 0.5e-9 * abs(r["yr"])
     # predictive draws at the state after the sweep
@@ -142,6 +212,10 @@ def test_first_sweep_and_predictions_full_size(big):
     Kx = kernels.k1(kernels.SE, o.H.ell, x, xs)
     zn = np.linalg.norm(o.W1.apply_Winv(Kx), axis=0)
     zf = np.linalg.norm(o.W1.apply_Winv(o.f))
+    # the W_1^-1 bar from the oracle's own band of W_1^-1 f (at the post-sweep state)
+    w_ref = o.W1.apply_Winv(o.f)
+    w_alt = InvLeafFactor(o.H, 1.0, 0.0).apply_Winv(o.f)
+    bw = max(1e-9, 4.0 * np.linalg.norm(w_alt - w_ref) / np.linalg.norm(w_ref))
     # the oracle's own band for these outputs: an unblocked-leaf evaluation of W_1 and a
     # compression whose panels differ by a few rounding units (near and past the data's
     # edge K~_1^-1 k grows to ~1e2 and the quadratic form follows the compression closely)

@@ -1,12 +1,14 @@
 """Serving loop: jobs of mixed n submitted while others run are admitted by memory
-footprint, advanced together one sweep at a time, and each job's result equals the
-same chain run alone, bit for bit (chains share no buffers, reductions are
-deterministic)."""
+footprint into blocks of one device arena, each advanced on its own stream, and each
+job's result equals the same chain run alone, bit for bit (chains share no buffers,
+reductions are deterministic); served results are also held to the oracle's chain."""
 import time
 
 import numpy as np
 import pytest
 
+from bands import InvLeafFactor
+from oracle import kernels, sampler
 from workloads import sinusoid_1d
 
 pytestmark = pytest.mark.gpu
@@ -24,11 +26,14 @@ JOBS = [  # n, ell0, iters, seed
 ]
 
 
-def alone(n, ell0, iters, seed):
+SLACK = 1 << 20  # a block is the footprint plus the 256-byte rounding of each allocation
+
+
+def alone(n, ell0, iters, seed, precision=0):
     x, y = sinusoid_1d(n, seed=seed)
     dev = torch.device("cuda:0")
     c = fg().Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0=ell0,
-                   tau0=400.0, leaf=64, tol=1e-10, seed=seed, stream_id=seed)
+                   tau0=400.0, leaf=64, tol=1e-10, seed=seed, stream_id=seed, precision=precision)
     c.step(iters)
     return c.state(with_vectors=True)
 
@@ -39,8 +44,9 @@ def test_served_jobs_equal_alone_and_respect_the_budget():
         x, _ = sinusoid_1d(n, seed=seed)
         est[seed] = fg().footprint_bytes(x, ell0, leaf=64)
     # room for about three of the jobs at a time
-    budget = int(sorted(est.values())[-1] + sorted(est.values())[-2] + min(est.values()))
-    srv = fg().Server(budget, max_active=8, nstreams=4, graphs=True)
+    budget = int(sorted(est.values())[-1] + sorted(est.values())[-2] + min(est.values())
+                 + 3 * SLACK)
+    srv = fg().Server(budget, max_active=8)
     ids = {}
     for k, (n, ell0, iters, seed) in enumerate(JOBS):
         x, y = sinusoid_1d(n, seed=seed)
@@ -65,7 +71,7 @@ def test_served_jobs_equal_alone_and_respect_the_budget():
     for k, (n, ell0, iters, seed) in enumerate(JOBS):
         r = by_k[k]
         assert r["status"] == 0 and r["iteration"] == iters
-        assert r["bytes"] == est[seed], (r["bytes"], est[seed])
+        assert est[seed] <= r["bytes"] <= est[seed] + SLACK, (r["bytes"], est[seed])
         s = alone(n, ell0, iters, seed)
         assert np.array_equal(r["f"], s["f"].cpu().numpy()), k
         for key in ["tau", "sigf2", "k", "accepts", "loglik"]:
@@ -78,3 +84,55 @@ def test_serve_rejects_unsorted_inputs():
     with pytest.raises(fg().FgError):
         srv.submit(x, x, 0.1, 2)
     srv.close()
+
+
+def test_served_jobs_match_the_oracle_and_reuse_slots():
+    """Twelve small jobs through four slots (FP64 and mixed precision alternating): slots
+    and arena blocks are reused as jobs retire; every FP64 job equals the oracle's chain
+    run for the same sweeps at 1e-9 (grid moves exact), and every mixed job equals the
+    same mixed chain run alone, bit for bit, and the oracle within kappa(M~) 1e-10."""
+    jobs = [(500 + 97 * k, 0.03 + 0.01 * k, 3 + k % 3, 40 + k, k % 2) for k in range(12)]
+    srv = fg().Server(4 << 30, max_active=4)
+    ids = {}
+    for k, (n, ell0, iters, seed, prec) in enumerate(jobs):
+        x, y = sinusoid_1d(n, seed=seed)
+        ids[srv.submit(x, y, ell0, iters, tau0=400.0, leaf=64, seed=seed, stream_id=seed,
+                       precision=prec)] = k
+    srv.drain(300.0)
+    res = srv.poll()
+    srv.close()
+    assert len(res) == len(jobs)
+    worst = 0.0
+    for r in res:
+        k = ids[r["id"]]
+        n, ell0, iters, seed, prec = jobs[k]
+        assert r["status"] == 0 and r["iteration"] == iters, (k, r["status"])
+        x, y = sinusoid_1d(n, seed=seed)
+        o = sampler.Chain(x, y, kernels.SE, ell0, 1e-6, 64, 1e-10, 400.0, 1.0, seed, stream=seed)
+        kappa, band_q = 1.0, 0.0
+        for _ in range(iters):
+            # kappa(M~) of this sweep's draw: 1 + tau sigma_f^2 lambda_max(K~_1)
+            kappa = max(kappa, 1.0 + o.tau * o.sigf2 * np.linalg.eigvalsh(o.H.dense())[-1])
+            Hd = o.H
+            rec = o.step()
+            # sigma_f^2 follows q = |W_1^-1 f|^2, taken with the factor of K~_1 itself: the
+            # oracle's own band for it (unblocked leaves, explicit leaf inverses)
+            u = InvLeafFactor(Hd, 1.0, 0.0).apply_Winv(o.f)
+            band_q = max(band_q, abs(float(u @ u) - rec["q"]) / rec["q"])
+        assert r["k"] == rec["k"] and r["last_accept"] == int(rec["accept"])
+        ef = np.linalg.norm(r["f"] - o.f) / np.linalg.norm(o.f)
+        et = abs(r["tau"] - o.tau) / o.tau
+        es = abs(r["sigf2"] - o.sigf2) / o.sigf2
+        if prec == 0:
+            bar = 1e-9
+            assert ef <= bar and et <= bar and es <= max(1e-9, 4.0 * band_q), (k, ef, et, es, band_q)
+        else:
+            a = alone(n, ell0, iters, seed, precision=1)
+            assert np.array_equal(r["f"], a["f"].cpu().numpy()) and r["tau"] == a["tau"], k
+            assert r["precision_used"] == 1
+            # PCG to 1e-10: forward error <= kappa(M~) 1e-10; tau follows |y - f|^2
+            bar = kappa * 1e-10 + 1e-9
+            amp = 2.0 * np.linalg.norm(o.f) / np.linalg.norm(y - o.f)
+            assert ef <= bar and et <= 1e-9 + amp * bar, (k, ef, et)
+        worst = max(worst, ef / bar)
+    print(f"served jobs vs oracle: worst f error / bar {worst:.2e}")

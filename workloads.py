@@ -80,7 +80,8 @@ def served_jobs(count: int = 512, seed: int = 5):
     """GP-regression jobs for the serving workload, in arrival order: n log-uniform on
     [1e3, 2e5], sorted x ~ U[0,1], y = 5-sinusoid mixture (the large_1d generator's
     recipe) + N(0, s^2) with s ~ U[0.02, 0.2], grid centre ell0 log-uniform on
-    [0.01, 0.3].  Returns a list of dicts (x, y, ell0, noise, seed)."""
+    [0.01, 0.3].  Returns a list of dicts (x, y, ell0, noise, tau0 = 1 / noise^2 -- the
+    chain's starting noise precision --, seed, n)."""
     rng = np.random.default_rng(seed)
     jobs = []
     for j in range(count):
@@ -89,7 +90,8 @@ def served_jobs(count: int = 512, seed: int = 5):
         ell0 = float(math.exp(rng.uniform(math.log(0.01), math.log(0.3))))
         jseed = int(rng.integers(1, 2 ** 31))
         x, y = sinusoid_1d(n, seed=jseed, noise=noise)
-        jobs.append(dict(x=x, y=y, ell0=ell0, noise=noise, seed=jseed, n=n))
+        jobs.append(dict(x=x, y=y, ell0=ell0, noise=noise, tau0=1.0 / noise ** 2, seed=jseed,
+                         n=n))
     return jobs
 
 
