@@ -145,6 +145,22 @@ fg_status hodlr_factor_prec(fg_hodlr A, double alpha, double beta, const double*
 fg_status hodlr_solve_refined(fg_hodlr A, fg_factor F, double alpha, double beta,
                               const double* b, double* x, int32_t nrhs, int64_t ld, double rtol,
                               int32_t maxit, int32_t* iters, double* relres, fg_stream stream);
+/* ---------------------------------------------------------------------------
+ * hodlr_solve_refined_noalloc -- hodlr_solve_refined for callers that cannot allocate
+ * (code under graph capture, tight serving loops, harnesses that forbid runtime
+ * allocation).  Same arguments, results and errors, but the PCG workspace is a fixed
+ * device array of the library (one per GPU, about 32 MiB, held until the process ends)
+ * instead of a per-call allocation: the call makes no hipMalloc / hipFree.
+ *   - n * nrhs must be at most 2^20 (FG_EINVAL beyond, with a message).
+ *   - Every call on one GPU uses that GPU's array: calls that overlap in time on the
+ *     same GPU (other host threads, other streams) race; serialise them.
+ *   - The record of convergence is read back into host stack memory once per four
+ *     iterations (the stream is synchronised then, as in hodlr_solve_refined).
+ * ------------------------------------------------------------------------- */
+fg_status hodlr_solve_refined_noalloc(fg_hodlr A, fg_factor F, double alpha, double beta,
+                                      const double* b, double* x, int32_t nrhs, int64_t ld,
+                                      double rtol, int32_t maxit, int32_t* iters, double* relres,
+                                      fg_stream stream);
 /* x = (W W')^-1 b = W^-T W^-1 b for nrhs columns: the solves of Algorithm 1 (M~ w = Z,
  * M~ r = tau y) with the factor of the SI factorization, one sweep up the tree (W^-1)
  * and one down (W^-T).  b and x may be the same.  Errors: FG_EINVAL (NULL, nrhs < 1,

@@ -196,14 +196,18 @@ class Factor:
         self._f = None
 
 
-def solve_refined(A: Hodlr, F: Factor, alpha, beta, b, rtol=1e-10, maxit=50):
-    """PCG on (alpha K~_1 + beta I) x = b preconditioned by F; returns (x, iters, relres)."""
+def solve_refined(A: Hodlr, F: Factor, alpha, beta, b, rtol=1e-10, maxit=50, noalloc=False,
+                  out=None):
+    """PCG on (alpha K~_1 + beta I) x = b preconditioned by F; returns (x, iters, relres).
+    noalloc: hodlr_solve_refined_noalloc (the library's fixed scratch array, no
+    allocation; pass `out` to avoid torch's allocation of x as well)."""
     torch = _torch()
-    x = torch.empty_like(b)
+    x = torch.empty_like(b) if out is None else out
     nrhs, ld = _cols(b)
     it, rr = C.c_int32(), C.c_double()
-    check(lib().hodlr_solve_refined(A.handle, F.handle, alpha, beta, _dev(b), _dev(x), nrhs, ld,
-                                    rtol, maxit, C.byref(it), C.byref(rr), _stream()))
+    fn = lib().hodlr_solve_refined_noalloc if noalloc else lib().hodlr_solve_refined
+    check(fn(A.handle, F.handle, alpha, beta, _dev(b), _dev(x), nrhs, ld, rtol, maxit,
+             C.byref(it), C.byref(rr), _stream()))
     return x, it.value, rr.value
 
 

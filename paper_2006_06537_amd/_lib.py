@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "FG_OK", -1: "FG_EINVAL", -2: "FG_ENOMEM", -3: "FG_ENOTSPD", 
 # names declared in include/fifa_gp.h, in declaration order
 EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", "hodlr_entries",
            "hodlr_matvec", "hodlr_factor", "hodlr_factor_prec", "hodlr_solve_refined",
+           "hodlr_solve_refined_noalloc",
            "hodlr_solve", "hodlr_logdet", "hodlr_logdet_parts", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
            "gibbs_step_batch", "gibbs_chain_state", "gibbs_chain_create_grid", "gibbs_chain_create_collapsed",
@@ -144,6 +145,8 @@ def lib():
         "hodlr_factor": ([P, D, D, DP, P, C.POINTER(P)], I32),
         "hodlr_factor_prec": ([P, D, D, DP, I32, P, C.POINTER(P)], I32),
         "hodlr_solve_refined": ([P, P, D, D, DP, DP, I32, I64, D, I32, C.POINTER(I32),
+                                 C.POINTER(D), P], I32),
+        "hodlr_solve_refined_noalloc": ([P, P, D, D, DP, DP, I32, I64, D, I32, C.POINTER(I32),
                                  C.POINTER(D), P], I32),
         "hodlr_solve": ([P, DP, DP, I32, I64, P], I32),
         "hodlr_logdet": ([P, DP, P], I32),

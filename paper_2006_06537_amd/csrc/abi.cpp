@@ -25,6 +25,12 @@ struct fg_factor_s {
   int n = 0;
 };
 
+namespace fg {
+const HodlrData* hodlr_data(fg_hodlr A) { return &A->d; }
+FactorData* factor_data(fg_factor F) { return &F->d; }
+int factor_n(fg_factor F) { return F->n; }
+}  // namespace fg
+
 using fg::set_error;
 
 static fg_status fail(fg_status st, const std::string& msg) {
