@@ -11,9 +11,10 @@ baseline).  Only one GPU is used: --gpus above 1 exits with a message.
 
 Other workloads (--workload), each printing its own JSON line:
   batch   64 independent chains, n = 32,768 each (the large-workload generator with
-          seeds 1000 + c), stepped together by gibbs_step_batch with captured sweep
-          graphs; value = chain sweeps per second over all chains.  The same chains
-          stepped one after the other (gibbs_step) are timed beside it.
+          seeds 1000 + c), stepped together by gibbs_step_batch in the mode its autotuner
+          picks (grouped launches, eager streams or captured graphs); value = chain sweeps
+          per second over all chains.  Every mode, and the same chains stepped one after
+          the other (gibbs_step), are timed beside it.
   tensor  the d = 4, n = 65,536 tensor-product surface chain; value = sweeps/s.
   copy    a plain 2 GiB FP64 copy kernel (one read, one write of 2 GiB per launch): the
           calibration run for the HBM byte counters (FETCH_SIZE, WRITE_SIZE).
@@ -184,18 +185,27 @@ def bench_batch(args):
 
     chains = make()
     print(f"bench: {args.chains} chains ready (n={n})", file=sys.stderr, flush=True)
-    fg.step_batch(chains, args.warmup, nstreams=4, graphs=False)
-    dt = timed(lambda: fg.step_batch(chains, args.steps, nstreams=4, graphs=False))
-    print(f"bench: batched eager {dt:.3f} s", file=sys.stderr, flush=True)
-    fg.step_batch(chains, 1, nstreams=4, graphs=True)  # capture outside the timing
-    dt_graph = timed(lambda: fg.step_batch(chains, args.steps, nstreams=4, graphs=True))
-    print(f"bench: batched with graphs {dt_graph:.3f} s", file=sys.stderr, flush=True)
+    # the autotuner's trials (8 sweeps) first, untimed
+    fg.step_batch(chains, 8, nstreams=4, mode=fg.BATCH_AUTO)
+    choice = fg.batch_tuning(chains)
+    print(f"bench: autotuner chose {choice}", file=sys.stderr, flush=True)
+    fg.step_batch(chains, args.warmup, mode=fg.BATCH_AUTO)
+    dt = timed(lambda: fg.step_batch(chains, args.steps, nstreams=4, mode=fg.BATCH_AUTO))
+    print(f"bench: batched, autotuned ({choice[0]}) {dt:.3f} s", file=sys.stderr, flush=True)
+    others = {}
+    for name, mode, ns in [("grouped", fg.BATCH_GROUPED, 1), ("eager_4_streams", fg.BATCH_EAGER, 4),
+                           ("graphs_4_streams", fg.BATCH_GRAPHS, 4)]:
+        fg.step_batch(chains, 1, nstreams=ns, mode=mode)  # graph capture outside the timing
+        d = timed(lambda: fg.step_batch(chains, args.steps, nstreams=ns, mode=mode))
+        others[name] = args.chains * args.steps / d
+        print(f"bench: batched {name} {d:.3f} s", file=sys.stderr, flush=True)
 
     def seq():
         for c in chains:
             c.step(args.steps)
     dt_seq = timed(seq)
     print(f"bench: sequential {dt_seq:.3f} s", file=sys.stderr, flush=True)
+    st = chains[0].state()
     tot = args.chains * args.steps
     pname = "mixed" if prec == fg.MIXED else "FP64"
     dname = "f32+f64" if prec == fg.MIXED else "f64"
@@ -203,10 +213,12 @@ def bench_batch(args):
           "chain Gibbs iters/s", args, dt, dname,
           {"workload": f"batch: {args.chains} independent {pname} chains, n={n} each (5-sinusoid y, "
                        "seeds 1000+c), SE kernel ell0=0.02, leaf 128, tol 1e-10; "
-                       "gibbs_step_batch on 4 streams, each chain forking its proposal build "
-                       "onto a second stream",
+                       "gibbs_step_batch with the autotuned mode (grouped launches, eager on "
+                       "2 or 4 streams, or captured graphs)",
            "chains": args.chains, "n": n},
-          batch_graphs_value=tot / dt_graph, sequential_value=tot / dt_seq)
+          autotuned=choice[0], autotuned_streams=choice[1], modes_chain_iters_per_s=others,
+          sequential_value=tot / dt_seq, status0=st["status"],
+          precision_used0=st["precision_used"], pcg_iters0=st["pcg_iters"])
 
 
 def bench_tensor(args):
@@ -511,12 +523,26 @@ def bench_serve(args):
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
-        srv.drain(1200.0)
+        while True:  # progress while the last jobs run
+            try:
+                srv.drain(30.0)
+                break
+            except fg.FgError as e:
+                if e.code != fg._lib.FG_ENOTCONV:
+                    raise
+                st_ = srv.stats()
+                print(f"bench: serving, {st_['outstanding']} jobs outstanding", file=sys.stderr,
+                      flush=True)
         span = time.perf_counter() - t0
         res = srv.poll(4096)
         st = srv.stats()
         srv.close()
         bad = [r for r in res if r["status"] != 0]
+        for r in bad[:10]:
+            j = r["id"] - 1
+            print(f"bench: job {j} (n={jobs[j]['n']}, ell0={jobs[j]['ell0']:.4g}, "
+                  f"tau0={jobs[j]['tau0']:.4g}) ended with status {r['status']} after "
+                  f"{r['iteration']} sweeps", file=sys.stderr, flush=True)
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         return span, lat, st, len(bad)
 
@@ -534,7 +560,7 @@ def bench_serve(args):
     # sequential FIFO of plain FP64 chains on the same arrivals: service times measured
     # one job at a time, queue replayed on the host
     dev = torch.device("cuda:0")
-    svc = []
+    svc, seq_bad = [], []
     for j, job in enumerate(jobs):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -544,7 +570,14 @@ def bench_serve(args):
         c.step(args.job_iters)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t1)
+        sst = c.state()["status"]
+        if sst != 0:
+            seq_bad.append(j)
+            print(f"bench: sequential job {j} (n={job['n']}) ended with status {sst}",
+                  file=sys.stderr, flush=True)
         del c
+        if j % 64 == 63:
+            print(f"bench: sequential FIFO, {j + 1} jobs timed", file=sys.stderr, flush=True)
     fin, seq_lat = 0.0, []
     for j in range(len(jobs)):
         fin = max(fin, arrivals[j]) + svc[j]
@@ -570,7 +603,8 @@ def bench_serve(args):
            "peak_bytes": st["peak_bytes"], "failed_jobs": bad,
            "sequential_fp64_fifo": {"p50": q(seq_lat, 50), "p99": q(seq_lat, 99),
                                     "throughput_jobs_per_s": len(jobs) / fin,
-                                    "mean_service_s": float(np.mean(svc))}}
+                                    "mean_service_s": float(np.mean(svc)),
+                                    "failed_jobs": len(seq_bad)}}
     print(json.dumps(out), flush=True)
 
 

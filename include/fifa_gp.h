@@ -285,18 +285,38 @@ fg_status gibbs_chain_create(const fg_chain_cfg* cfg, const double* x, const dou
  * selects which cached factor the next sweep uses). */
 fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream);
 /* ---------------------------------------------------------------------------
- * gibbs_step_batch -- `iters` sweeps of each of `nchains` distinct chains, spread
- * round-robin over `nstreams` (1..4) library streams of default priority, with one
- * host synchronisation per batched sweep instead of one per chain.  With
- * use_graphs != 0 each chain's sweep is captured once per (slot, grid index,
- * proposal) as a HIP graph and replayed (up to 48 captured sweeps per chain; none
- * while a kernel timer runs).  Results are identical to gibbs_step on each chain:
- * chains share no buffers and every reduction is deterministic.  The batch starts
- * after the work queued on `stream` and has finished when the call returns.
- * Errors: FG_EINVAL (NULL or repeated chain, nstreams out of range), FG_EDEVICE.
+ * gibbs_step_batch -- `iters` sweeps of each of `nchains` distinct chains (any sizes and
+ * precisions), with one host synchronisation per batched sweep instead of one per chain.
+ * `mode`:
+ *   FG_BATCH_EAGER    each chain's launches on one of `nstreams` (1..4) library streams
+ *                     (round-robin, default priority);
+ *   FG_BATCH_GRAPHS   as EAGER, each chain's sweep captured once per (slot, grid index,
+ *                     proposal, FP64 fallback, PCG budget) as a HIP graph and replayed (up
+ *                     to 48 captured sweeps per chain);
+ *   FG_BATCH_GROUPED  every chain's sweep is recorded, then the chains' launches of the
+ *                     same kernel at the same point are issued as ONE grouped launch (its
+ *                     blocks partitioned among the chains) on one stream: a batch issues
+ *                     about as many launches as one chain;
+ *   FG_BATCH_AUTO     an autotuner: the first eight sweeps of a batch signature (chain
+ *                     count, largest n, precision) try GROUPED and EAGER on 4 and 2
+ *                     streams and GRAPHS on 4, two sweeps each, the second timed; the
+ *                     fastest is kept for that signature (gibbs_batch_tuning reports it).
+ * While a kernel timer runs every mode runs as EAGER.  Results are identical to
+ * gibbs_step on each chain in every mode: chains share no buffers, every reduction is
+ * deterministic and the same kernels run on the same data.  The batch starts after the
+ * work queued on `stream` and has finished when the call returns.
+ * Errors: FG_EINVAL (NULL or repeated chain, nstreams or mode out of range), FG_EDEVICE.
  * ------------------------------------------------------------------------- */
+#define FG_BATCH_EAGER 0
+#define FG_BATCH_GRAPHS 1
+#define FG_BATCH_GROUPED 2
+#define FG_BATCH_AUTO 3
 fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int32_t nstreams,
-                           int32_t use_graphs, fg_stream stream);
+                           int32_t mode, fg_stream stream);
+/* The autotuner's choice for this batch's signature: *mode (-1 while still tuning),
+ * *nstreams and *ms_per_sweep (host, may be NULL) of the timed trial sweep. */
+fg_status gibbs_batch_tuning(fg_chain* chains, int32_t nchains, int32_t* mode, int32_t* nstreams,
+                             double* ms_per_sweep);
 /* Host snapshot of the scalars; if f_out (device, n) is not NULL it receives f
  * (and r_out, mu_out likewise: Sigma~^-1 y and K~ r of the last f-draw). */
 fg_status gibbs_chain_state(fg_chain c, fg_chain_snapshot* host_out, double* f_out,

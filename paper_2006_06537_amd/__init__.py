@@ -14,6 +14,7 @@ from ._lib import (FP64, MIXED, KERNEL_EXP, KERNEL_SE, KERNEL_MATERN32, KERNEL_M
                    Kernel, Result, ServeCfg, ServeStats, TpCfg, TpSnapshot, check, lib)
 
 __all__ = ["Hodlr", "Factor", "Chain", "TensorChain", "KernelTimer", "normals", "draw_f",
+           "batch_tuning", "BATCH_EAGER", "BATCH_GRAPHS", "BATCH_GROUPED", "BATCH_AUTO",
            "draw_f_hetero", "step_batch", "solve_refined", "Server", "footprint_bytes", "FP64", "MIXED", "KERNEL_SE",
            "KERNEL_EXP", "KERNEL_MATERN32", "KERNEL_MATERN52", "FgError", "lib", "KID_LEAF", "KID_REDUCE", "KID_UPDATE", "KID_WHITEN",
            "KID_PREDICT"]
@@ -292,10 +293,26 @@ class TensorChain:
         self._c = None
 
 
-def step_batch(chains, iters=1, nstreams=4, graphs=True):
-    """gibbs_step_batch over a list of Chain objects."""
+BATCH_EAGER, BATCH_GRAPHS, BATCH_GROUPED, BATCH_AUTO = 0, 1, 2, 3
+BATCH_MODE_NAMES = {0: "eager", 1: "graphs", 2: "grouped", 3: "auto"}
+
+
+def step_batch(chains, iters=1, nstreams=4, graphs=True, mode=None):
+    """gibbs_step_batch over a list of Chain objects.  mode: BATCH_EAGER / _GRAPHS /
+    _GROUPED / _AUTO (default: GRAPHS if graphs else EAGER)."""
+    if mode is None:
+        mode = BATCH_GRAPHS if graphs else BATCH_EAGER
     arr = (C.c_void_p * max(len(chains), 1))(*[c._c for c in chains])
-    check(lib().gibbs_step_batch(arr, len(chains), iters, nstreams, int(graphs), _stream()))
+    check(lib().gibbs_step_batch(arr, len(chains), iters, nstreams, int(mode), _stream()))
+
+
+def batch_tuning(chains):
+    """The autotuner's choice for this batch: (mode name or None while tuning, streams,
+    ms per timed trial sweep)."""
+    arr = (C.c_void_p * max(len(chains), 1))(*[c._c for c in chains])
+    m, ns, ms = C.c_int32(), C.c_int32(), C.c_double()
+    check(lib().gibbs_batch_tuning(arr, len(chains), C.byref(m), C.byref(ns), C.byref(ms)))
+    return (BATCH_MODE_NAMES.get(m.value), ns.value, ms.value)
 
 
 def footprint_bytes(x, ell0, leaf=128, tol=1e-10, nugget=1e-6, kind=KERNEL_SE, precision=FP64,

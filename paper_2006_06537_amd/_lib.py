@@ -24,7 +24,7 @@ EXPORTS = ["hodlr_build", "hodlr_ranks", "hodlr_info", "hodlr_singular_values", 
            "hodlr_solve_refined_noalloc",
            "hodlr_solve", "hodlr_logdet", "hodlr_logdet_parts", "hodlr_apply_w",
            "fg_normals", "gp_draw_f", "gp_draw_f_hetero", "gibbs_chain_create", "gibbs_step",
-           "gibbs_step_batch", "gibbs_chain_state", "gibbs_chain_create_grid", "gibbs_chain_create_collapsed",
+           "gibbs_step_batch", "gibbs_batch_tuning", "gibbs_chain_state", "gibbs_chain_create_grid", "gibbs_chain_create_collapsed",
            "gibbs_chain_inputs",
            "gibbs_predict_inputs", "gibbs_predict",
            "gibbs_predict_stats",
@@ -162,6 +162,7 @@ def lib():
         "gibbs_chain_create": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
         "gibbs_step": ([P, I32, P], I32),
         "gibbs_step_batch": ([C.POINTER(P), I32, I32, I32, I32, P], I32),
+        "gibbs_batch_tuning": ([C.POINTER(P), I32, C.POINTER(I32), C.POINTER(I32), C.POINTER(D)], I32),
         "gibbs_chain_state": ([P, C.POINTER(ChainSnapshot), DP, DP, DP, P], I32),
         "gibbs_chain_create_collapsed": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),
         "gibbs_chain_create_grid": ([C.POINTER(ChainCfg), DP, DP, I64, P, C.POINTER(P)], I32),

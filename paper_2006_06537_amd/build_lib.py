@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libfifagp.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["alloc.cpp", "plan.cpp", "resources.cpp", "abi.cpp", "chain.cpp", "chain_tp.cpp",
            "timer.cpp", "k_build.hip", "k_factor.hip", "k_apply.hip", "k_rng.hip",
-           "k_tensor.hip", "k_predict.hip", "pcg.cpp", "noalloc.cpp",
+           "k_tensor.hip", "k_predict.hip", "pcg.cpp", "noalloc.cpp", "group.cpp",
            "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

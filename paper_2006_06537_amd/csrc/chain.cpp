@@ -5,6 +5,7 @@
 // the proposal -- and swaps them on acceptance; all plans of the grid are made and
 // uploaded once, so a sweep only enqueues kernels and synchronises once at its end.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "fg_chain.h"
+#include "fg_group.h"
 #include "fg_internal.h"
 #include "fg_rng.h"
 #include "fg_pcg.h"
@@ -56,6 +58,7 @@ struct fg_chain_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_z = nullptr, ev_f = nullptr,
              ev_leaf = nullptr;
   bool own_streams = true;                    // false: lent by the caller (serving slots)
+  hipError_t enq_err = hipSuccess;            // first runtime error while enqueuing a sweep
   // exact discrete conditional of the length-scale: every grid point's K~_1 and W_1
   bool exact = false;
   std::vector<fg::HodlrData> Hg;
@@ -66,6 +69,8 @@ struct fg_chain_s {
   double* qdot = nullptr;                     // dot partials per q stream
   hipStream_t qs[4] = {};
   hipEvent_t qev[5] = {};
+  std::vector<fg::Recorder> qrec;             // one per grid point (grouped q_h)
+  fg::GroupExec qexec;
   // non-unique inputs: the chain runs on the unique inputs with the averages as y
   bool collapsed = false;
   double* cw = nullptr;                       // |Q_i| (n), then precisions and their inverses
@@ -184,6 +189,29 @@ void prepare_sweep(fg_chain c, const Proposal& pr) {
   }
 }
 
+// every runtime call that enqueues part of a sweep goes through here: the first failure
+// is kept and reported once the sweep has been enqueued (or captured)
+static inline void enq_check(fg_chain c, hipError_t e) {
+  if (e != hipSuccess && c->enq_err == hipSuccess) c->enq_err = e;
+}
+// stream-order helpers of the sweep: while a recorder is open (grouped batches) the whole
+// sweep is replayed on one stream in program order, so events are not needed and copies
+// are recorded like launches
+static void ev_record(fg_chain c, hipEvent_t e, hipStream_t s) {
+  if (!fg::recording()) enq_check(c, hipEventRecord(e, s));
+}
+static void ev_wait(fg_chain c, hipStream_t s, hipEvent_t e) {
+  if (!fg::recording()) enq_check(c, hipStreamWaitEvent(s, e, 0));
+}
+static void enq_copy(fg_chain c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind,
+                     hipStream_t s) {
+  if (kind == hipMemcpyDeviceToDevice) {
+    fg::launch_copy_d2d(dst, src, bytes, s);
+    return;
+  }
+  FG_RUN(s, enq_check(c, hipMemcpyAsync(dst, src, bytes, kind, q_)));
+}
+
 // f | - and tau | - on collapsed data (Appendix, non-unique input points): Algorithm 1.h
 // on g = f / sigma_f, whose prior is K~_1 and whose data ybar / sigma_f have precisions
 // D = tau sigma_f^2 |Q_i|; then f = sigma_f g, and tau from the full-data residual.
@@ -201,7 +229,7 @@ static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
   const uint64_t* itp = &c->st->iter;
   fg::launch_collapsed_weights(n, c->cw, &c->st->alphaM, dprec, dinv, s);
   fg::launch_factor(c->WM, nullptr, nullptr, dinv, s);
-  hipMemcpyAsync(&c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+  enq_copy(c, &c->st->logdetM, c->WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
   fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, s, itp);
   fg::launch_scale_sqrt(n, dprec, v0, s);  // a ~ N(0, D)
   fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, s, itp);
@@ -226,18 +254,43 @@ static void enqueue_f_tau_collapsed(fg_chain c, hipStream_t s) {
 // draw from the discrete conditional (k_rho_exact).
 static void enqueue_rho_exact(fg_chain c, hipStream_t s) {
   const int n = c->n, G = (int)c->Wg.size();
-  hipEventRecord(c->qev[0], s);
-  for (int q = 0; q < 4; ++q) hipStreamWaitEvent(c->qs[q], c->qev[0], 0);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  enq_check(c, hipStreamIsCapturing(s, &cap));
+  if (!fg::recording() && cap == hipStreamCaptureStatusNone) {
+    // Grouped: q_h = |W_h^-1 f|^2 of every grid point recorded separately (each on its
+    // own work vector), then replayed as grouped launches: about 30 launches for the
+    // whole grid instead of about 30 per grid point.  (Not under graph capture: the
+    // grouped launches' argument upload is staged per call.)
+    if (c->qrec.size() < (size_t)G) c->qrec.resize(G);
+    std::vector<fg::Recorder*> rp(G);
+    for (int h = 0; h < G; ++h) {
+      fg::Recorder* r = &c->qrec[h];
+      r->clear();
+      fg::RecordScope scope(r);
+      double* v = c->qbuf + (size_t)h * n;
+      enq_copy(c, v, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      fg::launch_apply_w(c->Wg[h], 2, v, 1, n, c->Wg[h].work, s);
+      fg::launch_dot(v, v, n, 0, c->qg + h, c->qdot + (size_t)h * 2048, s);
+      rp[h] = r;
+    }
+    std::string err;
+    if (c->qexec.run(rp, s, err) != FG_OK) enq_check(c, hipErrorLaunchFailure);
+    fg::launch_rho_exact(c->st, c->ldg, c->qg, G, c->cfg.seed, c->cfg.stream_id, s);
+    return;
+  }
+  // inside a grouped batch (already recording): the grid in order, one work vector
+  ev_record(c, c->qev[0], s);
+  for (int q = 0; q < 4; ++q) ev_wait(c, c->qs[q], c->qev[0]);
   for (int h = 0; h < G; ++h) {
     const int q = h & 3;
     double* v = c->qbuf + (size_t)q * n;
-    hipMemcpyAsync(v, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->qs[q]);
+    enq_copy(c, v, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->qs[q]);
     fg::launch_apply_w(c->Wg[h], 2, v, 1, n, c->Wg[h].work, c->qs[q]);
     fg::launch_dot(v, v, n, 0, c->qg + h, c->qdot + (size_t)q * 2048, c->qs[q]);
   }
   for (int q = 0; q < 4; ++q) {
-    hipEventRecord(c->qev[1 + q], c->qs[q]);
-    hipStreamWaitEvent(s, c->qev[1 + q], 0);
+    ev_record(c, c->qev[1 + q], c->qs[q]);
+    ev_wait(c, s, c->qev[1 + q]);
   }
   fg::launch_rho_exact(c->st, c->ldg, c->qg, G, c->cfg.seed, c->cfg.stream_id, s);
 }
@@ -263,21 +316,21 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   fg::launch_sweep_begin(c->st, c->st_prev, s);
   // The proposal's K~_1' and W_1' depend on the proposal only: build and factor them on
   // the chain's second stream while this stream factors M~ and draws f.
-  hipEventRecord(c->ev_fork, s);
-  hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+  ev_record(c, c->ev_fork, s);
+  ev_wait(c, c->aux, c->ev_fork);
   if (pr.ongrid && !side) {
     fg::launch_zero_int(c->H[oth].status, 1, c->aux);
     fg::launch_zero_int(c->W[oth].status, 1, c->aux);
     fg::launch_build(c->H[oth], c->aux);
     fg::launch_factor(c->W[oth], nullptr, nullptr, nullptr, c->aux);
-    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
-                   c->aux);
+    enq_copy(c, &c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
+             c->aux);
   } else if (pr.ongrid) {
     // its leaves need x and ell' only: a fourth stream factors them during the build
-    hipStreamWaitEvent(c->ls, c->ev_fork, 0);
+    ev_wait(c, c->ls, c->ev_fork);
     fg::launch_zero_int(c->W[oth].status, 1, c->ls);
     fg::launch_factor_leaves(c->W[oth], nullptr, nullptr, nullptr, c->ls);
-    hipEventRecord(c->ev_leaf, c->ls);
+    ev_record(c, c->ev_leaf, c->ls);
     fg::launch_zero_int(c->H[oth].status, 1, c->aux);
     fg::launch_build(c->H[oth], c->aux);
   }
@@ -288,10 +341,10 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   auto enqueue_proposal_levels = [&]() {
     if (!proposal_levels) return;
     proposal_levels = false;
-    hipStreamWaitEvent(c->aux, c->ev_leaf, 0);
+    ev_wait(c, c->aux, c->ev_leaf);
     fg::launch_factor_levels(c->W[oth], nullptr, c->aux);
-    hipMemcpyAsync(&c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
-                   c->aux);
+    enq_copy(c, &c->st->logdet1p, c->W[oth].logdet, sizeof(double), hipMemcpyDeviceToDevice,
+             c->aux);
   };
   if (c->collapsed) {
     enqueue_proposal_levels();
@@ -302,9 +355,9 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     // stream factors M~.
     fg::FactorData& WM = c->fell_back ? c->WM64 : c->WM;
     fg::launch_factor(WM, &c->st->alphaM, nullptr, nullptr, s);
-    hipMemcpyAsync(&c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
+    enq_copy(c, &c->st->logdetM, WM.logdet, sizeof(double), hipMemcpyDeviceToDevice, s);
     hipStream_t zq = side ? c->zs : s;
-    if (side) hipStreamWaitEvent(zq, c->ev_fork, 0);
+    if (side) ev_wait(c, zq, c->ev_fork);
     fg::launch_normals(cf.seed, 1, 0, cf.stream_id, n, v0, zq, itp);
     fg::launch_normals(cf.seed, 2, 0, cf.stream_id, n, v1, zq, itp);
     fg::launch_matvec(H1, 1.0, 0.0, nullptr, nullptr, v0, v2, 1, n, H1.work, zq);
@@ -312,9 +365,9 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     fg::launch_axpby(n, v2, v1, v2, &c->st->c_ka, 0.0, &c->st->sigf, 0.0, zq);
     fg::launch_axpby(n, c->y, nullptr, v3, &c->st->tau_draw, 0.0, nullptr, 0.0, zq);
     if (side) {
-      hipEventRecord(c->ev_z, zq);
+      ev_record(c, c->ev_z, zq);
       enqueue_proposal_levels();
-      hipStreamWaitEvent(s, c->ev_z, 0);
+      ev_wait(c, s, c->ev_z);
     }
     if (c->mixed && !c->fell_back) {
       // [w r] = M~^-1 [Z, tau y] by PCG on the FP64 HODLR M~, preconditioned with the
@@ -325,7 +378,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
       fg::pcg_enqueue(H1, 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n, PCG_RTOL, 0,
                       c->pcg_nit, c->pcg, s, true);
       fg::launch_pcg_record(c->pcg.sc, c->st, s);
-      hipMemcpyAsync(v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+      enq_copy(c, v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     } else {
       fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
       fg::launch_apply_w(WM, 3, v2, 2, n, WM.work, s);
@@ -333,7 +386,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
     fg::launch_matvec(H1, 0.0, 0.0, &c->st->sigf2, nullptr, v3, c->mu, 1, n,
                       H1.work, s);
     fg::launch_axpby(n, v2, c->mu, c->f, nullptr, 1.0, nullptr, 1.0, s);
-    hipMemcpyAsync(c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    enq_copy(c, c->r, v3, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     fg::launch_dot(c->y, c->r, n, 0, &c->st->yr, c->dotwork, s);
     fg::launch_dot(c->y, c->f, n, 1, &c->st->sse, c->dotwork + 1024, s);
     // tau | -
@@ -343,34 +396,34 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
   // beside this stream's |W_1^-1 f|^2 (v1 is free from here on).  This stream's part is
   // enqueued first: it is the longer one, and one host thread enqueues both.
   const bool qprop_side = side && !c->exact && pr.ongrid;
-  if (qprop_side) hipEventRecord(c->ev_f, s);
+  if (qprop_side) ev_record(c, c->ev_f, s);
   // sigma_f^-2 | -
-  hipMemcpyAsync(v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+  enq_copy(c, v0, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
   fg::launch_apply_w(W1, 2, v0, 1, n, W1.work, s);
   fg::launch_dot(v0, v0, n, 0, &c->st->q, c->dotwork, s);
   fg::launch_sigf_step(c->st, n, cf.a2, cf.b2, cf.seed, cf.stream_id, s);
   if (qprop_side) {
-    hipStreamWaitEvent(c->aux, c->ev_f, 0);
-    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->aux);
+    ev_wait(c, c->aux, c->ev_f);
+    enq_copy(c, v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, c->aux);
     fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, c->aux);
     fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork + 2048, c->aux);
   }
-  hipEventRecord(c->ev_join, c->aux);
-  hipStreamWaitEvent(s, c->ev_join, 0);
+  ev_record(c, c->ev_join, c->aux);
+  ev_wait(c, s, c->ev_join);
   if (c->exact) {  // length-scale | -  (exact, over the whole grid)
     enqueue_rho_exact(c, s);
-    hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+    enq_copy(c, c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
     return;
   }
   // length-scale | -  (Metropolis on the grid)
   if (!side && pr.ongrid) {
-    hipMemcpyAsync(v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    enq_copy(c, v1, c->f, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     fg::launch_apply_w(c->W[oth], 2, v1, 1, n, c->W[oth].work, s);
     fg::launch_dot(v1, v1, n, 0, &c->st->qprop, c->dotwork, s);
   }
   fg::launch_mh_step(c->st, pr.kp, pr.ongrid, cf.seed, cf.stream_id,
                      pr.ongrid ? c->H[oth].status : nullptr, pr.ongrid ? c->W[oth].status : nullptr, s);
-  hipMemcpyAsync(c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
+  enq_copy(c, c->st_host, c->st, sizeof(fg::DevState), hipMemcpyDeviceToHost, s);
 }
 
 // After the sweep's stream has been synchronised, before finish_sweep: whether the
@@ -403,7 +456,7 @@ bool sweep_retry(fg_chain c, hipStream_t s) {
     c->pcg_iters = 0;
     c->pcg_relres = 0.0;
   }
-  hipMemcpyAsync(c->st, c->st_prev, sizeof(fg::DevState), hipMemcpyDeviceToDevice, s);
+  enq_copy(c, c->st, c->st_prev, sizeof(fg::DevState), hipMemcpyDeviceToDevice, s);
   return true;
 }
 
@@ -422,11 +475,29 @@ void finish_sweep(fg_chain c, const Proposal& pr) {
 // a batched call holds them (g_batch.mu) for its whole duration: two host threads that
 // step batches at the same time take turns instead of interleaving on shared streams.
 constexpr int BATCH_STREAMS = 4;
+// the batch autotuner's candidates (mode, streams) and its record per batch signature
+struct BatchCand {
+  int mode, nstreams;
+};
+constexpr BatchCand TUNE_CANDS[] = {{FG_BATCH_GROUPED, 1},
+                                    {FG_BATCH_EAGER, 4},
+                                    {FG_BATCH_EAGER, 2},
+                                    {FG_BATCH_GRAPHS, 4}};
+constexpr int NTUNE = sizeof(TUNE_CANDS) / sizeof(TUNE_CANDS[0]);
+struct BatchTune {
+  int trial = 0;
+  bool done = false;
+  int mode = FG_BATCH_EAGER, nstreams = 4;
+  double best_ms = -1.0;
+};
 struct BatchStreams {
   std::mutex mu;
   bool init = false;
   hipStream_t s[BATCH_STREAMS] = {};
   hipEvent_t ev_in = nullptr;
+  std::vector<fg::Recorder> recs;       // one per chain of a grouped batch
+  fg::GroupExec exec;
+  std::map<uint64_t, BatchTune> tune;   // autotuner choices by batch signature
 };
 BatchStreams g_batch;
 
@@ -463,9 +534,16 @@ fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExe
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return cfail(FG_EDEVICE, "stream capture failed to start");
+  // captured sweeps always take the two-stream form (see DESIGN: a captured four-stream
+  // sweep once ended in a host fault whose cause was not found)
   enqueue_sweep(c, pr, q, false);
-  if (hipStreamEndCapture(q, &g) != hipSuccess || !g)
-    return cfail(FG_EDEVICE, "stream capture failed");
+  const hipError_t ce = hipStreamEndCapture(q, &g);
+  if (c->enq_err != hipSuccess || ce != hipSuccess || !g) {
+    const hipError_t e = c->enq_err != hipSuccess ? c->enq_err : ce;
+    c->enq_err = hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    return cfail(FG_EDEVICE, std::string("stream capture failed: ") + hipGetErrorString(e));
+  }
   hipGraphExec_t ge = nullptr;
   const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -620,10 +698,13 @@ fg_status chain_create_planned(const fg_chain_cfg& cfg, ChainPlans& plans, const
 
 void chain_destroy_idle(fg_chain c) { chain_free(c, false); }
 
-void chain_begin_sweep(fg_chain c, hipStream_t s, bool again) {
+hipError_t chain_begin_sweep(fg_chain c, hipStream_t s, bool again) {
   if (!again) c->pending = propose(c);
   prepare_sweep(c, c->pending);
   enqueue_sweep(c, c->pending, s, false);
+  const hipError_t e = c->enq_err;
+  c->enq_err = hipSuccess;
+  return e;
 }
 
 bool chain_end_sweep(fg_chain c, hipStream_t s) {
@@ -789,8 +870,8 @@ fg_status gibbs_chain_create_grid(const fg_chain_cfg* cfg, const double* x, cons
   const size_t nb = sizeof(double) * (size_t)c->n;
   if (fg::dev_alloc(reinterpret_cast<void**>(&c->ldg), sizeof(double) * G) != hipSuccess ||
       fg::dev_alloc(reinterpret_cast<void**>(&c->qg), sizeof(double) * G) != hipSuccess ||
-      fg::dev_alloc(reinterpret_cast<void**>(&c->qbuf), 4 * nb) != hipSuccess ||
-      fg::dev_alloc(reinterpret_cast<void**>(&c->qdot), sizeof(double) * 4 * 2048) != hipSuccess) {
+      fg::dev_alloc(reinterpret_cast<void**>(&c->qbuf), (size_t)std::max(G, 4) * nb) != hipSuccess ||
+      fg::dev_alloc(reinterpret_cast<void**>(&c->qdot), sizeof(double) * std::max(G, 4) * 2048) != hipSuccess) {
     chain_free(c);
     (void)hipGetLastError();
     return cfail(FG_ENOMEM, "grid chain allocation failed");
@@ -866,6 +947,11 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
     for (;;) {
       prepare_sweep(c, pr);
       enqueue_sweep(c, pr, s, true);
+      if (c->enq_err != hipSuccess) {
+        const hipError_t e = c->enq_err;
+        c->enq_err = hipSuccess;
+        return cfail(FG_EDEVICE, std::string("sweep enqueue: ") + hipGetErrorString(e));
+      }
       if (hipStreamSynchronize(s) != hipSuccess) return cfail(FG_EDEVICE, "sweep failed on the device");
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
@@ -876,9 +962,85 @@ fg_status gibbs_step(fg_chain c, int32_t iters, fg_stream stream) {
   return FG_OK;
 }
 
+// One batched sweep of `chains` in a fixed mode (the batch lock is held).
+static fg_status batch_sweep(fg_chain* chains, int nchains, int mode, int nstreams) {
+  fg_status st = FG_OK;
+  std::vector<Proposal> pr(nchains);
+  for (int i = 0; i < nchains; ++i) pr[i] = propose(chains[i]);
+  std::vector<int> run(nchains), again;
+  for (int i = 0; i < nchains; ++i) run[i] = i;
+  auto enq_fail = [&](fg_chain c) -> fg_status {
+    const hipError_t e = c->enq_err;
+    c->enq_err = hipSuccess;
+    return cfail(FG_EDEVICE, std::string("sweep enqueue: ") + hipGetErrorString(e));
+  };
+  // every chain's sweep, then again for the chains whose PCG budget was too small
+  while (!run.empty()) {
+    if (mode == FG_BATCH_GROUPED) {
+      // each chain's sweep is recorded, then all are replayed as grouped launches on the
+      // first batch stream
+      if (g_batch.recs.size() < (size_t)nchains) g_batch.recs.resize(nchains);
+      std::vector<fg::Recorder*> rp;
+      for (int i : run) {
+        fg_chain c = chains[i];
+        fg::Recorder* r = &g_batch.recs[i];
+        r->clear();
+        {
+          fg::RecordScope scope(r);
+          prepare_sweep(c, pr[i]);
+          enqueue_sweep(c, pr[i], g_batch.s[0], false);
+        }
+        if (c->enq_err != hipSuccess) return enq_fail(c);
+        rp.push_back(r);
+      }
+      std::string err;
+      if ((st = g_batch.exec.run(rp, g_batch.s[0], err)) != FG_OK) return cfail(st, err);
+    } else {
+      for (int i : run) {
+        fg_chain c = chains[i];
+        hipStream_t q = g_batch.s[i % nstreams];
+        prepare_sweep(c, pr[i]);
+        if (mode == FG_BATCH_EAGER) {
+          enqueue_sweep(c, pr[i], q, false);
+          if (c->enq_err != hipSuccess) return enq_fail(c);
+          continue;
+        }
+        hipGraphExec_t ge = nullptr;
+        if ((st = sweep_graph(c, pr[i], q, ge)) != FG_OK) return st;
+        if (hipGraphLaunch(ge, q) != hipSuccess) return cfail(FG_EDEVICE, "graph launch failed");
+      }
+    }
+    const int used = mode == FG_BATCH_GROUPED ? 1 : nstreams;
+    for (int q = 0; q < used; ++q)
+      if (hipStreamSynchronize(g_batch.s[q]) != hipSuccess)
+        return cfail(FG_EDEVICE, "batched sweep failed on the device");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("batched sweep: ") + hipGetErrorString(e));
+    again.clear();
+    for (int i : run)
+      if (sweep_retry(chains[i], g_batch.s[mode == FG_BATCH_GROUPED ? 0 : i % nstreams]))
+        again.push_back(i);
+    run.swap(again);
+  }
+  for (int i = 0; i < nchains; ++i) finish_sweep(chains[i], pr[i]);
+  return FG_OK;
+}
+
+// The batch autotuner's key: the chain count and the largest chain's size and precision.
+static uint64_t tune_key(fg_chain* chains, int nchains) {
+  int nmax = 0;
+  bool mixed = false;
+  for (int i = 0; i < nchains; ++i) {
+    nmax = std::max(nmax, chains[i]->n);
+    mixed |= chains[i]->mixed;
+  }
+  return ((uint64_t)nchains << 33) | ((uint64_t)nmax << 1) | (mixed ? 1u : 0u);
+}
+
 fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int32_t nstreams,
-                           int32_t use_graphs, fg_stream stream) {
-  if (!chains || nchains < 0 || iters < 0 || nstreams < 1 || nstreams > BATCH_STREAMS)
+                           int32_t mode, fg_stream stream) {
+  if (!chains || nchains < 0 || iters < 0 || nstreams < 1 || nstreams > BATCH_STREAMS ||
+      mode < FG_BATCH_EAGER || mode > FG_BATCH_AUTO)
     return cfail(FG_EINVAL, "bad arguments");
   for (int i = 0; i < nchains; ++i) {
     if (!chains[i]) return cfail(FG_EINVAL, "NULL chain");
@@ -889,44 +1051,67 @@ fg_status gibbs_step_batch(fg_chain* chains, int32_t nchains, int32_t iters, int
   std::lock_guard<std::mutex> batch_lock(g_batch.mu);
   fg_status st = batch_streams_init();
   if (st != FG_OK) return st;
-  const bool graphs = use_graphs && !fg::timer_active();
   // the batch starts after the work already queued on the caller's stream
   if (hipEventRecord(g_batch.ev_in, caller) != hipSuccess) return cfail(FG_EDEVICE, "event record failed");
-  for (int q = 0; q < nstreams; ++q) hipStreamWaitEvent(g_batch.s[q], g_batch.ev_in, 0);
-  std::vector<Proposal> pr(nchains);
-  std::vector<int> todo(nchains), again;
+  for (int q = 0; q < BATCH_STREAMS; ++q)
+    if (hipStreamWaitEvent(g_batch.s[q], g_batch.ev_in, 0) != hipSuccess)
+      return cfail(FG_EDEVICE, "stream wait failed");
+  // live kernel timing records events at launch: no recorded or captured launches then
+  const bool timing = fg::timer_active();
+  const uint64_t key = tune_key(chains, nchains);
   for (int it = 0; it < iters; ++it) {
-    for (int i = 0; i < nchains; ++i) {
-      todo[i] = i;
-      pr[i] = propose(chains[i]);
-    }
-    // every chain's sweep, then again for the chains whose PCG budget was too small
-    std::vector<int> run = todo;
-    while (!run.empty()) {
-      for (int i : run) {
-        fg_chain c = chains[i];
-        hipStream_t q = g_batch.s[i % nstreams];
-        prepare_sweep(c, pr[i]);
-        if (!graphs) {
-          enqueue_sweep(c, pr[i], q, false);
-          continue;
-        }
-        hipGraphExec_t ge = nullptr;
-        if ((st = sweep_graph(c, pr[i], q, ge)) != FG_OK) return st;
-        if (hipGraphLaunch(ge, q) != hipSuccess) return cfail(FG_EDEVICE, "graph launch failed");
+    int m = mode, ns = nstreams;
+    if (mode == FG_BATCH_AUTO) {
+      // The autotuner: while the batch's signature has no choice yet, each sweep runs in
+      // the next candidate (mode, streams), two sweeps per candidate (the second one timed,
+      // so that graph capture is not counted); then the fastest is kept.  Every mode gives
+      // the same results bit for bit, so the trial sweeps are ordinary sweeps.
+      BatchTune& t = g_batch.tune[key];
+      if (t.done) {
+        m = t.mode;
+        ns = t.nstreams;
+      } else {
+        const BatchCand& cd = TUNE_CANDS[t.trial / 2];
+        m = cd.mode;
+        ns = cd.nstreams;
       }
-      for (int q = 0; q < nstreams; ++q)
-        if (hipStreamSynchronize(g_batch.s[q]) != hipSuccess)
-          return cfail(FG_EDEVICE, "batched sweep failed on the device");
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return cfail(FG_EDEVICE, std::string("batched sweep: ") + hipGetErrorString(e));
-      again.clear();
-      for (int i : run)
-        if (sweep_retry(chains[i], g_batch.s[i % nstreams])) again.push_back(i);
-      run.swap(again);
     }
-    for (int i = 0; i < nchains; ++i) finish_sweep(chains[i], pr[i]);
+    if (timing && m != FG_BATCH_EAGER) m = FG_BATCH_EAGER;
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((st = batch_sweep(chains, nchains, m, ns)) != FG_OK) return st;
+    const double ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+    if (mode == FG_BATCH_AUTO && !timing) {
+      BatchTune& t = g_batch.tune[key];
+      if (!t.done) {
+        if (t.trial % 2 == 1 && (t.best_ms < 0 || ms < t.best_ms)) {
+          t.best_ms = ms;
+          t.mode = m;
+          t.nstreams = ns;
+        }
+        if (++t.trial == 2 * NTUNE) t.done = true;
+      }
+    }
   }
+  return FG_OK;
+}
+
+fg_status gibbs_batch_tuning(fg_chain* chains, int32_t nchains, int32_t* mode, int32_t* nstreams,
+                             double* ms_per_sweep) {
+  if (!chains || nchains < 1 || !mode || !nstreams) return cfail(FG_EINVAL, "bad arguments");
+  for (int i = 0; i < nchains; ++i)
+    if (!chains[i]) return cfail(FG_EINVAL, "NULL chain");
+  std::lock_guard<std::mutex> batch_lock(g_batch.mu);
+  auto itr = g_batch.tune.find(tune_key(chains, nchains));
+  if (itr == g_batch.tune.end() || !itr->second.done) {
+    *mode = -1;
+    *nstreams = 0;
+    if (ms_per_sweep) *ms_per_sweep = 0.0;
+    return FG_OK;
+  }
+  *mode = itr->second.mode;
+  *nstreams = itr->second.nstreams;
+  if (ms_per_sweep) *ms_per_sweep = itr->second.best_ms;
   return FG_OK;
 }
 

@@ -42,8 +42,9 @@ void chain_destroy_idle(fg_chain c);
 // One sweep in two halves, for callers that watch the stream themselves: begin enqueues
 // the sweep on s (again = the same proposal once more); end, called once s has finished,
 // returns true if the sweep must be run again (its state has been restored on s: call
-// begin with again = true), else applies the sweep's outcome.
-void chain_begin_sweep(fg_chain c, hipStream_t s, bool again);
+// begin with again = true), else applies the sweep's outcome.  begin returns the first
+// runtime error met while enqueuing (hipSuccess if none).
+hipError_t chain_begin_sweep(fg_chain c, hipStream_t s, bool again);
 bool chain_end_sweep(fg_chain c, hipStream_t s);
 size_t chain_device_bytes(fg_chain c);
 const double* chain_f(fg_chain c);  // device, n: f of the last sweep

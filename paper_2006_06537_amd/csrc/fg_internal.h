@@ -242,6 +242,8 @@ void launch_dot(const double* a, const double* b, int n, int mode, double* out, 
 // bounds the tasks of any one side (the plan's per-level maximum).
 void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
                  int nsides, int esz, double* zfin, int zf_side, int max_tasks, hipStream_t s);
+// device-to-device copy (a kernel, so that grouped batches can group it)
+void launch_copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 void launch_axpby(int n, const double* x, const double* y, double* out,
                   const double* ca_dev, double ca, const double* cb_dev, double cb, hipStream_t s);
 // non-unique inputs: sum w (a - b)^2, out = x / *den, and the averages' precisions

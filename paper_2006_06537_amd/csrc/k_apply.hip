@@ -9,6 +9,7 @@
 //   W^-1   : v_J += V~ (-s + F2 (t - G_V s))
 //   W^-T   : w = F2 t; v_I -= U~ (t + G_V w); v_J += V~ w
 // and the order of levels follows W = L_D W_(L-1) ... W_(0).
+#include "fg_group.h"
 #include "fg_internal.h"
 
 namespace fg {
@@ -30,13 +31,35 @@ __device__ __forceinline__ double wave_red(double v) {
 //           v_j = D_j^-1 t_j, then every row below takes t_r -= L_rj v_j, j = 0, 1, ...;
 //           a row's 16 coefficients of a step are loaded at the start of the step.
 // (Factor data of precision T; vectors and arithmetic in FP64.)
+// arguments of k_leaf_apply (one struct, so that grouped launches can stage one per member)
 template <typename T>
-__global__ void __launch_bounds__(BMAX) k_leaf_apply(const int* __restrict__ leaf_lo, int nleaf,
-                                                     const T* __restrict__ Lm,
-                                                     const T* __restrict__ Dinv, int Bc,
-                                                     int op, double* __restrict__ v,
-                                                     int nrhs, int ld) {
-  const int b = blockIdx.x;
+struct k_leaf_apply_args {
+  const int* leaf_lo;
+  int nleaf;
+  const T* Lm;
+  const T* Dinv;
+  int Bc;
+  int op;
+  double* v;
+  int nrhs;
+  int ld;
+};
+template <typename T>
+__device__ __forceinline__ void k_leaf_apply_body(const k_leaf_apply_args<T>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ leaf_lo = a_.leaf_lo;
+  int nleaf = a_.nleaf;
+  const T* __restrict__ Lm = a_.Lm;
+  const T* __restrict__ Dinv = a_.Dinv;
+  int Bc = a_.Bc;
+  int op = a_.op;
+  double* __restrict__ v = a_.v;
+  int nrhs = a_.nrhs;
+  int ld = a_.ld;
+  (void)by_;
+  (void)gy_;
+
+  const int b = bx_;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const int r = threadIdx.x;
@@ -131,6 +154,36 @@ __global__ void __launch_bounds__(BMAX) k_leaf_apply(const int* __restrict__ lea
   for (int c = 0; c < NRHS_MAX; ++c)
     if (live && c < nrhs) v[(size_t)c * ld + lo + r] = x[c];
 }
+template <typename T>
+__global__ void __launch_bounds__(BMAX) k_leaf_apply(const k_leaf_apply_args<T> a_) {
+  k_leaf_apply_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T>
+__global__ void __launch_bounds__(BMAX) k_leaf_apply_g(const k_leaf_apply_args<T>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_leaf_apply_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T>
+static void k_leaf_apply_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_leaf_apply_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_leaf_apply_args<T>* a, const int* st, const int* gy, int mm) {
+    k_leaf_apply_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_leaf_apply now, or records it while a recorder is open on this thread
+template <typename T>
+static void k_leaf_apply_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_leaf_apply_args<T>& a) {
+  if (recording())
+    record_group(k_leaf_apply_grp<T>, group_key((const void*)k_leaf_apply_grp<T>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_leaf_apply<T><<<g, b, lds, s>>>(a);
+}
 
 // transposed leaf block operators L' v (op 1) and L^-T v (op 3), in place on v.  Their
 // reads run along L's columns, so threads take consecutive entries of one column:
@@ -141,13 +194,35 @@ __global__ void __launch_bounds__(BMAX) k_leaf_apply(const int* __restrict__ lea
 //           four threads per (row of block i, vector column) reading consecutive rows of
 //           L's column, their partial sums combined by shuffles.
 // (Factor data of precision T; vectors and arithmetic in FP64.)
+// arguments of k_leaf_apply_t (one struct, so that grouped launches can stage one per member)
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t(const int* __restrict__ leaf_lo,
-                                                           int nleaf, const T* __restrict__ Lm,
-                                                           const T* __restrict__ Dinv, int Bc,
-                                                           int op, double* __restrict__ v,
-                                                           int nrhs, int ld) {
-  const int b = blockIdx.x;
+struct k_leaf_apply_t_args {
+  const int* leaf_lo;
+  int nleaf;
+  const T* Lm;
+  const T* Dinv;
+  int Bc;
+  int op;
+  double* v;
+  int nrhs;
+  int ld;
+};
+template <typename T>
+__device__ __forceinline__ void k_leaf_apply_t_body(const k_leaf_apply_t_args<T>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ leaf_lo = a_.leaf_lo;
+  int nleaf = a_.nleaf;
+  const T* __restrict__ Lm = a_.Lm;
+  const T* __restrict__ Dinv = a_.Dinv;
+  int Bc = a_.Bc;
+  int op = a_.op;
+  double* __restrict__ v = a_.v;
+  int nrhs = a_.nrhs;
+  int ld = a_.ld;
+  (void)by_;
+  (void)gy_;
+
+  const int b = bx_;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   __shared__ double vs[NRHS_MAX][BMAX];  // rows >= m hold zeros
@@ -199,6 +274,36 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t(const int* __restrict
   for (int idx = threadIdx.x; idx < m * nrhs; idx += NTHREADS)
     v[(size_t)(idx / m) * ld + lo + idx % m] = vs[idx / m][idx % m];
 }
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t(const k_leaf_apply_t_args<T> a_) {
+  k_leaf_apply_t_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t_g(const k_leaf_apply_t_args<T>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_leaf_apply_t_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T>
+static void k_leaf_apply_t_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_leaf_apply_t_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_leaf_apply_t_args<T>* a, const int* st, const int* gy, int mm) {
+    k_leaf_apply_t_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_leaf_apply_t now, or records it while a recorder is open on this thread
+template <typename T>
+static void k_leaf_apply_t_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_leaf_apply_t_args<T>& a) {
+  if (recording())
+    record_group(k_leaf_apply_t_grp<T>, group_key((const void*)k_leaf_apply_t_grp<T>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_leaf_apply_t<T><<<g, b, lds, s>>>(a);
+}
 
 // level reduce with a vector right operand: z[t][a][c] = sum_rows P[i, coff + a] v[i, c]
 //
@@ -209,13 +314,43 @@ __global__ void __launch_bounds__(NTHREADS) k_leaf_apply_t(const int* __restrict
 // task's groups; rows outside the task (partial first and last groups) are masked.  Lane
 // partials are summed over the 16 row lanes, then over the 4 waves in a fixed order.
 // NR >= nrhs bounds the vector columns held in registers.
+// arguments of k_reduce_vec (one struct, so that grouped launches can stage one per member)
 template <typename T, int NR>
-__global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
-    const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
-    const int* __restrict__ coff, const int* __restrict__ kmax, const T* __restrict__ P,
-    int K, const double* __restrict__ v, int nrhs, int ldv, double* __restrict__ zpart,
-    int zs_task) {
-  const int t = blockIdx.x;
+struct k_reduce_vec_args {
+  const Task* tasks;
+  int tbase;
+  int ntask;
+  const NodePlan* nodes;
+  const int* coff;
+  const int* kmax;
+  const T* P;
+  int K;
+  const double* v;
+  int nrhs;
+  int ldv;
+  double* zpart;
+  int zs_task;
+};
+template <typename T, int NR>
+__device__ __forceinline__ void k_reduce_vec_body(const k_reduce_vec_args<T, NR>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int tbase = a_.tbase;
+  int ntask = a_.ntask;
+  const NodePlan* __restrict__ nodes = a_.nodes;
+  const int* __restrict__ coff = a_.coff;
+  const int* __restrict__ kmax = a_.kmax;
+  const T* __restrict__ P = a_.P;
+  int K = a_.K;
+  const double* __restrict__ v = a_.v;
+  int nrhs = a_.nrhs;
+  int ldv = a_.ldv;
+  double* __restrict__ zpart = a_.zpart;
+  int zs_task = a_.zs_task;
+  (void)by_;
+  (void)gy_;
+
+  const int t = bx_;
   if (t >= ntask) return;
   const Task tk = tasks[tbase + t];
   const int l = nodes[tk.h].level;
@@ -279,6 +414,36 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
     __syncthreads();
   }
 }
+template <typename T, int NR>
+__global__ void __launch_bounds__(NTHREADS) k_reduce_vec(const k_reduce_vec_args<T, NR> a_) {
+  k_reduce_vec_body<T, NR>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T, int NR>
+__global__ void __launch_bounds__(NTHREADS) k_reduce_vec_g(const k_reduce_vec_args<T, NR>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_reduce_vec_body<T, NR>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T, int NR>
+static void k_reduce_vec_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_reduce_vec_args<T, NR>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_reduce_vec_args<T, NR>* a, const int* st, const int* gy, int mm) {
+    k_reduce_vec_g<T, NR><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_reduce_vec now, or records it while a recorder is open on this thread
+template <typename T, int NR>
+static void k_reduce_vec_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_reduce_vec_args<T, NR>& a) {
+  if (recording())
+    record_group(k_reduce_vec_grp<T, NR>, group_key((const void*)k_reduce_vec_grp<T, NR>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_reduce_vec<T, NR><<<g, b, lds, s>>>(a);
+}
 
 // per-node coefficients.  op: 0 W, 1 W', 2 W^-1, 3 W^-T, 4 matvec (alpha scaling)
 //
@@ -287,13 +452,47 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_vec(
 // per element sum tasks t0 + g, t0 + g + G, ... (eight loads in flight), and the G group
 // sums are added in group order.  A level whose sides hold many tasks runs 1 024 threads.
 constexpr int NC_MAX_THREADS = 1024;
-__global__ void __launch_bounds__(NC_MAX_THREADS) k_node_coef(
-    int op, int hbase, int nnode, const int* __restrict__ rank,
-    const int* __restrict__ node_task_off, int tbase, const double* __restrict__ zpart,
-    int zs_task, int nrhs, const double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
-    double alpha_v, const double* __restrict__ alpha_p, double* __restrict__ coef, int cs_node,
-    const double* __restrict__ zsum) {
-  const int jn = blockIdx.x;
+// arguments of k_node_coef (one struct, so that grouped launches can stage one per member)
+struct k_node_coef_args {
+  int op;
+  int hbase;
+  int nnode;
+  const int* rank;
+  const int* node_task_off;
+  int tbase;
+  const double* zpart;
+  int zs_task;
+  int nrhs;
+  const double* nodemat;
+  const int* nodemat_off;
+  double alpha_v;
+  const double* alpha_p;
+  double* coef;
+  int cs_node;
+  const double* zsum;
+};
+__device__ __forceinline__ void k_node_coef_body(const k_node_coef_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  int op = a_.op;
+  int hbase = a_.hbase;
+  int nnode = a_.nnode;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ node_task_off = a_.node_task_off;
+  int tbase = a_.tbase;
+  const double* __restrict__ zpart = a_.zpart;
+  int zs_task = a_.zs_task;
+  int nrhs = a_.nrhs;
+  const double* __restrict__ nodemat = a_.nodemat;
+  const int* __restrict__ nodemat_off = a_.nodemat_off;
+  double alpha_v = a_.alpha_v;
+  const double* __restrict__ alpha_p = a_.alpha_p;
+  double* __restrict__ coef = a_.coef;
+  int cs_node = a_.cs_node;
+  const double* __restrict__ zsum = a_.zsum;
+  (void)by_;
+  (void)gy_;
+
+  const int jn = bx_;
   if (jn >= nnode) return;
   const int h = hbase + jn;
   const int k = rank[h];
@@ -387,17 +586,77 @@ __global__ void __launch_bounds__(NC_MAX_THREADS) k_node_coef(
     cJ[e] = X[a][c];
   }
 }
+__global__ void __launch_bounds__(NC_MAX_THREADS) k_node_coef(const k_node_coef_args a_) {
+  k_node_coef_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NC_MAX_THREADS) k_node_coef_g(const k_node_coef_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_node_coef_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_node_coef_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_node_coef_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_node_coef_args* a, const int* st, const int* gy, int mm) {
+    k_node_coef_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_node_coef now, or records it while a recorder is open on this thread
+static void k_node_coef_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_node_coef_args& a) {
+  if (recording())
+    record_group(k_node_coef_grp, group_key((const void*)k_node_coef_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_node_coef<<<g, b, lds, s>>>(a);
+}
 
 // v[rows of side] += P[rows, coff + a] coef_side[a][c]
 // One row per thread (work-group y of a task takes rows r0 + 256 y + thread, stepping by
 // 256 gridDim.y); the row's panel columns are loaded 8 at a time before they are used.
+// arguments of k_update_vec (one struct, so that grouped launches can stage one per member)
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_update_vec(
-    const Task* __restrict__ tasks, int tbase, int ntask, const NodePlan* __restrict__ nodes,
-    int hbase, const int* __restrict__ rank, const int* __restrict__ coff,
-    const T* __restrict__ P, int K, double* __restrict__ v, int nrhs, int ldv,
-    const double* __restrict__ coef, int cs_node, int skip_left) {
-  const int t = blockIdx.x;
+struct k_update_vec_args {
+  const Task* tasks;
+  int tbase;
+  int ntask;
+  const NodePlan* nodes;
+  int hbase;
+  const int* rank;
+  const int* coff;
+  const T* P;
+  int K;
+  double* v;
+  int nrhs;
+  int ldv;
+  const double* coef;
+  int cs_node;
+  int skip_left;
+};
+template <typename T>
+__device__ __forceinline__ void k_update_vec_body(const k_update_vec_args<T>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int tbase = a_.tbase;
+  int ntask = a_.ntask;
+  const NodePlan* __restrict__ nodes = a_.nodes;
+  int hbase = a_.hbase;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ coff = a_.coff;
+  const T* __restrict__ P = a_.P;
+  int K = a_.K;
+  double* __restrict__ v = a_.v;
+  int nrhs = a_.nrhs;
+  int ldv = a_.ldv;
+  const double* __restrict__ coef = a_.coef;
+  int cs_node = a_.cs_node;
+  int skip_left = a_.skip_left;
+  (void)by_;
+  (void)gy_;
+
+  const int t = bx_;
   if (t >= ntask) return;
   const Task tk = tasks[tbase + t];
   if (skip_left && tk.side == 0) return;
@@ -409,8 +668,8 @@ __global__ void __launch_bounds__(NTHREADS) k_update_vec(
   for (int e = threadIdx.x; e < k * nrhs; e += NTHREADS) cs[e] = cf[e];
   __syncthreads();
   const int cb = coff[l];
-  for (int r = tk.r0 + blockIdx.y * NTHREADS + threadIdx.x; r < tk.r1;
-       r += NTHREADS * gridDim.y) {
+  for (int r = tk.r0 + by_ * NTHREADS + threadIdx.x; r < tk.r1;
+       r += NTHREADS * gy_) {
     double acc[NRHS_MAX] = {0.0, 0.0, 0.0, 0.0};
     const T* pr = P + ((size_t)(r >> 4) * K + cb) * 16 + (r & 15);
     int a = 0;
@@ -435,15 +694,89 @@ __global__ void __launch_bounds__(NTHREADS) k_update_vec(
       if (c < nrhs) v[(size_t)c * ldv + r] += acc[c];
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_update_vec(const k_update_vec_args<T> a_) {
+  k_update_vec_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_update_vec_g(const k_update_vec_args<T>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_update_vec_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T>
+static void k_update_vec_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_update_vec_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_update_vec_args<T>* a, const int* st, const int* gy, int mm) {
+    k_update_vec_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_update_vec now, or records it while a recorder is open on this thread
+template <typename T>
+static void k_update_vec_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_update_vec_args<T>& a) {
+  if (recording())
+    record_group(k_update_vec_grp<T>, group_key((const void*)k_update_vec_grp<T>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_update_vec<T><<<g, b, lds, s>>>(a);
+}
 
 // y = alpha (K_leaf + nugget I) v + beta v + sum_levels panel rows x coefficients
-__global__ void __launch_bounds__(BMAX) k_mv_apply(
-    const int* __restrict__ leaf_lo, int nleaf, int L, const double* __restrict__ x, int kind,
-    double ell, double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
-    const double* __restrict__ beta_p, const double* __restrict__ v, double* __restrict__ y,
-    int nrhs, int ld, const int* __restrict__ rank, const int* __restrict__ coff,
-    const double* __restrict__ P, int K, const double* __restrict__ coef, int cs_node) {
-  const int b = blockIdx.x;
+// arguments of k_mv_apply (one struct, so that grouped launches can stage one per member)
+struct k_mv_apply_args {
+  const int* leaf_lo;
+  int nleaf;
+  int L;
+  const double* x;
+  int kind;
+  double ell;
+  double nugget;
+  double alpha_v;
+  const double* alpha_p;
+  double beta_v;
+  const double* beta_p;
+  const double* v;
+  double* y;
+  int nrhs;
+  int ld;
+  const int* rank;
+  const int* coff;
+  const double* P;
+  int K;
+  const double* coef;
+  int cs_node;
+};
+__device__ __forceinline__ void k_mv_apply_body(const k_mv_apply_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ leaf_lo = a_.leaf_lo;
+  int nleaf = a_.nleaf;
+  int L = a_.L;
+  const double* __restrict__ x = a_.x;
+  int kind = a_.kind;
+  double ell = a_.ell;
+  double nugget = a_.nugget;
+  double alpha_v = a_.alpha_v;
+  const double* __restrict__ alpha_p = a_.alpha_p;
+  double beta_v = a_.beta_v;
+  const double* __restrict__ beta_p = a_.beta_p;
+  const double* __restrict__ v = a_.v;
+  double* __restrict__ y = a_.y;
+  int nrhs = a_.nrhs;
+  int ld = a_.ld;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ coff = a_.coff;
+  const double* __restrict__ P = a_.P;
+  int K = a_.K;
+  const double* __restrict__ coef = a_.coef;
+  int cs_node = a_.cs_node;
+  (void)by_;
+  (void)gy_;
+
+  const int b = bx_;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const double alpha = alpha_p ? *alpha_p : alpha_v;
@@ -492,6 +825,32 @@ __global__ void __launch_bounds__(BMAX) k_mv_apply(
   }
   for (int c = 0; c < nrhs; ++c) y[(size_t)c * ld + i] = acc[c];
 }
+__global__ void __launch_bounds__(BMAX) k_mv_apply(const k_mv_apply_args a_) {
+  k_mv_apply_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(BMAX) k_mv_apply_g(const k_mv_apply_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_mv_apply_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_mv_apply_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_mv_apply_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_mv_apply_args* a, const int* st, const int* gy, int mm) {
+    k_mv_apply_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_mv_apply now, or records it while a recorder is open on this thread
+static void k_mv_apply_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_mv_apply_args& a) {
+  if (recording())
+    record_group(k_mv_apply_grp, group_key((const void*)k_mv_apply_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_mv_apply<<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // launchers
@@ -523,18 +882,21 @@ static void sweep_level(FactorData& F, const T* panel, int op, int l, double* v,
   double* coef = work + (size_t)std::max(P.max_ltasks, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   const int hbase = (1 << l) - 1;
-  auto rv = nrhs <= 1 ? k_reduce_vec<T, 1> : nrhs <= 2 ? k_reduce_vec<T, 2> : k_reduce_vec<T, 4>;
-  rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, panel, P.Ktot, v, nrhs,
-                             ld, zpart, zs_task);
+#define FG_REDUCE_VEC(NR_)                                                                   \
+  k_reduce_vec_launch<T, NR_>(dim3(nt), dim3(NTHREADS), 0, s,                                  \
+                              k_reduce_vec_args<T, NR_>{D.ltasks, tb, nt, D.nodes, D.coff, H.kmax, \
+                                                        panel, P.Ktot, v, nrhs, ld, zpart, zs_task})
+  if (nrhs <= 1) FG_REDUCE_VEC(1); else if (nrhs <= 2) FG_REDUCE_VEC(2); else FG_REDUCE_VEC(4);
+#undef FG_REDUCE_VEC
   // the node coefficients sum the sides' task partials themselves (no separate pass)
-  k_node_coef<<<1 << l, P.max_tps[l] > 1 ? NC_MAX_THREADS : 64, 0, s>>>(
+  k_node_coef_launch(dim3(1 << l), dim3(P.max_tps[l] > 1 ? NC_MAX_THREADS : 64), 0, s, k_node_coef_args{
       op, hbase, 1 << l, H.rank, D.node_task_off, tb, zpart, zs_task, nrhs, F.nodemat,
-      D.nodemat_off, 0.0, nullptr, coef, cs_node, nullptr);
+      D.nodemat_off, 0.0, nullptr, coef, cs_node, nullptr});
   const int skip_left = (op == 0 || op == 2) ? 1 : 0;
   const dim3 grid_u(nt, (std::min(P.max_trows[l], RCH) + NTHREADS - 1) / NTHREADS);
-  k_update_vec<T><<<grid_u, NTHREADS, 0, s>>>(D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
+  k_update_vec_launch<T>(grid_u, dim3(NTHREADS), 0, s, k_update_vec_args<T>{D.ltasks, tb, nt, D.nodes, hbase, H.rank, D.coff,
                                               panel, P.Ktot, v, nrhs, ld, coef, cs_node,
-                                              skip_left);
+                                              skip_left});
 }
 
 template <typename T>
@@ -545,11 +907,11 @@ static void apply_w(FactorData& F, const T* leafL, const T* leafLinv, const doub
   // W = L_D W_(L-1) ... W_(0)
   auto leaf = [&](int lop) {
     if (lop == 0 || lop == 2)
-      k_leaf_apply<T><<<P.nleaf, BMAX, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop, v,
-                                               nrhs, ld);
+      k_leaf_apply_launch<T>(dim3(P.nleaf), dim3(BMAX), 0, s, k_leaf_apply_args<T>{leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop, v,
+                                               nrhs, ld});
     else
-      k_leaf_apply_t<T><<<P.nleaf, NTHREADS, 0, s>>>(leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop,
-                                                     v, nrhs, ld);
+      k_leaf_apply_t_launch<T>(dim3(P.nleaf), dim3(NTHREADS), 0, s, k_leaf_apply_t_args<T>{leaf_lo, P.nleaf, leafL, leafLinv, P.B, lop,
+                                                     v, nrhs, ld});
   };
   if (op == 0) {          // W v: W_(0) first, then finer levels, then L_D
     for (int l = 0; l < P.L; ++l) sweep_level<double>(F, panel, 0, l, v, nrhs, ld, work, s);
@@ -585,19 +947,25 @@ void launch_matvec(const HodlrData& H, double alpha, double beta, const double* 
   double* coef = work + (size_t)std::max(nt, 1) * zs_task;
   const int cs_node = 2 * PMAX * NRHS_MAX;
   if (P.L > 0) {
-    auto rv = nrhs <= 1 ? k_reduce_vec<double, 1>
-            : nrhs <= 2 ? k_reduce_vec<double, 2> : k_reduce_vec<double, 4>;
-    rv<<<nt, NTHREADS, 0, s>>>(D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel, P.Ktot, v,
-                               nrhs, ld, zpart, zs_task);
+#define FG_REDUCE_VEC(NR_)                                                                 \
+  k_reduce_vec_launch<double, NR_>(                                                          \
+      dim3(nt), dim3(NTHREADS), 0, s,                                                        \
+      k_reduce_vec_args<double, NR_>{D.ltasks, 0, nt, D.nodes, D.coff, H.kmax, H.panel, P.Ktot, \
+                                     v, nrhs, ld, zpart, zs_task})
+    if (nrhs <= 1) FG_REDUCE_VEC(1); else if (nrhs <= 2) FG_REDUCE_VEC(2); else FG_REDUCE_VEC(4);
+#undef FG_REDUCE_VEC
     double* zs = coef + (size_t)std::max(P.nint, 1) * cs_node;
     launch_zsum(zpart, zs_task, 0, D.node_task_off, 0, 2 * P.nint, zs_task, zs, zs_task,
                 *std::max_element(P.max_tps.begin(), P.max_tps.end()), s);
-    k_node_coef<<<P.nint, 64, 0, s>>>(4, 0, P.nint, H.rank, D.node_task_off, 0, zpart, zs_task,
-                                      nrhs, nullptr, nullptr, alpha, alpha_dev, coef, cs_node, zs);
+    k_node_coef_launch(dim3(P.nint), dim3(64), 0, s,
+                       k_node_coef_args{4, 0, P.nint, H.rank, D.node_task_off, 0, zpart, zs_task,
+                                        nrhs, nullptr, nullptr, alpha, alpha_dev, coef, cs_node,
+                                        zs});
   }
-  k_mv_apply<<<P.nleaf, BMAX, 0, s>>>(D.leaf_lo, P.nleaf, P.L, H.x, P.kind, P.ell, P.nugget,
-                                      alpha, alpha_dev, beta, beta_dev, v, y, nrhs, ld, H.rank,
-                                      D.coff, H.panel, P.Ktot, coef, cs_node);
+  k_mv_apply_launch(dim3(P.nleaf), dim3(BMAX), 0, s,
+                    k_mv_apply_args{D.leaf_lo, P.nleaf, P.L, H.x, P.kind, P.ell, P.nugget, alpha,
+                                    alpha_dev, beta, beta_dev, v, y, nrhs, ld, H.rank, D.coff,
+                                    H.panel, P.Ktot, coef, cs_node});
 }
 
 }  // namespace fg

@@ -13,6 +13,7 @@
 // as U = T_I(x) T_U, V = T_J(y) T_V with T_U = R_I^-1 U_X sqrt(S), T_V = R_J^-1 V_X sqrt(S).
 #include <cfloat>
 
+#include "fg_group.h"
 #include "fg_internal.h"
 #include "fg_timer.h"
 
@@ -31,12 +32,28 @@ constexpr int MRPT = MCHM / 64;  // rows per lane
 constexpr int MB = 16;           // moments per chunk
 static_assert(MRPT * 64 == MCHM, "a moment task must fit the lanes of one wave");
 
-__global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ tasks, int ntask,
-                                                      const NodePlan* __restrict__ nodes,
-                                                      const double* __restrict__ x,
-                                                      double* __restrict__ mpart, int stride) {
+// arguments of k_moments (one struct, so that grouped launches can stage one per member)
+struct k_moments_args {
+  const Task* tasks;
+  int ntask;
+  const NodePlan* nodes;
+  const double* x;
+  double* mpart;
+  int stride;
+};
+__device__ __forceinline__ void k_moments_body(const k_moments_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int ntask = a_.ntask;
+  const NodePlan* __restrict__ nodes = a_.nodes;
+  const double* __restrict__ x = a_.x;
+  double* __restrict__ mpart = a_.mpart;
+  int stride = a_.stride;
+  (void)by_;
+  (void)gy_;
+
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * (NTHREADS / 64) + (threadIdx.x >> 6);
+  const int t = bx_ * (NTHREADS / 64) + (threadIdx.x >> 6);
   if (t >= ntask) return;  // whole waves: no barrier below
   const Task tk = tasks[t];
   const NodePlan q = nodes[tk.h];
@@ -96,6 +113,32 @@ __global__ void __launch_bounds__(NTHREADS) k_moments(const Task* __restrict__ t
     sum += __shfl_xor(sum, 1, 64);
     if ((lane & 3) == 0 && mb + e < nm) out[mb + e] = sum;
   }
+}
+__global__ void __launch_bounds__(NTHREADS) k_moments(const k_moments_args a_) {
+  k_moments_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NTHREADS) k_moments_g(const k_moments_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_moments_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_moments_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_moments_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_moments_args* a, const int* st, const int* gy, int mm) {
+    k_moments_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_moments now, or records it while a recorder is open on this thread
+static void k_moments_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_moments_args& a) {
+  if (recording())
+    record_group(k_moments_grp, group_key((const void*)k_moments_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_moments<<<g, b, lds, s>>>(a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -431,14 +474,50 @@ __device__ bool lds_svd_qr(double* M, int mr, int qc, int ld, double* Q, double*
 // ---------------------------------------------------------------------------------
 // compression: one work-group per internal node
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTHREADS) k_compress(
-    const NodePlan* __restrict__ nodes, int nint, const double* __restrict__ x, int kind,
-    double ell, double tol, const double* __restrict__ mpart, int mstride,
-    const int* __restrict__ mtask_off, const int* __restrict__ kcap, double* __restrict__ tbuf,
-    double* __restrict__ sv, int* __restrict__ rank, int* __restrict__ status, int pm, int h0,
-    int h1) {
+// arguments of k_compress (one struct, so that grouped launches can stage one per member)
+struct k_compress_args {
+  const NodePlan* nodes;
+  int nint;
+  const double* x;
+  int kind;
+  double ell;
+  double tol;
+  const double* mpart;
+  int mstride;
+  const int* mtask_off;
+  const int* kcap;
+  double* tbuf;
+  double* sv;
+  int* rank;
+  int* status;
+  int pm;
+  int h0;
+  int h1;
+};
+__device__ __forceinline__ void k_compress_body(const k_compress_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const NodePlan* __restrict__ nodes = a_.nodes;
+  int nint = a_.nint;
+  const double* __restrict__ x = a_.x;
+  int kind = a_.kind;
+  double ell = a_.ell;
+  double tol = a_.tol;
+  const double* __restrict__ mpart = a_.mpart;
+  int mstride = a_.mstride;
+  const int* __restrict__ mtask_off = a_.mtask_off;
+  const int* __restrict__ kcap = a_.kcap;
+  double* __restrict__ tbuf = a_.tbuf;
+  double* __restrict__ sv = a_.sv;
+  int* __restrict__ rank = a_.rank;
+  int* __restrict__ status = a_.status;
+  int pm = a_.pm;
+  int h0 = a_.h0;
+  int h1 = a_.h1;
+  (void)by_;
+  (void)gy_;
+
   // nodes h0 .. h1-1, each with interpolation orders of at most pm
-  const int h = h0 + blockIdx.x;
+  const int h = h0 + bx_;
   if (h >= h1 || h >= nint) return;
   const NodePlan q = nodes[h];
   const int pI = q.pI, pJ = q.pJ;
@@ -629,15 +708,60 @@ __global__ void __launch_bounds__(NTHREADS) k_compress(
   }
   (void)kc;
 }
+__global__ void __launch_bounds__(NTHREADS) k_compress(const k_compress_args a_) {
+  k_compress_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NTHREADS) k_compress_g(const k_compress_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_compress_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_compress_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_compress_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_compress_args* a, const int* st, const int* gy, int mm) {
+    k_compress_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_compress now, or records it while a recorder is open on this thread
+static void k_compress_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_compress_args& a) {
+  if (recording())
+    record_group(k_compress_grp, group_key((const void*)k_compress_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_compress<<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // per-level maximum rank and the right-column lists used by the factorization
 // ---------------------------------------------------------------------------------
 constexpr int RL_THREADS = 1024;
-__global__ void __launch_bounds__(RL_THREADS) k_rank_levels(
-    const int* __restrict__ rank, int L, const int* __restrict__ coff, int Ktot,
-    int* __restrict__ kmax, int* __restrict__ rcols, int* __restrict__ rcount) {
-  if (blockIdx.x != 0) return;
+// arguments of k_rank_levels (one struct, so that grouped launches can stage one per member)
+struct k_rank_levels_args {
+  const int* rank;
+  int L;
+  const int* coff;
+  int Ktot;
+  int* kmax;
+  int* rcols;
+  int* rcount;
+};
+__device__ __forceinline__ void k_rank_levels_body(const k_rank_levels_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ rank = a_.rank;
+  int L = a_.L;
+  const int* __restrict__ coff = a_.coff;
+  int Ktot = a_.Ktot;
+  int* __restrict__ kmax = a_.kmax;
+  int* __restrict__ rcols = a_.rcols;
+  int* __restrict__ rcount = a_.rcount;
+  (void)by_;
+  (void)gy_;
+
+  if (bx_ != 0) return;
   __shared__ int km[32];
   if (threadIdx.x < 32) km[threadIdx.x] = 0;
   __syncthreads();
@@ -670,16 +794,65 @@ __global__ void __launch_bounds__(RL_THREADS) k_rank_levels(
     }
   }
 }
+__global__ void __launch_bounds__(RL_THREADS) k_rank_levels(const k_rank_levels_args a_) {
+  k_rank_levels_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(RL_THREADS) k_rank_levels_g(const k_rank_levels_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_rank_levels_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_rank_levels_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_rank_levels_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_rank_levels_args* a, const int* st, const int* gy, int mm) {
+    k_rank_levels_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_rank_levels now, or records it while a recorder is open on this thread
+static void k_rank_levels_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_rank_levels_args& a) {
+  if (recording())
+    record_group(k_rank_levels_grp, group_key((const void*)k_rank_levels_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_rank_levels<<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // panel generation: U rows of left children, V rows of right children (all levels)
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTHREADS) k_panel_gen(
-    const Task* __restrict__ tasks, int ntask, const NodePlan* __restrict__ nodes,
-    const double* __restrict__ x, const double* __restrict__ tbuf, const int* __restrict__ rank,
-    const int* __restrict__ kmax, const int* __restrict__ coff, double* __restrict__ panel,
-    int K) {
-  const int t = blockIdx.x;
+// arguments of k_panel_gen (one struct, so that grouped launches can stage one per member)
+struct k_panel_gen_args {
+  const Task* tasks;
+  int ntask;
+  const NodePlan* nodes;
+  const double* x;
+  const double* tbuf;
+  const int* rank;
+  const int* kmax;
+  const int* coff;
+  double* panel;
+  int K;
+};
+__device__ __forceinline__ void k_panel_gen_body(const k_panel_gen_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int ntask = a_.ntask;
+  const NodePlan* __restrict__ nodes = a_.nodes;
+  const double* __restrict__ x = a_.x;
+  const double* __restrict__ tbuf = a_.tbuf;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ kmax = a_.kmax;
+  const int* __restrict__ coff = a_.coff;
+  double* __restrict__ panel = a_.panel;
+  int K = a_.K;
+  (void)by_;
+  (void)gy_;
+
+  const int t = bx_;
   if (t >= ntask) return;
   const Task tk = tasks[t];
   const NodePlan q = nodes[tk.h];
@@ -744,6 +917,32 @@ __global__ void __launch_bounds__(NTHREADS) k_panel_gen(
     for (int cc = k; cc < kl; ++cc) panel[pix(r, cb + cc, K)] = 0.0;
   }
 }
+__global__ void __launch_bounds__(NTHREADS) k_panel_gen(const k_panel_gen_args a_) {
+  k_panel_gen_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NTHREADS) k_panel_gen_g(const k_panel_gen_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_panel_gen_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_panel_gen_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_panel_gen_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_panel_gen_args* a, const int* st, const int* gy, int mm) {
+    k_panel_gen_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_panel_gen now, or records it while a recorder is open on this thread
+static void k_panel_gen_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_panel_gen_args& a) {
+  if (recording())
+    record_group(k_panel_gen_grp, group_key((const void*)k_panel_gen_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_panel_gen<<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // sampled entries of K~_1
@@ -778,13 +977,17 @@ __global__ void k_entries(const NodePlan* __restrict__ nodes, int nint,
 // ---------------------------------------------------------------------------------
 void launch_build(HodlrData& H, hipStream_t s) {
   const HostPlan& P = H.pk->P;
-  const DevPlan& D = H.pk->D;
+  const DevPlan D = H.pk->D;
   timer_forget(H.kmax);  // the ranks change below
   if (P.L == 0) return;
-  const int nm = P.nmt;
+  // the plan's scalars (launches recorded for a grouped replay copy what they use)
+  const int nm = P.nmt, nint = P.nint, kind = P.kind, mstride = P.mpart_stride, L = P.L;
+  const int Ktot = P.Ktot;
+  const double ell = P.ell, tol = P.tol;
+  const HodlrData Hc = H;
   if (nm > 0)
-    k_moments<<<(nm + NTHREADS / 64 - 1) / (NTHREADS / 64), NTHREADS, 0, s>>>(
-        D.mtasks, nm, D.nodes, H.x, H.mpart, P.mpart_stride);
+    k_moments_launch(dim3((nm + NTHREADS / 64 - 1) / (NTHREADS / 64)), dim3(NTHREADS), 0, s,
+                     k_moments_args{D.mtasks, nm, D.nodes, Hc.x, Hc.mpart, mstride});
   // A work-group holds five p x p matrices in LDS, p the largest order of its launch.  The
   // top levels set the largest order; when every level from ls down needs at most half
   // that LDS and those levels hold far more nodes than the GPU keeps resident at the top
@@ -807,21 +1010,29 @@ void launch_build(HodlrData& H, hipStream_t s) {
   static const bool lds_set = [] {
     (void)hipFuncSetAttribute((const void*)k_compress, hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(sizeof(double) * 5 * PMAX * PMAX));
+    (void)hipFuncSetAttribute((const void*)k_compress_g,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(sizeof(double) * 5 * PMAX * PMAX));
     return true;
   }();
   (void)lds_set;
 
-  k_compress<<<h_split, NTHREADS, sizeof(double) * 5 * pm * pm, s>>>(
-      D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart, P.mpart_stride, D.mtask_off, D.kcap,
-      H.tbuf, H.sv, H.rank, H.status, pm, 0, h_split);
-  if (h_split < P.nint)
-    k_compress<<<P.nint - h_split, NTHREADS, sizeof(double) * 5 * pm_lo * pm_lo, s>>>(
-        D.nodes, P.nint, H.x, P.kind, P.ell, P.tol, H.mpart, P.mpart_stride, D.mtask_off,
-        D.kcap, H.tbuf, H.sv, H.rank, H.status, pm_lo, h_split, P.nint);
-  k_rank_levels<<<1, RL_THREADS, 0, s>>>(H.rank, P.L, D.coff, P.Ktot, H.kmax, H.rcols, H.rcount);
+  k_compress_launch(dim3(h_split), dim3(NTHREADS), (uint32_t)(sizeof(double) * 5 * pm * pm), s,
+                    k_compress_args{D.nodes, nint, Hc.x, kind, ell, tol, Hc.mpart, mstride,
+                                    D.mtask_off, D.kcap, Hc.tbuf, Hc.sv, Hc.rank, Hc.status, pm,
+                                    0, h_split});
+  if (h_split < nint)
+    k_compress_launch(dim3(nint - h_split), dim3(NTHREADS),
+                      (uint32_t)(sizeof(double) * 5 * pm_lo * pm_lo), s,
+                      k_compress_args{D.nodes, nint, Hc.x, kind, ell, tol, Hc.mpart, mstride,
+                                      D.mtask_off, D.kcap, Hc.tbuf, Hc.sv, Hc.rank, Hc.status,
+                                      pm_lo, h_split, nint});
+  k_rank_levels_launch(dim3(1), dim3(RL_THREADS), 0, s,
+                       k_rank_levels_args{Hc.rank, L, D.coff, Ktot, Hc.kmax, Hc.rcols, Hc.rcount});
   const int ng = P.ngt;
-  k_panel_gen<<<ng, NTHREADS, 0, s>>>(D.gtasks, ng, D.nodes, H.x, H.tbuf, H.rank, H.kmax,
-                                      D.coff, H.panel, P.Ktot);
+  k_panel_gen_launch(dim3(ng), dim3(NTHREADS), 0, s,
+                     k_panel_gen_args{D.gtasks, ng, D.nodes, Hc.x, Hc.tbuf, Hc.rank, Hc.kmax,
+                                      D.coff, Hc.panel, Ktot});
 }
 
 void launch_entries(const HodlrData& H, const int64_t* i, const int64_t* j, int64_t count,

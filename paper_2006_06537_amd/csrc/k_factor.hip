@@ -12,6 +12,7 @@
 // S = U~'Y_I, T = V~'Y_J.  log det W W' = 2 sum log diag L_D + sum_nodes sum log(1-s2).
 #include <cfloat>
 
+#include "fg_group.h"
 #include "fg_internal.h"
 #include "fg_timer.h"
 
@@ -121,14 +122,49 @@ __device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
 }
 
 #define LT(i, j) ((i) * ((i) + 1) / 2 + (j))
+// arguments of k_leaf (one struct, so that grouped launches can stage one per member)
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
-    const int* __restrict__ leaf_lo, int nleaf, const double* __restrict__ x, int kind, double ell,
-    double nugget, double alpha_v, const double* __restrict__ alpha_p, double beta_v,
-    const double* __restrict__ beta_p, const double* __restrict__ diag, int Bc,
-    T* __restrict__ leafL, T* __restrict__ leafLinv, double* __restrict__ leaf_ld,
-    int* __restrict__ status) {
-  const int b = blockIdx.x;
+struct k_leaf_args {
+  const int* leaf_lo;
+  int nleaf;
+  const double* x;
+  int kind;
+  double ell;
+  double nugget;
+  double alpha_v;
+  const double* alpha_p;
+  double beta_v;
+  const double* beta_p;
+  const double* diag;
+  int Bc;
+  T* leafL;
+  T* leafLinv;
+  double* leaf_ld;
+  int* status;
+};
+template <typename T>
+__device__ __forceinline__ void k_leaf_body(const k_leaf_args<T>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ leaf_lo = a_.leaf_lo;
+  int nleaf = a_.nleaf;
+  const double* __restrict__ x = a_.x;
+  int kind = a_.kind;
+  double ell = a_.ell;
+  double nugget = a_.nugget;
+  double alpha_v = a_.alpha_v;
+  const double* __restrict__ alpha_p = a_.alpha_p;
+  double beta_v = a_.beta_v;
+  const double* __restrict__ beta_p = a_.beta_p;
+  const double* __restrict__ diag = a_.diag;
+  int Bc = a_.Bc;
+  T* __restrict__ leafL = a_.leafL;
+  T* __restrict__ leafLinv = a_.leafLinv;
+  double* __restrict__ leaf_ld = a_.leaf_ld;
+  int* __restrict__ status = a_.status;
+  (void)by_;
+  (void)gy_;
+
+  const int b = bx_;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const int nb = (m + 15) >> 4;  // 16-row blocks in use
@@ -262,6 +298,36 @@ __global__ void __launch_bounds__(NTHREADS, 3) k_leaf(
   // itself is never formed: its products are blocked substitutions, k_whiten and
   // k_leaf_apply)
 }
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS, 3) k_leaf(const k_leaf_args<T> a_) {
+  k_leaf_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS, 3) k_leaf_g(const k_leaf_args<T>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_leaf_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T>
+static void k_leaf_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_leaf_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_leaf_args<T>* a, const int* st, const int* gy, int mm) {
+    k_leaf_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_leaf now, or records it while a recorder is open on this thread
+template <typename T>
+static void k_leaf_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_leaf_args<T>& a) {
+  if (recording())
+    record_group(k_leaf_grp<T>, group_key((const void*)k_leaf_grp<T>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_leaf<T><<<g, b, lds, s>>>(a);
+}
 
 #undef LT
 
@@ -317,17 +383,48 @@ __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
 // 16-row group, K-slot k holds row base + 4k + s, so lane l reads rows base + 4 (l/16)
 // .. +3 of its column: 32 contiguous bytes, and the four steps use each 128-byte line
 // of the 16-row tile completely.
+// arguments of k_reduce_panel (one struct, so that grouped launches can stage one per member)
 template <typename T, int NA>
-__global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
-    const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ coff,
-    const int* __restrict__ kmax, const int* __restrict__ rcols, const int* __restrict__ rcount,
-    int K, const T* __restrict__ P, double* __restrict__ zpart, int zs_a, int zs_task) {
+struct k_reduce_panel_args {
+  const Task* tasks;
+  int tbase;
+  int ntask;
+  int l;
+  const int* coff;
+  const int* kmax;
+  const int* rcols;
+  const int* rcount;
+  int K;
+  const T* P;
+  double* zpart;
+  int zs_a;
+  int zs_task;
+};
+template <typename T, int NA>
+__device__ __forceinline__ void k_reduce_panel_body(const k_reduce_panel_args<T, NA>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int tbase = a_.tbase;
+  int ntask = a_.ntask;
+  int l = a_.l;
+  const int* __restrict__ coff = a_.coff;
+  const int* __restrict__ kmax = a_.kmax;
+  const int* __restrict__ rcols = a_.rcols;
+  const int* __restrict__ rcount = a_.rcount;
+  int K = a_.K;
+  const T* __restrict__ P = a_.P;
+  double* __restrict__ zpart = a_.zpart;
+  int zs_a = a_.zs_a;
+  int zs_task = a_.zs_task;
+  (void)by_;
+  (void)gy_;
+
   typedef typename Mfma<T>::acc_t acc_t;
-  const int t = blockIdx.x;
+  const int t = bx_;
   if (t >= ntask) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c0 = coff[l], kl = kmax[l], W = rcount[l];
-  const int b0 = blockIdx.y * 64 + wv * 16;
+  const int b0 = by_ * 64 + wv * 16;
   if (b0 >= W || kl == 0) return;
   const Task tk = tasks[tbase + t];
   const int na = min(NA, (kl + 15) >> 4);  // left tiles in use (NA: capacity of the level)
@@ -389,6 +486,36 @@ __global__ void __launch_bounds__(NTHREADS) k_reduce_panel(
     }
   }
 }
+template <typename T, int NA>
+__global__ void __launch_bounds__(NTHREADS) k_reduce_panel(const k_reduce_panel_args<T, NA> a_) {
+  k_reduce_panel_body<T, NA>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T, int NA>
+__global__ void __launch_bounds__(NTHREADS) k_reduce_panel_g(const k_reduce_panel_args<T, NA>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_reduce_panel_body<T, NA>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T, int NA>
+static void k_reduce_panel_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_reduce_panel_args<T, NA>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_reduce_panel_args<T, NA>* a, const int* st, const int* gy, int mm) {
+    k_reduce_panel_g<T, NA><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_reduce_panel now, or records it while a recorder is open on this thread
+template <typename T, int NA>
+static void k_reduce_panel_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_reduce_panel_args<T, NA>& a) {
+  if (recording())
+    record_group(k_reduce_panel_grp<T, NA>, group_key((const void*)k_reduce_panel_grp<T, NA>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_reduce_panel<T, NA><<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // leaf whitening on matrix cores: dst = sqrt(alpha) L^-1 src for every active panel
@@ -406,14 +533,44 @@ constexpr int WB = BMAX / 16;          // 16-row blocks per leaf (8)
 constexpr int WTRI = WB * (WB + 1) / 2;  // lower blocks (36)
 constexpr int WPD = 17;                // LDS pitch of a staged block
 
+// arguments of k_whiten (one struct, so that grouped launches can stage one per member)
 template <typename T, typename TL>
-__global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
-    const int* __restrict__ leaf_lo, int nleaf, const TL* __restrict__ leafL,
-    const TL* __restrict__ leafLinv, int Bc, double alpha_v, const double* __restrict__ alpha_p,
-    const double* __restrict__ src, T* __restrict__ dst, int K, const int* __restrict__ coff,
-    const int* __restrict__ kmax, int L) {
+struct k_whiten_args {
+  const int* leaf_lo;
+  int nleaf;
+  const TL* leafL;
+  const TL* leafLinv;
+  int Bc;
+  double alpha_v;
+  const double* alpha_p;
+  const double* src;
+  T* dst;
+  int K;
+  const int* coff;
+  const int* kmax;
+  int L;
+};
+template <typename T, typename TL>
+__device__ __forceinline__ void k_whiten_body(const k_whiten_args<T, TL>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const int* __restrict__ leaf_lo = a_.leaf_lo;
+  int nleaf = a_.nleaf;
+  const TL* __restrict__ leafL = a_.leafL;
+  const TL* __restrict__ leafLinv = a_.leafLinv;
+  int Bc = a_.Bc;
+  double alpha_v = a_.alpha_v;
+  const double* __restrict__ alpha_p = a_.alpha_p;
+  const double* __restrict__ src = a_.src;
+  T* __restrict__ dst = a_.dst;
+  int K = a_.K;
+  const int* __restrict__ coff = a_.coff;
+  const int* __restrict__ kmax = a_.kmax;
+  int L = a_.L;
+  (void)by_;
+  (void)gy_;
+
   typedef typename Mfma<T>::acc_t acc_t;
-  const int b = blockIdx.x;
+  const int b = bx_;
   if (b >= nleaf) return;
   const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
   const int nb = (m + 15) >> 4;
@@ -496,22 +653,74 @@ __global__ void __launch_bounds__(NTHREADS, 2) k_whiten(
     }
   }
 }
+template <typename T, typename TL>
+__global__ void __launch_bounds__(NTHREADS, 2) k_whiten(const k_whiten_args<T, TL> a_) {
+  k_whiten_body<T, TL>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T, typename TL>
+__global__ void __launch_bounds__(NTHREADS, 2) k_whiten_g(const k_whiten_args<T, TL>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_whiten_body<T, TL>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T, typename TL>
+static void k_whiten_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_whiten_args<T, TL>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_whiten_args<T, TL>* a, const int* st, const int* gy, int mm) {
+    k_whiten_g<T, TL><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_whiten now, or records it while a recorder is open on this thread
+template <typename T, typename TL>
+static void k_whiten_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_whiten_args<T, TL>& a) {
+  if (recording())
+    record_group(k_whiten_grp<T, TL>, group_key((const void*)k_whiten_grp<T, TL>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_whiten<T, TL><<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // deterministic sum of task partials per node side: zfin[side][e] = sum_t zpart[t][e]
 // (4 task lanes per entry, combined in a fixed order).  Sides with a single task are
 // skipped: their consumers read zpart[t0] in place.
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zpart, int zs_task,
-                                                   int tbase, const int* __restrict__ node_task_off,
-                                                   int hbase, int nsides, int esz,
-                                                   double* __restrict__ zfin, int zf_side) {
-  const int sd = blockIdx.x;
+// arguments of k_zsum (one struct, so that grouped launches can stage one per member)
+struct k_zsum_args {
+  const double* zpart;
+  int zs_task;
+  int tbase;
+  const int* node_task_off;
+  int hbase;
+  int nsides;
+  int esz;
+  double* zfin;
+  int zf_side;
+};
+__device__ __forceinline__ void k_zsum_body(const k_zsum_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const double* __restrict__ zpart = a_.zpart;
+  int zs_task = a_.zs_task;
+  int tbase = a_.tbase;
+  const int* __restrict__ node_task_off = a_.node_task_off;
+  int hbase = a_.hbase;
+  int nsides = a_.nsides;
+  int esz = a_.esz;
+  double* __restrict__ zfin = a_.zfin;
+  int zf_side = a_.zf_side;
+  (void)by_;
+  (void)gy_;
+
+  const int sd = bx_;
   if (sd >= nsides) return;
   const int h = hbase + (sd >> 1), side = sd & 1;
   const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
   if (t1 - t0 <= 1) return;
-  const int e = blockIdx.y * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int e = by_ * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
   __shared__ double red[4][64];
   // group g sums tasks t0 + g, t0 + g + 4, ... in that order; eight loads are issued
   // before their additions, so a long side does not wait on one load at a time
@@ -533,20 +742,67 @@ __global__ void __launch_bounds__(NTHREADS) k_zsum(const double* __restrict__ zp
     zfin[(size_t)sd * zf_side + e] =
         (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
+__global__ void __launch_bounds__(NTHREADS) k_zsum(const k_zsum_args a_) {
+  k_zsum_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NTHREADS) k_zsum_g(const k_zsum_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_zsum_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_zsum_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_zsum_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_zsum_args* a, const int* st, const int* gy, int mm) {
+    k_zsum_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_zsum now, or records it while a recorder is open on this thread
+static void k_zsum_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_zsum_args& a) {
+  if (recording())
+    record_group(k_zsum_grp, group_key((const void*)k_zsum_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_zsum<<<g, b, lds, s>>>(a);
+}
 
 // sides of at most four tasks: one element per thread, summed as (z0 + z1) + (z2 + z3),
 // the value k_zsum's four groups give, so that both kernels agree to the bit
-__global__ void __launch_bounds__(NTHREADS) k_zsum_few(const double* __restrict__ zpart,
-                                                       int zs_task, int tbase,
-                                                       const int* __restrict__ node_task_off,
-                                                       int hbase, int nsides, int esz,
-                                                       double* __restrict__ zfin, int zf_side) {
-  const int sd = blockIdx.x;
+// arguments of k_zsum_few (one struct, so that grouped launches can stage one per member)
+struct k_zsum_few_args {
+  const double* zpart;
+  int zs_task;
+  int tbase;
+  const int* node_task_off;
+  int hbase;
+  int nsides;
+  int esz;
+  double* zfin;
+  int zf_side;
+};
+__device__ __forceinline__ void k_zsum_few_body(const k_zsum_few_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const double* __restrict__ zpart = a_.zpart;
+  int zs_task = a_.zs_task;
+  int tbase = a_.tbase;
+  const int* __restrict__ node_task_off = a_.node_task_off;
+  int hbase = a_.hbase;
+  int nsides = a_.nsides;
+  int esz = a_.esz;
+  double* __restrict__ zfin = a_.zfin;
+  int zf_side = a_.zf_side;
+  (void)by_;
+  (void)gy_;
+
+  const int sd = bx_;
   if (sd >= nsides) return;
   const int h = hbase + (sd >> 1), side = sd & 1;
   const int t0 = node_task_off[2 * h + side] - tbase, t1 = node_task_off[2 * h + side + 1] - tbase;
   const int nt = t1 - t0;
-  const int e = blockIdx.y * NTHREADS + threadIdx.x;
+  const int e = by_ * NTHREADS + threadIdx.x;
   if (nt <= 1 || e >= esz) return;
   const double* z = zpart + (size_t)t0 * zs_task + e;
   const double a = z[0] + z[zs_task];
@@ -555,19 +811,46 @@ __global__ void __launch_bounds__(NTHREADS) k_zsum_few(const double* __restrict_
   if (nt > 3) b += z[3 * (size_t)zs_task];
   zfin[(size_t)sd * zf_side + e] = a + b;
 }
+__global__ void __launch_bounds__(NTHREADS) k_zsum_few(const k_zsum_few_args a_) {
+  k_zsum_few_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(NTHREADS) k_zsum_few_g(const k_zsum_few_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_zsum_few_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_zsum_few_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_zsum_few_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_zsum_few_args* a, const int* st, const int* gy, int mm) {
+    k_zsum_few_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_zsum_few now, or records it while a recorder is open on this thread
+static void k_zsum_few_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_zsum_few_args& a) {
+  if (recording())
+    record_group(k_zsum_few_grp, group_key((const void*)k_zsum_few_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_zsum_few<<<g, b, lds, s>>>(a);
+}
 
 void launch_zsum(const double* zpart, int zs_task, int tbase, const int* node_task_off, int hbase,
                  int nsides, int esz, double* zfin, int zf_side, int max_tasks, hipStream_t s) {
   if (nsides <= 0 || esz <= 0) return;
   if (max_tasks <= 4) {
     const dim3 grid(nsides, (esz + NTHREADS - 1) / NTHREADS);
-    k_zsum_few<<<grid, NTHREADS, 0, s>>>(zpart, zs_task, tbase, node_task_off, hbase, nsides, esz,
-                                         zfin, zf_side);
+    k_zsum_few_launch(grid, dim3(NTHREADS), 0, s,
+                      k_zsum_few_args{zpart, zs_task, tbase, node_task_off, hbase, nsides, esz,
+                                      zfin, zf_side});
     return;
   }
   const dim3 grid(nsides, (esz + 63) / 64);
-  k_zsum<<<grid, NTHREADS, 0, s>>>(zpart, zs_task, tbase, node_task_off, hbase, nsides, esz, zfin,
-                                   zf_side);
+  k_zsum_launch(grid, dim3(NTHREADS), 0, s,
+                k_zsum_args{zpart, zs_task, tbase, node_task_off, hbase, nsides, esz, zfin, zf_side});
 }
 
 // ---------------------------------------------------------------------------------
@@ -891,14 +1174,53 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
 // node factor of one level (factorization): Gram blocks -> (G_V, F1, F2), log-det
 // and the update coefficients of the coarser panels
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_node_factor(
-    int l, const int* __restrict__ rank, const int* __restrict__ kmax,
-    const int* __restrict__ rcount, const int* __restrict__ node_task_off, int tbase,
-    double* __restrict__ zpart, int zs_a, int zs_task, double* __restrict__ zfin,
-    int zf_side, double* __restrict__ nodemat, const int* __restrict__ nodemat_off,
-    double* __restrict__ node_ld, double* __restrict__ coef, int cs_node, int cs_a,
-    int* __restrict__ status, int kc) {
-  const int j = blockIdx.x;
+// arguments of k_node_factor (one struct, so that grouped launches can stage one per member)
+struct k_node_factor_args {
+  int l;
+  const int* rank;
+  const int* kmax;
+  const int* rcount;
+  const int* node_task_off;
+  int tbase;
+  double* zpart;
+  int zs_a;
+  int zs_task;
+  double* zfin;
+  int zf_side;
+  double* nodemat;
+  const int* nodemat_off;
+  double* node_ld;
+  double* coef;
+  int cs_node;
+  int cs_a;
+  int* status;
+  int kc;
+};
+__device__ __forceinline__ void k_node_factor_body(const k_node_factor_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  int l = a_.l;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ kmax = a_.kmax;
+  const int* __restrict__ rcount = a_.rcount;
+  const int* __restrict__ node_task_off = a_.node_task_off;
+  int tbase = a_.tbase;
+  double* __restrict__ zpart = a_.zpart;
+  int zs_a = a_.zs_a;
+  int zs_task = a_.zs_task;
+  double* __restrict__ zfin = a_.zfin;
+  int zf_side = a_.zf_side;
+  double* __restrict__ nodemat = a_.nodemat;
+  const int* __restrict__ nodemat_off = a_.nodemat_off;
+  double* __restrict__ node_ld = a_.node_ld;
+  double* __restrict__ coef = a_.coef;
+  int cs_node = a_.cs_node;
+  int cs_a = a_.cs_a;
+  int* __restrict__ status = a_.status;
+  int kc = a_.kc;
+  (void)by_;
+  (void)gy_;
+
+  const int j = bx_;
   const int h = (1 << l) - 1 + j;
   const int k = rank[h], kl = kmax[l], W = rcount[l], Wc = W - kl;
   if (k == 0) {
@@ -1025,6 +1347,32 @@ __global__ void __launch_bounds__(256) k_node_factor(
     cf[(size_t)a * cs_a + bc] = acc;
   }
 }
+__global__ void __launch_bounds__(256) k_node_factor(const k_node_factor_args a_) {
+  k_node_factor_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void __launch_bounds__(256) k_node_factor_g(const k_node_factor_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_node_factor_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_node_factor_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_node_factor_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_node_factor_args* a, const int* st, const int* gy, int mm) {
+    k_node_factor_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_node_factor now, or records it while a recorder is open on this thread
+static void k_node_factor_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_node_factor_args& a) {
+  if (recording())
+    record_group(k_node_factor_grp, group_key((const void*)k_node_factor_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_node_factor<<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // level update (factorization): coarser columns of right-child rows += V~ A
@@ -1032,15 +1380,49 @@ __global__ void __launch_bounds__(256) k_node_factor(
 // tile (k x 64 columns) is broadcast from LDS, and every coarser column is read and
 // written once, coalesced along rows.
 // ---------------------------------------------------------------------------------
+// arguments of k_update_panel (one struct, so that grouped launches can stage one per member)
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_update_panel(
-    const Task* __restrict__ tasks, int tbase, int ntask, int l, const int* __restrict__ rank,
-    const int* __restrict__ coff, const int* __restrict__ kmax, const int* __restrict__ rcols,
-    const int* __restrict__ rcount, int K, T* __restrict__ P, int unused_ld,
-    const double* __restrict__ coef, int cs_node, int cs_a) {
+struct k_update_panel_args {
+  const Task* tasks;
+  int tbase;
+  int ntask;
+  int l;
+  const int* rank;
+  const int* coff;
+  const int* kmax;
+  const int* rcols;
+  const int* rcount;
+  int K;
+  T* P;
+  int unused_ld;
+  const double* coef;
+  int cs_node;
+  int cs_a;
+};
+template <typename T>
+__device__ __forceinline__ void k_update_panel_body(const k_update_panel_args<T>& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const Task* __restrict__ tasks = a_.tasks;
+  int tbase = a_.tbase;
+  int ntask = a_.ntask;
+  int l = a_.l;
+  const int* __restrict__ rank = a_.rank;
+  const int* __restrict__ coff = a_.coff;
+  const int* __restrict__ kmax = a_.kmax;
+  const int* __restrict__ rcols = a_.rcols;
+  const int* __restrict__ rcount = a_.rcount;
+  int K = a_.K;
+  T* __restrict__ P = a_.P;
+  int unused_ld = a_.unused_ld;
+  const double* __restrict__ coef = a_.coef;
+  int cs_node = a_.cs_node;
+  int cs_a = a_.cs_a;
+  (void)by_;
+  (void)gy_;
+
   const int Ktot = K;
   (void)unused_ld;
-  const int t = blockIdx.x;
+  const int t = bx_;
   if (t >= ntask) return;
   const Task tk = tasks[tbase + t];
   if (tk.side == 0) return;
@@ -1092,12 +1474,58 @@ __global__ void __launch_bounds__(NTHREADS) k_update_panel(
     }
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_update_panel(const k_update_panel_args<T> a_) {
+  k_update_panel_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+template <typename T>
+__global__ void __launch_bounds__(NTHREADS) k_update_panel_g(const k_update_panel_args<T>* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_update_panel_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+template <typename T>
+static void k_update_panel_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_update_panel_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_update_panel_args<T>* a, const int* st, const int* gy, int mm) {
+    k_update_panel_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_update_panel now, or records it while a recorder is open on this thread
+template <typename T>
+static void k_update_panel_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_update_panel_args<T>& a) {
+  if (recording())
+    record_group(k_update_panel_grp<T>, group_key((const void*)k_update_panel_grp<T>, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_update_panel<T><<<g, b, lds, s>>>(a);
+}
 
 // ---------------------------------------------------------------------------------
 // log-det: sum of leaf and node parts in a fixed order
 // ---------------------------------------------------------------------------------
-__global__ void k_logdet_sum(const double* __restrict__ leaf_ld, int nleaf,
-                             const double* __restrict__ node_ld, int nint, double* __restrict__ out) {
+// arguments of k_logdet_sum (one struct, so that grouped launches can stage one per member)
+struct k_logdet_sum_args {
+  const double* leaf_ld;
+  int nleaf;
+  const double* node_ld;
+  int nint;
+  double* out;
+};
+__device__ __forceinline__ void k_logdet_sum_body(const k_logdet_sum_args& a_, const int bx_, const int by_,
+                                             const int gy_) {
+  const double* __restrict__ leaf_ld = a_.leaf_ld;
+  int nleaf = a_.nleaf;
+  const double* __restrict__ node_ld = a_.node_ld;
+  int nint = a_.nint;
+  double* __restrict__ out = a_.out;
+  (void)by_;
+  (void)gy_;
+
   __shared__ double red[NTHREADS / 64];
   double s = 0.0;
   for (int i = threadIdx.x; i < nleaf; i += NTHREADS) s += leaf_ld[i];
@@ -1110,6 +1538,32 @@ __global__ void k_logdet_sum(const double* __restrict__ leaf_ld, int nleaf,
     for (int w = 0; w < NTHREADS / 64; ++w) t += red[w];
     *out = t;
   }
+}
+__global__ void  k_logdet_sum(const k_logdet_sum_args a_) {
+  k_logdet_sum_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
+}
+// grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
+__global__ void  k_logdet_sum_g(const k_logdet_sum_args* __restrict__ a_,
+                                   const int* __restrict__ st_, const int* __restrict__ gyv_,
+                                   int m_) {
+  const int j = group_member(st_, m_, blockIdx.x);
+  if ((int)blockIdx.y >= gyv_[j]) return;
+  k_logdet_sum_body(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+}
+static void k_logdet_sum_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
+  grouped_launch<k_logdet_sum_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_logdet_sum_args* a, const int* st, const int* gy, int mm) {
+    k_logdet_sum_g<<<g, b, lds, s>>>(a, st, gy, mm);
+  });
+}
+// launches k_logdet_sum now, or records it while a recorder is open on this thread
+static void k_logdet_sum_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                             const k_logdet_sum_args& a) {
+  if (recording())
+    record_group(k_logdet_sum_grp, group_key((const void*)k_logdet_sum_grp, b, lds), g, b, lds, &a,
+                 sizeof(a));
+  else
+    k_logdet_sum<<<g, b, lds, s>>>(a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1124,9 +1578,10 @@ static void factor_leaves(FactorData& F, T* leafL, T* leafLinv, const double* al
   const HostPlan& P = H.pk->P;
   const DevPlan& D = H.pk->D;
   timer_before(KID_LEAF, s, -1, P, nullptr, 0);  // the leaf bytes do not depend on the ranks
-  k_leaf<T><<<P.nleaf, NTHREADS, 0, s>>>(
-      D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha, alpha_dev, F.beta, beta_dev,
-      diag, P.B, leafL, leafLinv, F.leaf_ld, F.status);
+  k_leaf_launch<T>(dim3(P.nleaf), dim3(NTHREADS), 0, s,
+                   k_leaf_args<T>{D.leaf_lo, P.nleaf, H.x, P.kind, P.ell, P.nugget, F.alpha,
+                                  alpha_dev, F.beta, beta_dev, diag, P.B, leafL, leafLinv,
+                                  F.leaf_ld, F.status});
   timer_after(KID_LEAF, s);
 }
 
@@ -1145,18 +1600,23 @@ static void factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s)
   if (P.L > 0) {
     timer_before(KID_WHITEN, s, -1, P, H.kmax, 0);
     if (F.fp32)
-      k_whiten<double, float><<<P.nleaf, NTHREADS, 0, s>>>(
-          D.leaf_lo, P.nleaf, F.leafLf, F.leafLinvf, Bc, F.alpha, alpha_dev, H.panel, panel,
-          P.Ktot, D.coff, H.kmax, P.L);
+      k_whiten_launch<double, float>(
+          dim3(P.nleaf), dim3(NTHREADS), 0, s,
+          k_whiten_args<double, float>{D.leaf_lo, P.nleaf, F.leafLf, F.leafLinvf, Bc, F.alpha,
+                                       alpha_dev, H.panel, panel, P.Ktot, D.coff, H.kmax, P.L});
     else
-      k_whiten<double, double><<<P.nleaf, NTHREADS, 0, s>>>(
-          D.leaf_lo, P.nleaf, F.leafL, F.leafLinv, Bc, F.alpha, alpha_dev, H.panel, panel,
-          P.Ktot, D.coff, H.kmax, P.L);
+      k_whiten_launch<double, double>(
+          dim3(P.nleaf), dim3(NTHREADS), 0, s,
+          k_whiten_args<double, double>{D.leaf_lo, P.nleaf, F.leafL, F.leafLinv, Bc, F.alpha,
+                                        alpha_dev, H.panel, panel, P.Ktot, D.coff, H.kmax, P.L});
     timer_after(KID_WHITEN, s);
   }
   // raised once to the largest size any plan can ask for (thread-safe one-time init)
   static const bool lds_set = [] {
     (void)hipFuncSetAttribute((const void*)k_node_factor,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(sizeof(double) * 5 * PMAX * PMAX));
+    (void)hipFuncSetAttribute((const void*)k_node_factor_g,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(sizeof(double) * 5 * PMAX * PMAX));
     return true;
@@ -1169,10 +1629,18 @@ static void factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s)
     timer_before(KID_REDUCE, s, l, P, H.kmax, nt);
     const dim3 grid_r(nt, (Wcap + 63) / 64);
     const int na_cap = std::max(1, std::min(4, (P.kcap[l] + 15) / 16));
-    auto rp = na_cap == 1 ? k_reduce_panel<double, 1> : na_cap == 2 ? k_reduce_panel<double, 2>
-            : na_cap == 3 ? k_reduce_panel<double, 3> : k_reduce_panel<double, 4>;
-    rp<<<grid_r, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols, H.rcount, P.Ktot,
-                                   panel, F.zpart, zs_a, zs_task);
+#define FG_REDUCE_PANEL(NA_)                                                                 \
+  k_reduce_panel_launch<double, NA_>(                                                        \
+      grid_r, dim3(NTHREADS), 0, s,                                                          \
+      k_reduce_panel_args<double, NA_>{D.ltasks, tb, nt, l, D.coff, H.kmax, H.rcols, H.rcount, \
+                                       P.Ktot, panel, F.zpart, zs_a, zs_task})
+    switch (na_cap) {
+      case 1: FG_REDUCE_PANEL(1); break;
+      case 2: FG_REDUCE_PANEL(2); break;
+      case 3: FG_REDUCE_PANEL(3); break;
+      default: FG_REDUCE_PANEL(4); break;
+    }
+#undef FG_REDUCE_PANEL
     timer_after(KID_REDUCE, s);
     const int cs_node = P.kcap[l] * Wcap, cs_a = Wcap;
     if (P.max_tps[l] > 1)
@@ -1180,15 +1648,15 @@ static void factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s)
                   zs_task, P.max_tps[l], s);
     const int kc = std::max(P.kcap[l], 1) + (std::max(P.kcap[l], 1) & 1);  // even pitch
     const size_t lds_node = sizeof(double) * 5 * (size_t)kc * kc;
-    k_node_factor<<<1 << l, kc > 8 ? 256 : 64, lds_node, s>>>(
+    k_node_factor_launch(dim3(1 << l), dim3(kc > 8 ? 256 : 64), (uint32_t)lds_node, s, k_node_factor_args{
         l, H.rank, H.kmax, H.rcount, D.node_task_off, tb, F.zpart, zs_a, zs_task, F.zfin,
         P.kcap[l] * Wcap, F.nodemat, D.nodemat_off, F.node_ld, F.coef, cs_node, cs_a, F.status,
-        kc);
+        kc});
     if (l > 0) {
       timer_before(KID_UPDATE, s, l, P, H.kmax, nt);
-      k_update_panel<double><<<nt, NTHREADS, 0, s>>>(D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
+      k_update_panel_launch<double>(dim3(nt), dim3(NTHREADS), 0, s, k_update_panel_args<double>{D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
                                                 H.rcols, H.rcount, P.Ktot, panel, H.ld, F.coef,
-                                                cs_node, cs_a);
+                                                cs_node, cs_a});
       timer_after(KID_UPDATE, s);
     }
   }
@@ -1248,7 +1716,8 @@ void launch_logdet_parts(const FactorData& F, double* out, hipStream_t s) {
 
 void launch_logdet_sum(FactorData& F, hipStream_t s) {
   const HostPlan& P = F.H->pk->P;
-  k_logdet_sum<<<1, NTHREADS, 0, s>>>(F.leaf_ld, P.nleaf, F.node_ld, P.nint, F.logdet);
+  k_logdet_sum_launch(dim3(1), dim3(NTHREADS), 0, s,
+                      k_logdet_sum_args{F.leaf_ld, P.nleaf, F.node_ld, P.nint, F.logdet});
 }
 
 }  // namespace fg

@@ -6,6 +6,7 @@
 // kept in the ascending order of dimension h (perm_h[j] = observation index of sorted
 // position j); the factors themselves are kept in observation order.  |g| is floored
 // at 1e-150 (sign kept, zero taken as positive) so that 1/D stays finite.
+#include "fg_group.h"
 #include "fg_internal.h"
 #include "fg_rng.h"
 #include "fg_tensor.h"
@@ -127,36 +128,36 @@ static inline unsigned nblk(int n) { return (unsigned)((n + 255) / 256); }
 void launch_tp_prepare(int n, int d, int h, const int* perm, const double* F, const double* y,
                        const TpState* st, const double* beta_p, double* D, double* Dinv,
                        double* yt, hipStream_t s) {
-  if (n > 0) k_tp_prepare<<<nblk(n), 256, 0, s>>>(n, d, h, perm, F, y, st, beta_p, D, Dinv, yt);
+  if (n > 0) FG_RUN(s, k_tp_prepare<<<nblk(n), 256, 0, q_>>>(n, d, h, perm, F, y, st, beta_p, D, Dinv, yt));
 }
 void launch_tp_partial(int n, int C, int c, const double* y, const double* G, const TpState* st,
                        double* r, hipStream_t s) {
-  if (n > 0) k_tp_partial<<<nblk(n), 256, 0, s>>>(n, C, c, y, G, st, r);
+  if (n > 0) FG_RUN(s, k_tp_partial<<<nblk(n), 256, 0, q_>>>(n, C, c, y, G, st, r));
 }
 void launch_tp_fit(int n, int C, const double* G, const TpState* st, double* fit, hipStream_t s) {
-  if (n > 0) k_tp_fit<<<nblk(n), 256, 0, s>>>(n, C, G, st, fit);
+  if (n > 0) FG_RUN(s, k_tp_fit<<<nblk(n), 256, 0, q_>>>(n, C, G, st, fit));
 }
 void launch_scale_sqrt(int n, const double* D, double* v, hipStream_t s) {
-  if (n > 0) k_scale_sqrt<<<nblk(n), 256, 0, s>>>(n, D, v);
+  if (n > 0) FG_RUN(s, k_scale_sqrt<<<nblk(n), 256, 0, q_>>>(n, D, v));
 }
 void launch_hetero_finish(int n, const double* R, const double* Zs, const double* D, double* f,
                           const int* perm, double* Fh, hipStream_t s) {
-  if (n > 0) k_hetero_finish<<<nblk(n), 256, 0, s>>>(n, R, Zs, D, f, perm, Fh);
+  if (n > 0) FG_RUN(s, k_hetero_finish<<<nblk(n), 256, 0, q_>>>(n, R, Zs, D, f, perm, Fh));
 }
 void launch_tp_product(int n, int d, const double* F, double* G, hipStream_t s) {
-  if (n > 0) k_tp_product<<<nblk(n), 256, 0, s>>>(n, d, F, G);
+  if (n > 0) FG_RUN(s, k_tp_product<<<nblk(n), 256, 0, q_>>>(n, d, F, G));
 }
 void launch_tp_beta_step(TpState* st, int c, double s_beta, uint64_t seed, uint64_t iter,
                          uint64_t strm, hipStream_t s) {
-  k_tp_beta_step<<<1, 1, 0, s>>>(st, c, s_beta, seed, iter, strm);
+  FG_RUN(s, k_tp_beta_step<<<1, 1, 0, q_>>>(st, c, s_beta, seed, iter, strm));
 }
 void launch_tp_tau_step(TpState* st, int n, double a1, double b1, uint64_t seed, uint64_t iter,
                         uint64_t strm, hipStream_t s) {
-  k_tp_tau_step<<<1, 1, 0, s>>>(st, n, a1, b1, seed, iter, strm);
+  FG_RUN(s, k_tp_tau_step<<<1, 1, 0, q_>>>(st, n, a1, b1, seed, iter, strm));
 }
 void launch_tp_mh_step(TpState* st, int h, int kprop, int ongrid, uint64_t seed, uint64_t iter,
                        uint64_t strm, const int* pst_a, const int* pst_b, hipStream_t s) {
-  k_tp_mh_step<<<1, 1, 0, s>>>(st, h, kprop, ongrid, seed, iter, strm, pst_a, pst_b);
+  FG_RUN(s, k_tp_mh_step<<<1, 1, 0, q_>>>(st, h, kprop, ongrid, seed, iter, strm, pst_a, pst_b));
 }
 
 }  // namespace fg

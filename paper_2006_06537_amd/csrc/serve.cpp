@@ -305,7 +305,10 @@ static void serve_loop(fg_server s) {
           again = fg::chain_end_sweep(sl.chain, sl.s);
         }
         if (again) {  // PCG budget too small: run it again
-          fg::chain_begin_sweep(sl.chain, sl.s, true);
+          if (fg::chain_begin_sweep(sl.chain, sl.s, true) != hipSuccess) {
+            set_fatal(s, "serving: a sweep could not be enqueued");
+            break;
+          }
           (void)hipEventRecord(sl.done, sl.s);
           ++busy;
           continue;
@@ -317,9 +320,9 @@ static void serve_loop(fg_server s) {
         retire(s, sl);
         continue;
       }
-      fg::chain_begin_sweep(sl.chain, sl.s, false);
-      if (hipEventRecord(sl.done, sl.s) != hipSuccess) {
-        set_fatal(s, "event record failed");
+      if (fg::chain_begin_sweep(sl.chain, sl.s, false) != hipSuccess ||
+          hipEventRecord(sl.done, sl.s) != hipSuccess) {
+        set_fatal(s, "serving: a sweep could not be enqueued");
         break;
       }
       ++busy;
