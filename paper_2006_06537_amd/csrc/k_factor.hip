@@ -1104,7 +1104,11 @@ __device__ bool lds_sym_eig256(double* A, double* E, double* T, int m, int lda) 
 __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
   const int lane = threadIdx.x & 63;
   // in a work-group of several waves every wave takes the same decisions from the same
-  // reads, and wave 0 alone writes
+  // reads, and wave 0 alone writes.  Every read of G that feeds a decision is separated
+  // from wave 0's next write by a barrier: a wave that falls behind (waves of one
+  // work-group drift apart when other kernels share the compute unit) must not see a
+  // half-swapped diagonal, or it would choose another pivot or rank than wave 0 and the
+  // barriers of the two would no longer pair up.
   const bool w0 = threadIdx.x < 64;
   const double d0 = lane < m ? G[lane + lane * lda] : 0.0;
   if (__ballot(d0 != d0) != 0) return -1;
@@ -1125,7 +1129,9 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
         iv = i2;
       }
     }
-    // every lane holds the same (v, iv): the butterfly's comparisons are symmetric
+    // every lane holds the same (v, iv): the butterfly's comparisons are symmetric.  All
+    // waves have read the diagonal before wave 0 swaps rows and columns.
+    __syncthreads();
     if (__builtin_amdgcn_readfirstlane((int)!(v > dfloor))) {
       r = j;
       break;
@@ -1150,7 +1156,8 @@ __device__ int wave_pchol(double* G, int m, int lda, double* S, int* perm) {
       }
       __syncthreads();
     }
-    const double ljj = sqrt(G[j + j * lda]);
+    // (only wave 0 uses the pivot's root; the other waves do not read G here)
+    const double ljj = w0 ? sqrt(G[j + j * lda]) : 1.0;
     double lij = 0.0;
     if (w0 && lane > j && lane < m) {
       lij = G[lane + j * lda] / ljj;

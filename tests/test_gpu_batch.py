@@ -108,3 +108,34 @@ def test_grouped_batch_of_equal_chains_matches_oracle():
             assert abs(s[key] - r[key]) <= 1e-9 * abs(r[key]), key
         f = s["f"].cpu().numpy()
         assert np.linalg.norm(f - o.f) <= 1e-9 * np.linalg.norm(o.f)
+
+
+def test_eager_batch_of_served_jobs_equals_alone():
+    """48 jobs of the serving workload (n from 1e3 to 2e5) stepped 60 sweeps as one eager
+    batch on four streams, where the kernels of different chains run side by side on the
+    device and the waves of one work-group drift apart, against each chain stepped alone:
+    every chain must end in the same state bit for bit, with no failed factorization.  The
+    list includes jobs whose node factors pivot often (the pivoted Cholesky of a node's
+    Gram block must give one decision to every wave of its work-group)."""
+    from workloads import served_jobs
+    jobs = served_jobs(512, seed=5)
+    pick = list(range(40)) + [44, 76, 128, 170, 233, 273, 357, 439]
+    dev = torch.device("cuda:0")
+
+    def chain(j):
+        job = jobs[j]
+        return fg().Chain(torch.tensor(job["x"], device=dev), torch.tensor(job["y"], device=dev),
+                          job["ell0"], job["tau0"], leaf=128, tol=1e-10, seed=job["seed"],
+                          stream_id=j)
+
+    batch = [chain(j) for j in pick]
+    fg().step_batch(batch, 60, nstreams=4, mode=fg().BATCH_EAGER)
+    torch.cuda.synchronize()
+    got = [snap(c) for c in batch]
+    del batch
+    for j, b in zip(pick, got):
+        assert b["status"] == 0, (j, b["status"])
+        a = chain(j)
+        a.step(60)
+        same(snap(a), b)
+        del a
