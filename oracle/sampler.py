@@ -37,7 +37,11 @@ GRID_CENTER = 50
 
 
 def ell_grid(ell0, size=GRID_SIZE, center=GRID_CENTER):
-    return ell0 * 10.0 ** ((np.arange(size) - center) / 50.0)
+    """The length-scale grid ell0 10^((g - center) / 50), g = 0 .. size - 1 (Section 4.1's
+    discrete grid).  Each point is evaluated by the C library's pow, one point at a time,
+    as the HIP library evaluates it: numpy's vectorised power can round a point
+    differently by one unit, and both sides must run at the same length-scales."""
+    return np.array([ell0 * math.pow(10.0, (g - center) / 50.0) for g in range(size)])
 
 
 def draw_f(H: hodlr.HODLR, W1: hodlr.Factor, WM: hodlr.Factor, sigf2, tau, y, a, b):

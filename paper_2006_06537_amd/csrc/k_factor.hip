@@ -29,98 +29,37 @@ __device__ __forceinline__ double wsum(double v) {
 //
 // One work-group of 256 threads per leaf (m <= 128 rows).  The leaf matrix lives in
 // registers in a 16 x 16 thread grid: thread (tr, tc) holds the 8 x 8 elements
-// (16 i + tr, 16 j + tc), so diagonal block kb of a 16 x 16 blocking is element
-// [kb][kb] of every thread.  Blocked right-looking Cholesky: wave 0 factors the 16 x 16
-// diagonal block (and inverts it) with cross-lane shuffles, the block column below is
-// multiplied by that inverse, and the trailing matrix takes a rank-16 update.  Three
-// barriers per block step.  Output: L (lower triangle), the inverses of its 16 x 16
-// diagonal blocks, and the log-det.
+// (16 i + tr, 16 j + tc) of the block lower triangle.  Right-looking Cholesky one column
+// at a time, with every thread of the work-group in every column step: the 16 threads
+// that hold column j (one quarter of one wave) take its pivot from the lane that holds
+// it, scale the column and publish it in LDS; after one barrier every thread subtracts
+// L[r][j] L[c][j] from its entries right of and below it.  A step is a short chain of
+// register operations, one LDS write and read and one barrier, so no wave waits on a
+// serial factorization of a diagonal block.  After each 16 columns the finished block
+// column is written out and the register tile shifts by one block, so that the current
+// block column is always register column 0 and every register index is fixed at
+// compile time.  The inverses of the 16 x 16 diagonal blocks of L (used by the
+// whitening and the solves) are then formed by forward substitution, one column of one
+// block per thread.  Output: L (lower triangle), those inverses and the log-det.
 // ---------------------------------------------------------------------------------
 constexpr int LG = 16;        // thread grid side
 constexpr int LE = BMAX / LG; // 16-row blocks per leaf (8)
-constexpr int LPD = 18;       // LDS pitch of 16-wide rows: even, so that entries (t, t + 1)
-                              // of a row are one aligned pair, and 16 rows fall in distinct banks
+constexpr int LPD = 17;       // LDS pitch of a stored 16 x 16 diagonal block
 
-// entries t, t + 1 (t even) of an LDS row, in one read
-template <typename T> struct PairOf;
-template <> struct PairOf<double> { typedef double2 type; };
-template <> struct PairOf<float> { typedef float2 type; };
-template <typename T>
-__device__ __forceinline__ typename PairOf<T>::type lds_pair(const T* p) {
-  return *reinterpret_cast<const typename PairOf<T>::type*>(p);
+// a value of lane l, as a wave-uniform value (l a compile-time index after unrolling)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// LDS ordering between the lanes of one wave (no work-group barrier: only the factoring
-// wave runs diag_factor16)
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// One wave: Cholesky and inverse of the 16 x 16 block Dk (LDS, pitch LPD), worked in LDS
-// so that the caller's registers (the leaf's blocks) stay free of it: lane l owns the
-// elements (l & 15, (l >> 4) + 4 q), q = 0..3, of the block.  Writes L into Lk and L^-1
-// into Lik (pitch LPD, zero upper triangles); returns the sum of the log pivots (every
-// lane) and flags a non-positive pivot (which then counts as 1).
-template <typename T>
-__device__ double diag_factor16(const T* Dk, T* Lk, T* Lik, bool& bad) {
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, c0 = lane >> 4;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = c0 + 4 * q;
-    Lk[r * LPD + c] = (c <= r) ? Dk[r * LPD + c] : T(0);
-    Lik[r * LPD + c] = (c == r) ? T(1) : T(0);
-  }
-  wave_lds_sync();
-  // right-looking Cholesky: column j scaled by 1/sqrt(pivot), then the trailing lower
-  // triangle takes the rank-one update with column j
-  for (int j = 0; j < 16; ++j) {
-    const T piv = Lk[j * LPD + j];
-    const bool ok = piv > T(0);
-    bad |= !ok;
-    const T sq = ok ? sqrt(piv) : T(1);
-    const T invj = T(1) / sq;
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 4 * q;
-      if (c == j && r > j) Lk[r * LPD + j] *= invj;
-      if (c == j && r == j) Lk[j * LPD + j] = sq;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 4 * q;
-      if (c > j && c <= r) Lk[r * LPD + c] -= Lk[r * LPD + j] * Lk[c * LPD + j];
-    }
-    wave_lds_sync();
-  }
-  // L^-1 by rows: row k is finished (scaled by 1/L[k][k]) at step k, then the rows below
-  // take its multiple
-  for (int k = 0; k < 16; ++k) {
-    const T dinv = T(1) / Lk[k * LPD + k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 4 * q;
-      if (r == k && c <= k) Lik[k * LPD + c] *= dinv;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 4 * q;
-      if (r > k && c <= k) Lik[r * LPD + c] -= Lk[r * LPD + k] * Lik[k * LPD + c];
-    }
-    wave_lds_sync();
-  }
-  // log pivots: lane r takes 2 log L[r][r], summed over the 16 rows
-  const T dr = Lk[r * LPD + r];
-  double ls = (dr > T(0)) ? 2.0 * log((double)dr) : 0.0;
-  for (int o = 8; o > 0; o >>= 1) ls += __shfl_xor(ls, o, 16);
-  return ls;
-}
-
+#ifndef LEAF_OCC
+#define LEAF_OCC 4  // work-groups per CU the leaf kernel's registers are sized for
+#endif
 #define LT(i, j) ((i) * ((i) + 1) / 2 + (j))
 // arguments of k_leaf (one struct, so that grouped launches can stage one per member)
 template <typename T>
@@ -171,21 +110,21 @@ __device__ __forceinline__ void k_leaf_body(const k_leaf_args<T>& a_, const int 
   const double alpha = alpha_p ? *alpha_p : alpha_v;
   const double beta = beta_p ? *beta_p : beta_v;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  // LDS: Likk (the current diagonal block's inverse) | Lk | Dk | Lp 128 rows | Pp 128 rows
-  // (42 KB in FP64: three work-groups per CU)
+  const int wave = threadIdx.x >> 6;
+  // LDS: the inputs, column j of L (two buffers: column j + 1 is written while slower
+  // waves may still read column j), the pivots and their reciprocals, and the diagonal
+  // blocks of L for their inverses (19 KB in FP64)
   __shared__ double xs[BMAX];
-  __shared__ __align__(16) T Likk[16 * LPD];
-  __shared__ __align__(16) T Lk[16 * LPD];
-  __shared__ __align__(16) T Dk[16 * LPD];
-  __shared__ __align__(16) T Lp[BMAX * LPD];
-  __shared__ __align__(16) T Pp[BMAX * LPD];
-  T* Lig = leafLinv + (size_t)b * Bc * Bc;
+  __shared__ T colb[2][BMAX];
+  __shared__ T piv_s[BMAX], pinv_s[BMAX];
+  __shared__ T Ld[LE][16 * LPD];
   __shared__ int bad;
-  __shared__ double ldsum;
-  if (threadIdx.x == 0) { bad = 0; ldsum = 0.0; }
+  if (threadIdx.x == 0) bad = 0;
   for (int r = threadIdx.x; r < m; r += NTHREADS) xs[r] = x[lo + r];
+  colb[threadIdx.x >> 7][threadIdx.x & 127] = T(0);
   __syncthreads();
-  // block-lower part only: element (16 i + tr, 16 jj + tc), jj <= i, at a[LT(i, jj)]
+  // block-lower part only: element (16 i + tr, 16 jj + tc), jj <= i, at a[LT(i, jj)]; after
+  // kb block columns are done, a[LT(i, jj)] holds block (kb + i, kb + jj)
   T a[LE * (LE + 1) / 2];
 #pragma unroll
   for (int i = 0; i < LE; ++i) {
@@ -201,110 +140,119 @@ __device__ __forceinline__ void k_leaf_body(const k_leaf_args<T>& a_, const int 
       a[LT(i, jj)] = (T)v;  // entries are formed in FP64 and stored in T
     }
   }
-  // blocked Cholesky
   bool mybad = false;
-  for (int kb = 0; kb < nb; ++kb) {
-#pragma unroll
-    for (int i = 0; i < LE; ++i) {
-#pragma unroll
-      for (int jj = 0; jj <= i; ++jj) {
-        if (jj == kb) {
-          if (i == kb) Dk[tr * LPD + tc] = a[LT(i, jj)];
-          if (i > kb && i < nb) Pp[(LG * i + tr) * LPD + tc] = a[LT(i, jj)];
-        }
-      }
-    }
-    __syncthreads();
-    if ((threadIdx.x >> 6) == (kb & 3)) {  // the factoring wave rotates over the SIMDs
-      bool wb = false;
-      const double ls = diag_factor16(Dk, Lk, Likk, wb);
-      if ((threadIdx.x & 63) == 0) ldsum += ls;
-      if (wb) bad = 1;
-    }
-    __syncthreads();
-    // the inverse of the diagonal block goes to the diagonal block of the leaf's L^-1 slot
-    {
-      const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
-      if (kb * 16 + r < m && c <= r)
-        Lig[(kb * 16 + r) + (size_t)(kb * 16 + c) * Bc] = Likk[r * LPD + c];
-    }
-    const T* Li = Likk;
-    T* L1 = Lp;
-#pragma unroll
-    for (int i = 0; i < LE; ++i) {
-      if (i == kb) a[LT(i, i)] = Lk[tr * LPD + tc];
-      if (i > kb && i < nb) {
-        // L[i][kb] = A[i][kb] L_kk^-T : row (16 i + tr) of the panel times column tc of Li'
-        T s = T(0);
-#pragma unroll
-        for (int t = 0; t < 16; t += 2) {
-          const auto pv = lds_pair(Pp + (LG * i + tr) * LPD + t);
-          const auto lv = lds_pair(Li + tc * LPD + t);
-          s += pv.x * lv.x;
-          s += pv.y * lv.y;
-        }
-#pragma unroll
-        for (int jj = 0; jj < i; ++jj)
-          if (jj == kb) a[LT(i, jj)] = s;
-        L1[(LG * i + tr) * LPD + tc] = s;
-      }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int t = 0; t < 16; t += 2) {  // columns t and t + 1 of the panel, one read each
-      T lc0[LE], lc1[LE];
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        lc0[i] = lc1[i] = T(0);
-        if (i > kb && i < nb) {
-          const auto pc = lds_pair(L1 + (LG * i + tc) * LPD + t);
-          lc0[i] = pc.x;
-          lc1[i] = pc.y;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < LE; ++i) {
-        if (i > kb && i < nb) {
-          const auto pr = lds_pair(L1 + (LG * i + tr) * LPD + t);
-#pragma unroll
-          for (int jj = 0; jj <= i; ++jj)
-            if (jj > kb) {
-              a[LT(i, jj)] -= pr.x * lc0[jj];
-              a[LT(i, jj)] -= pr.y * lc1[jj];
-            }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    leaf_ld[b] = ldsum;  // sum log(pivot) = 2 sum log diag(L)
-    if (bad) atomicOr(status, ST_NOTSPD);
-  }
-  (void)mybad;
-  // L to global (lower triangle, column-major, ld = Bc); the upper triangle and rows/cols
-  // beyond m are never written (no reader touches them)
   T* Lg = leafL + (size_t)b * Bc * Bc;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int nbr = nb - kb;  // block rows from the current one down
 #pragma unroll
-  for (int jj = 0; jj < LE; ++jj) {
-    const int c = LG * jj + tc;
+    for (int t = 0; t < 16; ++t) {
+      const int j = 16 * kb + t;
+      if (j < m) {  // (uniform: the last block may be partial)
+        T* col = colb[t & 1];
+        if (wave == (t >> 2)) {
+          // the pivot sits in thread (t, t), the column in threads (., t): one wave
+          const T piv = lane_value(a[LT(0, 0)], (17 * t) & 63);
+          const bool ok = piv > T(0);
+          mybad |= !ok;
+          const T sq = ok ? sqrt(piv) : T(1);
+          const T inv = T(1) / sq;
+          if (tc == t) {
 #pragma unroll
-    for (int i = jj; i < LE; ++i) {
-      const int r = LG * i + tr;
-      if (r < m && c <= r) Lg[r + (size_t)c * Bc] = a[LT(i, jj)];  // lower triangle only
+            for (int i = 0; i < LE; ++i) {
+              if (i < nbr) {
+                const int rho = LG * i + tr;  // row within the current block row and below
+                if (rho > t) {
+                  a[LT(i, 0)] *= inv;
+                  col[rho] = a[LT(i, 0)];
+                } else {
+                  col[rho] = T(0);  // rows up to the pivot take no update
+                  if (rho == t) {
+                    a[LT(0, 0)] = sq;
+                    piv_s[j] = sq;
+                    pinv_s[j] = inv;
+                  }
+                }
+              }
+            }
+          }
+        }
+        __syncthreads();
+        // trailing update: entries (rho, c) with t < c <= rho take -L[rho][j] L[c][j].  The
+        // published column is zero at rows up to the pivot, so every entry of the tile can
+        // take the product with no test: the finished columns (c <= t) and rows (rho <= t)
+        // are multiplied by zero, and the upper triangles of the diagonal blocks, which
+        // nothing reads, take the mirror image of their lower triangles' updates.
+        T lr[LE], lc[LE];
+#pragma unroll
+        for (int i = 0; i < LE; ++i) {
+          lr[i] = (i < nbr) ? col[LG * i + tr] : T(0);
+          lc[i] = (i < nbr) ? col[LG * i + tc] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < LE; ++i) {
+          if (i < nbr) {
+#pragma unroll
+            for (int jj = 0; jj <= i; ++jj) a[LT(i, jj)] -= lr[i] * lc[jj];
+          }
+        }
+      }
+    }
+    // block column kb is final: L to global (lower triangle, column-major, ld = Bc), the
+    // diagonal block to LDS for its inverse; then the tile moves up one block
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int r = 16 * kb + LG * i + tr, c = 16 * kb + tc;
+      if (i < nbr && r < m && c <= r) Lg[r + (size_t)c * Bc] = a[LT(i, 0)];
+    }
+    Ld[kb][tr * LPD + tc] = (tc <= tr) ? a[LT(0, 0)] : T(0);
+#pragma unroll
+    for (int i = 0; i + 1 < LE; ++i) {
+#pragma unroll
+      for (int jj = 0; jj <= i; ++jj) a[LT(i, jj)] = a[LT(i + 1, jj + 1)];
     }
   }
-  // (the inverses of the 16 x 16 diagonal blocks were written at each block step; L^-1
-  // itself is never formed: its products are blocked substitutions, k_whiten and
-  // k_leaf_apply)
+  if (mybad) bad = 1;
+  __syncthreads();
+  // inverses of the diagonal blocks: thread (block bb, column c) solves L_bb x = e_c by
+  // forward substitution (row k: x_k = (e_c,k - sum_{jj<k} L[k][jj] x_jj) / L[k][k], the
+  // terms in increasing jj) and writes x into column c of the block's slot
+  if (threadIdx.x < 16 * LE) {
+    const int bb = threadIdx.x >> 4, c = threadIdx.x & 15;
+    if (bb < nb) {
+      const T* Lb = Ld[bb];
+      T* Lig = leafLinv + (size_t)b * Bc * Bc + (size_t)(16 * bb) * (Bc + 1);
+      T xv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        T acc = (k == c) ? T(1) : T(0);
+#pragma unroll
+        for (int jj = 0; jj < k; ++jj)
+          if (jj >= c) acc -= Lb[k * LPD + jj] * xv[jj];
+        const int kk = 16 * bb + k;
+        xv[k] = (k >= c && kk < m) ? acc * pinv_s[kk] : T(0);
+        if (k >= c && kk < m) Lig[k + (size_t)c * Bc] = xv[k];
+      }
+    }
+  }
+  // log-det: sum of 2 log L[j][j], wave 0 with two rows per lane, in a fixed order
+  if (wave == 0) {
+    const int l = threadIdx.x;
+    double ls = (l < m && piv_s[l] > T(0)) ? 2.0 * log((double)piv_s[l]) : 0.0;
+    if (l + 64 < m && piv_s[l + 64] > T(0)) ls += 2.0 * log((double)piv_s[l + 64]);
+    ls = wsum(ls);
+    if (l == 0) {
+      leaf_ld[b] = ls;  // sum log(pivot) = 2 sum log diag(L)
+      if (bad) atomicOr(status, ST_NOTSPD);
+    }
+  }
 }
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS, 3) k_leaf(const k_leaf_args<T> a_) {
+__global__ void __launch_bounds__(NTHREADS, LEAF_OCC) k_leaf(const k_leaf_args<T> a_) {
   k_leaf_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
 }
 // grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
 template <typename T>
-__global__ void __launch_bounds__(NTHREADS, 3) k_leaf_g(const k_leaf_args<T>* __restrict__ a_,
+__global__ void __launch_bounds__(NTHREADS, LEAF_OCC) k_leaf_g(const k_leaf_args<T>* __restrict__ a_,
                                    const int* __restrict__ st_, const int* __restrict__ gyv_,
                                    int m_) {
   const int j = group_member(st_, m_, blockIdx.x);

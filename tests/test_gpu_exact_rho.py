@@ -10,7 +10,7 @@ spread of the q_h / (2 sigma_f^2) terms."""
 import numpy as np
 import pytest
 
-from oracle import exact_rho, kernels
+from oracle import exact_rho, kernels, sampler
 from workloads import SMALL_1D, small_1d
 
 pytestmark = pytest.mark.gpu
@@ -32,7 +32,7 @@ def _pair(n, seed):
     g = fg().Chain(torch.tensor(x, device=dev), torch.tensor(y, device=dev), ell0=c["ell0"],
                    tau0=c["tau0"], sigf2_0=c["sigf2_0"], nugget=c["nugget"], leaf=c["leaf"],
                    tol=c["tol"], seed=seed, grid_size=G, grid_center=CENTER, exact_rho=True)
-    grid = c["ell0"] * 10.0 ** ((np.arange(G) - CENTER) / 50.0)
+    grid = sampler.ell_grid(c["ell0"], G, CENTER)  # the library's grid values
     o = exact_rho.ExactGridChain(x, y, kernels.SE, c["ell0"], c["nugget"], c["leaf"], c["tol"],
                                  c["tau0"], c["sigf2_0"], seed, grid=grid)
     return g, o

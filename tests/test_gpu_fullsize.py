@@ -76,9 +76,8 @@ def test_ranks_and_sampled_entries(big):
 
 def _oracle_parts(OF):
     """(leaf part, node part) of the oracle factor's log-determinant."""
-    leaf = sum(2.0 * float(np.sum(np.log(np.diag(Lb)))) for Lb in OF.leafL)
-    node = sum(float(np.sum(np.log((1.0 - nf.sig) * (1.0 + nf.sig)))) for nf in OF.nodes.values())
-    return leaf, node
+    from bands import logdet_parts
+    return logdet_parts(OF)
 
 
 def _check_parts(W, OF, what, node_bar=1e-9):
@@ -132,23 +131,13 @@ def test_logdet_k1(big):
         (s^2 are eigenvalues of products of Gram matrices summed over the m rows of the
         node): |d s_i^2| <= 2 s_i^2 sqrt(m) u, the usual rounding estimate of an m-term
         FP64 sum, so |d node part| <= sum_nodes sum_i 2 s_i^2 sqrt(m) u / (1 - s_i^2)."""
-    from bands import InvLeafFactor, perturbed_panels
+    from bands import node_part_bar
     fg, H, K1 = big["fg"], big["H"], big["K1"]
     W1 = fg.Factor(K1, 1.0, 0.0)
     O1 = oh.Factor(H, 1.0, 0.0)
-    node = _oracle_parts(O1)[1]
-    alts = [InvLeafFactor(H, 1.0, 0.0)] + [oh.Factor(perturbed_panels(H, seed=s_), 1.0, 0.0)
-                                           for s_ in (1, 2)]
-    band = max(abs(_oracle_parts(v)[1] - node) / abs(node) for v in alts)
-    u = 2.0 ** -53
-    gram = 0.0
-    for (l, j), nf in O1.nodes.items():
-        lo, mid, hi = H.tree.node(l, j)
-        s2 = nf.sig ** 2
-        gram += float(np.sum(2.0 * s2 / (1.0 - s2))) * np.sqrt(hi - lo) * u
-    gram /= abs(node)
+    bar, band, gram = node_part_bar(H, O1)
     print(f"node part of log|K~_1|: oracle band {band:.2e}, Gram-route bound {gram:.2e}")
-    _check_parts(W1, O1, "log|K~_1|", node_bar=max(1e-9, 4.0 * band, gram))
+    _check_parts(W1, O1, "log|K~_1|", node_bar=bar)
 
 
 def test_first_sweep_and_predictions_full_size(big):
