@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--slots", type=int, default=32, help="serve workload: jobs running at once")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturation")
     ap.add_argument("--chains", type=int, default=64, help="batch workload: number of chains")
+    ap.add_argument("--batch-mode", default="auto", choices=["auto", "grouped", "eager", "graphs"],
+                    help="batch workload: one stepping mode only (profiling), or the autotuner")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: M~ factored in FP32, its solves refined by PCG to 1e-10")
     ap.add_argument("--kernel", type=int, default=0,
@@ -185,6 +187,20 @@ def bench_batch(args):
 
     chains = make()
     print(f"bench: {args.chains} chains ready (n={n})", file=sys.stderr, flush=True)
+    pname = "mixed" if prec == fg.MIXED else "FP64"
+    dname = "f32+f64" if prec == fg.MIXED else "f64"
+    if args.batch_mode != "auto":  # one mode alone (for a profile of that mode)
+        mode, ns = {"grouped": (fg.BATCH_GROUPED, 1), "eager": (fg.BATCH_EAGER, 4),
+                    "graphs": (fg.BATCH_GRAPHS, 4)}[args.batch_mode]
+        fg.step_batch(chains, max(args.warmup, 1), nstreams=ns, mode=mode)
+        dt = timed(lambda: fg.step_batch(chains, args.steps, nstreams=ns, mode=mode))
+        bad = sum(1 for c in chains if c.state()["status"] != 0)
+        _line(f"chain Gibbs iters/s, {args.chains} chains x n={n} ({pname}, {args.batch_mode})",
+              args.chains * args.steps / dt, "chain Gibbs iters/s", args, dt, dname,
+              {"workload": f"batch: {args.chains} independent {pname} chains, n={n} each, "
+                           f"gibbs_step_batch in {args.batch_mode} mode only",
+               "chains": args.chains, "n": n}, failed_chains=bad)
+        return
     # the autotuner's trials (8 sweeps) first, untimed
     fg.step_batch(chains, 8, nstreams=4, mode=fg.BATCH_AUTO)
     choice = fg.batch_tuning(chains)
@@ -206,9 +222,8 @@ def bench_batch(args):
     dt_seq = timed(seq)
     print(f"bench: sequential {dt_seq:.3f} s", file=sys.stderr, flush=True)
     st = chains[0].state()
+    bad = sum(1 for c in chains if c.state()["status"] != 0)
     tot = args.chains * args.steps
-    pname = "mixed" if prec == fg.MIXED else "FP64"
-    dname = "f32+f64" if prec == fg.MIXED else "f64"
     _line(f"chain Gibbs iters/s, {args.chains} chains x n={n} ({pname})", tot / dt,
           "chain Gibbs iters/s", args, dt, dname,
           {"workload": f"batch: {args.chains} independent {pname} chains, n={n} each (5-sinusoid y, "
@@ -217,7 +232,7 @@ def bench_batch(args):
                        "2 or 4 streams, or captured graphs)",
            "chains": args.chains, "n": n},
           autotuned=choice[0], autotuned_streams=choice[1], modes_chain_iters_per_s=others,
-          sequential_value=tot / dt_seq, status0=st["status"],
+          sequential_value=tot / dt_seq, failed_chains=bad, status0=st["status"],
           precision_used0=st["precision_used"], pcg_iters0=st["pcg_iters"])
 
 
@@ -372,7 +387,7 @@ def bench_collapse(args):
     t_create = time.perf_counter() - t0
     ch.step(args.warmup)
     torch.cuda.synchronize()
-    timer = fg.KernelTimer(args.kernel)
+    timer = fg.KernelTimer(args.kernel or fg.KID_UPDATE)  # 0: the dominant kernel
     timer.start()
     t0 = time.perf_counter()
     ch.step(args.steps)
