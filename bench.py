@@ -537,7 +537,11 @@ def bench_serve(args):
                            stream_id=j, tau0=job["tau0"], **common)
         th = threading.Thread(target=feeder)
         th.start()
-        th.join()
+        while th.is_alive():  # progress while the arrivals are fed
+            th.join(30.0)
+            if th.is_alive():
+                print(f"bench: arrivals in progress, {srv.stats()['outstanding']} jobs "
+                      "outstanding", file=sys.stderr, flush=True)
         while True:  # progress while the last jobs run
             try:
                 srv.drain(30.0)

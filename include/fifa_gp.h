@@ -466,7 +466,8 @@ fg_status tp_chain_state(fg_tp_chain c, fg_tp_snapshot* host_out, double* F_out,
 
 /* Host-only count of the device bytes gibbs_chain_create(cfg) takes for these inputs
  * (x host, sorted): every grid point is planned on the host and the buffers are sized
- * for the largest, as the chain does.  No device call. */
+ * for the largest, as the chain does.  A mixed-precision chain's count includes the FP64
+ * factor of M~ it allocates if it falls back to FP64.  No device call. */
 fg_status fg_footprint_bytes(const fg_chain_cfg* cfg, const double* x_host, int64_t n,
                              uint64_t* bytes);
 

@@ -377,7 +377,7 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
       // this point) and back into v2, v3.
       fg::pcg_enqueue(H1, 0.0, &c->st->alphaM, 1.0, c->WM, v2, v0, 2, n, PCG_RTOL, 0,
                       c->pcg_nit, c->pcg, s, true);
-      fg::launch_pcg_record(c->pcg.sc, c->st, s);
+      fg::launch_pcg_record(c->pcg.sc, c->st, c->WM.status, s);
       enq_copy(c, v2, v0, 2 * sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     } else {
       fg::launch_apply_w(WM, 2, v2, 2, n, WM.work, s);
@@ -430,8 +430,9 @@ void enqueue_sweep(fg_chain c, const Proposal& pr, hipStream_t s, bool side) {
 // mixed-precision f-draw's PCG converged within its budget.  If it did, the budget of the
 // next sweep becomes the iterations it needed plus one.  If not, the state is restored
 // (enqueued on s) and the caller runs the same sweep again: with twice the budget, or,
-// once the budget is at its cap or a residual was not finite, with M~ factored in FP64
-// from then on (the FP32 leaf factor is then no preconditioner).  A sweep run again from
+// once the budget is at its cap, a residual was not finite or the FP32 leaf Cholesky met a
+// non-positive pivot, with M~ factored in FP64 from then on (the FP32 leaf factor is then
+// no preconditioner).  A sweep run again from
 // the same state gives what it would have given with the larger budget at once.
 bool sweep_retry(fg_chain c, hipStream_t s) {
   if (!c->mixed || c->fell_back || c->exact || c->collapsed) return false;
@@ -558,8 +559,10 @@ fg_status sweep_graph(fg_chain c, const Proposal& pr, hipStream_t q, hipGraphExe
 size_t chain_bytes_from(const fg::Caps& caps, size_t plan_bytes, int n, bool mixed) {
   size_t b = plan_bytes + 2 * fg::hodlr_bytes(caps) + 2 * fg::factor_bytes(caps, false) +
              fg::factor_bytes(caps, mixed);
-  b += sizeof(double) * ((size_t)9 * n + 2048) + 2 * sizeof(fg::DevState);
-  if (mixed) b += sizeof(double) * ((size_t)4 * fg::NRHS_PCG * n + 4096);
+  b += sizeof(double) * ((size_t)9 * n + 3072) + 2 * sizeof(fg::DevState);
+  // a mixed chain keeps room for the FP64 factor of M~ it falls back to, so that the
+  // fallback allocates from the chain's own memory (a served job's block) and cannot fail
+  if (mixed) b += sizeof(double) * ((size_t)4 * fg::NRHS_PCG * n + 4096) + fg::factor_bytes(caps, false);
   return b;
 }
 
@@ -724,9 +727,7 @@ size_t chain_alloc_count(const fg_chain_cfg& cfg) {
 size_t chain_device_bytes(fg_chain c) {
   size_t pb = 0;
   for (auto* p : c->packs) pb += plan_device_bytes(*p);
-  size_t b = chain_bytes_from(c->caps, pb, c->n, c->mixed);
-  if (c->fell_back) b += factor_bytes(c->caps, false);
-  return b;
+  return chain_bytes_from(c->caps, pb, c->n, c->mixed);  // (a fallback uses the room kept)
 }
 int64_t chain_iteration(fg_chain c) { return c->iter; }
 }  // namespace fg

@@ -83,8 +83,9 @@ struct DevState {
 // first keeps a copy of the state there, from which the sweep can be run again.
 void launch_sweep_begin(DevState* st, DevState* prev, hipStream_t s);
 struct PcgScalars;
-// copies a PCG solve's convergence record into the state
-void launch_pcg_record(const PcgScalars* sc, DevState* st, hipStream_t s);
+// copies a PCG solve's convergence record into the state (pcg_done = -1 when the status word
+// fstatus of the preconditioning factor, if given, reports a non-positive pivot)
+void launch_pcg_record(const PcgScalars* sc, DevState* st, const int* fstatus, hipStream_t s);
 void launch_set_draw_scalars(DevState* st, double tau, double sigf2, hipStream_t s);
 // the steps below take the iteration word from st->iter; the Metropolis step ends the
 // sweep and advances it

@@ -1090,17 +1090,21 @@ void launch_pcg_check(int nrhs, double rtol, int it, PcgScalars* sc, hipStream_t
 struct k_pcg_record_args {
   const PcgScalars* sc;
   DevState* st;
+  const int* fstatus;  // status word of the preconditioning factor, or null
 };
 __device__ __forceinline__ void k_pcg_record_body(const k_pcg_record_args& a_, const int bx_, const int by_,
                                              const int gy_) {
   const PcgScalars* sc = a_.sc;
   DevState* st = a_.st;
+  const int* fstatus = a_.fstatus;
   (void)by_;
   (void)gy_;
 
   st->pcg_relres = sc->relres;
   st->pcg_iters = sc->iters;
-  st->pcg_done = sc->done;
+  // a preconditioner whose Cholesky met a non-positive pivot is no factor of M~ at all:
+  // reported as a failed solve, so that the sweep is run again on an FP64 factor
+  st->pcg_done = (fstatus && (*fstatus & ST_NOTSPD)) ? -1 : sc->done;
 }
 __global__ void  k_pcg_record(const k_pcg_record_args a_) {
   k_pcg_record_body(a_, blockIdx.x, blockIdx.y, gridDim.y);
@@ -1128,8 +1132,8 @@ static void k_pcg_record_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
   else
     k_pcg_record<<<g, b, lds, s>>>(a);
 }
-void launch_pcg_record(const PcgScalars* sc, DevState* st, hipStream_t s) {
-  k_pcg_record_launch(dim3(1), dim3(1), 0, s, k_pcg_record_args{sc, st});
+void launch_pcg_record(const PcgScalars* sc, DevState* st, const int* fstatus, hipStream_t s) {
+  k_pcg_record_launch(dim3(1), dim3(1), 0, s, k_pcg_record_args{sc, st, fstatus});
 }
 void launch_pcg_copy(int n, int nrhs, const double* a, double* out, hipStream_t s) {
   if (n > 0) k_pcg_copy_launch(dim3(pblk(n)), dim3(256), 0, s, k_pcg_copy_args{n, nrhs, a, out});

@@ -62,7 +62,8 @@ def test_argument_errors_without_device(L):
 
 def test_footprint_estimate_host_only():
     """fg_footprint_bytes plans on the host only (no device call): positive, growing
-    with n, and smaller for the FP32 factor of M~."""
+    with n, and larger for a mixed-precision chain, which holds the PCG workspace and keeps
+    room for the FP64 factor of M~ it falls back to when the FP32 one fails."""
     import numpy as np
     import paper_2006_06537_amd as fg
     from workloads import sinusoid_1d
@@ -73,6 +74,6 @@ def test_footprint_estimate_host_only():
     assert 0 < sizes[0] < sizes[1] < sizes[2]
     assert sizes[2] / sizes[1] > 3.0  # at least linear in n
     x, _ = sinusoid_1d(8000, seed=2)
-    assert fg.footprint_bytes(x, 0.05, precision=fg.MIXED) < sizes[1]
+    assert fg.footprint_bytes(x, 0.05, precision=fg.MIXED) > sizes[1]
     with pytest.raises(fg.FgError):
         fg.footprint_bytes(x, 0.05, leaf=1)
