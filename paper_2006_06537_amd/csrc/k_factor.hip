@@ -1331,12 +1331,19 @@ static void k_node_factor_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
 
 // ---------------------------------------------------------------------------------
 // level update (factorization): coarser columns of right-child rows += V~ A
-// One thread per row: the row of V~ sits in registers (16 at a time), the coefficient
-// tile (k x 64 columns) is broadcast from LDS, and every coarser column is read and
-// written once, coalesced along rows.
+// On FP64 matrix cores with the output transposed: for one 16-row tile and 16 coarser
+// columns, Y^T (16 x 16) += A^T (16 x k) V^T (k x 16), in steps of v_mfma_f64_16x16x4f64
+// (4 ranks each).  In the row-tiled panel layout every operand a wave reads or writes is
+// one 512-byte run (4 ranks x 16 rows of V) or four 128-byte runs (one coarser column
+// each), so no entry is touched by more than one lane and the VALU only forms addresses.
+// A work-group stages A for up to 16 QB coarser columns in LDS in operand order, and a
+// wave updates all of them on a tile in one visit, reading that tile's V once.  Wider
+// levels take further work-groups along grid.y, and gy work-groups share one level task
+// so that the grid fills the chip.
 // ---------------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) double gdouble;
 // arguments of k_update_panel (one struct, so that grouped launches can stage one per member)
-template <typename T>
 struct k_update_panel_args {
   const Task* tasks;
   int tbase;
@@ -1348,116 +1355,205 @@ struct k_update_panel_args {
   const int* rcols;
   const int* rcount;
   int K;
-  T* P;
-  int unused_ld;
+  double* P;
   const double* coef;
   int cs_node;
   int cs_a;
+  int gy;  // work-groups per level task and column chunk
 };
-template <typename T>
-__device__ __forceinline__ void k_update_panel_body(const k_update_panel_args<T>& a_, const int bx_, const int by_,
-                                             const int gy_) {
-  const Task* __restrict__ tasks = a_.tasks;
-  int tbase = a_.tbase;
-  int ntask = a_.ntask;
-  int l = a_.l;
-  const int* __restrict__ rank = a_.rank;
-  const int* __restrict__ coff = a_.coff;
-  const int* __restrict__ kmax = a_.kmax;
-  const int* __restrict__ rcols = a_.rcols;
-  const int* __restrict__ rcount = a_.rcount;
-  int K = a_.K;
-  T* __restrict__ P = a_.P;
-  int unused_ld = a_.unused_ld;
-  const double* __restrict__ coef = a_.coef;
-  int cs_node = a_.cs_node;
-  int cs_a = a_.cs_a;
-  (void)by_;
-  (void)gy_;
-
-  const int Ktot = K;
-  (void)unused_ld;
-  const int t = bx_;
-  if (t >= ntask) return;
-  const Task tk = tasks[tbase + t];
-  if (tk.side == 0) return;
-  const int k = rank[tk.h];
-  const int kl = kmax[l], Wc = rcount[l] - kl;
-  if (k == 0 || Wc <= 0) return;
-  const int c0 = coff[l];
-  const int j = tk.h - ((1 << l) - 1);
-  const int* yc = rcols + (size_t)l * Ktot + kl;
-  const double* cf = coef + (size_t)j * cs_node;
-  __shared__ T As[64][64];
-  __shared__ int ycol[64];
-  for (int bt = 0; bt < Wc; bt += 64) {
-    const int bw = min(64, Wc - bt);
-    __syncthreads();
-    const int k16 = (k + 15) & ~15;  // rows read by the 16-wide register blocks
-    for (int idx = threadIdx.x; idx < k16 * 64; idx += NTHREADS) {
-      const int a = idx >> 6, b = idx & 63;
-      As[a][b] = (a < k && b < bw) ? (T)cf[(size_t)a * cs_a + bt + b] : T(0);
+// This wave's row tiles of one task for one staged chunk of bw <= 16 NQ coarser columns.
+// SM: MFMA steps held in registers (4 ranks each; the host picks SM >= ceil(kcap / 4));
+// ranks past 4 S read as zero.  Every load of a tile is issued before any of its stores:
+// the memory counter that a wave waits on is in order over loads and stores, so a load
+// issued behind a store would also wait for that store.
+template <int SM, int QB, int NQ>
+__device__ __forceinline__ void update_tiles(const double* __restrict__ Acf,
+                                             const int* __restrict__ ycol, double* __restrict__ P,
+                                             int K, int c0, int k, int S, int bw, int r0, int r1,
+                                             int tfirst, int tend, int tstep) {
+  const int lane = threadIdx.x & 63, kg = lane >> 4, jr = lane & 15;
+  // ycol holds, at [16 q + 4 kg + v], the column of accumulator register v of block q for
+  // lane group kg; it is read per tile, four at a time, rather than held in registers
+  const uint4* yq = reinterpret_cast<const uint4*>(ycol);
+#pragma unroll 1
+  for (int tt = tfirst; tt < tend; tt += tstep) {
+    const int row = tt * 16 + jr;
+    const bool ok = row >= r0 && row < r1;
+    // whole row tiles lie inside the panel (its leading dimension is a multiple of 64), so
+    // every load is in bounds; entries that are not ours are read and discarded.  The tile
+    // base is wave-uniform and in the global address space (a pointer read from a grouped
+    // launch's member array would otherwise be accessed as flat).
+    gchar* tp = (gchar*)(P + (size_t)tt * K * 16);
+    // B operands: ranks 4s + kg of row jr; ranks >= k and rows outside the task give 0
+    double vb[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const bool va = s < S && ok && 4 * s + kg < k;
+      const unsigned o = va ? (unsigned)((c0 + 4 * s) * 16 + lane) : (unsigned)(c0 * 16 + jr);
+      vb[s] = *(const gdouble*)(tp + o * 8u);
     }
-    if (threadIdx.x < 64) ycol[threadIdx.x] = threadIdx.x < bw ? yc[bt + threadIdx.x] : 0;
-    __syncthreads();
-#pragma unroll 1
-    for (int r = tk.r0 + threadIdx.x; r < tk.r1; r += NTHREADS) {
-#pragma unroll 1
-      for (int a0 = 0; a0 < k; a0 += 16) {
-        T v[16];
+    // accumulators: register v of block q holds coarser column 16 q + row(kg, v), row jr;
+    // byte offsets within the tile are below 2^32 (K * 128 bytes per tile).  The table index
+    // is made opaque per tile so that its reads stay in the loop (an index, not a pointer,
+    // so that they stay LDS reads).
+    int yi = kg;
+    asm volatile("" : "+v"(yi));
+    d4 acc[NQ];
 #pragma unroll
-        for (int a = 0; a < 16; ++a) v[a] = (a0 + a < k) ? P[pix(r, c0 + a0 + a, K)] : T(0);
-        // 8 coarser columns at a time: their loads are issued together before any store
-        // (the columns are distinct, so no store can feed a later load)
-#pragma unroll 1
-        for (int b0 = 0; b0 < bw; b0 += 8) {
-          T old[8];
+    for (int q = 0; q < NQ; ++q) {
+      const uint4 c = yq[yi + 4 * q];
+      const unsigned cv[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
-          for (int j = 0; j < 8; ++j)
-            old[j] = (b0 + j < bw) ? P[pix(r, ycol[b0 + j], K)] : T(0);
-#pragma unroll 2
-          for (int a = 0; a < 16; ++a) {
-            const T va = v[a];
+      for (int v = 0; v < 4; ++v) acc[q][v] = *(const gdouble*)(tp + (cv[v] * 16u + (unsigned)jr) * 8u);
+    }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) old[j] += va * As[a0 + a][(b0 + j) & 63];
-          }
+    for (int s = 0; s < SM; ++s) vb[s] = (s < S && ok && 4 * s + kg < k) ? vb[s] : 0.0;
+    // the A operands are read from LDS per tile (an opaque base keeps the compiler from
+    // holding all of them in registers across tiles)
+    unsigned ab = (unsigned)lane * 8u;
+    asm volatile("" : "+v"(ab));
+    const char* Ab = reinterpret_cast<const char*>(Acf) + ab;
+    // all SM steps run (steps past the rank multiply zeros): a branch here would sink the
+    // loads of V into it and serialise their latencies
 #pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (b0 + j < bw) P[pix(r, ycol[b0 + j], K)] = old[j];
-        }
+    for (int s = 0; s < SM; ++s)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc[q] = Mfma<double>::step(*reinterpret_cast<const double*>(Ab + ((s * QB + q) * 64) * 8),
+                                    vb[s], acc[q]);
+    // the offsets are read again for the stores rather than kept live across the steps
+    int ys = kg;
+    asm volatile("" : "+v"(ys));
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const uint4 c = yq[ys + 4 * q];
+      const unsigned cv[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * q + Mfma<double>::row(kg, v);
+        if (ok && i < bw) *(gdouble*)(tp + (cv[v] * 16u + (unsigned)jr) * 8u) = acc[q][v];
       }
     }
   }
 }
-template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_update_panel(const k_update_panel_args<T> a_) {
-  k_update_panel_body<T>(a_, blockIdx.x, blockIdx.y, gridDim.y);
+// QB: 16-column blocks staged per work-group (8 when the A operands fit in 32 KB of LDS)
+template <int SM, int QB>
+__device__ __forceinline__ void k_update_panel_body(const k_update_panel_args& a_, const int bx_,
+                                                    const int by_, const int gy_) {
+  static_assert(QB == 4 || QB == 8, "chunks of 64 or 128 columns");
+  const Task* __restrict__ tasks = a_.tasks;
+  const int K = a_.K;
+  const int l = a_.l;
+  const int t = bx_;
+  (void)gy_;
+  if (t >= a_.ntask) return;
+  // every scalar below is block-uniform; readfirstlane says so to the compiler (a grouped
+  // launch reads them through pointers it cannot see as uniform), so that the tile walk and
+  // the tile base stay in scalar registers
+  Task tk = tasks[a_.tbase + t];
+  tk.h = __builtin_amdgcn_readfirstlane(tk.h);
+  tk.side = __builtin_amdgcn_readfirstlane(tk.side);
+  tk.r0 = __builtin_amdgcn_readfirstlane(tk.r0);
+  tk.r1 = __builtin_amdgcn_readfirstlane(tk.r1);
+  if (tk.side == 0) return;
+  const int k = __builtin_amdgcn_readfirstlane(a_.rank[tk.h]);
+  const int kl = __builtin_amdgcn_readfirstlane(a_.kmax[l]);
+  const int Wc = __builtin_amdgcn_readfirstlane(a_.rcount[l]) - kl;
+  if (k == 0 || Wc <= 0) return;
+  const int S = min((k + 3) >> 2, SM);  // MFMA steps (ranks never exceed the level's cap)
+  const int c0 = __builtin_amdgcn_readfirstlane(a_.coff[l]);
+  const int j = tk.h - ((1 << l) - 1);
+  const int* yc = a_.rcols + (size_t)l * K + kl;
+  const double* cf = a_.coef + (size_t)j * a_.cs_node;
+  const int cs_a = a_.cs_a;
+  constexpr int NW = NTHREADS / 64;
+  constexpr int CW = 16 * QB;  // columns per chunk
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform tile walk
+  const int T0 = tk.r0 >> 4, T1 = (tk.r1 + 15) >> 4;
+  // grid.y = gy x (column chunks): this work-group takes one chunk and every gy-th group of
+  // NW tiles of the task, so it stages its A operands once
+  const int gy = a_.gy;
+  const int chunk = by_ / gy, sub = by_ - chunk * gy;
+  const int bt = chunk * CW;
+  if (bt >= Wc) return;
+  const int bw = min(CW, Wc - bt);
+  __shared__ double Acf[SM][QB][64];  // step s, column block q: lane-ordered A operand
+  __shared__ __align__(16) int ycol[CW];
+  for (int idx = threadIdx.x; idx < SM * QB * 64; idx += NTHREADS) {  // zeros past step S
+    const int s = idx / (QB * 64), q = (idx >> 6) % QB, ln = idx & 63;
+    const int a = 4 * s + (ln >> 4), b = 16 * q + (ln & 15);
+    Acf[s][q][ln] = (a < k && b < bw) ? cf[(size_t)a * cs_a + bt + b] : 0.0;
+  }
+  // column table in accumulator order, entry (q, kg, v) = column 16 q + row(kg, v) of the
+  // chunk; a column past the chunk is the first column of V, which this kernel never writes
+  // (it is read and masked at the store)
+  if (threadIdx.x < CW) {
+    const int q = threadIdx.x >> 4, g = (threadIdx.x >> 2) & 3, v = threadIdx.x & 3;
+    const int i = 16 * q + Mfma<double>::row(g, v);
+    ycol[threadIdx.x] = i < bw ? yc[bt + i] : c0;
+  }
+  __syncthreads();
+  const int t0 = T0 + sub * NW + wv, ts = gy * NW;
+  const double* A = &Acf[0][0][0];
+#define FG_UPD_TILES(NQ) \
+  update_tiles<SM, QB, NQ>(A, ycol, a_.P, K, c0, k, S, bw, tk.r0, tk.r1, t0, T1, ts)
+  switch ((bw + 15) >> 4) {
+    case 1: FG_UPD_TILES(1); break;
+    case 2: FG_UPD_TILES(2); break;
+    case 3: FG_UPD_TILES(3); break;
+    case 4: FG_UPD_TILES(4); break;
+    case 5: if constexpr (QB == 8) FG_UPD_TILES(5); break;
+    case 6: if constexpr (QB == 8) FG_UPD_TILES(6); break;
+    case 7: if constexpr (QB == 8) FG_UPD_TILES(7); break;
+    default: if constexpr (QB == 8) FG_UPD_TILES(8); break;
+  }
+#undef FG_UPD_TILES
+}
+template <int SM, int QB>
+__global__ void __launch_bounds__(NTHREADS) k_update_panel(const k_update_panel_args a_) {
+  k_update_panel_body<SM, QB>(a_, blockIdx.x, blockIdx.y, gridDim.y);
 }
 // grouped: blocks [st_[j], st_[j+1]) of the grid run member j; gy_[j] is its grid.y
-template <typename T>
-__global__ void __launch_bounds__(NTHREADS) k_update_panel_g(const k_update_panel_args<T>* __restrict__ a_,
+template <int SM, int QB>
+__global__ void __launch_bounds__(NTHREADS) k_update_panel_g(const k_update_panel_args* __restrict__ a_,
                                    const int* __restrict__ st_, const int* __restrict__ gyv_,
                                    int m_) {
   const int j = group_member(st_, m_, blockIdx.x);
   if ((int)blockIdx.y >= gyv_[j]) return;
-  k_update_panel_body<T>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
+  k_update_panel_body<SM, QB>(a_[j], blockIdx.x - st_[j], blockIdx.y, gyv_[j]);
 }
-template <typename T>
+template <int SM, int QB>
 static void k_update_panel_grp(GroupExec& ex, const RecLaunch* const* mem, int m) {
-  grouped_launch<k_update_panel_args<T>>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
-                                  const k_update_panel_args<T>* a, const int* st, const int* gy, int mm) {
-    k_update_panel_g<T><<<g, b, lds, s>>>(a, st, gy, mm);
+  grouped_launch<k_update_panel_args>(ex, mem, m, [](dim3 g, dim3 b, uint32_t lds, hipStream_t s,
+                                  const k_update_panel_args* a, const int* st, const int* gy, int mm) {
+    k_update_panel_g<SM, QB><<<g, b, lds, s>>>(a, st, gy, mm);
   });
 }
 // launches k_update_panel now, or records it while a recorder is open on this thread
-template <typename T>
-static void k_update_panel_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
-                             const k_update_panel_args<T>& a) {
+template <int SM, int QB>
+static void k_update_panel_launch1(int ntask, int wcap, hipStream_t s, k_update_panel_args a) {
+  const dim3 g(ntask, a.gy * std::max(1, (wcap + 16 * QB - 1) / (16 * QB))), b(NTHREADS);
   if (recording())
-    record_group(k_update_panel_grp<T>, group_key((const void*)k_update_panel_grp<T>, b, lds), g, b, lds, &a,
-                 sizeof(a));
+    record_group(k_update_panel_grp<SM, QB>, group_key((const void*)k_update_panel_grp<SM, QB>, b, 0),
+                 g, b, 0, &a, sizeof(a));
   else
-    k_update_panel<T><<<g, b, lds, s>>>(a);
+    k_update_panel<SM, QB><<<g, b, 0, s>>>(a);
+}
+// The variant whose registers hold ceil(kcap / 4) steps, with 128-column chunks while their
+// A operands fit in 32 KB of LDS; wcap bounds the coarser columns and trows the rows of a
+// task.  One work-group per task while a task has at most 32 row tiles, two above.
+static void k_update_panel_launch(int kcap, int wcap, int trows, int ntask, hipStream_t s,
+                                  k_update_panel_args a) {
+  a.gy = trows / 16 > 32 ? 2 : 1;
+  const int sm = (std::max(kcap, 1) + 3) / 4;
+  if (sm <= 4)
+    k_update_panel_launch1<4, 8>(ntask, wcap, s, a);
+  else if (sm <= 8)
+    k_update_panel_launch1<8, 8>(ntask, wcap, s, a);
+  else if (sm <= 12)
+    k_update_panel_launch1<12, 4>(ntask, wcap, s, a);
+  else
+    k_update_panel_launch1<16, 4>(ntask, wcap, s, a);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1609,9 +1705,9 @@ static void factor_levels(FactorData& F, const double* alpha_dev, hipStream_t s)
         kc});
     if (l > 0) {
       timer_before(KID_UPDATE, s, l, P, H.kmax, nt);
-      k_update_panel_launch<double>(dim3(nt), dim3(NTHREADS), 0, s, k_update_panel_args<double>{D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax,
-                                                H.rcols, H.rcount, P.Ktot, panel, H.ld, F.coef,
-                                                cs_node, cs_a});
+      k_update_panel_launch(P.kcap[l], P.coff[l], P.max_trows[l], nt, s,
+                            k_update_panel_args{D.ltasks, tb, nt, l, H.rank, D.coff, H.kmax, H.rcols,
+                                                H.rcount, P.Ktot, panel, F.coef, cs_node, cs_a, 1});
       timer_after(KID_UPDATE, s);
     }
   }
