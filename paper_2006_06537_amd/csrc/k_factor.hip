@@ -286,11 +286,14 @@ static void k_leaf_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
 // v_mfma_f64_16x16x4f64 takes A (16 x 4) with lane l holding A[l%16][l/16], B (4 x 16)
 // with lane l holding B[l/16][l%16], and accumulates D (16 x 16) with lane l holding
 // D[l/16 + 4 v][l%16], v = 0..3 (layout checked on gfx950).  Here M = left columns a, N = right columns b and
-// K = rows.  A work-group stages 32 rows x (left + 64 right) columns in LDS per step
-// (coalesced along rows); each wave owns 16 right columns and all left tiles.
+// K = rows.  Each wave owns 16 right columns and all left tiles and reads 16 rows of them
+// per step straight from the panel (16-byte loads of four rows of a column).
 // ---------------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+// global-address-space views, for accesses the compiler would otherwise make flat
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) double gdouble;
 
 // one 16 x 16 x 4 MFMA step in the precision of the panel, and the accumulator row of
 // (lane group kg, register v): f64 puts row kg + 4 v in register v, f32 row 4 kg + v
@@ -472,10 +475,11 @@ static void k_reduce_panel_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
 // stored in FP32 (TL = float, the mixed-precision factor); the substitution is FP64.
 //
 // The 28 strictly lower 16 x 16 blocks of L (negated) and the 8 diagonal-block inverses
-// D_j^-1 are staged in LDS once (pitch 17).  Each wave owns 16 panel columns at a time
-// and keeps the leaf's 8 row blocks in MFMA accumulators; a finished block's register s
-// is exactly the B operand of K-step s (rows Mfma::kcol), so results feed the next
-// products without moving.  Every column is read once and written once.
+// D_j^-1 are staged in LDS once (pitch 17), with each thread's loads issued in batches.
+// Each wave owns two groups of 16 panel columns at a time, keeps the leaf's 8 row blocks
+// of both in MFMA accumulators, and feeds every operand read from LDS to both; a finished
+// block's register s is exactly the B operand of K-step s (rows Mfma::kcol), so results
+// feed the next products without moving.  Every column is read once and written once.
 // ---------------------------------------------------------------------------------
 constexpr int WB = BMAX / 16;          // 16-row blocks per leaf (8)
 constexpr int WTRI = WB * (WB + 1) / 2;  // lower blocks (36)
@@ -517,88 +521,160 @@ __device__ __forceinline__ void k_whiten_body(const k_whiten_args<T, TL>& a_, co
   (void)by_;
   (void)gy_;
 
-  typedef typename Mfma<T>::acc_t acc_t;
+  static_assert(sizeof(T) == 8, "the whitening runs in FP64");
   const int b = bx_;
   if (b >= nleaf) return;
-  const int lo = leaf_lo[b], m = leaf_lo[b + 1] - lo;
+  const int lo = __builtin_amdgcn_readfirstlane(leaf_lo[b]);
+  const int m = __builtin_amdgcn_readfirstlane(leaf_lo[b + 1]) - lo;
   const int nb = (m + 15) >> 4;
-  __shared__ T Ls[WTRI * 16 * WPD];
+  __shared__ double Ls[WTRI * 16 * WPD];
   const TL* Lg = leafL + (size_t)b * Bc * Bc;
   const TL* Dg = leafLinv + (size_t)b * Bc * Bc;
+  int total = 0;
+  for (int l = 0; l < L; ++l) total += kmax[l];
+  total = __builtin_amdgcn_readfirstlane(total);
+  const int ngrp = (total + 15) >> 4;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cl = lane & 15, kg = lane >> 4;
+  // panel entries as byte offsets from the leaf's first row tile (below 2^32: at most 9
+  // tiles of K * 128 bytes), wave-uniform base in the global address space
+  const gchar* sb = (const gchar*)(src + (size_t)(lo >> 4) * K * 16);
+  gchar* db = (gchar*)(dst + (size_t)(lo >> 4) * K * 16);
+  const int r0 = lo & 15;
+  auto off = [&](int row, int gc) -> unsigned {
+    const int rr = r0 + row;
+    return (unsigned)((((rr >> 4) * K + gc) * 16 + (rr & 15)) * 8);
+  };
+  // panel column of group g for this lane (-1 past the last active column)
+  auto column = [&](int g) -> int {
+    int f = 16 * g + cl;
+    if (f >= total) return -1;
+    for (int l = 0; l < L; ++l) {
+      const int km = kmax[l];
+      if (f < km) return coff[l] + f;
+      f -= km;
+    }
+    return -1;
+  };
+  // rows past the leaf and columns past the last read a valid entry (row 0, column 0) and
+  // are replaced by zero; all loads are issued before any is used
+  auto load = [&](int gc, d4 (&acc)[WB]) {
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + Mfma<double>::row(kg, v);
+        const bool ok = gc >= 0 && row < m;
+        acc[i][v] = *(const gdouble*)(sb + (ok ? off(row, gc) : off(0, 0)));
+      }
+#pragma unroll
+    for (int i = 0; i < WB; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + Mfma<double>::row(kg, v);
+        acc[i][v] = (gc >= 0 && row < m) ? acc[i][v] : 0.0;
+      }
+  };
+  // Each wave takes column groups w and w + 4 (then w + 8 and w + 12, ...) together: two
+  // independent substitutions share every A operand read from LDS.  The first pair's panel
+  // reads are issued before the factor is staged, so their latency overlaps the staging.
+  int g0 = w;
+  int gcA = column(g0), gcB = column(g0 + 4);
+  d4 accA[WB], accB[WB];
+  load(gcA, accA);
+  load(gcB, accB);
   // stage: element (r, c) of block t = (bi, bj) at Ls[t*16*WPD + r*WPD + c]; r runs
   // fastest so that reads of the column-major factors are contiguous.  A factor held in
-  // FP32 is widened exactly: the products below are those of that factor, in FP64.
-  for (int idx = threadIdx.x; idx < WTRI * 256; idx += NTHREADS) {
-    const int t = idx >> 8, e = idx & 255, r = e & 15, c = e >> 4;
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-    const int bj = t - bi * (bi + 1) / 2;
-    const int gr = bi * 16 + r, gcol = bj * 16 + c;
-    T v = T(0);
-    if (bi == bj) {
-      if (gr < m && c <= r) v = (T)Dg[gr + (size_t)gcol * Bc];
-    } else if (bi < nb && gr < m) {
-      v = -(T)Lg[gr + (size_t)gcol * Bc];
+  // FP32 is widened exactly: the products below are those of that factor, in FP64.  Blocks
+  // and rows past the leaf are zero, so the substitution below runs on all WB blocks.
+  // Thread x stages element x of every block (WTRI x 256 elements, 256 threads), so each
+  // block index is a compile-time constant and the loads go out SB at a time rather than
+  // one round trip each.
+  static_assert(NTHREADS == 256, "one element of every staged block per thread");
+  {
+    constexpr int SB = 12;  // loads in flight per thread while staging
+    static_assert(WTRI % SB == 0, "staging batches");
+    const int r = threadIdx.x & 15, c = threadIdx.x >> 4;
+#pragma unroll
+    for (int t0 = 0; t0 < WTRI; t0 += SB) {
+      double v[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int t = t0 + u;
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+        const int bj = t - bi * (bi + 1) / 2;
+        const int gr = bi * 16 + r, gcol = bj * 16 + c;
+        // entries outside the leaf read entry 0 (always valid) and are replaced by zero
+        const bool ok = bi == bj ? (gr < m && c <= r) : (bi < nb && gr < m);
+        const size_t e = ok ? gr + (size_t)gcol * Bc : 0;
+        v[u] = (double)(bi == bj ? Dg[e] : Lg[e]);
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int t = t0 + u;
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+        const int bj = t - bi * (bi + 1) / 2;
+        const int gr = bi * 16 + r;
+        const bool ok = bi == bj ? (gr < m && c <= r) : (bi < nb && gr < m);
+        Ls[t * 16 * WPD + r * WPD + c] = ok ? (bi == bj ? v[u] : -v[u]) : 0.0;
+      }
     }
-    Ls[t * 16 * WPD + r * WPD + c] = v;
   }
   __syncthreads();
   const double alpha = alpha_p ? *alpha_p : alpha_v;
-  const T sa = (T)sqrt(alpha);
-  int total = 0;
-  for (int l = 0; l < L; ++l) total += kmax[l];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int cl = lane & 15, kg = lane >> 4;
-  for (int p0 = 16 * w; p0 < total; p0 += 64) {
-    int f = p0 + cl, gc = -1;
-    if (f < total) {
-      for (int l = 0; l < L; ++l) {
-        const int km = kmax[l];
-        if (f < km) { gc = coff[l] + f; break; }
-        f -= km;
-      }
-    }
-    acc_t acc[WB];
-#pragma unroll
-    for (int i = 0; i < WB; ++i) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = i * 16 + Mfma<T>::row(kg, v);
-        acc[i][v] = (gc >= 0 && row < m) ? (T)src[pix(lo + row, gc, K)] : T(0);
-      }
-    }
+  const double sa = sqrt(alpha);
+  for (;;) {
+    if (g0 >= ngrp) break;
 #pragma unroll
     for (int j = 0; j < WB; ++j) {
-      if (j < nb) {
-        const T* Dj = Ls + (j * (j + 1) / 2 + j) * 16 * WPD + cl * WPD;
-        acc_t y = acc_t{T(0), T(0), T(0), T(0)};
+      // the lane's operand offset is made opaque per block, so that the compiler reads a
+      // block's four operands just before its steps rather than all of them up front
+      auto opnd = [&](int i, int s4, unsigned lb) -> double {
+        return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Ls) + lb +
+                                                (((i * (i + 1) / 2 + j) * 16 * WPD) + 4 * s4) * 8);
+      };
+      unsigned lb = (unsigned)(cl * WPD + kg) * 8u;
+      asm volatile("" : "+v"(lb));
+      d4 yA = d4{0.0, 0.0, 0.0, 0.0}, yB = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          y = Mfma<T>::step(Dj[Mfma<T>::kcol(kg, s4)], acc[j][s4], y);
-        acc[j] = y;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double d = opnd(j, s4, lb);
+        yA = Mfma<double>::step(d, accA[j][s4], yA);
+        yB = Mfma<double>::step(d, accB[j][s4], yB);
+      }
+      accA[j] = yA;
+      accB[j] = yB;
 #pragma unroll
-        for (int i = 0; i < WB; ++i) {
-          if (i > j && i < nb) {
-            const T* A = Ls + (i * (i + 1) / 2 + j) * 16 * WPD + cl * WPD;
+      for (int i = j + 1; i < WB; ++i) {
+        unsigned li = (unsigned)(cl * WPD + kg) * 8u;
+        asm volatile("" : "+v"(li));
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-              acc[i] = Mfma<T>::step(A[Mfma<T>::kcol(kg, s4)], acc[j][s4], acc[i]);
-          }
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double a = opnd(i, s4, li);
+          accA[i] = Mfma<double>::step(a, accA[j][s4], accA[i]);
+          accB[i] = Mfma<double>::step(a, accB[j][s4], accB[i]);
         }
       }
     }
-    if (gc >= 0) {
 #pragma unroll
-      for (int bi = 0; bi < WB; ++bi) {
-        if (bi < nb) {
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = bi * 16 + Mfma<T>::row(kg, v);
-            if (row < m) dst[pix(lo + row, gc, K)] = sa * acc[bi][v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int row = i * 16 + Mfma<double>::row(kg, v);
+        if (row < m) {
+          if (gcA >= 0) *(gdouble*)(db + off(row, gcA)) = sa * accA[i][v];
+          if (gcB >= 0) *(gdouble*)(db + off(row, gcB)) = sa * accB[i][v];
         }
       }
-    }
+    g0 += 8;
+    if (g0 >= ngrp) break;
+    gcA = column(g0);
+    gcB = column(g0 + 4);
+    load(gcA, accA);
+    load(gcB, accB);
   }
 }
 template <typename T, typename TL>
@@ -1341,8 +1417,6 @@ static void k_node_factor_launch(dim3 g, dim3 b, uint32_t lds, hipStream_t s,
 // levels take further work-groups along grid.y, and gy work-groups share one level task
 // so that the grid fills the chip.
 // ---------------------------------------------------------------------------------
-typedef __attribute__((address_space(1))) char gchar;
-typedef __attribute__((address_space(1))) double gdouble;
 // arguments of k_update_panel (one struct, so that grouped launches can stage one per member)
 struct k_update_panel_args {
   const Task* tasks;
