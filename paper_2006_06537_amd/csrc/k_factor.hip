@@ -1553,10 +1553,26 @@ __device__ __forceinline__ void k_update_panel_body(const k_update_panel_args& a
   const int bw = min(CW, Wc - bt);
   __shared__ double Acf[SM][QB][64];  // step s, column block q: lane-ordered A operand
   __shared__ __align__(16) int ycol[CW];
-  for (int idx = threadIdx.x; idx < SM * QB * 64; idx += NTHREADS) {  // zeros past step S
-    const int s = idx / (QB * 64), q = (idx >> 6) % QB, ln = idx & 63;
-    const int a = 4 * s + (ln >> 4), b = 16 * q + (ln & 15);
-    Acf[s][q][ln] = (a < k && b < bw) ? cf[(size_t)a * cs_a + bt + b] : 0.0;
+  {
+    // zeros past step S; each thread's NST loads are issued together (an entry outside
+    // reads entry 0 and is replaced by zero)
+    constexpr int NST = SM * QB * 64 / NTHREADS;
+    static_assert(NST * NTHREADS == SM * QB * 64, "whole staging trips");
+    double st[NST];
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int idx = threadIdx.x + u * NTHREADS;
+      const int s = idx / (QB * 64), q = (idx >> 6) % QB, ln = idx & 63;
+      const int a = 4 * s + (ln >> 4), b = 16 * q + (ln & 15);
+      st[u] = cf[(a < k && b < bw) ? (size_t)a * cs_a + bt + b : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int idx = threadIdx.x + u * NTHREADS;
+      const int s = idx / (QB * 64), q = (idx >> 6) % QB, ln = idx & 63;
+      const int a = 4 * s + (ln >> 4), b = 16 * q + (ln & 15);
+      Acf[s][q][ln] = (a < k && b < bw) ? st[u] : 0.0;
+    }
   }
   // column table in accumulator order, entry (q, kg, v) = column 16 q + row(kg, v) of the
   // chunk; a column past the chunk is the first column of V, which this kernel never writes
@@ -1633,6 +1649,21 @@ static void k_update_panel_launch(int kcap, int wcap, int trows, int ntask, hipS
 // ---------------------------------------------------------------------------------
 // log-det: sum of leaf and node parts in a fixed order
 // ---------------------------------------------------------------------------------
+// s += v[i] for i = tid, tid + NTHREADS, ... < n, in that order, with 8 loads in flight
+__device__ __forceinline__ double strided_sum(const double* __restrict__ v, int n, double s) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * NTHREADS) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NTHREADS;
+      x[u] = i < n ? v[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * NTHREADS < n) s += x[u];
+  }
+  return s;
+}
 // arguments of k_logdet_sum (one struct, so that grouped launches can stage one per member)
 struct k_logdet_sum_args {
   const double* leaf_ld;
@@ -1652,9 +1683,8 @@ __device__ __forceinline__ void k_logdet_sum_body(const k_logdet_sum_args& a_, c
   (void)gy_;
 
   __shared__ double red[NTHREADS / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nleaf; i += NTHREADS) s += leaf_ld[i];
-  for (int i = threadIdx.x; i < nint; i += NTHREADS) s += node_ld[i];
+  double s = strided_sum(leaf_ld, nleaf, 0.0);
+  s = strided_sum(node_ld, nint, s);
   s = wsum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -1813,9 +1843,7 @@ __global__ void k_logdet_parts(const double* __restrict__ leaf_ld, int nleaf,
                                const double* __restrict__ node_ld, int nint,
                                double* __restrict__ out) {
   __shared__ double red[2][NTHREADS / 64];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nleaf; i += NTHREADS) a += leaf_ld[i];
-  for (int i = threadIdx.x; i < nint; i += NTHREADS) b += node_ld[i];
+  double a = strided_sum(leaf_ld, nleaf, 0.0), b = strided_sum(node_ld, nint, 0.0);
   a = wsum(a);
   b = wsum(b);
   if ((threadIdx.x & 63) == 0) {
