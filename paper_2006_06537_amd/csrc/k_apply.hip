@@ -256,7 +256,18 @@ __device__ __forceinline__ void k_leaf_apply_t_body(const k_leaf_apply_t_args<T>
     const int r = i * 16 + rr;
     double t = 0.0;
     if (c < nrhs && r < m)
-      for (int s = (i + 1) * 16 + q; s < m; s += 4) t += (double)Mb[s + (size_t)r * Bc] * vs[c][s];
+      // eight loads in flight, added in the order of s (a row past the leaf reads row 0)
+      for (int s0 = (i + 1) * 16 + q; s0 < m; s0 += 32) {
+        double p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int s = s0 + 4 * u;
+          p[u] = (double)Mb[(s < m ? s : 0) + (size_t)r * Bc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (s0 + 4 * u < m) t += p[u] * vs[c][s0 + 4 * u];
+      }
     t += __shfl_xor(t, 1, 64);
     t += __shfl_xor(t, 2, 64);
     if (q == 0 && c < nrhs) ts[c][rr] = (r < m) ? vs[c][r] - t : 0.0;
@@ -265,8 +276,16 @@ __device__ __forceinline__ void k_leaf_apply_t_body(const k_leaf_apply_t_args<T>
     if (q == 0 && c < nrhs && r < m) {
       double u = 0.0;
       const int r0 = i * 16, mi = min(16, m - r0);
-      for (int s2 = rr; s2 < mi; ++s2)
-        u += (double)Db[(r0 + s2) + (size_t)(r0 + rr) * Bc] * ts[c][s2];
+      // the row's entries loaded together, then added in the order of s2
+      double p[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int s2 = rr + k;
+        p[k] = (double)Db[(r0 + (s2 < mi ? s2 : rr)) + (size_t)(r0 + rr) * Bc];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (rr + k < mi) u += p[k] * ts[c][rr + k];
       vs[c][r] = u;
     }
     __syncthreads();
